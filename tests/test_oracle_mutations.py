@@ -1,0 +1,48 @@
+"""Plant plausible mistakes in copies of the oracle (on the CPU) and check that the pins
+in test_oracle.py catch every one.  Shows the pins are sensitive to a dropped term, a
+wrong sign, a wrong factor and a transposed operand."""
+import os
+import subprocess
+
+import pytest
+
+import oracle as O
+import tests.test_oracle as T
+
+SRC = os.path.join(os.path.dirname(O.__file__), "md_oracle.c")
+
+MUTATIONS = [
+    # (name, original text, replacement, pin that must fail)
+    ("drop F'(rho_j) term of Eq. 1", "g += (dF[i] + dF[j]) * dens_df(p, r);",
+     "g += (dF[i] + dF[i]) * dens_df(p, r);", T.test_force_is_minus_energy_gradient_bulk),
+    ("wrong sign of the minimum-image shift", "            d -= b->len[a];\n        else if (d < -half)",
+     "            d += b->len[a];\n        else if (d < -half)",
+     lambda: T.test_neighbor_sets_vs_kdtree(300, 12.0, (1, 1, 1))),
+    ("pair energy not halved", "e += 0.5 * pair_phi(p, r);", "e += pair_phi(p, r);",
+     T.test_perfect_bcc_lattice_closed_form),
+    ("Verlet drift without the 1/2", "v[3 * i + a] * dt + 0.5 * ai * dt * dt;",
+     "v[3 * i + a] * dt + ai * dt * dt;", T.test_morse_oscillator_matches_ode_solution),
+    ("Morse force direction transposed", "for (int a = 0; a < 3; ++a) fi[a] += -g * (-s[a]) / r;\n                e += morse_phi",
+     "for (int a = 0; a < 3; ++a) fi[a] += -g * (s[a]) / r;\n                e += morse_phi",
+     T.test_force_is_minus_energy_gradient_film_with_indenter),
+    ("density cutoff uses the pair cutoff", "if (r < p->d) acc += dens_f(p, r);\n        });",
+     "if (r < p->c) acc += dens_f(p, r);\n        });",
+     T.test_lattice_energy_vs_lattice_constant_is_smooth_and_consistent),
+    ("rebuild test at full skin", "double lim = 0.5 * P->skin;", "double lim = P->skin;",
+     T.test_half_skin_rule_catches_approaching_pair),
+]
+
+
+@pytest.mark.parametrize("name,old,new,pin", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pin_catches_planted_mistake(tmp_path, name, old, new, pin):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor not unique: {name}"
+    mutated = tmp_path / "md_oracle_mut.c"
+    mutated.write_text(src.replace(old, new))
+    so = tmp_path / "liborc_mut.so"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+                    "-o", str(so), str(mutated), "-lm"], check=True)
+    pin()  # the pin passes on the real oracle
+    with O.use_library(str(so)):
+        with pytest.raises((AssertionError, ValueError)):
+            pin()
