@@ -1,0 +1,256 @@
+/*
+ * md.h -- C ABI of the MI355X (gfx950) short-range molecular-dynamics step:
+ * cell binning + Verlet neighbour lists, two-pass Embedded Atom Method (EAM) forces for
+ * Cr-Cr, Morse forces between Cr and a rigid carbon indenter, velocity-Verlet update.
+ *
+ * The calls follow the five tasks of one MD time step in the paper (Section 2.1 and
+ * Table 1):
+ *   Task 1  neighbour-list update             -> md_build_neighbors
+ *   Task 2  indenter motion                   -> md_verlet_step (MD_PHASE_KICK_DRIFT)
+ *   Task 3  positions + half-step velocities  -> md_verlet_step (MD_PHASE_KICK_DRIFT)
+ *   Task 4  density, forces, energies         -> md_eam_forces, md_morse_forces, md_energy
+ *   Task 5  final velocity update             -> md_verlet_step (MD_PHASE_KICK), or fused
+ *                                                into md_eam_forces with MD_F_KICK
+ *
+ * Conventions shared by every call
+ *   - Units: eV, Angstrom, fs, u.  All state is FP64.
+ *   - Every pointer inside md_atoms / md_lists and the workspace is DEVICE memory owned by
+ *     the caller; the library never allocates or frees device memory.  The md_system
+ *     handle is host memory allocated by md_system_create and freed by md_system_destroy.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Calls only
+ *     enqueue work; they return before the GPU is done, except md_check and
+ *     md_workspace_bind, which synchronise the stream.
+ *   - Return value: MD_OK (0) or an MD_ERR_* code, detected on the host before anything is
+ *     enqueued (bad arguments) or reported by the HIP runtime.  Conditions found on the
+ *     GPU (list overflow, non-finite forces) are raised as device flags read by md_check.
+ *   - Atoms of one system ("replica") occupy a contiguous range of the atom arrays,
+ *     padded up to a multiple of MD_TILE atoms; several replicas are laid out one after
+ *     the other (batched mode).  Padding slots are never read or written.
+ *   - The library is not thread safe for one md_system; distinct systems are independent.
+ */
+#ifndef MD_H
+#define MD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MD_API __attribute__((visibility("default")))
+
+/* Status codes */
+#define MD_OK 0
+#define MD_ERR_ARG 1       /* invalid argument (NULL pointer, bad size, box too small, ...) */
+#define MD_ERR_HIP 2       /* a HIP runtime call failed */
+#define MD_ERR_STATE 3     /* call out of order (e.g. no workspace bound) */
+
+/* Atoms per tile: replica ranges are padded to a multiple of this. */
+#define MD_TILE 256
+
+/* Arithmetic of the pair/density loops. */
+#define MD_FP64 0          /* everything in FP64 */
+#define MD_MIXED 1         /* pair, density and force arithmetic in FP32; state, Verlet update
+                              and energy/virial reductions in FP64 */
+
+/* md_verlet_step phases */
+#define MD_PHASE_KICK_DRIFT 1  /* Tasks 2 + 3: indenter moves by v_ind*dt; v += a dt/2; x += v dt */
+#define MD_PHASE_KICK 2        /* Task 5: v += a dt/2 */
+
+/* md_eam_forces / md_morse_forces flags */
+#define MD_F_DENSITY 0x01  /* pass 1: rho_i, F'(rho_i) into q[i][3] */
+#define MD_F_FORCE 0x02    /* pass 2: Eq. (1) forces into f (overwrites f) */
+#define MD_F_MORSE 0x04    /* pass 2 also adds the Cr-C Morse forces (fused Task 4c) */
+#define MD_F_KICK 0x08     /* pass 2 also applies the Task 5 half kick with the total force */
+#define MD_F_ENERGY 0x10   /* write per-block energy / virial / load partials for md_energy */
+#define MD_F_MIXED 0x20    /* FP32 pair arithmetic (MD_MIXED) */
+
+/* md_build_neighbors flags */
+#define MD_B_FORCE 0x01    /* rebuild now, whatever the skin test says */
+
+/* Observables written by md_energy, per replica (MD_NOBS doubles each). */
+#define MD_E_EMBED 0       /* sum_i F(rho_i)                         (Eq. A1, first term) */
+#define MD_E_PAIR 1        /* 1/2 sum_{i != j} phi(r_ij)             (Eq. A1, second term) */
+#define MD_E_MORSE 2       /* sum over Cr-C pairs of phiM(r) - phiM(rc) */
+#define MD_E_KIN 3         /* 1/2 m v^2 over mobile atoms */
+#define MD_W_XX 4          /* EAM virial W_ab = sum_{i<j} (q_i-q_j)_a F_ij,b: xx yy zz xy xz yz */
+#define MD_F_IND_X 10      /* load on the indenter = -(sum of Morse forces on Cr), x y z */
+#define MD_IND_Z 13        /* indenter displacement along z */
+#define MD_NBUILDS 14      /* number of list builds so far */
+#define MD_NOBS 16
+
+/* ---------------------------------------------------------------------------------- */
+/* Descriptions                                                                         */
+/* ---------------------------------------------------------------------------------- */
+
+/* Synthetic Finnis-Sinclair-form EAM (Section 3.1, Eq. 1; energy of Eq. A1 without M):
+ *   phi(r) = (r-c)^2 (c0 + c1 r + c2 r^2), r < c;  f(r) = (r-d)^2, r < d;  F(rho) = -A sqrt(rho). */
+typedef struct md_eam_params {
+    double A, c, d, c0, c1, c2;
+} md_eam_params;
+
+/* Cr-C Morse (form of Eq. A5): phiM(r) = D [exp(-2 alpha (r-r0)) - 2 exp(-alpha (r-r0))],
+ * r < rc; the energy is shifted by -phiM(rc), the force is not. */
+typedef struct md_morse_params {
+    double D, alpha, r0, rc;
+} md_morse_params;
+
+typedef struct md_params {
+    md_eam_params eam;
+    md_morse_params morse;
+    double mass;        /* Cr mass, u */
+    double dt;          /* time step, fs */
+    double v_ind;       /* indenter velocity along z, Angstrom/fs (Task 2) */
+    double skin;        /* Verlet skin, Angstrom; lists hold pairs closer than cutoff + skin */
+    int32_t cap;        /* Cr-Cr list capacity per atom */
+    int32_t xcap;       /* Cr-C list capacity per atom */
+} md_params;
+
+/* One system (replica). */
+typedef struct md_replica_desc {
+    double lo[3];       /* box lower corner */
+    double len[3];      /* periodic length (periodic axes) or extent of the cell grid (open
+                           axes; atoms outside are still handled correctly) */
+    int32_t periodic[3];
+    int32_t n;          /* Cr atoms */
+    int32_t n_c;        /* carbon atoms of the indenter (may be 0) */
+    int32_t pad;
+} md_replica_desc;
+
+/* Device arrays of all replicas (n_total = md_system_atoms(sys) slots). */
+typedef struct md_atoms {
+    double *q;          /* [n_total][4]: x, y, z and F'(rho) -- the paper's position +
+                           embedding-derivative array (Section 3.1) */
+    double *v;          /* [n_total][3] velocities, Angstrom/fs */
+    double *f;          /* [n_total][3] forces, eV/Angstrom */
+    uint8_t *fixed;     /* [n_total] 1 = atom held fixed (bottom layer) */
+    int32_t *id;        /* [n_total] caller's atom id; permuted together with the atoms */
+    const double *xc;   /* [c_total][3] carbon positions at zero indenter displacement */
+} md_atoms;
+
+/* Device neighbour lists (caller-owned, written by md_build_neighbors). */
+typedef struct md_lists {
+    int32_t *idx;       /* [cap][n_total]: entry k of atom i at idx[k * n_total + i] (atom slot) */
+    int32_t *cnt;       /* [n_total] */
+    int32_t *xidx;      /* [xcap][n_total]: carbon indices (into xc) of atom i's Cr-C list */
+    int32_t *xcnt;      /* [n_total] */
+} md_lists;
+
+/* Host copy of the device status flags (md_check). */
+typedef struct md_status {
+    int32_t overflow;       /* largest Cr-Cr list count that did not fit in cap (0 = none) */
+    int32_t xoverflow;      /* same for the Cr-C list and xcap */
+    int32_t nonfinite;      /* 1 if a non-finite force or density was produced */
+    int32_t nbuilds;        /* list builds so far (summed over replicas) */
+    int32_t sync_timeout;   /* 1 if a grid-wide wait gave up (the affected call is invalid) */
+    int32_t pad[3];
+} md_status;
+
+typedef struct md_system md_system;
+
+/* ---------------------------------------------------------------------------------- */
+/* Set-up                                                                               */
+/* ---------------------------------------------------------------------------------- */
+
+/* Create a handle for nrep replicas (host allocation only).  Checks that every periodic
+ * axis holds at least 3 list cells (length >= 3 (c + skin)).  MD_ERR_ARG on bad input. */
+MD_API int md_system_create(const md_replica_desc *reps, int32_t nrep, const md_params *p,
+                            md_system **out);
+MD_API void md_system_destroy(md_system *sys);
+
+/* Atom slots (n_total), carbon slots (c_total), and the first atom slot of replica r. */
+MD_API int64_t md_system_atoms(const md_system *sys);
+MD_API int64_t md_system_carbons(const md_system *sys);
+MD_API int64_t md_replica_offset(const md_system *sys, int32_t r);
+
+/* Bytes of device workspace the system needs (cell grids, sort buffers, reference
+ * positions, flags, reduction partials). */
+MD_API size_t md_workspace_bytes(const md_system *sys);
+
+/* Bind a caller-owned device workspace of at least md_workspace_bytes bytes: writes the
+ * replica descriptors, clears flags, and synchronises `stream`.  MD_ERR_ARG if too small. */
+MD_API int md_workspace_bind(md_system *sys, void *ws, size_t bytes, void *stream);
+
+/* ---------------------------------------------------------------------------------- */
+/* The step                                                                             */
+/* ---------------------------------------------------------------------------------- */
+
+/* Task 1 (Section 2.6): if any atom moved more than skin/2 since the last build (or the
+ * indenter did, or MD_B_FORCE), wrap periodic coordinates into the box, bin atoms into
+ * cells of edge >= cutoff + skin, sort the atoms of each replica by (cell, id) -- the atom
+ * arrays q, v, f, fixed, id are permuted in place --, record reference positions and
+ * rebuild the full Cr-Cr list {j != i: |q_j - q_i|^2 < (c+skin)^2} and the Cr-C list
+ * {k: |xc_k + ind_z - q_i|^2 < (rc+skin)^2}.  The test runs on the device; when it fails
+ * the call costs one short kernel.  Overflow is flagged, not fatal: the list keeps cap
+ * entries and md_check reports the count needed. */
+MD_API int md_build_neighbors(md_system *sys, const md_atoms *a, const md_lists *l,
+                              uint32_t flags, void *stream);
+
+/* Task 4a/4b (Section 3.1, Eq. 1; Section 3.3.1.2-3): MD_F_DENSITY computes
+ * rho_i = sum_j f(r_ij) and stores F'(rho_i) in q[i][3] (rho_out, if not NULL, receives rho
+ * per atom slot); MD_F_FORCE computes
+ *   F_i = - sum_j [(F'(rho_i) + F'(rho_j)) f'(r_ij) + phi'(r_ij)] (q_i - q_j) / r_ij
+ * into f over the Cr-Cr list (each atom gathers over its full list: no atomics).  With
+ * MD_F_MORSE the Cr-C Morse forces of md_morse_forces are added in the same pass; with
+ * MD_F_KICK the Task 5 half kick v += F/m dt/2 follows (mobile atoms).  MD_F_MIXED selects
+ * FP32 arithmetic.  Lists must be current (md_build_neighbors in the same step). */
+MD_API int md_eam_forces(md_system *sys, const md_atoms *a, const md_lists *l, uint32_t flags,
+                         double *rho_out, void *stream);
+
+/* Task 4c: Cr-C Morse forces added into f (F_i += -phiM'(r) (q_i - q_k)/r over the Cr-C
+ * list) and the load on the indenter (minus their sum).  Flags: MD_F_KICK applies the half
+ * kick of these forces only, MD_F_ENERGY writes partials, MD_F_MIXED FP32 arithmetic. */
+MD_API int md_morse_forces(md_system *sys, const md_atoms *a, const md_lists *l, uint32_t flags,
+                           void *stream);
+
+/* Tasks 2+3 (MD_PHASE_KICK_DRIFT, Eqs. A11-A12) or Task 5 (MD_PHASE_KICK) for all mobile
+ * atoms, a = F/m.  KICK_DRIFT also moves the indenter and measures displacements for the
+ * skin test of the next md_build_neighbors.  Positions are not wrapped here. */
+MD_API int md_verlet_step(md_system *sys, int32_t phase, const md_atoms *a, void *stream);
+
+/* Task 4d: energies, virial, indenter load and counters (MD_NOBS doubles per replica,
+ * device pointer out[nrep][MD_NOBS]), reduced in a fixed order in FP64 from the partials of
+ * the last md_eam_forces / md_morse_forces calls made with MD_F_ENERGY, plus the kinetic
+ * energy of the current velocities. */
+MD_API int md_energy(md_system *sys, const md_atoms *a, double *out, void *stream);
+
+/* ---------------------------------------------------------------------------------- */
+/* Whole steps                                                                          */
+/* ---------------------------------------------------------------------------------- */
+
+/* Enqueue nsteps whole time steps in the order of Table 1 (Tasks 2+3 -> 1 -> 4 -> 5):
+ * md_verlet_step(KICK_DRIFT), md_build_neighbors, md_eam_forces(DENSITY), then
+ * md_eam_forces(FORCE | MORSE | KICK) -- the Task 4b/4c/5 pass -- for every replica.
+ * flags: MD_F_MIXED selects FP32 arithmetic.  energy_every > 0: after step k with
+ * k % energy_every == 0 the energies are written as by md_energy to
+ * obs[(k / energy_every - 1) * nrep * MD_NOBS ...] (device memory, caller-owned).
+ * events: NULL, or 2*nsteps hipEvent_t handles (created by the caller) recorded on
+ * `stream` just before and just after each step's force kernel, for timing.
+ * Lists must have been built and forces evaluated once before the first step
+ * (md_build_neighbors with MD_B_FORCE, md_eam_forces with DENSITY|FORCE|MORSE). */
+MD_API int md_run(md_system *sys, const md_atoms *a, const md_lists *l, int32_t nsteps,
+                  uint32_t flags, int32_t energy_every, double *obs, void *const *events,
+                  void *stream);
+
+/* Capture md_run(nsteps, flags, energy_every, obs, no events) on `stream` into an
+ * instantiated HIP graph (*graph_exec, host handle) that replays the same steps on the
+ * same buffers with one launch.  The graph holds no memset nodes. */
+MD_API int md_graph_create(md_system *sys, const md_atoms *a, const md_lists *l, int32_t nsteps,
+                           uint32_t flags, int32_t energy_every, double *obs, void *stream,
+                           void **graph_exec);
+MD_API int md_graph_launch(void *graph_exec, void *stream);
+MD_API int md_graph_destroy(void *graph_exec);
+
+/* Synchronise `stream` and copy the device flags to *st (summed / maxed over replicas). */
+MD_API int md_check(md_system *sys, md_status *st, void *stream);
+
+/* Clear overflow / non-finite flags (e.g. after enlarging the lists). */
+MD_API int md_clear_flags(md_system *sys, void *stream);
+
+MD_API const char *md_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MD_H */

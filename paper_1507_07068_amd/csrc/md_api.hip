@@ -1,0 +1,518 @@
+// Host side of the C ABI declared in include/md.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "md.h"
+#include "md_kernels.hip"
+
+using namespace md;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+// Byte offsets of the workspace regions.
+struct Layout {
+  size_t desc, state, tile_rep, misc, xref, dmax, cellid, perm, tq, tv, tf, tfixed, tid, count,
+      start, hcell, hlist, bsum, p_embed, p_force, p_morse, p_kin, total;
+};
+
+constexpr int MAX_GRID = 4096;   // upper bound of the persistent rebuild grid
+constexpr int MISC_INTS = 16;    // any flag, barrier words, status words
+
+}  // namespace
+
+struct md_system {
+  md_params p;
+  int nrep;
+  std::vector<RepDesc> desc;
+  std::vector<int> tile_rep;
+  int64_t ntot, ctot;
+  int ntiles;
+  int ncell_cr, ncell_all;
+  Consts K;
+  Layout L;
+  char* ws;
+  int rebuild_grid;
+  bool have_embed, have_force, have_morse;
+};
+
+namespace {
+
+int cells_along(double len, double edge) {
+  double n = std::floor(len / (edge * (1.0 + 1e-9)));
+  return n < 1.0 ? 1 : (int)n;
+}
+
+Layout make_layout(const md_system& s) {
+  Layout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + std::max<size_t>(bytes, 1));
+    return at;
+  };
+  const size_t n = (size_t)s.ntot, nt = (size_t)s.ntiles;
+  L.desc = take(sizeof(RepDesc) * s.nrep);
+  L.state = take(sizeof(RepState) * s.nrep);
+  L.tile_rep = take(sizeof(int) * nt);
+  L.misc = take(sizeof(int) * MISC_INTS);
+  L.xref = take(sizeof(double) * 3 * n);
+  L.dmax = take(sizeof(double) * nt);
+  L.cellid = take(sizeof(int) * n);
+  L.perm = take(sizeof(int) * n);
+  L.tq = take(sizeof(double) * 4 * n);
+  L.tv = take(sizeof(double) * 3 * n);
+  L.tf = take(sizeof(double) * 3 * n);
+  L.tfixed = take(n);
+  L.tid = take(sizeof(int) * n);
+  L.count = take(sizeof(int) * (size_t)s.ncell_all);
+  L.start = take(sizeof(int) * ((size_t)s.ncell_all + 1));
+  L.hcell = take(sizeof(int) * (size_t)s.ctot);
+  L.hlist = take(sizeof(int) * (size_t)s.ctot);
+  L.bsum = take(sizeof(int) * MAX_GRID);
+  L.p_embed = take(sizeof(double) * nt);
+  L.p_force = take(sizeof(double) * nt * NP_FORCE);
+  L.p_morse = take(sizeof(double) * nt * 4);
+  L.p_kin = take(sizeof(double) * nt);
+  L.total = o;
+  return L;
+}
+
+template <class T>
+T* at(const md_system* s, size_t off) {
+  return reinterpret_cast<T*>(s->ws + off);
+}
+
+int hip_status(hipError_t e) {
+  if (e == hipSuccess) return MD_OK;
+  std::fprintf(stderr, "md: HIP error %d: %s\n", (int)e, hipGetErrorString(e));
+  return MD_ERR_HIP;
+}
+
+int check_launch() { return hip_status(hipGetLastError()); }
+
+bool atoms_ok(const md_atoms* a) {
+  return a && a->q && a->v && a->f && a->fixed && a->id;
+}
+
+bool lists_ok(const md_lists* l) { return l && l->idx && l->cnt && l->xidx && l->xcnt; }
+
+int grid_tiles(const md_system* s) { return s->ntiles; }
+
+}  // namespace
+
+extern "C" {
+
+MD_API const char* md_strerror(int code) {
+  switch (code) {
+    case MD_OK: return "ok";
+    case MD_ERR_ARG: return "invalid argument";
+    case MD_ERR_HIP: return "HIP runtime error";
+    case MD_ERR_STATE: return "no workspace bound";
+    default: return "unknown error";
+  }
+}
+
+MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_params* p,
+                            md_system** out) {
+  if (!out) return MD_ERR_ARG;
+  *out = nullptr;
+  if (!reps || !p || nrep < 1 || nrep > MAXREP) return MD_ERR_ARG;
+  if (!(p->mass > 0) || !(p->dt > 0) || !(p->skin >= 0) || p->cap < 1 || p->xcap < 1) return MD_ERR_ARG;
+  if (!(p->eam.c > 0) || !(p->eam.d > 0) || !(p->eam.d <= p->eam.c) || !(p->morse.rc > 0) ||
+      !(p->morse.alpha > 0))
+    return MD_ERR_ARG;
+  md_system* s = new (std::nothrow) md_system();
+  if (!s) return MD_ERR_ARG;
+  s->p = *p;
+  s->nrep = nrep;
+  s->ws = nullptr;
+  s->rebuild_grid = 0;
+  s->have_embed = s->have_force = s->have_morse = false;
+  const double rlist = p->eam.c + p->skin;
+  const double rxlist = p->morse.rc + p->skin;
+  int64_t a0 = 0, c0 = 0;
+  int t0 = 0, g0 = 0;
+  std::vector<int> hcells(nrep);
+  for (int r = 0; r < nrep; ++r) {
+    const md_replica_desc& rd = reps[r];
+    if (rd.n < 0 || rd.n_c < 0) { delete s; return MD_ERR_ARG; }
+    RepDesc d{};
+    for (int a = 0; a < 3; ++a) {
+      if (!(rd.len[a] > 0) || !std::isfinite(rd.lo[a])) { delete s; return MD_ERR_ARG; }
+      d.lo[a] = rd.lo[a];
+      d.len[a] = rd.len[a];
+      d.half[a] = 0.5 * rd.len[a];
+      d.per[a] = rd.periodic[a] ? 1 : 0;
+      d.gd[a] = cells_along(rd.len[a], rlist);
+      d.hd[a] = rd.n_c > 0 ? cells_along(rd.len[a], rxlist) : 1;
+      // the minimum image must be the only image within the list radius
+      if (d.per[a] && !(rd.len[a] > 2.0 * rlist)) { delete s; return MD_ERR_ARG; }
+      if (d.per[a] && rd.n_c > 0 && !(rd.len[a] > 2.0 * rxlist)) { delete s; return MD_ERR_ARG; }
+      d.ginv[a] = d.gd[a] / rd.len[a];
+      d.hinv[a] = d.hd[a] / rd.len[a];
+    }
+    d.a0 = (int)a0;
+    d.n = rd.n;
+    int ntile = std::max(1, (rd.n + TILE - 1) / TILE);
+    d.npad = ntile * TILE;
+    d.t0 = t0;
+    d.nt = ntile;
+    d.c0 = (int)c0;
+    d.nc = rd.n_c;
+    int64_t ncr = (int64_t)d.gd[0] * d.gd[1] * d.gd[2];
+    int64_t nch = (int64_t)d.hd[0] * d.hd[1] * d.hd[2];
+    if (ncr > (1 << 28) || nch > (1 << 28)) { delete s; return MD_ERR_ARG; }
+    d.g0 = g0;
+    g0 += (int)ncr;
+    hcells[r] = (int)nch;
+    a0 += d.npad;
+    c0 += rd.n_c;
+    t0 += ntile;
+    if (a0 > (int64_t)INT32_MAX / 2 || c0 > (int64_t)INT32_MAX / 2) { delete s; return MD_ERR_ARG; }
+    s->desc.push_back(d);
+    for (int t = 0; t < ntile; ++t) s->tile_rep.push_back(r);
+  }
+  s->ncell_cr = g0;
+  int h = g0;
+  for (int r = 0; r < nrep; ++r) {
+    s->desc[r].h0 = h;
+    h += hcells[r];
+  }
+  s->ncell_all = h;
+  s->ntot = a0;
+  s->ctot = c0;
+  s->ntiles = t0;
+
+  Consts& K = s->K;
+  std::memset(&K, 0, sizeof K);
+  K.A = p->eam.A;
+  K.c = p->eam.c;
+  K.d = p->eam.d;
+  K.c0 = p->eam.c0;
+  K.c1 = p->eam.c1;
+  K.c2 = p->eam.c2;
+  K.c_sq = p->eam.c * p->eam.c;
+  K.d_sq = p->eam.d * p->eam.d;
+  if (p->eam.c2 != 0.0) {
+    K.rv = -p->eam.c1 / (2.0 * p->eam.c2);
+    K.pmin = p->eam.c0 - p->eam.c1 * p->eam.c1 / (4.0 * p->eam.c2);
+  }
+  K.D = p->morse.D;
+  K.alpha = p->morse.alpha;
+  K.r0 = p->morse.r0;
+  K.mrc = p->morse.rc;
+  K.mrc_sq = p->morse.rc * p->morse.rc;
+  {
+    double e = std::exp(-p->morse.alpha * (p->morse.rc - p->morse.r0));
+    K.mshift = p->morse.D * (e * e - 2.0 * e);
+  }
+  K.acc = ACC_CONV / p->mass;
+  K.ke_fac = p->mass / (2.0 * ACC_CONV);
+  K.dt = p->dt;
+  K.v_ind = p->v_ind;
+  K.half_skin = 0.5 * p->skin;
+  K.half_skin_sq = K.half_skin * K.half_skin;
+  K.rlist_sq = rlist * rlist;
+  K.rxlist_sq = rxlist * rxlist;
+  K.cap = p->cap;
+  K.xcap = p->xcap;
+  K.nrep = nrep;
+  K.ntot = s->ntot;
+  s->L = make_layout(*s);
+  *out = s;
+  return MD_OK;
+}
+
+MD_API void md_system_destroy(md_system* s) { delete s; }
+
+MD_API int64_t md_system_atoms(const md_system* s) { return s ? s->ntot : -1; }
+MD_API int64_t md_system_carbons(const md_system* s) { return s ? s->ctot : -1; }
+MD_API int64_t md_replica_offset(const md_system* s, int32_t r) {
+  if (!s || r < 0 || r >= s->nrep) return -1;
+  return s->desc[r].a0;
+}
+
+MD_API size_t md_workspace_bytes(const md_system* s) { return s ? s->L.total : 0; }
+
+MD_API int md_workspace_bind(md_system* s, void* ws, size_t bytes, void* stream) {
+  if (!s || !ws || bytes < s->L.total) return MD_ERR_ARG;
+  if (((uintptr_t)ws) % ALIGN) return MD_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  s->ws = (char*)ws;
+  int e;
+  if ((e = hip_status(hipMemsetAsync(ws, 0, s->L.total, st)))) return e;
+  if ((e = hip_status(hipMemcpyAsync(at<RepDesc>(s, s->L.desc), s->desc.data(),
+                                     sizeof(RepDesc) * s->nrep, hipMemcpyHostToDevice, st))))
+    return e;
+  if ((e = hip_status(hipMemcpyAsync(at<int>(s, s->L.tile_rep), s->tile_rep.data(),
+                                     sizeof(int) * s->ntiles, hipMemcpyHostToDevice, st))))
+    return e;
+  // Persistent rebuild grid: every block must be resident at once.
+  int dev = 0, ncu = 0, per_cu = 0;
+  if ((e = hip_status(hipGetDevice(&dev)))) return e;
+  if ((e = hip_status(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)))) return e;
+  if ((e = hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rebuild, BLOCK, 0)))) return e;
+  if (per_cu < 1) return MD_ERR_HIP;
+  s->rebuild_grid = std::min(MAX_GRID, ncu * std::min(per_cu, 2));
+  s->have_embed = s->have_force = s->have_morse = false;
+  return hip_status(hipStreamSynchronize(st));
+}
+
+MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l, uint32_t flags,
+                              void* stream) {
+  if (!s || !atoms_ok(a) || !lists_ok(l) || (s->ctot > 0 && !a->xc)) return MD_ERR_ARG;
+  if (!s->ws) return MD_ERR_STATE;
+  hipStream_t st = (hipStream_t)stream;
+  int* misc = at<int>(s, s->L.misc);
+  RepState* S = at<RepState>(s, s->L.state);
+  const RepDesc* R = at<RepDesc>(s, s->L.desc);
+  k_decide<<<s->nrep, BLOCK, 0, st>>>(s->K, R, S, at<double>(s, s->L.dmax), (flags & MD_B_FORCE) ? 1 : 0,
+                                      misc + 0);
+  RebuildArgs A;
+  A.R = R;
+  A.S = S;
+  A.tile_rep = at<int>(s, s->L.tile_rep);
+  A.any = misc + 0;
+  A.bar = reinterpret_cast<unsigned*>(misc + 2);
+  A.q = reinterpret_cast<double4*>(a->q);
+  A.v = a->v;
+  A.f = a->f;
+  A.fixed = a->fixed;
+  A.id = a->id;
+  A.xc = a->xc;
+  A.xref = at<double>(s, s->L.xref);
+  A.dmax_tile = at<double>(s, s->L.dmax);
+  A.cellid = at<int>(s, s->L.cellid);
+  A.perm = at<int>(s, s->L.perm);
+  A.tq = at<double4>(s, s->L.tq);
+  A.tv = at<double>(s, s->L.tv);
+  A.tf = at<double>(s, s->L.tf);
+  A.tfixed = at<uint8_t>(s, s->L.tfixed);
+  A.tid = at<int>(s, s->L.tid);
+  A.count = at<int>(s, s->L.count);
+  A.start = at<int>(s, s->L.start);
+  A.hcell = at<int>(s, s->L.hcell);
+  A.hlist = at<int>(s, s->L.hlist);
+  A.bsum = at<int>(s, s->L.bsum);
+  A.idx = l->idx;
+  A.cnt = l->cnt;
+  A.xidx = l->xidx;
+  A.xcnt = l->xcnt;
+  A.ncell_all = s->ncell_all;
+  A.ncell_cr = s->ncell_cr;
+  A.ntiles = s->ntiles;
+  A.c_total = (int)s->ctot;
+  k_rebuild<<<s->rebuild_grid, BLOCK, 0, st>>>(s->K, A);
+  return check_launch();
+}
+
+MD_API int md_eam_forces(md_system* s, const md_atoms* a, const md_lists* l, uint32_t flags,
+                         double* rho_out, void* stream) {
+  if (!s || !atoms_ok(a) || !lists_ok(l)) return MD_ERR_ARG;
+  if ((flags & MD_F_MORSE) && s->ctot > 0 && !a->xc) return MD_ERR_ARG;
+  if ((flags & MD_F_MIXED) && s->p.eam.c2 == 0.0) return MD_ERR_ARG;
+  if (!s->ws) return MD_ERR_STATE;
+  hipStream_t st = (hipStream_t)stream;
+  const RepDesc* R = at<RepDesc>(s, s->L.desc);
+  RepState* S = at<RepState>(s, s->L.state);
+  const int* tr = at<int>(s, s->L.tile_rep);
+  double4* q = reinterpret_cast<double4*>(a->q);
+  const int nb = grid_tiles(s);
+  const bool mixed = flags & MD_F_MIXED, energy = flags & MD_F_ENERGY;
+  if (flags & MD_F_DENSITY) {
+    double* pe = at<double>(s, s->L.p_embed);
+#define DENS(M, E) k_density<M, E><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, l->idx, l->cnt, rho_out, pe)
+    if (mixed) { if (energy) DENS(true, true); else DENS(true, false); }
+    else { if (energy) DENS(false, true); else DENS(false, false); }
+#undef DENS
+    s->have_embed = energy;
+    int e = check_launch();
+    if (e) return e;
+  }
+  if (flags & MD_F_FORCE) {
+    double* pf = at<double>(s, s->L.p_force);
+    const bool morse = (flags & MD_F_MORSE) && s->ctot > 0, kick = flags & MD_F_KICK;
+    const double* xc = a->xc;
+#define FORCE(M, MO, KI, E)                                                                    \
+  k_force<M, MO, KI, E><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, a->v, a->f, a->fixed, l->idx, \
+                                              l->cnt, xc, l->xidx, l->xcnt, pf)
+#define FORCE_E(M, MO, KI) \
+  if (energy) FORCE(M, MO, KI, true); else FORCE(M, MO, KI, false)
+#define FORCE_K(M, MO) \
+  if (kick) { FORCE_E(M, MO, true); } else { FORCE_E(M, MO, false); }
+#define FORCE_MO(M) \
+  if (morse) { FORCE_K(M, true); } else { FORCE_K(M, false); }
+    if (mixed) { FORCE_MO(true); } else { FORCE_MO(false); }
+#undef FORCE_MO
+#undef FORCE_K
+#undef FORCE_E
+#undef FORCE
+    s->have_force = energy;
+    if (energy) s->have_morse = false;   // the Morse share (if any) is inside the force partials
+    int e = check_launch();
+    if (e) return e;
+  }
+  return MD_OK;
+}
+
+MD_API int md_morse_forces(md_system* s, const md_atoms* a, const md_lists* l, uint32_t flags,
+                           void* stream) {
+  if (!s || !atoms_ok(a) || !lists_ok(l)) return MD_ERR_ARG;
+  if (s->ctot > 0 && !a->xc) return MD_ERR_ARG;
+  if (!s->ws) return MD_ERR_STATE;
+  hipStream_t st = (hipStream_t)stream;
+  const RepDesc* R = at<RepDesc>(s, s->L.desc);
+  RepState* S = at<RepState>(s, s->L.state);
+  const int* tr = at<int>(s, s->L.tile_rep);
+  const double4* q = reinterpret_cast<const double4*>(a->q);
+  double* pm = at<double>(s, s->L.p_morse);
+  const int nb = grid_tiles(s);
+  const bool mixed = flags & MD_F_MIXED, kick = flags & MD_F_KICK, energy = flags & MD_F_ENERGY;
+#define MORSE(M, KI, E)                                                                        \
+  k_morse<M, KI, E><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, a->v, a->f, a->fixed, a->xc, l->xidx, \
+                                          l->xcnt, pm)
+#define MORSE_E(M, KI) \
+  if (energy) MORSE(M, KI, true); else MORSE(M, KI, false)
+#define MORSE_K(M) \
+  if (kick) { MORSE_E(M, true); } else { MORSE_E(M, false); }
+  if (mixed) { MORSE_K(true); } else { MORSE_K(false); }
+#undef MORSE_K
+#undef MORSE_E
+#undef MORSE
+  s->have_morse = energy;
+  return check_launch();
+}
+
+MD_API int md_verlet_step(md_system* s, int32_t phase, const md_atoms* a, void* stream) {
+  if (!s || !atoms_ok(a)) return MD_ERR_ARG;
+  if (phase != MD_PHASE_KICK_DRIFT && phase != MD_PHASE_KICK) return MD_ERR_ARG;
+  if (!s->ws) return MD_ERR_STATE;
+  hipStream_t st = (hipStream_t)stream;
+  const RepDesc* R = at<RepDesc>(s, s->L.desc);
+  const int* tr = at<int>(s, s->L.tile_rep);
+  const int nb = grid_tiles(s);
+  if (phase == MD_PHASE_KICK_DRIFT)
+    k_kick_drift<<<nb, BLOCK, 0, st>>>(s->K, R, at<RepState>(s, s->L.state), tr,
+                                       reinterpret_cast<double4*>(a->q), a->v, a->f, a->fixed,
+                                       at<double>(s, s->L.xref), at<double>(s, s->L.dmax));
+  else
+    k_kick<<<nb, BLOCK, 0, st>>>(s->K, R, tr, a->v, a->f, a->fixed);
+  return check_launch();
+}
+
+MD_API int md_energy(md_system* s, const md_atoms* a, double* out, void* stream) {
+  if (!s || !atoms_ok(a) || !out) return MD_ERR_ARG;
+  if (!s->ws) return MD_ERR_STATE;
+  hipStream_t st = (hipStream_t)stream;
+  const RepDesc* R = at<RepDesc>(s, s->L.desc);
+  const int* tr = at<int>(s, s->L.tile_rep);
+  double* pk = at<double>(s, s->L.p_kin);
+  k_kinetic<<<grid_tiles(s), BLOCK, 0, st>>>(s->K, R, tr, a->v, a->fixed, pk);
+  k_reduce<<<s->nrep, BLOCK, 0, st>>>(R, at<RepState>(s, s->L.state),
+                                      s->have_embed ? at<double>(s, s->L.p_embed) : nullptr,
+                                      s->have_force ? at<double>(s, s->L.p_force) : nullptr,
+                                      s->have_morse ? at<double>(s, s->L.p_morse) : nullptr, pk, out);
+  return check_launch();
+}
+
+MD_API int md_run(md_system* s, const md_atoms* a, const md_lists* l, int32_t nsteps, uint32_t flags,
+                  int32_t energy_every, double* obs, void* const* events, void* stream) {
+  if (!s || !atoms_ok(a) || !lists_ok(l) || nsteps < 0) return MD_ERR_ARG;
+  if (energy_every > 0 && !obs) return MD_ERR_ARG;
+  if (!s->ws) return MD_ERR_STATE;
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t mixed = flags & MD_F_MIXED;
+  int e;
+  for (int k = 1; k <= nsteps; ++k) {
+    const bool en = energy_every > 0 && k % energy_every == 0;
+    if ((e = md_verlet_step(s, MD_PHASE_KICK_DRIFT, a, stream))) return e;
+    if ((e = md_build_neighbors(s, a, l, 0, stream))) return e;
+    if ((e = md_eam_forces(s, a, l, MD_F_DENSITY | mixed | (en ? MD_F_ENERGY : 0), nullptr, stream)))
+      return e;
+    if (events && (e = hip_status(hipEventRecord((hipEvent_t)events[2 * (k - 1)], st)))) return e;
+    if ((e = md_eam_forces(s, a, l, MD_F_FORCE | MD_F_MORSE | MD_F_KICK | mixed | (en ? MD_F_ENERGY : 0),
+                           nullptr, stream)))
+      return e;
+    if (events && (e = hip_status(hipEventRecord((hipEvent_t)events[2 * (k - 1) + 1], st)))) return e;
+    if (en) {
+      double* out = obs + (int64_t)(k / energy_every - 1) * s->nrep * MD_NOBS;
+      if ((e = md_energy(s, a, out, stream))) return e;
+    }
+  }
+  return MD_OK;
+}
+
+MD_API int md_graph_create(md_system* s, const md_atoms* a, const md_lists* l, int32_t nsteps,
+                           uint32_t flags, int32_t energy_every, double* obs, void* stream,
+                           void** graph_exec) {
+  if (!graph_exec) return MD_ERR_ARG;
+  *graph_exec = nullptr;
+  hipStream_t st = (hipStream_t)stream;
+  if (!st) return MD_ERR_ARG;   // the null stream cannot be captured
+  int e;
+  if ((e = hip_status(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal)))) return e;
+  int rc = md_run(s, a, l, nsteps, flags, energy_every, obs, nullptr, stream);
+  hipGraph_t g = nullptr;
+  hipError_t ce = hipStreamEndCapture(st, &g);
+  if (rc) {
+    if (g) hipGraphDestroy(g);
+    return rc;
+  }
+  if ((e = hip_status(ce))) return e;
+  hipGraphExec_t ex = nullptr;
+  e = hip_status(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+  hipGraphDestroy(g);
+  if (e) return e;
+  *graph_exec = (void*)ex;
+  return MD_OK;
+}
+
+MD_API int md_graph_launch(void* graph_exec, void* stream) {
+  if (!graph_exec) return MD_ERR_ARG;
+  return hip_status(hipGraphLaunch((hipGraphExec_t)graph_exec, (hipStream_t)stream));
+}
+
+MD_API int md_graph_destroy(void* graph_exec) {
+  if (!graph_exec) return MD_ERR_ARG;
+  return hip_status(hipGraphExecDestroy((hipGraphExec_t)graph_exec));
+}
+
+MD_API int md_check(md_system* s, md_status* st_out, void* stream) {
+  if (!s || !st_out) return MD_ERR_ARG;
+  if (!s->ws) return MD_ERR_STATE;
+  hipStream_t st = (hipStream_t)stream;
+  int* misc = at<int>(s, s->L.misc);
+  k_status<<<1, 64, 0, st>>>(at<RepState>(s, s->L.state), s->nrep, misc + 8);
+  int e = check_launch();
+  if (e) return e;
+  int host[8] = {0};
+  if ((e = hip_status(hipMemcpyAsync(host, misc + 8, sizeof(int) * 5, hipMemcpyDeviceToHost, st)))) return e;
+  if ((e = hip_status(hipStreamSynchronize(st)))) return e;
+  std::memset(st_out, 0, sizeof *st_out);
+  st_out->overflow = host[0];
+  st_out->xoverflow = host[1];
+  st_out->nonfinite = host[2];
+  st_out->nbuilds = host[3];
+  st_out->sync_timeout = host[4];
+  return MD_OK;
+}
+
+MD_API int md_clear_flags(md_system* s, void* stream) {
+  if (!s) return MD_ERR_ARG;
+  if (!s->ws) return MD_ERR_STATE;
+  k_clear_flags<<<(s->nrep + 63) / 64, 64, 0, (hipStream_t)stream>>>(at<RepState>(s, s->L.state), s->nrep);
+  return check_launch();
+}
+
+}  // extern "C"

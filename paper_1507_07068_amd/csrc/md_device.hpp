@@ -1,0 +1,176 @@
+// Device-side data structures and helpers shared by the MD kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "md.h"
+
+namespace md {
+
+constexpr int TILE = MD_TILE;   // atoms per tile (replica ranges are tile aligned)
+constexpr int BLOCK = 256;      // threads of the atom-parallel kernels (one tile per block)
+constexpr int WAVE = 64;
+
+// (eV / (Angstrom u)) -> Angstrom / fs^2, from e = 1.602176634e-19 C and u = 1.66053906660e-27 kg.
+constexpr double ACC_CONV = 1.602176634e-19 / 1.66053906660e-27 * 1e-10;
+
+// One replica as the kernels see it (read only).
+struct RepDesc {
+  double lo[3];
+  double len[3];
+  double half[3];
+  int per[3];
+  int a0, n, npad;      // first atom slot, atom count, padded slot count
+  int c0, nc;           // first carbon, carbon count
+  int t0, nt;           // first tile, tile count
+  int g0, gd[3];        // Cr-Cr cell grid: first cell (global), dims
+  int h0, hd[3];        // Cr-C cell grid: first cell (global, after all Cr grids), dims
+  double ginv[3];       // cells per Angstrom of the Cr grid
+  double hinv[3];       // cells per Angstrom of the carbon grid
+};
+
+// Mutable per-replica flags and counters.
+struct alignas(64) RepState {
+  double ind_z;           // indenter displacement along z
+  double ind_z_ref;       // ind_z at the last list build
+  unsigned long long czmin, czmax;  // ordered bits of the current carbon z extent (at a build)
+  int rebuild;            // 1: the next k_rebuild rebuilds this replica
+  int nbuilds;
+  int overflow;           // needed Cr-Cr capacity (0 = fits)
+  int xoverflow;          // needed Cr-C capacity
+  int nonfinite;
+  int sync_timeout;
+};
+
+// Constants of the potential and the integrator (passed by value).
+struct Consts {
+  // EAM
+  double A, c, d, c0, c1, c2;
+  double c_sq, d_sq;      // cutoffs squared
+  double rv, pmin;        // vertex form of c0 + c1 r + c2 r^2 = pmin + c2 (r - rv)^2
+  // Morse
+  double D, alpha, r0, mrc, mrc_sq, mshift;
+  // integration / lists
+  double acc;             // ACC_CONV / mass: acceleration per unit force
+  double ke_fac;          // mass / (2 ACC_CONV): kinetic energy per v^2
+  double dt, v_ind;
+  double half_skin, half_skin_sq;
+  double rlist_sq, rxlist_sq;
+  int cap, xcap;
+  int nrep;
+  int pad;
+  int64_t ntot;           // atom slots (all replicas)
+};
+
+// Order-preserving map of a double to an unsigned 64-bit integer (for atomic min/max).
+__device__ __forceinline__ unsigned long long ordered_bits(double v) {
+  unsigned long long b = __double_as_longlong(v);
+  return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double from_ordered_bits(unsigned long long b) {
+  b = (b & 0x8000000000000000ull) ? (b & 0x7fffffffffffffffull) : ~b;
+  return __longlong_as_double(b);
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs; give each XCD a contiguous run of
+// logical blocks so that neighbouring tiles share that XCD's L2.
+__device__ __forceinline__ int xcd_block(int bid, int nb) {
+  int per = nb >> 3;
+  if (bid < (per << 3)) return (bid & 7) * per + (bid >> 3);
+  return bid;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+  return v;
+}
+
+// Sum K values over a block of NT threads (NT multiple of 64) in a fixed order; thread
+// t < K of the block receives sum k = t in out[t].  Contains __syncthreads.
+template <int K, int NT>
+__device__ __forceinline__ void block_sum_store(double (&v)[K], double* out) {
+  constexpr int NW = NT / WAVE;
+  __shared__ double sh[K][NW];
+  const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double s = wave_sum(v[k]);
+    if (lane == 0) sh[k][w] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) s += sh[threadIdx.x][i];
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+template <int NT>
+__device__ __forceinline__ double block_max(double v) {
+  constexpr int NW = NT / WAVE;
+  __shared__ double sh[NW];
+  const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  v = wave_max(v);
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double m = sh[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) m = fmax(m, sh[i]);
+  __syncthreads();
+  return m;
+}
+
+// Minimum-image component of a separation along one axis.
+__device__ __forceinline__ double min_image(double d, double len, double half, int per) {
+  if (per) {
+    if (d > half)
+      d -= len;
+    else if (d < -half)
+      d += len;
+  }
+  return d;
+}
+
+// Squared length (dx dx + dy dy) + dz dz with every product and sum rounded on its own:
+// the exact list predicate, evaluated identically wherever a list is built.
+__device__ __forceinline__ double dist_sq_exact(double dx, double dy, double dz) {
+#pragma clang fp contract(off)
+  double xx = dx * dx;
+  double yy = dy * dy;
+  double zz = dz * dz;
+  double s = xx + yy;
+  return s + zz;
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Cell coordinate along one axis, clamped into the grid (also for far-away or NaN x).
+__device__ __forceinline__ int cell_coord(double x, double lo, double inv, int dim) {
+  double t = floor((x - lo) * inv);
+  t = fmin(fmax(t, 0.0), (double)(dim - 1));
+  return (int)t;
+}
+
+// The 27-cell stencil, one axis at a time: offsets t = 0..stencil_n-1 map to cells
+// c-1, c, c+1 (periodic wrap, or -1 = outside an open axis).  A periodic axis with fewer
+// than 3 cells visits each of its cells once instead, so no cell is met twice.
+__device__ __forceinline__ int stencil_n(int gd, int per) { return (per && gd < 3) ? gd : 3; }
+__device__ __forceinline__ int stencil_cell(int c, int t, int gd, int per) {
+  if (per && gd < 3) return t;
+  int x = c + t - 1;
+  if (per) return x < 0 ? x + gd : (x >= gd ? x - gd : x);
+  return (x < 0 || x >= gd) ? -1 : x;
+}
+
+}  // namespace md

@@ -1,0 +1,315 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bars: neighbour lists bit-exact as sorted id sets (and wrapped positions bit-exact);
+FP64 forces rel-RMS <= 1e-10 and max |dF_i| <= 1e-10 * RMS|F|; energies <= 1e-12
+relative; mixed precision rel-RMS <= 1e-5.  Inputs come from the seeded generator only.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1507_07068_amd import inputs as I
+from paper_1507_07068_amd import md
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-5
+
+
+def sim_of(s, precision="fp64", cap=64, xcap=128):
+    print(f"[case] {s.name} n={s.n} n_c={s.n_c} precision={precision}", flush=True)
+    return md.Simulation(s, precision=precision, cap=cap, xcap=xcap)
+
+
+def min_image_diff(a, b, s):
+    d = a - b
+    per = np.asarray(s.periodic, bool)
+    d[:, per] -= s.box_len[per] * np.round(d[:, per] / s.box_len[per])
+    return d
+
+
+def force_errors(f, ref):
+    rms = np.sqrt(np.mean(np.sum(ref ** 2, axis=1)))
+    diff = np.sqrt(np.sum((f - ref) ** 2, axis=1))
+    rel_rms = np.sqrt(np.sum(diff ** 2) / max(np.sum(ref ** 2), 1e-300))
+    return rel_rms, diff.max() / max(rms, 1e-300)
+
+
+def assert_forces(f, ref, tol):
+    rel, mx = force_errors(f, ref)
+    print(f"  force rel-RMS {rel:.3e}  max/RMS {mx:.3e}", flush=True)
+    assert rel <= tol and mx <= tol * (10 if tol > FP64_TOL else 1), (rel, mx)
+
+
+def check_lists(sim, s, cross=False, ind_z=0.0, rows=None):
+    """GPU neighbour sets (id space) vs the oracle's brute force on its own wrap."""
+    xw = O.wrap(s)
+    st = sim.state()[0]
+    assert np.array_equal(st["x"], xw), "wrapped positions differ"
+    got = sim.neighbor_sets(0, cross=cross)
+    if cross:
+        cnt, idx = O.cross_neighbors(s, s.r_list_cross, x=xw, ind_z=ind_z, rows=rows, cap=256)
+    else:
+        cnt, idx = O.neighbors(s, s.r_list, x=xw, rows=rows, cap=256)
+    ref = O.neighbor_sets(cnt, idx)
+    ids = range(s.n) if rows is None else rows
+    for t, i in enumerate(ids):
+        assert got[i] == ref[t], (i, got[i], ref[t])
+    return sum(len(r) for r in ref)
+
+
+# ------------------------------------------------------------------------------------------
+# Lists
+# ------------------------------------------------------------------------------------------
+def test_lists_bulk_c0():
+    s = I.config(0)
+    sim = sim_of(s)
+    sim.md_build_neighbors(force=True)
+    st = sim.md_check()
+    assert st["overflow"] == 0 and st["nbuilds"] == 1 and st["sync_timeout"] == 0
+    assert check_lists(sim, s) > 0
+
+
+@pytest.mark.parametrize("n,per", [(1, (1, 1, 1)), (2, (1, 1, 0)), (255, (1, 1, 1)),
+                                   (257, (1, 1, 0)), (1000, (1, 1, 1)), (2999, (0, 0, 0)),
+                                   (4097, (1, 1, 0))])
+def test_lists_random_gas_ragged(n, per):
+    """Irregular counts (one partial tile, several tiles + a ragged tail), atoms outside the
+    box on periodic axes (wrapped at the build), open axes, close pairs."""
+    box = max((n / 0.08) ** (1 / 3), 9.0)
+    s = I.random_gas(n, box, seed=100 + n, periodic=per)
+    sim = sim_of(s, cap=96)
+    sim.md_build_neighbors(force=True)
+    assert sim.md_check()["overflow"] == 0
+    check_lists(sim, s)
+
+
+def test_lists_small_periodic_box_fewer_than_three_cells():
+    """A 3x3x3-cell box (8.655 A): fewer than 3 list cells per periodic axis."""
+    s = I.bulk(3, seed=4, noise=0.05)
+    sim = sim_of(s)
+    sim.md_build_neighbors(force=True)
+    check_lists(sim, s)
+
+
+def test_lists_pairs_at_the_list_radius():
+    """Pairs placed within a few ulps of the list radius, along awkward directions: the
+    predicate must round exactly like the oracle's (no fused multiply-add)."""
+    rng = np.random.default_rng(7)
+    r = I.EAM["c"] + I.SKIN
+    pts = []
+    for k in range(400):
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        base = rng.uniform(2, 40, size=3)
+        dist = r * (1 + rng.integers(-6, 7) * 2.0 ** -52)
+        pts += [base, base + dist * u]
+    s = I.random_gas(len(pts), 45.0, 0, periodic=(0, 0, 0))
+    s.x = np.array(pts)
+    sim = sim_of(s)
+    sim.md_build_neighbors(force=True)
+    check_lists(sim, s)
+
+
+def test_cross_lists_film():
+    s = I.small_film(nx=8, ny=8, nz=5, radius=8.0, gap=-1.5, seed=3, noise=0.05)
+    sim = sim_of(s)
+    sim.md_build_neighbors(force=True)
+    assert sim.md_check()["xoverflow"] == 0
+    check_lists(sim, s)
+    assert check_lists(sim, s, cross=True) > 0
+
+
+def test_cross_list_overflow_is_flagged():
+    s = I.small_film(nx=8, ny=8, nz=5, radius=8.0, gap=-1.5, seed=3, noise=0.05)
+    sim = sim_of(s, xcap=16)
+    sim.md_build_neighbors(force=True)
+    cnt, _ = O.cross_neighbors(s, s.r_list_cross, x=O.wrap(s), cap=256)
+    assert sim.md_check()["xoverflow"] == int(cnt.max()) > 16
+
+
+def test_list_overflow_is_flagged():
+    s = I.config(0)
+    sim = sim_of(s, cap=8, xcap=8)
+    sim.md_build_neighbors(force=True)
+    st = sim.md_check()
+    cnt, _ = O.neighbors(s, s.r_list, x=O.wrap(s), cap=64)
+    assert st["overflow"] == int(cnt.max())
+    assert int(sim.cnt.max().item()) == 8
+    sim.md_clear_flags()
+    assert sim.md_check()["overflow"] == 0
+
+
+# ------------------------------------------------------------------------------------------
+# Forces, densities, energies
+# ------------------------------------------------------------------------------------------
+def _initial(sim):
+    sim.md_build_neighbors(force=True)
+    sim.md_eam_forces(md.MD_F_DENSITY | md.MD_F_FORCE | md.MD_F_MORSE | md.MD_F_ENERGY, rho=True)
+    st = sim.md_check()
+    assert st["overflow"] == 0 and st["xoverflow"] == 0 and st["nonfinite"] == 0, st
+    return sim.md_energy()[0], sim.state()[0]
+
+
+def _assert_obs(obs, ref, tol):
+    names = ["e_embed", "e_pair", "e_morse", "e_kin", "w_xx", "w_yy", "w_zz", "w_xy", "w_xz", "w_yz",
+             "find_x", "find_y", "find_z"]
+    scale_e = max(abs(ref[0]) + abs(ref[1]), 1.0)
+    scale_w = max(np.abs(ref[4:10]).max(), 1.0)
+    scale_f = max(np.abs(ref[10:13]).max(), 1e-3)
+    for k, nm in enumerate(names):
+        sc = scale_e if k < 4 else (scale_w if k < 10 else scale_f)
+        assert abs(obs[k] - ref[k]) <= tol * sc, (nm, obs[k], ref[k])
+
+
+def test_density_and_forces_bulk_c0():
+    s = I.config(0)
+    sim = sim_of(s)
+    obs, st = _initial(sim)
+    ref = O.evaluate(s, O.wrap(s))
+    assert np.allclose(st["rho"], ref["rho"], rtol=1e-13, atol=0)
+    assert np.allclose(st["dF"], ref["dF"], rtol=1e-13, atol=0)
+    assert_forces(st["f"], ref["f"], FP64_TOL)
+    ref_obs = ref["obs"].copy()
+    ref_obs[3] = 0.5 * s.mass * np.sum(s.v ** 2) / I.EV_PER_U_TO_A2_FS2
+    _assert_obs(obs, ref_obs, 1e-12)
+
+
+@pytest.mark.parametrize("seed,gap", [(3, -1.5), (9, 0.4)])
+def test_forces_film_with_indenter(seed, gap):
+    s = I.small_film(nx=8, ny=8, nz=6, radius=8.0, gap=gap, seed=seed, noise=0.05)
+    sim = sim_of(s)
+    obs, st = _initial(sim)
+    ref = O.evaluate(s, O.wrap(s))
+    assert_forces(st["f"], ref["f"], FP64_TOL)
+    mob = s.fixed == 0
+    ref_obs = ref["obs"].copy()
+    ref_obs[3] = 0.5 * s.mass * np.sum(s.v[mob] ** 2) / I.EV_PER_U_TO_A2_FS2
+    _assert_obs(obs, ref_obs, 1e-12)
+
+
+def test_morse_standalone_equals_fused():
+    s = I.small_film(nx=8, ny=8, nz=6, radius=8.0, gap=-1.0, seed=2, noise=0.05)
+    a = sim_of(s)
+    a.md_build_neighbors(force=True)
+    a.md_eam_forces(md.MD_F_DENSITY | md.MD_F_FORCE | md.MD_F_MORSE | md.MD_F_ENERGY)
+    oa = a.md_energy()[0]
+    b = sim_of(s)
+    b.md_build_neighbors(force=True)
+    b.md_eam_forces(md.MD_F_DENSITY | md.MD_F_FORCE | md.MD_F_ENERGY)
+    b.md_morse_forces(md.MD_F_ENERGY)
+    ob = b.md_energy()[0]
+    fa, fb = a.state()[0]["f"], b.state()[0]["f"]
+    assert np.allclose(fa, fb, rtol=0, atol=1e-13)
+    assert np.allclose(oa[[2, 10, 11, 12]], ob[[2, 10, 11, 12]], rtol=1e-12, atol=1e-14)
+
+
+def test_mixed_precision_force_error():
+    for s in (I.config(0), I.small_film(nx=8, ny=8, nz=6, radius=8.0, gap=-1.0, seed=4, noise=0.05)):
+        sim = sim_of(s, precision="mixed")
+        obs, st = _initial(sim)
+        ref = O.evaluate(s, O.wrap(s))
+        rel, mx = force_errors(st["f"], ref["f"])
+        print(f"  mixed: force rel-RMS {rel:.3e} max/RMS {mx:.3e}", flush=True)
+        assert rel <= MIXED_TOL
+        assert abs(obs[1] + obs[0] - ref["obs"][0] - ref["obs"][1]) <= 1e-6 * abs(ref["obs"][0])
+
+
+# ------------------------------------------------------------------------------------------
+# Trajectories (Tasks 1-5 over many steps, with list rebuilds)
+# ------------------------------------------------------------------------------------------
+def _traj(s, nsteps, precision="fp64", fused=True):
+    sim = sim_of(s, precision=precision)
+    sim.initial_forces()
+    st = sim.md_check()
+    assert st["overflow"] == 0 and st["xoverflow"] == 0, st
+    rows = [sim.md_energy()[0]]
+    for _ in range(nsteps):
+        (sim.step if fused else sim.step_unfused)(energy=True)
+        rows.append(sim.md_energy()[0])
+    return sim, np.array(rows)
+
+
+def test_trajectory_c0_100_steps():
+    s = I.config(0)
+    sim, obs = _traj(s, 100)
+    ref = O.md_run(s, 100)
+    st = sim.state()[0]
+    dx = np.abs(min_image_diff(st["x"], ref["x"], s)).max()
+    dv = np.abs(st["v"] - ref["v"]).max()
+    print(f"  c0 100 steps: max|dx| {dx:.2e}  max|dv| {dv:.2e}", flush=True)
+    assert dx < 1e-9 and dv < 1e-11
+    assert_forces(st["f"], ref["f"], 1e-9)
+    ro = ref["obs"]
+    assert np.array_equal(obs[:, 14], ro[:, 14]), "list rebuild schedule differs"
+    etot, rtot = obs[:, 0:4].sum(1), ro[:, 0:4].sum(1)
+    assert np.abs(etot - rtot).max() < 1e-9 * np.abs(rtot).max()
+    assert sim.md_check()["overflow"] == 0
+
+
+def test_trajectory_film_with_moving_indenter():
+    s = I.small_film(nx=8, ny=8, nz=6, radius=8.0, gap=0.2, seed=12, noise=0.03, steps=60)
+    sim, obs = _traj(s, 60)
+    ref = O.md_run(s, 60)
+    st = sim.state()[0]
+    dx = np.abs(min_image_diff(st["x"], ref["x"], s)).max()
+    print(f"  film 60 steps: max|dx| {dx:.2e}", flush=True)
+    assert dx < 1e-9
+    assert np.array_equal(obs[:, 14], ref["obs"][:, 14])
+    assert abs(obs[-1, 13] - ref["ind_z"]) < 1e-15
+    assert np.abs(obs[:, 10:13] - ref["obs"][:, 10:13]).max() < 1e-9
+
+
+def test_unfused_step_matches_fused():
+    s = I.small_film(nx=8, ny=8, nz=6, radius=8.0, gap=-0.5, seed=5, noise=0.03)
+    a, oa = _traj(s, 20, fused=True)
+    b, ob = _traj(s, 20, fused=False)
+    xa, xb = a.state()[0]["x"], b.state()[0]["x"]
+    assert np.abs(xa - xb).max() < 1e-12
+    assert np.abs(oa[:, :4] - ob[:, :4]).max() < 1e-9
+
+
+def test_fixed_atoms_do_not_move():
+    s = I.small_film(nx=8, ny=8, nz=5, radius=6.0, gap=0.5, seed=1)
+    sim, _ = _traj(s, 30)
+    st = sim.state()[0]
+    fx = s.fixed.astype(bool)
+    assert np.array_equal(st["x"][fx], O.wrap(s)[fx])
+    assert np.all(st["v"][fx] == 0)
+
+
+def test_mixed_trajectory_stays_close():
+    s = I.config(0)
+    sim, obs = _traj(s, 50, precision="mixed")
+    ref = O.md_run(s, 50)
+    st = sim.state()[0]
+    rel, _ = force_errors(st["f"], ref["f"])
+    print(f"  mixed 50 steps: force rel-RMS vs FP64 oracle {rel:.2e}", flush=True)
+    assert rel < 1e-3          # chaotic divergence over 50 fs, bounded
+    e, er = obs[:, :4].sum(1), ref["obs"][:, :4].sum(1)
+    assert np.abs(e - er).max() < 1e-3 * np.abs(er).max()
+
+
+# ------------------------------------------------------------------------------------------
+# Edge cases
+# ------------------------------------------------------------------------------------------
+def test_dimer_and_single_atom():
+    s = I.random_gas(2, 20.0, 0, periodic=(0, 0, 0))
+    s.x = np.array([[5.0, 5.0, 5.0], [7.1, 6.0, 5.4]])
+    s.v = np.array([[0.001, 0.0, 0.0], [-0.001, 0.0, 0.0]])
+    sim, obs = _traj(s, 30)
+    ref = O.md_run(s, 30)
+    assert np.abs(sim.state()[0]["x"] - ref["x"]).max() < 1e-12
+    s1 = I.random_gas(1, 20.0, 0, periodic=(1, 1, 1))
+    s1.v = np.array([[0.01, -0.02, 0.005]])
+    sim1, _ = _traj(s1, 10)
+    ref1 = O.md_run(s1, 10)
+    assert np.abs(min_image_diff(sim1.state()[0]["x"], ref1["x"], s1)).max() < 1e-13
+
+
+def test_empty_system():
+    s = I.random_gas(0, 20.0, 0)
+    sim, obs = _traj(s, 3)
+    assert np.all(obs[:, :13] == 0)
+    assert sim.md_check()["nonfinite"] == 0
