@@ -67,6 +67,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
     ap.add_argument("--energy-every", type=int, default=10)
+    ap.add_argument("--tpa", type=int, default=1, choices=[1, 2, 4, 8],
+                    help="lanes per atom in the density / force passes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args(argv)
 
@@ -93,7 +95,7 @@ def main(argv=None):
 
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        sim = md.Simulation(systems, precision=precision, cap=64, xcap=160)
+        sim = md.Simulation(systems, precision=precision, cap=64, xcap=160, tpa=args.tpa)
         sim.initial_forces()
         if args.warmup:
             sim.md_run(args.warmup)
@@ -144,7 +146,8 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": wname, "cr_atoms": n_atoms, "c_atoms": sum(s.n_c for s in systems),
                    "replicas": len(systems), "precision": precision, "energy_every": ee,
-                   "list_builds": builds, "mean_list_len": round(mean_list, 3)},
+                   "list_builds": builds, "mean_list_len": round(mean_list, 3),
+                   "lanes_per_atom": args.tpa},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_force (EAM Eq. 1 + Morse + final kick)",

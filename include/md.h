@@ -105,6 +105,9 @@ typedef struct md_params {
     double skin;        /* Verlet skin, Angstrom; lists hold pairs closer than cutoff + skin */
     int32_t cap;        /* Cr-Cr list capacity per atom */
     int32_t xcap;       /* Cr-C list capacity per atom */
+    int32_t tpa;        /* lanes per atom in the density / force passes: 1, 2, 4 or 8 (the
+                           Cr-Cr list is interleaved by tpa to match) */
+    int32_t pad;
 } md_params;
 
 /* One system (replica). */
@@ -131,9 +134,10 @@ typedef struct md_atoms {
 
 /* Device neighbour lists (caller-owned, written by md_build_neighbors). */
 typedef struct md_lists {
-    int32_t *idx;       /* [cap][n_total]: entry k of atom i at idx[k * n_total + i] (atom slot) */
+    int32_t *idx;       /* [cap * n_total]: entry k of atom i (an atom slot) at
+                           idx[(k / tpa) * n_total * tpa + i * tpa + k % tpa] */
     int32_t *cnt;       /* [n_total] */
-    int32_t *xidx;      /* [xcap][n_total]: carbon indices (into xc) of atom i's Cr-C list */
+    int32_t *xidx;      /* [n_total][xcap]: carbon indices (into xc) of atom i's Cr-C list */
     int32_t *xcnt;      /* [n_total] */
 } md_lists;
 
@@ -143,8 +147,10 @@ typedef struct md_status {
     int32_t xoverflow;      /* same for the Cr-C list and xcap */
     int32_t nonfinite;      /* 1 if a non-finite force or density was produced */
     int32_t nbuilds;        /* list builds so far (summed over replicas) */
-    int32_t sync_timeout;   /* 1 if a grid-wide wait gave up (the affected call is invalid) */
-    int32_t pad[3];
+    int32_t sync_timeout;   /* reserved (always 0) */
+    int32_t nnear;          /* Cr atoms whose carbon cells are within reach of a carbon at the
+                               last build (the candidates of the Cr-C lists), all replicas */
+    int32_t pad[2];
 } md_status;
 
 typedef struct md_system md_system;
@@ -199,8 +205,9 @@ MD_API int md_eam_forces(md_system *sys, const md_atoms *a, const md_lists *l, u
                          double *rho_out, void *stream);
 
 /* Task 4c: Cr-C Morse forces added into f (F_i += -phiM'(r) (q_i - q_k)/r over the Cr-C
- * list) and the load on the indenter (minus their sum).  Flags: MD_F_KICK applies the half
- * kick of these forces only, MD_F_ENERGY writes partials, MD_F_MIXED FP32 arithmetic. */
+ * list), recorded per atom for the load on the indenter (minus their sum) and the Morse
+ * energy reported by md_energy.  Flags: MD_F_KICK applies the half kick of these forces
+ * only, MD_F_MIXED FP32 arithmetic. */
 MD_API int md_morse_forces(md_system *sys, const md_atoms *a, const md_lists *l, uint32_t flags,
                            void *stream);
 
@@ -210,9 +217,10 @@ MD_API int md_morse_forces(md_system *sys, const md_atoms *a, const md_lists *l,
 MD_API int md_verlet_step(md_system *sys, int32_t phase, const md_atoms *a, void *stream);
 
 /* Task 4d: energies, virial, indenter load and counters (MD_NOBS doubles per replica,
- * device pointer out[nrep][MD_NOBS]), reduced in a fixed order in FP64 from the partials of
- * the last md_eam_forces / md_morse_forces calls made with MD_F_ENERGY, plus the kinetic
- * energy of the current velocities. */
+ * device pointer out[nrep][MD_NOBS]), reduced in a fixed order in FP64: embedding and pair
+ * energy and virial from the partials of the last md_eam_forces call made with
+ * MD_F_ENERGY, Morse energy and load from the last Morse evaluation (zero before any and
+ * after a list build), kinetic energy of the current velocities. */
 MD_API int md_energy(md_system *sys, const md_atoms *a, double *out, void *stream);
 
 /* ---------------------------------------------------------------------------------- */

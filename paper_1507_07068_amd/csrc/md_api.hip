@@ -22,12 +22,13 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Byte offsets of the workspace regions.
 struct Layout {
-  size_t desc, state, tile_rep, misc, xref, dmax, cellid, perm, tq, tv, tf, tfixed, tid, count,
-      start, hcell, hlist, bsum, p_embed, p_force, p_morse, p_kin, total;
+  size_t desc, state, tile_rep, c_rep, cell_rep, misc, xref, dmax, tbox, cellid, perm, tq, tv, tf, tfixed,
+      tid, count, start, hcell, hlist, hsorted, bsum, hnear, near, fme, p_embed, p_force, p_morse, p_kin, total;
 };
 
-constexpr int MAX_GRID = 4096;   // upper bound of the persistent rebuild grid
-constexpr int MISC_INTS = 16;    // any flag, barrier words, status words
+constexpr int MISC_INTS = 16;    // rebuild flag, status words
+constexpr int SCAN_CHUNK = 2048; // cells per block of the cell-count scan
+constexpr int MAXREP = 16384;    // replicas per system
 
 }  // namespace
 
@@ -36,14 +37,16 @@ struct md_system {
   int nrep;
   std::vector<RepDesc> desc;
   std::vector<int> tile_rep;
+  std::vector<int> c_rep;
+  std::vector<int> cell_rep;
   int64_t ntot, ctot;
   int ntiles;
   int ncell_cr, ncell_all;
   Consts K;
   Layout L;
   char* ws;
-  int rebuild_grid;
-  bool have_embed, have_force, have_morse;
+  int scan_blocks;
+  bool have_embed, have_force;
 };
 
 namespace {
@@ -65,9 +68,12 @@ Layout make_layout(const md_system& s) {
   L.desc = take(sizeof(RepDesc) * s.nrep);
   L.state = take(sizeof(RepState) * s.nrep);
   L.tile_rep = take(sizeof(int) * nt);
+  L.c_rep = take(sizeof(int) * (size_t)s.ctot);
+  L.cell_rep = take(sizeof(int) * (size_t)s.ncell_all);
   L.misc = take(sizeof(int) * MISC_INTS);
   L.xref = take(sizeof(double) * 3 * n);
   L.dmax = take(sizeof(double) * nt);
+  L.tbox = take(sizeof(double) * 6 * nt);
   L.cellid = take(sizeof(int) * n);
   L.perm = take(sizeof(int) * n);
   L.tq = take(sizeof(double) * 4 * n);
@@ -79,9 +85,13 @@ Layout make_layout(const md_system& s) {
   L.start = take(sizeof(int) * ((size_t)s.ncell_all + 1));
   L.hcell = take(sizeof(int) * (size_t)s.ctot);
   L.hlist = take(sizeof(int) * (size_t)s.ctot);
-  L.bsum = take(sizeof(int) * MAX_GRID);
-  L.p_embed = take(sizeof(double) * nt);
-  L.p_force = take(sizeof(double) * nt * NP_FORCE);
+  L.hsorted = take(sizeof(int) * (size_t)s.ctot);
+  L.bsum = take(sizeof(int) * (size_t)s.scan_blocks);
+  L.hnear = take(sizeof(int) * (size_t)s.ncell_all);
+  L.near = take(sizeof(int) * n);
+  L.fme = take(sizeof(double) * 4 * n);
+  L.p_embed = take(sizeof(double) * nt * s.K.lt);
+  L.p_force = take(sizeof(double) * nt * s.K.lt * NP_FORCE);
   L.p_morse = take(sizeof(double) * nt * 4);
   L.p_kin = take(sizeof(double) * nt);
   L.total = o;
@@ -109,6 +119,64 @@ bool lists_ok(const md_lists* l) { return l && l->idx && l->cnt && l->xidx && l-
 
 int grid_tiles(const md_system* s) { return s->ntiles; }
 
+// Grid of the kernels that walk the near-indenter atoms (one wavefront per atom, grid-stride).
+int near_blocks(const md_system* s) { return std::max(1, std::min(2048, s->ntiles)); }
+
+}  // namespace
+
+namespace {
+
+template <int T>
+void launch_density(md_system* s, const md_atoms* a, const md_lists* l, bool mixed, bool energy,
+                    double* rho_out, hipStream_t st) {
+  const RepDesc* R = at<RepDesc>(s, s->L.desc);
+  RepState* S = at<RepState>(s, s->L.state);
+  const int* tr = at<int>(s, s->L.tile_rep);
+  double4* q = reinterpret_cast<double4*>(a->q);
+  double* pe = at<double>(s, s->L.p_embed);
+  const int nb = s->ntiles * T;
+#define DENS(M, E) k_density<T, M, E><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, l->idx, l->cnt, rho_out, pe)
+  if (mixed) { if (energy) DENS(true, true); else DENS(true, false); }
+  else { if (energy) DENS(false, true); else DENS(false, false); }
+#undef DENS
+}
+
+template <int T>
+void launch_force(md_system* s, const md_atoms* a, const md_lists* l, bool mixed, bool kick, bool energy,
+                  hipStream_t st) {
+  const RepDesc* R = at<RepDesc>(s, s->L.desc);
+  RepState* S = at<RepState>(s, s->L.state);
+  const int* tr = at<int>(s, s->L.tile_rep);
+  const double4* q = reinterpret_cast<const double4*>(a->q);
+  double* pf = at<double>(s, s->L.p_force);
+  const int nb = s->ntiles * T;
+#define FORCE(M, KI, E) \
+  k_force<T, M, KI, E><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, a->v, a->f, a->fixed, l->idx, l->cnt, pf)
+#define FORCE_E(M, KI) \
+  if (energy) FORCE(M, KI, true); else FORCE(M, KI, false)
+#define FORCE_K(M) \
+  if (kick) { FORCE_E(M, true); } else { FORCE_E(M, false); }
+  if (mixed) { FORCE_K(true); } else { FORCE_K(false); }
+#undef FORCE_K
+#undef FORCE_E
+#undef FORCE
+}
+
+void launch_morse(md_system* s, const md_atoms* a, const md_lists* l, bool mixed, bool kick,
+                  hipStream_t st) {
+  const RepDesc* R = at<RepDesc>(s, s->L.desc);
+  const RepState* S = at<RepState>(s, s->L.state);
+  const double4* q = reinterpret_cast<const double4*>(a->q);
+  const int* nr = at<int>(s, s->L.near);
+  double* fme = at<double>(s, s->L.fme);
+  const int nb = near_blocks(s);
+#define MORSE(M, KI) \
+  k_morse<M, KI><<<nb, BLOCK, 0, st>>>(s->K, R, S, q, a->v, a->f, a->fixed, a->xc, l->xidx, l->xcnt, nr, fme)
+  if (mixed) { if (kick) MORSE(true, true); else MORSE(true, false); }
+  else { if (kick) MORSE(false, true); else MORSE(false, false); }
+#undef MORSE
+}
+
 }  // namespace
 
 extern "C" {
@@ -129,6 +197,7 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
   *out = nullptr;
   if (!reps || !p || nrep < 1 || nrep > MAXREP) return MD_ERR_ARG;
   if (!(p->mass > 0) || !(p->dt > 0) || !(p->skin >= 0) || p->cap < 1 || p->xcap < 1) return MD_ERR_ARG;
+  if (p->tpa != 1 && p->tpa != 2 && p->tpa != 4 && p->tpa != 8) return MD_ERR_ARG;
   if (!(p->eam.c > 0) || !(p->eam.d > 0) || !(p->eam.d <= p->eam.c) || !(p->morse.rc > 0) ||
       !(p->morse.alpha > 0))
     return MD_ERR_ARG;
@@ -137,8 +206,7 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
   s->p = *p;
   s->nrep = nrep;
   s->ws = nullptr;
-  s->rebuild_grid = 0;
-  s->have_embed = s->have_force = s->have_morse = false;
+  s->have_embed = s->have_force = false;
   const double rlist = p->eam.c + p->skin;
   const double rxlist = p->morse.rc + p->skin;
   int64_t a0 = 0, c0 = 0;
@@ -154,12 +222,15 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
       d.len[a] = rd.len[a];
       d.half[a] = 0.5 * rd.len[a];
       d.per[a] = rd.periodic[a] ? 1 : 0;
-      d.gd[a] = cells_along(rd.len[a], rlist);
+      // allocated cells along the axis: the box along periodic axes; room for the atoms to
+      // spread to about twice the given extent along open axes (beyond that cells stretch)
+      const int nb = cells_along(rd.len[a], rlist);
+      d.gcap[a] = d.per[a] ? nb : std::max(2 * nb, nb + 8);
       d.hd[a] = rd.n_c > 0 ? cells_along(rd.len[a], rxlist) : 1;
       // the minimum image must be the only image within the list radius
       if (d.per[a] && !(rd.len[a] > 2.0 * rlist)) { delete s; return MD_ERR_ARG; }
       if (d.per[a] && rd.n_c > 0 && !(rd.len[a] > 2.0 * rxlist)) { delete s; return MD_ERR_ARG; }
-      d.ginv[a] = d.gd[a] / rd.len[a];
+      d.ginv[a] = nb / rd.len[a];
       d.hinv[a] = d.hd[a] / rd.len[a];
     }
     d.a0 = (int)a0;
@@ -170,7 +241,7 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
     d.nt = ntile;
     d.c0 = (int)c0;
     d.nc = rd.n_c;
-    int64_t ncr = (int64_t)d.gd[0] * d.gd[1] * d.gd[2];
+    int64_t ncr = (int64_t)d.gcap[0] * d.gcap[1] * d.gcap[2];
     int64_t nch = (int64_t)d.hd[0] * d.hd[1] * d.hd[2];
     if (ncr > (1 << 28) || nch > (1 << 28)) { delete s; return MD_ERR_ARG; }
     d.g0 = g0;
@@ -182,14 +253,23 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
     if (a0 > (int64_t)INT32_MAX / 2 || c0 > (int64_t)INT32_MAX / 2) { delete s; return MD_ERR_ARG; }
     s->desc.push_back(d);
     for (int t = 0; t < ntile; ++t) s->tile_rep.push_back(r);
+    for (int k = 0; k < rd.n_c; ++k) s->c_rep.push_back(r);
+    for (int64_t c = 0; c < ncr; ++c) s->cell_rep.push_back(r);
   }
   s->ncell_cr = g0;
   int h = g0;
   for (int r = 0; r < nrep; ++r) {
     s->desc[r].h0 = h;
     h += hcells[r];
+    for (int c = 0; c < hcells[r]; ++c) s->cell_rep.push_back(r);
   }
   s->ncell_all = h;
+  // list offsets are 32-bit
+  if ((int64_t)p->cap * a0 >= (int64_t)INT32_MAX || (int64_t)p->xcap * a0 >= (int64_t)INT32_MAX) {
+    delete s;
+    return MD_ERR_ARG;
+  }
+  s->scan_blocks = (h + SCAN_CHUNK - 1) / SCAN_CHUNK;
   s->ntot = a0;
   s->ctot = c0;
   s->ntiles = t0;
@@ -224,10 +304,13 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
   K.half_skin = 0.5 * p->skin;
   K.half_skin_sq = K.half_skin * K.half_skin;
   K.rlist_sq = rlist * rlist;
+  K.rlist = rlist;
   K.rxlist_sq = rxlist * rxlist;
   K.cap = p->cap;
   K.xcap = p->xcap;
   K.nrep = nrep;
+  K.lt = p->tpa;
+  K.lt_shift = p->tpa == 1 ? 0 : (p->tpa == 2 ? 1 : (p->tpa == 4 ? 2 : 3));
   K.ntot = s->ntot;
   s->L = make_layout(*s);
   *out = s;
@@ -258,14 +341,14 @@ MD_API int md_workspace_bind(md_system* s, void* ws, size_t bytes, void* stream)
   if ((e = hip_status(hipMemcpyAsync(at<int>(s, s->L.tile_rep), s->tile_rep.data(),
                                      sizeof(int) * s->ntiles, hipMemcpyHostToDevice, st))))
     return e;
-  // Persistent rebuild grid: every block must be resident at once.
-  int dev = 0, ncu = 0, per_cu = 0;
-  if ((e = hip_status(hipGetDevice(&dev)))) return e;
-  if ((e = hip_status(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)))) return e;
-  if ((e = hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rebuild, BLOCK, 0)))) return e;
-  if (per_cu < 1) return MD_ERR_HIP;
-  s->rebuild_grid = std::min(MAX_GRID, ncu * std::min(per_cu, 2));
-  s->have_embed = s->have_force = s->have_morse = false;
+  if (s->ctot > 0 &&
+      (e = hip_status(hipMemcpyAsync(at<int>(s, s->L.c_rep), s->c_rep.data(), sizeof(int) * s->ctot,
+                                     hipMemcpyHostToDevice, st))))
+    return e;
+  if ((e = hip_status(hipMemcpyAsync(at<int>(s, s->L.cell_rep), s->cell_rep.data(),
+                                     sizeof(int) * s->ncell_all, hipMemcpyHostToDevice, st))))
+    return e;
+  s->have_embed = s->have_force = false;
   return hip_status(hipStreamSynchronize(st));
 }
 
@@ -275,16 +358,13 @@ MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l
   if (!s->ws) return MD_ERR_STATE;
   hipStream_t st = (hipStream_t)stream;
   int* misc = at<int>(s, s->L.misc);
-  RepState* S = at<RepState>(s, s->L.state);
-  const RepDesc* R = at<RepDesc>(s, s->L.desc);
-  k_decide<<<s->nrep, BLOCK, 0, st>>>(s->K, R, S, at<double>(s, s->L.dmax), (flags & MD_B_FORCE) ? 1 : 0,
-                                      misc + 0);
-  RebuildArgs A;
-  A.R = R;
-  A.S = S;
+  BuildArgs A;
+  A.R = at<RepDesc>(s, s->L.desc);
+  A.S = at<RepState>(s, s->L.state);
   A.tile_rep = at<int>(s, s->L.tile_rep);
+  A.c_rep = at<int>(s, s->L.c_rep);
+  A.cell_rep = at<int>(s, s->L.cell_rep);
   A.any = misc + 0;
-  A.bar = reinterpret_cast<unsigned*>(misc + 2);
   A.q = reinterpret_cast<double4*>(a->q);
   A.v = a->v;
   A.f = a->f;
@@ -292,7 +372,6 @@ MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l
   A.id = a->id;
   A.xc = a->xc;
   A.xref = at<double>(s, s->L.xref);
-  A.dmax_tile = at<double>(s, s->L.dmax);
   A.cellid = at<int>(s, s->L.cellid);
   A.perm = at<int>(s, s->L.perm);
   A.tq = at<double4>(s, s->L.tq);
@@ -304,16 +383,35 @@ MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l
   A.start = at<int>(s, s->L.start);
   A.hcell = at<int>(s, s->L.hcell);
   A.hlist = at<int>(s, s->L.hlist);
+  A.hsorted = at<int>(s, s->L.hsorted);
   A.bsum = at<int>(s, s->L.bsum);
   A.idx = l->idx;
   A.cnt = l->cnt;
   A.xidx = l->xidx;
   A.xcnt = l->xcnt;
+  A.near = at<int>(s, s->L.near);
+  A.hnear = at<int>(s, s->L.hnear);
+  A.fme = at<double>(s, s->L.fme);
+  A.near_blocks = near_blocks(s);
   A.ncell_all = s->ncell_all;
   A.ncell_cr = s->ncell_cr;
   A.ntiles = s->ntiles;
-  A.c_total = (int)s->ctot;
-  k_rebuild<<<s->rebuild_grid, BLOCK, 0, st>>>(s->K, A);
+  A.ctot = (int)s->ctot;
+  A.scan_chunk = SCAN_CHUNK;
+  A.scan_blocks = s->scan_blocks;
+  const int cblocks = (int)((s->ctot + BLOCK - 1) / BLOCK);
+  if (flags & MD_B_FORCE)
+    k_tile_box<<<s->ntiles, BLOCK, 0, st>>>(A.R, A.tile_rep, A.q, at<double>(s, s->L.tbox));
+  k_decide<<<1, BLOCK, 0, st>>>(s->K, A, at<double>(s, s->L.dmax), at<double>(s, s->L.tbox),
+                                (flags & MD_B_FORCE) ? 1 : 0);
+  k_bin<<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A);
+  k_scan_reduce<<<s->scan_blocks, BLOCK, 0, st>>>(A);
+  k_scan_top<<<1, BLOCK, 0, st>>>(A);
+  k_scan_apply<<<s->scan_blocks, BLOCK, 0, st>>>(A);
+  k_scatter<<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A);
+  k_sort_gather<<<(s->ncell_all + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, BLOCK, 0, st>>>(s->K, A);
+  k_list<<<(s->ncell_cr + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, BLOCK, 0, st>>>(s->K, A);
+  k_xlist<<<A.near_blocks, BLOCK, 0, st>>>(s->K, A);
   return check_launch();
 }
 
@@ -324,42 +422,28 @@ MD_API int md_eam_forces(md_system* s, const md_atoms* a, const md_lists* l, uin
   if ((flags & MD_F_MIXED) && s->p.eam.c2 == 0.0) return MD_ERR_ARG;
   if (!s->ws) return MD_ERR_STATE;
   hipStream_t st = (hipStream_t)stream;
-  const RepDesc* R = at<RepDesc>(s, s->L.desc);
-  RepState* S = at<RepState>(s, s->L.state);
-  const int* tr = at<int>(s, s->L.tile_rep);
-  double4* q = reinterpret_cast<double4*>(a->q);
-  const int nb = grid_tiles(s);
-  const bool mixed = flags & MD_F_MIXED, energy = flags & MD_F_ENERGY;
+  const bool mixed = flags & MD_F_MIXED, energy = flags & MD_F_ENERGY, kick = flags & MD_F_KICK;
+  const int T = s->K.lt;
   if (flags & MD_F_DENSITY) {
-    double* pe = at<double>(s, s->L.p_embed);
-#define DENS(M, E) k_density<M, E><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, l->idx, l->cnt, rho_out, pe)
-    if (mixed) { if (energy) DENS(true, true); else DENS(true, false); }
-    else { if (energy) DENS(false, true); else DENS(false, false); }
-#undef DENS
+    switch (T) {
+      case 1: launch_density<1>(s, a, l, mixed, energy, rho_out, st); break;
+      case 2: launch_density<2>(s, a, l, mixed, energy, rho_out, st); break;
+      case 4: launch_density<4>(s, a, l, mixed, energy, rho_out, st); break;
+      default: launch_density<8>(s, a, l, mixed, energy, rho_out, st); break;
+    }
     s->have_embed = energy;
     int e = check_launch();
     if (e) return e;
   }
   if (flags & MD_F_FORCE) {
-    double* pf = at<double>(s, s->L.p_force);
-    const bool morse = (flags & MD_F_MORSE) && s->ctot > 0, kick = flags & MD_F_KICK;
-    const double* xc = a->xc;
-#define FORCE(M, MO, KI, E)                                                                    \
-  k_force<M, MO, KI, E><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, a->v, a->f, a->fixed, l->idx, \
-                                              l->cnt, xc, l->xidx, l->xcnt, pf)
-#define FORCE_E(M, MO, KI) \
-  if (energy) FORCE(M, MO, KI, true); else FORCE(M, MO, KI, false)
-#define FORCE_K(M, MO) \
-  if (kick) { FORCE_E(M, MO, true); } else { FORCE_E(M, MO, false); }
-#define FORCE_MO(M) \
-  if (morse) { FORCE_K(M, true); } else { FORCE_K(M, false); }
-    if (mixed) { FORCE_MO(true); } else { FORCE_MO(false); }
-#undef FORCE_MO
-#undef FORCE_K
-#undef FORCE_E
-#undef FORCE
+    switch (T) {
+      case 1: launch_force<1>(s, a, l, mixed, kick, energy, st); break;
+      case 2: launch_force<2>(s, a, l, mixed, kick, energy, st); break;
+      case 4: launch_force<4>(s, a, l, mixed, kick, energy, st); break;
+      default: launch_force<8>(s, a, l, mixed, kick, energy, st); break;
+    }
     s->have_force = energy;
-    if (energy) s->have_morse = false;   // the Morse share (if any) is inside the force partials
+    if ((flags & MD_F_MORSE) && s->ctot > 0) launch_morse(s, a, l, mixed, kick, st);
     int e = check_launch();
     if (e) return e;
   }
@@ -371,26 +455,7 @@ MD_API int md_morse_forces(md_system* s, const md_atoms* a, const md_lists* l, u
   if (!s || !atoms_ok(a) || !lists_ok(l)) return MD_ERR_ARG;
   if (s->ctot > 0 && !a->xc) return MD_ERR_ARG;
   if (!s->ws) return MD_ERR_STATE;
-  hipStream_t st = (hipStream_t)stream;
-  const RepDesc* R = at<RepDesc>(s, s->L.desc);
-  RepState* S = at<RepState>(s, s->L.state);
-  const int* tr = at<int>(s, s->L.tile_rep);
-  const double4* q = reinterpret_cast<const double4*>(a->q);
-  double* pm = at<double>(s, s->L.p_morse);
-  const int nb = grid_tiles(s);
-  const bool mixed = flags & MD_F_MIXED, kick = flags & MD_F_KICK, energy = flags & MD_F_ENERGY;
-#define MORSE(M, KI, E)                                                                        \
-  k_morse<M, KI, E><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, a->v, a->f, a->fixed, a->xc, l->xidx, \
-                                          l->xcnt, pm)
-#define MORSE_E(M, KI) \
-  if (energy) MORSE(M, KI, true); else MORSE(M, KI, false)
-#define MORSE_K(M) \
-  if (kick) { MORSE_E(M, true); } else { MORSE_E(M, false); }
-  if (mixed) { MORSE_K(true); } else { MORSE_K(false); }
-#undef MORSE_K
-#undef MORSE_E
-#undef MORSE
-  s->have_morse = energy;
+  if (s->ctot > 0) launch_morse(s, a, l, flags & MD_F_MIXED, flags & MD_F_KICK, (hipStream_t)stream);
   return check_launch();
 }
 
@@ -405,7 +470,8 @@ MD_API int md_verlet_step(md_system* s, int32_t phase, const md_atoms* a, void* 
   if (phase == MD_PHASE_KICK_DRIFT)
     k_kick_drift<<<nb, BLOCK, 0, st>>>(s->K, R, at<RepState>(s, s->L.state), tr,
                                        reinterpret_cast<double4*>(a->q), a->v, a->f, a->fixed,
-                                       at<double>(s, s->L.xref), at<double>(s, s->L.dmax));
+                                       at<double>(s, s->L.xref), at<double>(s, s->L.dmax),
+                                       at<double>(s, s->L.tbox));
   else
     k_kick<<<nb, BLOCK, 0, st>>>(s->K, R, tr, a->v, a->f, a->fixed);
   return check_launch();
@@ -418,11 +484,12 @@ MD_API int md_energy(md_system* s, const md_atoms* a, double* out, void* stream)
   const RepDesc* R = at<RepDesc>(s, s->L.desc);
   const int* tr = at<int>(s, s->L.tile_rep);
   double* pk = at<double>(s, s->L.p_kin);
-  k_kinetic<<<grid_tiles(s), BLOCK, 0, st>>>(s->K, R, tr, a->v, a->fixed, pk);
+  double* pm = at<double>(s, s->L.p_morse);
+  k_kinetic<<<grid_tiles(s), BLOCK, 0, st>>>(s->K, R, tr, a->v, a->fixed, at<double>(s, s->L.fme), pk, pm);
   k_reduce<<<s->nrep, BLOCK, 0, st>>>(R, at<RepState>(s, s->L.state),
-                                      s->have_embed ? at<double>(s, s->L.p_embed) : nullptr,
-                                      s->have_force ? at<double>(s, s->L.p_force) : nullptr,
-                                      s->have_morse ? at<double>(s, s->L.p_morse) : nullptr, pk, out);
+                                      s->have_embed ? at<double>(s, s->L.p_embed) : nullptr, s->K.lt,
+                                      s->have_force ? at<double>(s, s->L.p_force) : nullptr, s->K.lt,
+                                      pm, pk, out);
   return check_launch();
 }
 
@@ -466,13 +533,13 @@ MD_API int md_graph_create(md_system* s, const md_atoms* a, const md_lists* l, i
   hipGraph_t g = nullptr;
   hipError_t ce = hipStreamEndCapture(st, &g);
   if (rc) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return rc;
   }
   if ((e = hip_status(ce))) return e;
   hipGraphExec_t ex = nullptr;
   e = hip_status(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (e) return e;
   *graph_exec = (void*)ex;
   return MD_OK;
@@ -497,7 +564,7 @@ MD_API int md_check(md_system* s, md_status* st_out, void* stream) {
   int e = check_launch();
   if (e) return e;
   int host[8] = {0};
-  if ((e = hip_status(hipMemcpyAsync(host, misc + 8, sizeof(int) * 5, hipMemcpyDeviceToHost, st)))) return e;
+  if ((e = hip_status(hipMemcpyAsync(host, misc + 8, sizeof(int) * 6, hipMemcpyDeviceToHost, st)))) return e;
   if ((e = hip_status(hipStreamSynchronize(st)))) return e;
   std::memset(st_out, 0, sizeof *st_out);
   st_out->overflow = host[0];
@@ -505,6 +572,7 @@ MD_API int md_check(md_system* s, md_status* st_out, void* stream) {
   st_out->nonfinite = host[2];
   st_out->nbuilds = host[3];
   st_out->sync_timeout = host[4];
+  st_out->nnear = host[5];
   return MD_OK;
 }
 

@@ -24,9 +24,10 @@ struct RepDesc {
   int a0, n, npad;      // first atom slot, atom count, padded slot count
   int c0, nc;           // first carbon, carbon count
   int t0, nt;           // first tile, tile count
-  int g0, gd[3];        // Cr-Cr cell grid: first cell (global), dims
+  int g0, gcap[3];      // Cr-Cr cell grid: first cell (global), allocated dims (the dims in
+                        // use along open axes follow the atoms, see RepState)
   int h0, hd[3];        // Cr-C cell grid: first cell (global, after all Cr grids), dims
-  double ginv[3];       // cells per Angstrom of the Cr grid
+  double ginv[3];       // cells per Angstrom of the Cr grid along periodic axes
   double hinv[3];       // cells per Angstrom of the carbon grid
 };
 
@@ -34,13 +35,17 @@ struct RepDesc {
 struct alignas(64) RepState {
   double ind_z;           // indenter displacement along z
   double ind_z_ref;       // ind_z at the last list build
-  unsigned long long czmin, czmax;  // ordered bits of the current carbon z extent (at a build)
   int rebuild;            // 1: the next k_rebuild rebuilds this replica
   int nbuilds;
   int overflow;           // needed Cr-Cr capacity (0 = fits)
   int xoverflow;          // needed Cr-C capacity
   int nonfinite;
   int sync_timeout;
+  int nnear;              // Cr atoms within reach of the carbons (entries of the near list)
+  // Cr cell grid of the current build: origin, cells per Angstrom, dims (<= gcap).  Along
+  // periodic axes it is the box; along open axes it spans the atoms' current extent.
+  double glo[3], ginv[3];
+  int gd[3];
 };
 
 // Constants of the potential and the integrator (passed by value).
@@ -57,9 +62,11 @@ struct Consts {
   double dt, v_ind;
   double half_skin, half_skin_sq;
   double rlist_sq, rxlist_sq;
+  double rlist;           // cutoff + skin
   int cap, xcap;
   int nrep;
-  int pad;
+  int lt;                 // list interleave: entries k..k+lt-1 of an atom are adjacent
+  int lt_shift;           // log2(lt)
   int64_t ntot;           // atom slots (all replicas)
 };
 
@@ -160,6 +167,44 @@ __device__ __forceinline__ int cell_coord(double x, double lo, double inv, int d
   double t = floor((x - lo) * inv);
   t = fmin(fmax(t, 0.0), (double)(dim - 1));
   return (int)t;
+}
+
+// Block-wide exclusive scan of one int per thread; returns the prefix, *total = block sum.
+__device__ __forceinline__ int block_exclusive_scan(int v, int* total) {
+  __shared__ int sh[BLOCK / WAVE];
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    int y = __shfl_up(x, o, WAVE);
+    if (lane >= o) x += y;
+  }
+  if (lane == WAVE - 1) sh[w] = x;
+  __syncthreads();
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < BLOCK / WAVE; ++i) {
+    if (i < w) off += sh[i];
+    tot += sh[i];
+  }
+  __syncthreads();
+  *total = tot;
+  return off + x - v;
+}
+
+// Value of `v` in lane `l` (l uniform across the wavefront), as a scalar.
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const unsigned long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffull), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Orders the LDS accesses of one wavefront (lanes exchanging data through LDS).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // The 27-cell stencil, one axis at a time: offsets t = 0..stencil_n-1 map to cells

@@ -1,0 +1,346 @@
+// Task 4 (and the fused Task 5 kick) of the MD step on gfx950.  Included by md_kernels.hip.
+//
+//   k_density<T>   rho_i = sum_j f(r_ij), F'(rho_i) -> q[i].w   (Section 3.3.1.2)
+//   k_force<T>     Eq. (1): F_i = -sum_j [(F'_i + F'_j) f'(r) + phi'(r)] (q_i - q_j) / r
+//   k_morse        Cr-C Morse forces: one wavefront per Cr atom that has carbons in range
+//   k_kick         Task 5 on its own
+//
+// T lanes cooperate on one atom (entries k = sub, sub + T, ... of its list; the list is
+// interleaved by T so those lanes read adjacent words) and combine their partial sums with
+// a fixed butterfly, so results do not depend on scheduling.  Each atom's sums are written
+// by one lane only: no atomics.
+#pragma once
+
+#include "md_device.hpp"
+
+namespace md {
+
+// Sum over the T lanes of one atom (T a power of two <= 64).
+template <int T, class V>
+__device__ __forceinline__ V group_sum(V v) {
+#pragma unroll
+  for (int o = T / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+
+// Visit the entries k = sub, sub + T, ... (< n) of atom i's list in order, calling
+// body(q[j]) for each neighbour j.  Entries are fetched U at a time so that U independent
+// index loads, then U independent position gathers, are in flight together.
+constexpr int UNROLL = 1;
+
+template <int T, int U, class Q, class Body>
+__device__ __forceinline__ void for_neighbors(const int* __restrict__ idx, const Q* q, int i, int n,
+                                              int sub, int ntot, int shift, Body body) {
+  int k = sub;
+  for (; k + (U - 1) * T < n; k += U * T) {
+    int j[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) j[u] = idx[list_pos(k + u * T, i, ntot, T, shift)];
+    double4 p[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) p[u] = q[j[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) body(p[u]);
+  }
+  for (; k < n; k += T) body(q[idx[list_pos(k, i, ntot, T, shift)]]);
+}
+
+// Atom of this thread in a launch with T lanes per atom and one block per 256/T atoms.
+struct AtomCtx {
+  int blk;       // logical block (XCD-aware)
+  int r;         // replica
+  int sub;       // lane within the atom's group
+  int64_t i;     // atom slot
+  bool live;
+};
+
+template <int T>
+__device__ __forceinline__ AtomCtx atom_ctx(const int* tile_rep, const RepDesc* R) {
+  constexpr int APB = BLOCK / T;
+  AtomCtx c;
+  c.blk = xcd_block(blockIdx.x, gridDim.x);
+  const int tile = c.blk / T;
+  c.r = tile_rep[tile];
+  c.sub = threadIdx.x % T;
+  c.i = (int64_t)tile * TILE + (c.blk % T) * APB + threadIdx.x / T;
+  const RepDesc& d = R[c.r];
+  c.live = c.i < (int64_t)d.a0 + d.n;
+  return c;
+}
+
+template <int T, bool MIXED, bool ENERGY>
+__global__ __launch_bounds__(BLOCK) void k_density(Consts K, const RepDesc* __restrict__ R,
+                                                   RepState* __restrict__ S,
+                                                   const int* __restrict__ tile_rep,
+                                                   double4* __restrict__ q,
+                                                   const int* __restrict__ idx,
+                                                   const int* __restrict__ cnt,
+                                                   double* __restrict__ rho_out,
+                                                   double* __restrict__ part) {
+  const AtomCtx c = atom_ctx<T>(tile_rep, R);
+  const RepDesc& d = R[c.r];
+  double rho = 0.0;
+  double4 pi = make_double4(0.0, 0.0, 0.0, 0.0);
+  if (c.live) {
+    const int64_t i = c.i;
+    pi = q[i];
+    const int n = cnt[i];
+    if (MIXED) {
+      float acc = 0.0f;
+      const float dd = (float)K.d, dd2 = (float)K.d_sq;
+      for_neighbors<T, UNROLL>(idx, q, (int)i, n, c.sub, (int)K.ntot, K.lt_shift, [&](const double4& pj) {
+        const float ex = (float)min_image(pj.x - pi.x, d.len[0], d.half[0], d.per[0]);
+        const float ey = (float)min_image(pj.y - pi.y, d.len[1], d.half[1], d.per[1]);
+        const float ez = (float)min_image(pj.z - pi.z, d.len[2], d.half[2], d.per[2]);
+        const float r2 = ex * ex + ey * ey + ez * ez;
+        if (r2 < dd2) {
+          const float u = __fsqrt_rn(r2) - dd;
+          acc += u * u;
+        }
+      });
+      rho = (double)acc;
+    } else {
+      for_neighbors<T, UNROLL>(idx, q, (int)i, n, c.sub, (int)K.ntot, K.lt_shift, [&](const double4& pj) {
+        const double ex = min_image(pj.x - pi.x, d.len[0], d.half[0], d.per[0]);
+        const double ey = min_image(pj.y - pi.y, d.len[1], d.half[1], d.per[1]);
+        const double ez = min_image(pj.z - pi.z, d.len[2], d.half[2], d.per[2]);
+        const double r2 = ex * ex + ey * ey + ez * ez;
+        if (r2 < K.d_sq) {
+          const double u = sqrt(r2) - K.d;
+          rho += u * u;
+        }
+      });
+    }
+  }
+  rho = group_sum<T>(rho);
+  double e_embed = 0.0;
+  if (c.live && c.sub == 0) {
+    const double sr = sqrt(rho);
+    q[c.i].w = rho > 0.0 ? -K.A / (2.0 * sr) : 0.0;
+    if (rho_out) rho_out[c.i] = rho;
+    if (ENERGY) e_embed = -K.A * sr;
+    if (!(rho == rho)) S[c.r].nonfinite = 1;
+  }
+  if (ENERGY) {
+    double vals[1] = {e_embed};
+    block_sum_store<1, BLOCK>(vals, part + c.blk);
+  }
+}
+
+// Partial sums written per block by k_force.
+enum { P_PAIR = 0, P_WXX, P_WYY, P_WZZ, P_WXY, P_WXZ, P_WYZ, NP_FORCE };
+
+template <int T, bool MIXED, bool KICK, bool ENERGY>
+__global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __restrict__ R,
+                                                 RepState* __restrict__ S,
+                                                 const int* __restrict__ tile_rep,
+                                                 const double4* __restrict__ q,
+                                                 double* __restrict__ v, double* __restrict__ f,
+                                                 const uint8_t* __restrict__ fixed,
+                                                 const int* __restrict__ idx,
+                                                 const int* __restrict__ cnt,
+                                                 double* __restrict__ part) {
+  const AtomCtx c = atom_ctx<T>(tile_rep, R);
+  const RepDesc& d = R[c.r];
+  double acc[NP_FORCE];
+#pragma unroll
+  for (int k = 0; k < NP_FORCE; ++k) acc[k] = 0.0;
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+  if (c.live) {
+    const int64_t i = c.i;
+    const double4 pi = q[i];
+    const int n = cnt[i];
+    if (MIXED) {
+      const float cc = (float)K.c, dd = (float)K.d, c2 = (float)K.c2, rv = (float)K.rv,
+                  pmin = (float)K.pmin, csq = (float)K.c_sq, dsq = (float)K.d_sq;
+      const float Fi = (float)pi.w;
+      float ax = 0.f, ay = 0.f, az = 0.f;
+      float ep = 0.f, w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f, w4 = 0.f, w5 = 0.f;
+      for_neighbors<T, UNROLL>(idx, q, (int)i, n, c.sub, (int)K.ntot, K.lt_shift, [&](const double4& pj) {
+        const float ex = (float)min_image(pj.x - pi.x, d.len[0], d.half[0], d.per[0]);
+        const float ey = (float)min_image(pj.y - pi.y, d.len[1], d.half[1], d.per[1]);
+        const float ez = (float)min_image(pj.z - pi.z, d.len[2], d.half[2], d.per[2]);
+        const float r2 = ex * ex + ey * ey + ez * ez;
+        if (r2 < csq) {
+          const float rinv = __frsqrt_rn(r2);
+          const float r = r2 * rinv;
+          const float u = r - cc, t = r - rv;
+          const float p = pmin + c2 * t * t;                    // c0 + c1 r + c2 r^2, vertex form
+          float g = u * (2.0f * p + u * (2.0f * c2 * t));        // phi'(r)
+          if (r2 < dsq) g += (Fi + (float)pj.w) * (2.0f * (r - dd));
+          const float s = g * rinv;                              // F_i += g (q_j - q_i) / r
+          ax += s * ex;
+          ay += s * ey;
+          az += s * ez;
+          if (ENERGY) {
+            ep += 0.5f * u * u * p;
+            w0 -= 0.5f * s * ex * ex;
+            w1 -= 0.5f * s * ey * ey;
+            w2 -= 0.5f * s * ez * ez;
+            w3 -= 0.5f * s * ex * ey;
+            w4 -= 0.5f * s * ex * ez;
+            w5 -= 0.5f * s * ey * ez;
+          }
+        }
+      });
+      fx = ax;
+      fy = ay;
+      fz = az;
+      if (ENERGY) {
+        acc[P_PAIR] = ep;
+        acc[P_WXX] = w0;
+        acc[P_WYY] = w1;
+        acc[P_WZZ] = w2;
+        acc[P_WXY] = w3;
+        acc[P_WXZ] = w4;
+        acc[P_WYZ] = w5;
+      }
+    } else {
+      const double Fi = pi.w;
+      for_neighbors<T, UNROLL>(idx, q, (int)i, n, c.sub, (int)K.ntot, K.lt_shift, [&](const double4& pj) {
+        const double ex = min_image(pj.x - pi.x, d.len[0], d.half[0], d.per[0]);
+        const double ey = min_image(pj.y - pi.y, d.len[1], d.half[1], d.per[1]);
+        const double ez = min_image(pj.z - pi.z, d.len[2], d.half[2], d.per[2]);
+        const double r2 = ex * ex + ey * ey + ez * ez;
+        if (r2 < K.c_sq) {
+          const double rinv = rsqrt(r2);
+          const double r = r2 * rinv;
+          const double u = r - K.c;
+          const double p = K.c0 + r * (K.c1 + r * K.c2);
+          double g = u * (2.0 * p + u * (K.c1 + 2.0 * K.c2 * r));   // phi'(r)
+          if (r2 < K.d_sq) g += (Fi + pj.w) * (2.0 * (r - K.d));
+          const double s = g * rinv;
+          fx += s * ex;
+          fy += s * ey;
+          fz += s * ez;
+          if (ENERGY) {
+            acc[P_PAIR] += 0.5 * u * u * p;
+            acc[P_WXX] -= 0.5 * s * ex * ex;
+            acc[P_WYY] -= 0.5 * s * ey * ey;
+            acc[P_WZZ] -= 0.5 * s * ez * ez;
+            acc[P_WXY] -= 0.5 * s * ex * ey;
+            acc[P_WXZ] -= 0.5 * s * ex * ez;
+            acc[P_WYZ] -= 0.5 * s * ey * ez;
+          }
+        }
+      });
+    }
+  }
+  fx = group_sum<T>(fx);
+  fy = group_sum<T>(fy);
+  fz = group_sum<T>(fz);
+  if (c.live && c.sub == 0) {
+    const int64_t i = c.i;
+    f[3 * i + 0] = fx;
+    f[3 * i + 1] = fy;
+    f[3 * i + 2] = fz;
+    if (!(fabs(fx) + fabs(fy) + fabs(fz) < INFINITY)) S[c.r].nonfinite = 1;
+    if (KICK && !fixed[i]) {
+      const double h = 0.5 * K.dt * K.acc;
+      v[3 * i + 0] += h * fx;
+      v[3 * i + 1] += h * fy;
+      v[3 * i + 2] += h * fz;
+    }
+  }
+  if (ENERGY) block_sum_store<NP_FORCE, BLOCK>(acc, part + (int64_t)c.blk * NP_FORCE);
+}
+
+// Task 4c: Cr-C Morse forces, F_i += -phiM'(r) (q_i - q_k)/r over atom i's Cr-C list,
+// added into f (and, with KICK, their half kick into v).  One wavefront per atom of each
+// replica's near list (grid-stride); the 64 lanes share that atom's carbons and combine
+// their sums with a fixed butterfly.  fme[i] receives (F_i, E_i) of the atom for the
+// energy pass, which sums it in atom order.
+template <bool MIXED, bool KICK>
+__global__ __launch_bounds__(BLOCK) void k_morse(Consts K, const RepDesc* __restrict__ R,
+                                                 const RepState* __restrict__ S,
+                                                 const double4* __restrict__ q,
+                                                 double* __restrict__ v, double* __restrict__ f,
+                                                 const uint8_t* __restrict__ fixed,
+                                                 const double* __restrict__ xc,
+                                                 const int* __restrict__ xidx,
+                                                 const int* __restrict__ xcnt,
+                                                 const int* __restrict__ near,
+                                                 double* __restrict__ fme) {
+  const int lane = threadIdx.x % WAVE;
+  const int gw = blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE, nw = gridDim.x * (BLOCK / WAVE);
+  for (int r = 0; r < K.nrep; ++r) {
+    const RepDesc& d = R[r];
+    const int nnear = S[r].nnear;
+    const double iz = S[r].ind_z;
+    for (int item = gw; item < nnear; item += nw) {
+      const int64_t pa = near[d.a0 + item];
+      const int na = xcnt[pa];
+      const double4 pi = q[pa];
+      double fm0 = 0.0, fm1 = 0.0, fm2 = 0.0, em = 0.0;
+      for (int k = lane; k < na; k += WAVE) {
+        const int kk = xidx[pa * K.xcap + k];
+        const double ex = min_image(xc[3 * kk + 0] - pi.x, d.len[0], d.half[0], d.per[0]);
+        const double ey = min_image(xc[3 * kk + 1] - pi.y, d.len[1], d.half[1], d.per[1]);
+        const double ez = min_image((xc[3 * kk + 2] + iz) - pi.z, d.len[2], d.half[2], d.per[2]);
+        if (MIXED) {
+          const float fx = (float)ex, fy = (float)ey, fz = (float)ez;
+          const float r2 = fx * fx + fy * fy + fz * fz;
+          if (r2 < (float)K.mrc_sq) {
+            const float rinv = __frsqrt_rn(r2);
+            const float rr = r2 * rinv;
+            const float e = __expf(-(float)K.alpha * (rr - (float)K.r0));
+            const float g = 2.0f * (float)(K.alpha * K.D) * (e - e * e);   // phiM'(r)
+            const float s = g * rinv;                                     // F_i += g (q_k - q_i)/r
+            fm0 += s * fx;
+            fm1 += s * fy;
+            fm2 += s * fz;
+            em += (double)((float)K.D * (e * e - 2.0f * e)) - K.mshift;
+          }
+        } else {
+          const double r2 = ex * ex + ey * ey + ez * ez;
+          if (r2 < K.mrc_sq) {
+            const double rr = sqrt(r2);
+            const double e = exp(-K.alpha * (rr - K.r0));
+            const double g = 2.0 * K.alpha * K.D * (e - e * e);
+            const double s = g / rr;
+            fm0 += s * ex;
+            fm1 += s * ey;
+            fm2 += s * ez;
+            em += K.D * (e * e - 2.0 * e) - K.mshift;
+          }
+        }
+      }
+      fm0 = wave_sum(fm0);
+      fm1 = wave_sum(fm1);
+      fm2 = wave_sum(fm2);
+      em = wave_sum(em);
+      if (lane == 0) {
+        f[3 * pa + 0] += fm0;
+        f[3 * pa + 1] += fm1;
+        f[3 * pa + 2] += fm2;
+        if (KICK && !fixed[pa]) {
+          const double h = 0.5 * K.dt * K.acc;
+          v[3 * pa + 0] += h * fm0;
+          v[3 * pa + 1] += h * fm1;
+          v[3 * pa + 2] += h * fm2;
+        }
+        fme[4 * pa + 0] = fm0;
+        fme[4 * pa + 1] = fm1;
+        fme[4 * pa + 2] = fm2;
+        fme[4 * pa + 3] = em;
+      }
+    }
+  }
+}
+
+// Task 5 alone.
+__global__ __launch_bounds__(BLOCK) void k_kick(Consts K, const RepDesc* __restrict__ R,
+                                                const int* __restrict__ tile_rep,
+                                                double* __restrict__ v, const double* __restrict__ f,
+                                                const uint8_t* __restrict__ fixed) {
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  const RepDesc& d = R[tile_rep[tile]];
+  const int64_t i = (int64_t)tile * TILE + threadIdx.x;
+  if (i >= (int64_t)d.a0 + d.n || fixed[i]) return;
+  const double h = 0.5 * K.dt * K.acc;
+  v[3 * i + 0] += h * f[3 * i + 0];
+  v[3 * i + 1] += h * f[3 * i + 1];
+  v[3 * i + 2] += h * f[3 * i + 2];
+}
+
+}  // namespace md

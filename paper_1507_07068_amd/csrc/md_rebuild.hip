@@ -1,0 +1,616 @@
+// Task 1 of the MD step on gfx950: skin test and Verlet-list rebuild.  Included by
+// md_kernels.hip.
+//
+//   k_decide        one block: per-replica skin test (Section 2.6) -> rebuild flags
+//   k_bin           wrap periodic coordinates, cell of every atom / carbon, cell counts
+//   k_scan_*        exclusive scan of all cell counts (three short kernels)
+//   k_scatter       atom slots / carbon indices into their cells (arbitrary order)
+//   k_sort_gather   one wavefront per cell: order the cell by atom id, gather the atom
+//                   state into sorted order (so the final order is canonical)
+//   k_list          one wavefront per Cr cell: the 27-cell candidates are loaded once into
+//                   registers, every atom of the cell tests them together, a ballot +
+//                   popcount compacts the passing ones in candidate order; copies the
+//                   sorted state back
+//   k_xlist         Cr-C lists: one wavefront per Cr atom within reach of the carbons
+//
+// Every kernel after k_decide returns at once when no replica needs a rebuild, so a step
+// without a rebuild costs a few empty launches.
+#pragma once
+
+#include "md_device.hpp"
+
+namespace md {
+
+struct BuildArgs {
+  const RepDesc* R;
+  RepState* S;
+  const int* tile_rep;   // [ntiles]
+  const int* c_rep;      // [ctot] replica of each carbon
+  const int* cell_rep;   // [ncell_all] replica of each cell (Cr cells, then carbon cells)
+  int* any;              // 1 if some replica rebuilds in this step
+  double4* q;
+  double* v;
+  double* f;
+  uint8_t* fixed;
+  int* id;
+  const double* xc;
+  double* xref;
+  int* cellid;           // [ntot]
+  int* perm;             // [ntot]
+  double4* tq;
+  double* tv;
+  double* tf;
+  uint8_t* tfixed;
+  int* tid;
+  int* count;            // [ncell_all]
+  int* start;            // [ncell_all + 1]
+  int* hcell;            // [ctot]
+  int* hlist;            // [ctot] carbons by cell (arbitrary order within a cell)
+  int* hsorted;          // [ctot] carbons by cell, ascending index within a cell
+  int* bsum;             // [scan_blocks]
+  int* hnear;            // [ncell_all]: carbon cell c has a carbon in its 27-cell stencil
+  int* idx;
+  int* cnt;
+  int* xidx;
+  int* xcnt;
+  int* near;             // [ntot]: replica r's near atoms at near[a0_r ...]
+  double* fme;           // [ntot][4]: last Morse force and energy per atom (0 if none)
+  int ncell_all, ncell_cr, ntiles, ctot;
+  int near_blocks;       // grid of k_xlist
+  int scan_chunk, scan_blocks;
+};
+
+constexpr int MAXC = 512;           // candidates staged per window in k_xlist
+constexpr int SUPER_X = 4;             // cells along x handled by one wavefront
+
+// Cells per wavefront along x: SUPER_X, or 1 when a periodic x axis is too short for the
+// widened stencil to stay free of repeated cells.
+__device__ __forceinline__ int super_x(const RepDesc& d, int gx) {
+  return (d.per[0] && gx < SUPER_X + 2) ? 1 : SUPER_X;
+}
+constexpr int WAVES_PER_BLOCK = BLOCK / WAVE;
+
+// Slot of entry k of atom i in the Cr-Cr list (interleave T: entries k..k+T-1 of one atom
+// are adjacent, so T lanes of one atom read consecutive words).
+__device__ __forceinline__ int list_pos(int k, int i, int ntot, int T, int Tshift) {
+  return ((k >> Tshift) * ntot + i) * T + (k & (T - 1));
+}
+
+__device__ __forceinline__ bool rebuild_off(const BuildArgs& A) { return *A.any == 0; }
+
+__global__ __launch_bounds__(BLOCK) void k_decide(Consts K, BuildArgs A, const double* __restrict__ dmax_tile,
+                                                  const double* __restrict__ tile_box, int force) {
+  __shared__ int any_sh, need_sh;
+  if (threadIdx.x == 0) any_sh = 0;
+  __syncthreads();
+  for (int r = 0; r < K.nrep; ++r) {
+    const RepDesc& d = A.R[r];
+    double m = 0.0;
+    for (int t = threadIdx.x; t < d.nt; t += BLOCK) m = fmax(m, dmax_tile[d.t0 + t]);
+    m = block_max<BLOCK>(m);
+    if (threadIdx.x == 0) {
+      RepState& s = A.S[r];
+      const int need = force || (m > K.half_skin_sq) || (fabs(s.ind_z - s.ind_z_ref) > K.half_skin);
+      s.rebuild = need;
+      need_sh = need;
+      if (need) {
+        s.nnear = 0;
+        any_sh = 1;
+      }
+    }
+    __syncthreads();
+    if (!need_sh) continue;   // uniform: read after the barrier
+    // cell grid of this build: the box along periodic axes, the atoms' extent along open ones
+    for (int a = 0; a < 3; ++a) {
+      RepState& s = A.S[r];
+      if (d.per[a]) {
+        if (threadIdx.x == 0) {
+          s.glo[a] = d.lo[a];
+          s.ginv[a] = d.ginv[a];
+          s.gd[a] = d.gcap[a];
+        }
+        continue;
+      }
+      double mn = INFINITY, mx = -INFINITY;
+      for (int t = threadIdx.x; t < d.nt; t += BLOCK) {
+        mn = fmin(mn, tile_box[6 * (int64_t)(d.t0 + t) + a]);
+        mx = fmax(mx, tile_box[6 * (int64_t)(d.t0 + t) + 3 + a]);
+      }
+      mn = -block_max<BLOCK>(-mn);
+      mx = block_max<BLOCK>(mx);
+      if (threadIdx.x == 0) {
+        if (!(mn <= mx)) {   // no atoms (or non-finite positions): fall back to the box
+          mn = d.lo[a];
+          mx = d.lo[a] + d.len[a];
+        }
+        const double edge = K.rlist * (1.0 + 1e-9);
+        const double ext = fmax(mx - mn, edge);
+        const int g = (int)fmin(fmax(floor(ext / edge), 1.0), (double)d.gcap[a]);
+        s.glo[a] = mn;
+        s.ginv[a] = g / ext;
+        s.gd[a] = g;
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *A.any = any_sh;
+}
+
+__device__ __forceinline__ int cr_cell_of(const RepDesc& d, const RepState& s, double x, double y, double z) {
+  int cx = cell_coord(x, s.glo[0], s.ginv[0], s.gd[0]);
+  int cy = cell_coord(y, s.glo[1], s.ginv[1], s.gd[1]);
+  int cz = cell_coord(z, s.glo[2], s.ginv[2], s.gd[2]);
+  return d.g0 + (cz * s.gd[1] + cy) * s.gd[0] + cx;
+}
+
+// Coordinate folded into [lo, lo + len) on a periodic axis (binning of carbons only).
+__device__ __forceinline__ double fold(double x, double lo, double len, int per) {
+  if (!per) return x;
+  return x - len * floor((x - lo) / len);
+}
+
+__device__ __forceinline__ void c_cell_coords(const RepDesc& d, double x, double y, double z, int& hx,
+                                              int& hy, int& hz) {
+  hx = cell_coord(fold(x, d.lo[0], d.len[0], d.per[0]), d.lo[0], d.hinv[0], d.hd[0]);
+  hy = cell_coord(fold(y, d.lo[1], d.len[1], d.per[1]), d.lo[1], d.hinv[1], d.hd[1]);
+  hz = cell_coord(fold(z, d.lo[2], d.len[2], d.per[2]), d.lo[2], d.hinv[2], d.hd[2]);
+}
+
+// Blocks [0, ntiles): one tile of Cr atoms each.  Blocks [ntiles, ...): 256 carbons each.
+__global__ __launch_bounds__(BLOCK) void k_bin(Consts K, BuildArgs A) {
+  if (rebuild_off(A)) return;
+  const int b = blockIdx.x;
+  if (b < A.ntiles) {
+    const int r = A.tile_rep[b];
+    if (!A.S[r].rebuild) return;
+    const RepDesc& d = A.R[r];
+    const int64_t i = (int64_t)b * TILE + threadIdx.x;
+    if (i >= (int64_t)d.a0 + d.n) return;
+    double4 p = A.q[i];
+    double xyz[3] = {p.x, p.y, p.z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (!d.per[a]) continue;
+      const double hi = d.lo[a] + d.len[a];
+      if (xyz[a] >= hi)
+        xyz[a] -= d.len[a];
+      else if (xyz[a] < d.lo[a])
+        xyz[a] += d.len[a];
+    }
+    p.x = xyz[0];
+    p.y = xyz[1];
+    p.z = xyz[2];
+    A.q[i] = p;
+    const int cid = cr_cell_of(d, A.S[r], p.x, p.y, p.z);
+    A.cellid[i] = cid;
+    atomicAdd(&A.count[cid], 1);
+  } else {
+    const int64_t k = (int64_t)(b - A.ntiles) * BLOCK + threadIdx.x;
+    int r = -1;
+    if (k < A.ctot) {
+      r = A.c_rep[k];
+      if (!A.S[r].rebuild) r = -1;
+    }
+    if (r >= 0) {
+      const RepDesc& d = A.R[r];
+      const double z = A.xc[3 * k + 2] + A.S[r].ind_z;
+      int hx, hy, hz;
+      c_cell_coords(d, A.xc[3 * k + 0], A.xc[3 * k + 1], z, hx, hy, hz);
+      const int hid = d.h0 + (hz * d.hd[1] + hy) * d.hd[0] + hx;
+      A.hcell[k] = hid;
+      atomicAdd(&A.count[hid], 1);
+    }
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_reduce(BuildArgs A) {
+  if (rebuild_off(A)) return;
+  const int c0 = blockIdx.x * A.scan_chunk, c1 = min(c0 + A.scan_chunk, A.ncell_all);
+  int s = 0;
+  for (int c = c0 + threadIdx.x; c < c1; c += BLOCK) s += A.count[c];
+  int tot;
+  block_exclusive_scan(s, &tot);
+  if (threadIdx.x == 0) A.bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_top(BuildArgs A) {
+  if (rebuild_off(A)) return;
+  int carry = 0;
+  for (int b0 = 0; b0 < A.scan_blocks; b0 += BLOCK) {
+    const int b = b0 + threadIdx.x;
+    const int v = b < A.scan_blocks ? A.bsum[b] : 0;
+    int tot;
+    const int ex = block_exclusive_scan(v, &tot);
+    if (b < A.scan_blocks) A.bsum[b] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) A.start[A.ncell_all] = carry;
+}
+
+// start[c] = exclusive prefix; count[c] = 0 (it becomes the fill cursor of k_scatter).
+__global__ __launch_bounds__(BLOCK) void k_scan_apply(BuildArgs A) {
+  if (rebuild_off(A)) return;
+  const int c0 = blockIdx.x * A.scan_chunk, c1 = min(c0 + A.scan_chunk, A.ncell_all);
+  int carry = A.bsum[blockIdx.x];
+  for (int cb = c0; cb < c1; cb += BLOCK) {
+    const int c = cb + threadIdx.x;
+    const int v = c < c1 ? A.count[c] : 0;
+    int tot;
+    const int ex = block_exclusive_scan(v, &tot);
+    if (c < c1) {
+      A.start[c] = carry + ex;
+      A.count[c] = 0;
+      A.hnear[c] = 0;
+    }
+    carry += tot;
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scatter(Consts K, BuildArgs A) {
+  if (rebuild_off(A)) return;
+  const int b = blockIdx.x;
+  if (b < A.ntiles) {
+    const int r = A.tile_rep[b];
+    if (!A.S[r].rebuild) return;
+    const RepDesc& d = A.R[r];
+    const int64_t i = (int64_t)b * TILE + threadIdx.x;
+    if (i >= (int64_t)d.a0 + d.n) return;
+    const int cid = A.cellid[i];
+    const int slot = atomicAdd(&A.count[cid], 1);
+    A.perm[d.a0 + (A.start[cid] - A.start[d.g0]) + slot] = (int)i;
+  } else {
+    const int64_t k = (int64_t)(b - A.ntiles) * BLOCK + threadIdx.x;
+    if (k >= A.ctot) return;
+    const int r = A.c_rep[k];
+    if (!A.S[r].rebuild) return;
+    const RepDesc& d = A.R[r];
+    const int hid = A.hcell[k];
+    const int slot = atomicAdd(&A.count[hid], 1);
+    A.hlist[d.c0 + (A.start[hid] - A.start[d.h0]) + slot] = (int)k;
+  }
+}
+
+// Rank of element u among the m elements of a segment, by (key, tie) ascending.  Each lane
+// holds one element; keys of all elements are visited 64 at a time through shuffles.
+template <class LoadKey>
+__device__ __forceinline__ int segment_rank(int m, long long my_key, int my_tie, bool have, LoadKey load) {
+  const int lane = threadIdx.x % WAVE;
+  int rank = 0;
+  for (int t0 = 0; t0 < m; t0 += WAVE) {
+    long long kk = 0;
+    int tt = 0;
+    if (t0 + lane < m) load(t0 + lane, kk, tt);
+    const int nt = min(WAVE, m - t0);
+    for (int s = 0; s < nt; ++s) {
+      const long long ks = __shfl(kk, s, WAVE);
+      const int ts = __shfl(tt, s, WAVE);
+      rank += (have && (ks < my_key || (ks == my_key && ts < my_tie))) ? 1 : 0;
+    }
+  }
+  return rank;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_sort_gather(Consts K, BuildArgs A) {
+  if (rebuild_off(A)) return;
+  const int lane = threadIdx.x % WAVE;
+  const int c = blockIdx.x * WAVES_PER_BLOCK + threadIdx.x / WAVE;
+  if (c >= A.ncell_all) return;
+  const int r = A.cell_rep[c];
+  if (!A.S[r].rebuild) return;
+  const RepDesc& d = A.R[r];
+  if (c < A.ncell_cr) {
+    // the run of sx consecutive cells along x that k_list also takes together
+    const RepState& S = A.S[r];
+    const int lc = c - d.g0;
+    const int gx = S.gd[0], gy = S.gd[1], gz = S.gd[2];
+    const int sx = super_x(d, gx);
+    const int ngx = (gx + sx - 1) / sx;
+    if (lc >= ngx * gy * gz) return;
+    const int cx0 = (lc % ngx) * sx, cy = (lc / ngx) % gy, cz = lc / (ngx * gy);
+    const int cx1 = min(cx0 + sx, gx);
+    const int crow = d.g0 + (cz * gy + cy) * gx;
+    if (lane < cx1 - cx0) A.count[crow + cx0 + lane] = 0;   // zero again for the next rebuild
+    const int s0 = A.start[crow + cx0], m = A.start[crow + cx1] - s0;
+    if (m == 0) return;
+    const int base = d.a0 + (s0 - A.start[d.g0]);
+    for (int u0 = 0; u0 < m; u0 += WAVE) {
+      const int u = u0 + lane;
+      const bool have = u < m;
+      const int e = have ? A.perm[base + u] : 0;
+      // order by (cell, id): within the run, the rank is the atom's final position
+      const long long key = have ? (((long long)(A.cellid[e] - crow)) << 32) | (unsigned)A.id[e] : 0;
+      const int rank = segment_rank(m, key, e, have, [&](int t, long long& kk, int& tt) {
+        tt = A.perm[base + t];
+        kk = (((long long)(A.cellid[tt] - crow)) << 32) | (unsigned)A.id[tt];
+      });
+      if (have) {
+        const int p = base + rank;
+        A.tq[p] = A.q[e];
+        A.tv[3 * p + 0] = A.v[3 * e + 0];
+        A.tv[3 * p + 1] = A.v[3 * e + 1];
+        A.tv[3 * p + 2] = A.v[3 * e + 2];
+        A.tf[3 * p + 0] = A.f[3 * e + 0];
+        A.tf[3 * p + 1] = A.f[3 * e + 1];
+        A.tf[3 * p + 2] = A.f[3 * e + 2];
+        A.tfixed[p] = A.fixed[e];
+        A.tid[p] = A.id[e];
+      }
+    }
+  } else {
+    const int s0 = A.start[c], m = A.start[c + 1] - s0;
+    if (lane == 0) A.count[c] = 0;   // zero again for the next rebuild
+    if (m == 0) return;
+    // every cell of this carbon cell's stencil can hold Cr atoms within reach of a carbon
+    const int lc = c - d.h0;
+    const int hx = lc % d.hd[0], hy = (lc / d.hd[0]) % d.hd[1], hz = lc / (d.hd[0] * d.hd[1]);
+    const int msx = stencil_n(d.hd[0], d.per[0]), msy = stencil_n(d.hd[1], d.per[1]),
+              msz = stencil_n(d.hd[2], d.per[2]);
+    if (lane < msx * msy * msz) {
+      const int tx = lane % msx, ty = (lane / msx) % msy, tz = lane / (msx * msy);
+      const int x = stencil_cell(hx, tx, d.hd[0], d.per[0]);
+      const int y = stencil_cell(hy, ty, d.hd[1], d.per[1]);
+      const int z = stencil_cell(hz, tz, d.hd[2], d.per[2]);
+      if (x >= 0 && y >= 0 && z >= 0) A.hnear[d.h0 + (z * d.hd[1] + y) * d.hd[0] + x] = 1;
+    }
+    const int base = d.c0 + (s0 - A.start[d.h0]);
+    for (int u0 = 0; u0 < m; u0 += WAVE) {
+      const int u = u0 + lane;
+      const bool have = u < m;
+      const int e = have ? A.hlist[base + u] : 0;
+      const int rank = segment_rank(m, (long long)e, 0, have, [&](int t, long long& kk, int& tt) {
+        kk = A.hlist[base + t];
+        tt = 0;
+      });
+      if (have) A.hsorted[base + rank] = e;
+    }
+  }
+}
+
+constexpr int LCH = 4;                 // candidate chunks of 64 held in registers at once
+
+__global__ __launch_bounds__(BLOCK) void k_list(Consts K, BuildArgs A) {
+  if (rebuild_off(A)) return;
+  __shared__ int cand_sh[WAVES_PER_BLOCK][LCH * WAVE];    // candidate slot
+  __shared__ int code_sh[WAVES_PER_BLOCK][LCH * WAVE];    // its periodic image code
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int c = blockIdx.x * WAVES_PER_BLOCK + w;
+  if (c >= A.ncell_cr) return;
+  const int r = A.cell_rep[c];
+  if (!A.S[r].rebuild) return;
+  const RepDesc& d = A.R[r];
+  RepState& S = A.S[r];
+  if (c == d.g0 && lane == 0) {   // once per replica: the build is counted
+    S.nbuilds += 1;
+    S.ind_z_ref = S.ind_z;
+  }
+  const int lc = c - d.g0;
+  const int gx = S.gd[0], gy = S.gd[1], gz = S.gd[2];
+  // one wavefront per run of sx consecutive cells along x (their atoms are contiguous)
+  const int sx = super_x(d, gx);
+  const int ngx = (gx + sx - 1) / sx;
+  if (lc >= ngx * gy * gz) return;
+  const int cx0 = (lc % ngx) * sx, cy = (lc / ngx) % gy, cz = lc / (ngx * gy);
+  const int cx1 = min(cx0 + sx, gx);
+  const int crow = d.g0 + (cz * gy + cy) * gx;
+  const int sbase = A.start[d.g0];
+  const int m = A.start[crow + cx1] - A.start[crow + cx0];
+  if (m == 0) return;
+  const int base = d.a0 + (A.start[crow + cx0] - sbase);
+  // Along a periodic axis with >= 3 cells the image of a candidate is fixed by the stencil
+  // cell it comes from (separation + 0 or -+ length: the same rounding as the minimum
+  // image for every pair inside the list radius); with fewer cells the minimum image is
+  // taken pair by pair.
+  const bool mix = d.per[0] && gx < 3, miy = d.per[1] && gy < 3, miz = d.per[2] && gz < 3;
+
+  // Stencil cells: lane t < ns describes the t-th of up to (sx+2)*3*3 cells.
+  const int nsx = mix ? gx : (cx1 - cx0) + 2;
+  const int nsy = stencil_n(gy, d.per[1]), nsz = stencil_n(gz, d.per[2]);
+  const int ns = nsx * nsy * nsz;
+  int js = 0, jn = 0, code = 0;
+  if (lane < ns) {
+    const int tx = lane % nsx, ty = (lane / nsx) % nsy, tz = lane / (nsx * nsy);
+    int x = mix ? tx : cx0 - 1 + tx;
+    if (!mix) {
+      if (d.per[0]) x = x < 0 ? x + gx : (x >= gx ? x - gx : x);
+      else if (x < 0 || x >= gx) x = -1;
+    }
+    const int y = stencil_cell(cy, ty, gy, d.per[1]);
+    const int z = stencil_cell(cz, tz, gz, d.per[2]);
+    if (x >= 0 && y >= 0 && z >= 0) {
+      const int cid = d.g0 + (z * gy + y) * gx + x;
+      js = d.a0 + (A.start[cid] - sbase);
+      jn = A.start[cid + 1] - A.start[cid];
+      // image code per axis: 0 none, 1 subtract length, 2 add length
+      const int ux = cx0 - 1 + tx;
+      const int ix = (!mix && d.per[0]) ? (ux >= gx ? 2 : (ux < 0 ? 1 : 0)) : 0;
+      const int iy = (!miy && d.per[1]) ? (cy + ty - 1 >= gy ? 2 : (cy + ty - 1 < 0 ? 1 : 0)) : 0;
+      const int iz = (!miz && d.per[2]) ? (cz + tz - 1 >= gz ? 2 : (cz + tz - 1 < 0 ? 1 : 0)) : 0;
+      code = ix | (iy << 2) | (iz << 4);
+    }
+  }
+  int pref = jn;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int y = __shfl_up(pref, o, WAVE);
+    if (lane >= o) pref += y;
+  }
+  const int total = __shfl(pref, WAVE - 1, WAVE);
+  pref -= jn;
+
+  const int T = K.lt, Ts = K.lt_shift;
+  const int row = (int)K.ntot * T;          // words between list rows (cap * ntot < 2^31)
+  for (int a0 = 0; a0 < m; a0 += WAVE) {    // center atoms in groups of 64
+    const int ma = min(WAVE, m - a0);
+    double4 mine = make_double4(0.0, 0.0, 0.0, 0.0);   // lane a holds center atom a0 + a
+    if (lane < ma) mine = A.tq[base + a0 + lane];
+    int count = 0;                                     // lane a: list length of atom a0 + a
+    for (int w0 = 0; w0 < total; w0 += LCH * WAVE) {
+      // stage this window's candidates (slot and image code) in candidate order
+      const int lo = max(0, w0 - pref), hi = min(jn, w0 + LCH * WAVE - pref);
+      for (int e = lo; e < hi; ++e) {
+        cand_sh[w][pref + e - w0] = js + e;
+        code_sh[w][pref + e - w0] = code;
+      }
+      wave_sync();
+      const int wn = min(LCH * WAVE, total - w0);
+      const int nch = (wn + WAVE - 1) / WAVE;
+      int cj[LCH];
+      double px[LCH], py[LCH], pz[LCH], sx[LCH], sy[LCH], sz[LCH];
+#pragma unroll
+      for (int h = 0; h < LCH; ++h) {
+        cj[h] = -1;
+        px[h] = py[h] = pz[h] = 0.0;
+        sx[h] = sy[h] = sz[h] = 0.0;
+        if (h < nch && h * WAVE + lane < wn) {
+          cj[h] = cand_sh[w][h * WAVE + lane];
+          const int cd = code_sh[w][h * WAVE + lane];
+          const double4 pj = A.tq[cj[h]];
+          px[h] = pj.x;
+          py[h] = pj.y;
+          pz[h] = pj.z;
+          sx[h] = (cd & 3) == 1 ? -d.len[0] : ((cd & 3) == 2 ? d.len[0] : 0.0);
+          sy[h] = ((cd >> 2) & 3) == 1 ? -d.len[1] : (((cd >> 2) & 3) == 2 ? d.len[1] : 0.0);
+          sz[h] = ((cd >> 4) & 3) == 1 ? -d.len[2] : (((cd >> 4) & 3) == 2 ? d.len[2] : 0.0);
+        }
+      }
+      wave_sync();
+      for (int a = 0; a < ma; ++a) {
+        const int i = base + a0 + a;
+        const double pix = readlane_d(mine.x, a), piy = readlane_d(mine.y, a), piz = readlane_d(mine.z, a);
+        int na = __builtin_amdgcn_readlane(count, a);
+        const int ibase = i * T;
+#pragma unroll
+        for (int h = 0; h < LCH; ++h) {
+          if (h >= nch) break;
+          bool pred = false;
+          if (cj[h] >= 0 && cj[h] != i) {
+            const double ex = mix ? min_image(px[h] - pix, d.len[0], d.half[0], 1) : (px[h] - pix) + sx[h];
+            const double ey = miy ? min_image(py[h] - piy, d.len[1], d.half[1], 1) : (py[h] - piy) + sy[h];
+            const double ez = miz ? min_image(pz[h] - piz, d.len[2], d.half[2], 1) : (pz[h] - piz) + sz[h];
+            pred = dist_sq_exact(ex, ey, ez) < K.rlist_sq;
+          }
+          const unsigned long long mask = __ballot(pred);
+          const int k = na + __popcll(mask & ((1ull << lane) - 1ull));
+          if (pred && k < K.cap) A.idx[(k >> Ts) * row + ibase + (k & (T - 1))] = cj[h];
+          na += __popcll(mask);
+        }
+        if (lane == a) count = na;
+      }
+    }
+    // counts, overflow, near list and copy-back of these center atoms (one lane per atom)
+    bool near = false;
+    if (lane < ma) {
+      const int p = base + a0 + lane;
+      A.cnt[p] = min(count, K.cap);
+      if (count > K.cap) atomicMax(&S.overflow, count);
+      const double4 pi = mine;
+      if (d.nc > 0) {
+        int hx, hy, hz;
+        c_cell_coords(d, pi.x, pi.y, pi.z, hx, hy, hz);
+        near = A.hnear[d.h0 + (hz * d.hd[1] + hy) * d.hd[0] + hx] != 0;
+      }
+      A.xcnt[p] = 0;
+      A.fme[4 * (int64_t)p + 0] = 0.0;
+      A.fme[4 * (int64_t)p + 1] = 0.0;
+      A.fme[4 * (int64_t)p + 2] = 0.0;
+      A.fme[4 * (int64_t)p + 3] = 0.0;
+      // copy back the sorted state; reference positions for the skin test
+      A.q[p] = pi;
+      A.xref[3 * p + 0] = pi.x;
+      A.xref[3 * p + 1] = pi.y;
+      A.xref[3 * p + 2] = pi.z;
+      A.v[3 * p + 0] = A.tv[3 * p + 0];
+      A.v[3 * p + 1] = A.tv[3 * p + 1];
+      A.v[3 * p + 2] = A.tv[3 * p + 2];
+      A.f[3 * p + 0] = A.tf[3 * p + 0];
+      A.f[3 * p + 1] = A.tf[3 * p + 1];
+      A.f[3 * p + 2] = A.tf[3 * p + 2];
+      A.fixed[p] = A.tfixed[p];
+      A.id[p] = A.tid[p];
+    }
+    const unsigned long long nm = __ballot(near);
+    if (nm) {   // append this wave's near atoms (order within the near list is irrelevant)
+      int first = 0;
+      if (lane == 0) first = atomicAdd(&S.nnear, __popcll(nm));
+      first = __shfl(first, 0, WAVE);
+      if (near) A.near[d.a0 + first + __popcll(nm & ((1ull << lane) - 1ull))] = base + a0 + lane;
+    }
+  }
+}
+
+// Cr-C list {k : |xc_k + ind_z - q_p|^2 < (rc + skin)^2}, atom-major: xidx[p * xcap + n],
+// for the atoms of the near list of each rebuilding replica.  One wavefront per near atom
+// (grid-stride), its lanes sharing the 27 carbon cells around the atom; the passing
+// carbons are compacted in candidate order with a ballot.
+__global__ __launch_bounds__(BLOCK) void k_xlist(Consts K, BuildArgs A) {
+  if (rebuild_off(A)) return;
+  __shared__ int cand_sh[WAVES_PER_BLOCK][MAXC];
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int gw = blockIdx.x * WAVES_PER_BLOCK + w, nw = gridDim.x * WAVES_PER_BLOCK;
+  for (int r = 0; r < K.nrep; ++r) {
+    RepState& S = A.S[r];
+    if (!S.rebuild) continue;
+    const RepDesc& d = A.R[r];
+    const int nnear = S.nnear;
+    const double iz = S.ind_z;
+    const int hbase = A.start[d.h0];
+    const int msx = stencil_n(d.hd[0], d.per[0]), msy = stencil_n(d.hd[1], d.per[1]),
+              msz = stencil_n(d.hd[2], d.per[2]);
+    const int ms = msx * msy * msz;
+    for (int item = gw; item < nnear; item += nw) {
+      const int64_t pa = A.near[d.a0 + item];
+      const double4 pi = A.q[pa];
+      int hx, hy, hz;
+      c_cell_coords(d, pi.x, pi.y, pi.z, hx, hy, hz);
+      int ks = 0, kn = 0;
+      if (lane < ms) {
+        const int tx = lane % msx, ty = (lane / msx) % msy, tz = lane / (msx * msy);
+        const int x = stencil_cell(hx, tx, d.hd[0], d.per[0]);
+        const int y = stencil_cell(hy, ty, d.hd[1], d.per[1]);
+        const int z = stencil_cell(hz, tz, d.hd[2], d.per[2]);
+        if (x >= 0 && y >= 0 && z >= 0) {
+          const int hid = d.h0 + (z * d.hd[1] + y) * d.hd[0] + x;
+          ks = d.c0 + (A.start[hid] - hbase);
+          kn = A.start[hid + 1] - A.start[hid];
+        }
+      }
+      int pref = kn;
+#pragma unroll
+      for (int o = 1; o < WAVE; o <<= 1) {
+        const int y = __shfl_up(pref, o, WAVE);
+        if (lane >= o) pref += y;
+      }
+      const int total = __shfl(pref, WAVE - 1, WAVE);
+      pref -= kn;
+      int n = 0;
+      for (int w0 = 0; w0 < total; w0 += MAXC) {
+        const int lo = max(0, w0 - pref), hi = min(kn, w0 + MAXC - pref);
+        for (int e = lo; e < hi; ++e) cand_sh[w][pref + e - w0] = A.hsorted[ks + e];
+        wave_sync();
+        const int wn = min(MAXC, total - w0);
+        for (int k0 = 0; k0 < wn; k0 += WAVE) {
+          bool pred = false;
+          int k = 0;
+          if (k0 + lane < wn) {
+            k = cand_sh[w][k0 + lane];
+            const double ex = min_image(A.xc[3 * k + 0] - pi.x, d.len[0], d.half[0], d.per[0]);
+            const double ey = min_image(A.xc[3 * k + 1] - pi.y, d.len[1], d.half[1], d.per[1]);
+            const double ez = min_image((A.xc[3 * k + 2] + iz) - pi.z, d.len[2], d.half[2], d.per[2]);
+            pred = dist_sq_exact(ex, ey, ez) < K.rxlist_sq;
+          }
+          const unsigned long long m2 = __ballot(pred);
+          const int below = __popcll(m2 & ((1ull << lane) - 1ull));
+          if (pred && n + below < K.xcap) A.xidx[pa * K.xcap + n + below] = k;
+          n += __popcll(m2);
+        }
+        wave_sync();
+      }
+      if (lane == 0) {
+        A.xcnt[pa] = min(n, K.xcap);
+        if (n > K.xcap) atomicMax(&S.xoverflow, n);
+      }
+    }
+  }
+}
+
+}  // namespace md

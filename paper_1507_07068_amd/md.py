@@ -47,7 +47,7 @@ class MorseParams(C.Structure):
 class Params(C.Structure):
     _fields_ = [("eam", EamParams), ("morse", MorseParams), ("mass", C.c_double),
                 ("dt", C.c_double), ("v_ind", C.c_double), ("skin", C.c_double),
-                ("cap", C.c_int32), ("xcap", C.c_int32)]
+                ("cap", C.c_int32), ("xcap", C.c_int32), ("tpa", C.c_int32), ("pad", C.c_int32)]
 
 
 class ReplicaDesc(C.Structure):
@@ -67,7 +67,8 @@ class Lists(C.Structure):
 
 class Status(C.Structure):
     _fields_ = [("overflow", C.c_int32), ("xoverflow", C.c_int32), ("nonfinite", C.c_int32),
-                ("nbuilds", C.c_int32), ("sync_timeout", C.c_int32), ("pad", C.c_int32 * 3)]
+                ("nbuilds", C.c_int32), ("sync_timeout", C.c_int32), ("nnear", C.c_int32),
+                ("pad", C.c_int32 * 2)]
 
 
 class MDError(RuntimeError):
@@ -126,7 +127,7 @@ def _ok(code: int, what: str):
         raise MDError(f"{what}: {msg} ({code})")
 
 
-def make_params(s, cap: int = 64, xcap: int = 64) -> Params:
+def make_params(s, cap: int = 64, xcap: int = 64, tpa: int = 1) -> Params:
     p = Params()
     p.eam = EamParams(**{k: float(s.eam[k]) for k in ("A", "c", "d", "c0", "c1", "c2")})
     p.morse = MorseParams(**{k: float(s.morse[k]) for k in ("D", "alpha", "r0", "rc")})
@@ -136,6 +137,7 @@ def make_params(s, cap: int = 64, xcap: int = 64) -> Params:
     p.skin = float(s.skin)
     p.cap = int(cap)
     p.xcap = int(xcap)
+    p.tpa = int(tpa)
     return p
 
 
@@ -158,7 +160,7 @@ class Simulation:
     """
 
     def __init__(self, systems, precision: str = "fp64", cap: int = 64, xcap: int = 160,
-                 device: str = "cuda:0"):
+                 tpa: int = 1, device: str = "cuda:0"):
         import torch
         if not torch.cuda.is_available():
             raise MDError("no GPU visible: the MD path runs only on the GPU")
@@ -170,7 +172,8 @@ class Simulation:
         self.mixed = precision == "mixed"
         self.device = torch.device(device)
         s0 = self.systems[0]
-        self.params = make_params(s0, cap, xcap)
+        self.params = make_params(s0, cap, xcap, tpa)
+        self.tpa = tpa
         descs = (ReplicaDesc * self.nrep)(*[make_replica_desc(s) for s in self.systems])
         h = C.c_void_p()
         _ok(self.lib.md_system_create(C.cast(descs, C.c_void_p), self.nrep, C.byref(self.params),
@@ -191,9 +194,9 @@ class Simulation:
             self.fixed = torch.ones(n, dtype=torch.uint8, device=dev)
             self.id = torch.full((n,), -1, dtype=torch.int32, device=dev)
             self.xc = torch.zeros((max(nc, 1), 3), dtype=torch.float64, device=dev)
-            self.idx = torch.zeros((cap, n), dtype=torch.int32, device=dev)
+            self.idx = torch.zeros(cap * n, dtype=torch.int32, device=dev)
             self.cnt = torch.zeros(n, dtype=torch.int32, device=dev)
-            self.xidx = torch.zeros((xcap, n), dtype=torch.int32, device=dev)
+            self.xidx = torch.zeros((n, xcap), dtype=torch.int32, device=dev)
             self.xcnt = torch.zeros(n, dtype=torch.int32, device=dev)
             self.rho = torch.zeros(n, dtype=torch.float64, device=dev)
             self.obs_dev = torch.zeros((self.nrep, MD_NOBS), dtype=torch.float64, device=dev)
@@ -299,7 +302,7 @@ class Simulation:
         st = Status()
         _ok(self.lib.md_check(self.handle, C.byref(st), self.stream), "md_check")
         return dict(overflow=st.overflow, xoverflow=st.xoverflow, nonfinite=st.nonfinite,
-                    nbuilds=st.nbuilds, sync_timeout=st.sync_timeout)
+                    nbuilds=st.nbuilds, sync_timeout=st.sync_timeout, nnear=st.nnear)
 
     def md_clear_flags(self):
         _ok(self.lib.md_clear_flags(self.handle, self.stream), "md_clear_flags")
@@ -389,11 +392,28 @@ class Simulation:
         """Neighbour sets of replica r in id space: [sorted ids of neighbours of id 0, ...]."""
         ids = self.id.cpu().numpy()
         cnt = (self.xcnt if cross else self.cnt).cpu().numpy()
-        idx = (self.xidx if cross else self.idx).cpu().numpy()
         s = self.systems[r]
         a0 = self.offsets[r]
         sets = [None] * s.n
+        if cross:
+            xidx = self.xidx.cpu().numpy()
+            c0 = sum(t.n_c for t in self.systems[:r])
+            for p in range(a0, a0 + s.n):
+                sets[ids[p]] = sorted((xidx[p, :cnt[p]] - c0).tolist())
+            return sets
+        lists = self.list_rows()
         for p in range(a0, a0 + s.n):
-            row = idx[:cnt[p], p]
-            sets[ids[p]] = sorted(row.tolist()) if cross else sorted(ids[row].tolist())
+            sets[ids[p]] = sorted(ids[lists[p]].tolist())
         return sets
+
+    def list_rows(self) -> list:
+        """Cr-Cr list of every atom slot (slots of its neighbours, in list order)."""
+        T, n = self.tpa, self.ntot
+        idx = self.idx.cpu().numpy()
+        cnt = self.cnt.cpu().numpy()
+        k = np.arange(self.cap)
+        rows = []
+        for p in range(n):
+            kk = k[:cnt[p]]
+            rows.append(idx[(kk // T) * n * T + p * T + kk % T])
+        return rows

@@ -17,9 +17,9 @@ FP64_TOL = 1e-10
 MIXED_TOL = 1e-5
 
 
-def sim_of(s, precision="fp64", cap=64, xcap=128):
-    print(f"[case] {s.name} n={s.n} n_c={s.n_c} precision={precision}", flush=True)
-    return md.Simulation(s, precision=precision, cap=cap, xcap=xcap)
+def sim_of(s, precision="fp64", cap=64, xcap=128, tpa=1):
+    print(f"[case] {s.name} n={s.n} n_c={s.n_c} precision={precision} tpa={tpa}", flush=True)
+    return md.Simulation(s, precision=precision, cap=cap, xcap=xcap, tpa=tpa)
 
 
 def min_image_diff(a, b, s):
@@ -116,9 +116,17 @@ def test_cross_lists_film():
     s = I.small_film(nx=8, ny=8, nz=5, radius=8.0, gap=-1.5, seed=3, noise=0.05)
     sim = sim_of(s)
     sim.md_build_neighbors(force=True)
-    assert sim.md_check()["xoverflow"] == 0
+    st = sim.md_check()
+    assert st["xoverflow"] == 0
     check_lists(sim, s)
     assert check_lists(sim, s, cross=True) > 0
+    # the near-atom candidates cover every atom with carbons in range, and stay within two
+    # carbon-cell diagonals of a carbon
+    xw = O.wrap(s)
+    cnt, _ = O.cross_neighbors(s, s.r_list_cross, x=xw, cap=256)
+    edge = max(L / max(1, np.floor(L / (s.r_list_cross * (1 + 1e-9)))) for L in s.box_len)
+    far, _ = O.cross_neighbors(s, s.r_list_cross + 2 * np.sqrt(3) * edge, x=xw, cap=4096)
+    assert (cnt > 0).sum() <= st["nnear"] <= (far > 0).sum()
 
 
 def test_cross_list_overflow_is_flagged():
@@ -219,8 +227,8 @@ def test_mixed_precision_force_error():
 # ------------------------------------------------------------------------------------------
 # Trajectories (Tasks 1-5 over many steps, with list rebuilds)
 # ------------------------------------------------------------------------------------------
-def _traj(s, nsteps, precision="fp64", fused=True):
-    sim = sim_of(s, precision=precision)
+def _traj(s, nsteps, precision="fp64", fused=True, tpa=1):
+    sim = sim_of(s, precision=precision, tpa=tpa)
     sim.initial_forces()
     st = sim.md_check()
     assert st["overflow"] == 0 and st["xoverflow"] == 0, st
@@ -313,3 +321,67 @@ def test_empty_system():
     sim, obs = _traj(s, 3)
     assert np.all(obs[:, :13] == 0)
     assert sim.md_check()["nonfinite"] == 0
+
+
+@pytest.mark.parametrize("tpa", [2, 4, 8])
+def test_lanes_per_atom(tpa):
+    """T lanes per atom (list interleaved by T): same lists, forces within the FP64 bar,
+    same trajectory as the oracle."""
+    s = I.small_film(nx=8, ny=8, nz=6, radius=8.0, gap=-0.8, seed=21, noise=0.05)
+    sim = sim_of(s, tpa=tpa)
+    obs, st = _initial(sim)
+    check_lists(sim, s)
+    ref = O.evaluate(s, O.wrap(s))
+    assert_forces(st["f"], ref["f"], FP64_TOL)
+    for mixed in (False, True):
+        m = sim_of(s, precision="mixed" if mixed else "fp64", tpa=tpa)
+        _, stm = _initial(m)
+        rel, _ = force_errors(stm["f"], ref["f"])
+        assert rel <= (MIXED_TOL if mixed else FP64_TOL)
+    sim2, obs2 = _traj(s, 40, tpa=tpa)
+    r2 = O.md_run(s, 40)
+    assert np.abs(min_image_diff(sim2.state()[0]["x"], r2["x"], s)).max() < 1e-9
+    assert np.array_equal(obs2[:, 14], r2["obs"][:, 14])
+
+
+def test_lists_atoms_far_outside_the_given_open_extent():
+    """Open-axis cell grids follow the atoms: a film whose upper part has moved far above
+    the extent given at set-up (and atoms below it) still gets exact lists."""
+    s = I.small_film(nx=8, ny=8, nz=6, radius=6.0, gap=0.5, seed=31, noise=0.05)
+    x = s.x.copy()
+    top = x[:, 2] > 8.0
+    x[top, 2] += 150.0 + 0.01 * np.arange(top.sum())
+    x[:5, 2] -= 40.0
+    s.x = x
+    sim = sim_of(s)
+    sim.md_build_neighbors(force=True)
+    st = sim.md_check()
+    assert st["overflow"] == 0 and st["xoverflow"] == 0
+    check_lists(sim, s)
+    check_lists(sim, s, cross=True)
+
+
+def test_lists_pairs_at_the_list_radius_across_periodic_faces():
+    """Pairs within a few ulps of the list radius whose separation crosses a periodic face
+    (the image is taken from the cell stencil on the GPU, from the minimum image in the
+    oracle: both must round identically)."""
+    rng = np.random.default_rng(17)
+    r = I.EAM["c"] + I.SKIN
+    L = 30.0
+    pts = []
+    for k in range(300):
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        base = rng.uniform(0.0, L, size=3)
+        ax = k % 3
+        base[ax] = rng.uniform(0.0, 1.0)          # near the lower face of axis ax
+        if u[ax] > 0:
+            u[ax] = -u[ax]                          # partner reaches across that face
+        dist = r * (1 + rng.integers(-6, 7) * 2.0 ** -52)
+        pts += [base, base + dist * u]
+    s = I.random_gas(len(pts), L, 0, periodic=(1, 1, 1))
+    s.x = np.array(pts)
+    sim = sim_of(s, cap=96)
+    sim.md_build_neighbors(force=True)
+    assert sim.md_check()["overflow"] == 0
+    check_lists(sim, s)
