@@ -46,6 +46,7 @@ struct md_system {
   Layout L;
   char* ws;
   int scan_blocks;
+  bool list_mix;   // some periodic axis has fewer than 3 list cells
   bool have_embed, have_force;
 };
 
@@ -206,6 +207,7 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
   s->p = *p;
   s->nrep = nrep;
   s->ws = nullptr;
+  s->list_mix = false;
   s->have_embed = s->have_force = false;
   const double rlist = p->eam.c + p->skin;
   const double rxlist = p->morse.rc + p->skin;
@@ -231,6 +233,7 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
       if (d.per[a] && !(rd.len[a] > 2.0 * rlist)) { delete s; return MD_ERR_ARG; }
       if (d.per[a] && rd.n_c > 0 && !(rd.len[a] > 2.0 * rxlist)) { delete s; return MD_ERR_ARG; }
       d.ginv[a] = nb / rd.len[a];
+      if (d.per[a] && nb < 3) s->list_mix = true;
       d.hinv[a] = d.hd[a] / rd.len[a];
     }
     d.a0 = (int)a0;
@@ -410,7 +413,10 @@ MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l
   k_scan_apply<<<s->scan_blocks, BLOCK, 0, st>>>(A);
   k_scatter<<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A);
   k_sort_gather<<<(s->ncell_all + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, BLOCK, 0, st>>>(s->K, A);
-  k_list<<<(s->ncell_cr + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, BLOCK, 0, st>>>(s->K, A);
+  if (s->list_mix)
+    k_list<true><<<(s->ncell_cr + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, BLOCK, 0, st>>>(s->K, A);
+  else
+    k_list<false><<<(s->ncell_cr + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, BLOCK, 0, st>>>(s->K, A);
   k_xlist<<<A.near_blocks, BLOCK, 0, st>>>(s->K, A);
   return check_launch();
 }

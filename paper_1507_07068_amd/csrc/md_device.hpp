@@ -138,15 +138,13 @@ __device__ __forceinline__ double block_max(double v) {
   return m;
 }
 
-// Minimum-image component of a separation along one axis.
+// Minimum-image component of a separation along one axis: d - len if d > len/2, d + len if
+// d < -len/2 (periodic axes only).  Written as selects so that it compiles without branches.
 __device__ __forceinline__ double min_image(double d, double len, double half, int per) {
-  if (per) {
-    if (d > half)
-      d -= len;
-    else if (d < -half)
-      d += len;
-  }
-  return d;
+  // d + (-len) rounds exactly like d - len; the shift is chosen with selects on constants
+  double s = (per && d > half) ? -len : 0.0;
+  s = (per && d < -half) ? len : s;
+  return d + s;
 }
 
 // Squared length (dx dx + dy dy) + dz dz with every product and sum rounded on its own:

@@ -26,7 +26,10 @@ __device__ __forceinline__ V group_sum(V v) {
 // Visit the entries k = sub, sub + T, ... (< n) of atom i's list in order, calling
 // body(q[j]) for each neighbour j.  Entries are fetched U at a time so that U independent
 // index loads, then U independent position gathers, are in flight together.
-constexpr int UNROLL = 1;
+#ifndef MD_UNROLL
+#define MD_UNROLL 1
+#endif
+constexpr int UNROLL = MD_UNROLL;
 
 template <int T, int U, class Q, class Body>
 __device__ __forceinline__ void for_neighbors(const int* __restrict__ idx, const Q* q, int i, int n,

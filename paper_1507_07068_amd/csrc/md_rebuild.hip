@@ -368,6 +368,9 @@ __global__ __launch_bounds__(BLOCK) void k_sort_gather(Consts K, BuildArgs A) {
 
 constexpr int LCH = 4;                 // candidate chunks of 64 held in registers at once
 
+// MIX: some replica has a periodic axis with fewer than 3 cells (the image is then taken
+// pair by pair on that axis).
+template <bool MIX>
 __global__ __launch_bounds__(BLOCK) void k_list(Consts K, BuildArgs A) {
   if (rebuild_off(A)) return;
   __shared__ int cand_sh[WAVES_PER_BLOCK][LCH * WAVE];    // candidate slot
@@ -400,7 +403,10 @@ __global__ __launch_bounds__(BLOCK) void k_list(Consts K, BuildArgs A) {
   // cell it comes from (separation + 0 or -+ length: the same rounding as the minimum
   // image for every pair inside the list radius); with fewer cells the minimum image is
   // taken pair by pair.
-  const bool mix = d.per[0] && gx < 3, miy = d.per[1] && gy < 3, miz = d.per[2] && gz < 3;
+  const bool mix = MIX && d.per[0] && gx < 3, miy = MIX && d.per[1] && gy < 3,
+             miz = MIX && d.per[2] && gz < 3;
+  const double Lx = d.len[0], Ly = d.len[1], Lz = d.len[2];
+  const double Hx = d.half[0], Hy = d.half[1], Hz = d.half[2];
 
   // Stencil cells: lane t < ns describes the t-th of up to (sx+2)*3*3 cells.
   const int nsx = mix ? gx : (cx1 - cx0) + 2;
@@ -438,6 +444,8 @@ __global__ __launch_bounds__(BLOCK) void k_list(Consts K, BuildArgs A) {
   pref -= jn;
 
   const int T = K.lt, Ts = K.lt_shift;
+  const double rl2 = K.rlist_sq;
+  const int cap = K.cap;
   const int row = (int)K.ntot * T;          // words between list rows (cap * ntot < 2^31)
   for (int a0 = 0; a0 < m; a0 += WAVE) {    // center atoms in groups of 64
     const int ma = min(WAVE, m - a0);
@@ -468,9 +476,9 @@ __global__ __launch_bounds__(BLOCK) void k_list(Consts K, BuildArgs A) {
           px[h] = pj.x;
           py[h] = pj.y;
           pz[h] = pj.z;
-          sx[h] = (cd & 3) == 1 ? -d.len[0] : ((cd & 3) == 2 ? d.len[0] : 0.0);
-          sy[h] = ((cd >> 2) & 3) == 1 ? -d.len[1] : (((cd >> 2) & 3) == 2 ? d.len[1] : 0.0);
-          sz[h] = ((cd >> 4) & 3) == 1 ? -d.len[2] : (((cd >> 4) & 3) == 2 ? d.len[2] : 0.0);
+          sx[h] = (cd & 3) == 1 ? -Lx : ((cd & 3) == 2 ? Lx : 0.0);
+          sy[h] = ((cd >> 2) & 3) == 1 ? -Ly : (((cd >> 2) & 3) == 2 ? Ly : 0.0);
+          sz[h] = ((cd >> 4) & 3) == 1 ? -Lz : (((cd >> 4) & 3) == 2 ? Lz : 0.0);
         }
       }
       wave_sync();
@@ -482,16 +490,21 @@ __global__ __launch_bounds__(BLOCK) void k_list(Consts K, BuildArgs A) {
 #pragma unroll
         for (int h = 0; h < LCH; ++h) {
           if (h >= nch) break;
-          bool pred = false;
-          if (cj[h] >= 0 && cj[h] != i) {
-            const double ex = mix ? min_image(px[h] - pix, d.len[0], d.half[0], 1) : (px[h] - pix) + sx[h];
-            const double ey = miy ? min_image(py[h] - piy, d.len[1], d.half[1], 1) : (py[h] - piy) + sy[h];
-            const double ez = miz ? min_image(pz[h] - piz, d.len[2], d.half[2], 1) : (pz[h] - piz) + sz[h];
-            pred = dist_sq_exact(ex, ey, ez) < K.rlist_sq;
+          const double dx = px[h] - pix, dy = py[h] - piy, dz = pz[h] - piz;
+          double ex, ey, ez;
+          if (MIX) {
+            ex = mix ? min_image(dx, Lx, Hx, 1) : dx + sx[h];
+            ey = miy ? min_image(dy, Ly, Hy, 1) : dy + sy[h];
+            ez = miz ? min_image(dz, Lz, Hz, 1) : dz + sz[h];
+          } else {
+            ex = dx + sx[h];
+            ey = dy + sy[h];
+            ez = dz + sz[h];
           }
+          const bool pred = cj[h] >= 0 && cj[h] != i && dist_sq_exact(ex, ey, ez) < rl2;
           const unsigned long long mask = __ballot(pred);
           const int k = na + __popcll(mask & ((1ull << lane) - 1ull));
-          if (pred && k < K.cap) A.idx[(k >> Ts) * row + ibase + (k & (T - 1))] = cj[h];
+          if (pred && k < cap) A.idx[(k >> Ts) * row + ibase + (k & (T - 1))] = cj[h];
           na += __popcll(mask);
         }
         if (lane == a) count = na;

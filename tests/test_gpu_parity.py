@@ -385,3 +385,79 @@ def test_lists_pairs_at_the_list_radius_across_periodic_faces():
     sim.md_build_neighbors(force=True)
     assert sim.md_check()["overflow"] == 0
     check_lists(sim, s)
+
+
+# ------------------------------------------------------------------------------------------
+# Batched replicas and graph replay
+# ------------------------------------------------------------------------------------------
+def _small_replicas():
+    """Ensemble members of the batched workload, cut to sizes a test can afford."""
+    out = []
+    for r in (0, 5, 9):
+        d = I.replica_draws(r)
+        rng = d.pop("rng")
+        s = I.film(10 + (d["nx"] - 10) // 4, 10 + (d["ny"] - 10) // 4, 8 + (d["nz"] - 8) // 4,
+                   d["radius"], d["gap"], 3000 + r, steps=30, name=f"replica{r}", rng=rng)
+        out.append(s)
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_replicas_equal_single_bitwise(precision):
+    reps = _small_replicas()
+    print(f"[case] batched {len(reps)} replicas sizes {[s.n for s in reps]} {precision}", flush=True)
+    b = md.Simulation(reps, precision=precision, cap=64, xcap=160)
+    b.initial_forces()
+    b.run(30)
+    stb = b.state()
+    assert b.md_check()["overflow"] == 0
+    for r, s in enumerate(reps):
+        a = sim_of(s, precision=precision)
+        a.initial_forces()
+        a.run(30)
+        sta = a.state()[0]
+        for k in ("x", "v", "f", "dF"):
+            assert np.array_equal(sta[k], stb[r][k]), (r, k)
+
+
+def test_batched_observables_per_replica():
+    reps = _small_replicas()
+    b = md.Simulation(reps, cap=64, xcap=160)
+    b.initial_forces()
+    ob = b.md_energy()
+    for r, s in enumerate(reps):
+        ref = O.evaluate(s, O.wrap(s))
+        mob = s.fixed == 0
+        ref_obs = ref["obs"].copy()
+        ref_obs[3] = 0.5 * s.mass * np.sum(s.v[mob] ** 2) / I.EV_PER_U_TO_A2_FS2
+        _assert_obs(ob[r], ref_obs, 1e-12)
+
+
+def test_graph_replay_equals_eager():
+    import torch
+    s = I.small_film(nx=10, ny=10, nz=6, radius=8.0, gap=0.2, seed=41, noise=0.03)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        a = sim_of(s)
+        a.initial_forces()
+        obs_a = torch.zeros((3, 1, md.MD_NOBS), dtype=torch.float64, device="cuda")
+        for k in range(3):
+            a.md_run(10, energy_every=10, obs=obs_a[k:k + 1])
+        b = sim_of(s)
+        b.initial_forces()
+        obs_b = torch.zeros((1, 1, md.MD_NOBS), dtype=torch.float64, device="cuda")
+        g = b.md_graph_create(10, energy_every=10, obs=obs_b)
+        rows = []
+        for k in range(3):               # eager work and syncs between the replays
+            b.md_graph_launch(g)
+            torch.cuda.synchronize()
+            rows.append(obs_b.cpu().numpy().copy())
+            _ = b.md_check()
+        torch.cuda.synchronize()
+    sa, sb = a.state()[0], b.state()[0]
+    for k in ("x", "v", "f"):
+        assert np.array_equal(sa[k], sb[k]), k
+    oa = obs_a.cpu().numpy()
+    for k in range(3):
+        assert np.array_equal(oa[k], rows[k][0]), k
+    assert a.md_check()["nbuilds"] == b.md_check()["nbuilds"]
