@@ -96,10 +96,8 @@ __global__ __launch_bounds__(BLOCK) void k_density(Consts K, const RepDesc* __re
         const float ey = (float)min_image(pj.y - pi.y, d.len[1], d.half[1], d.per[1]);
         const float ez = (float)min_image(pj.z - pi.z, d.len[2], d.half[2], d.per[2]);
         const float r2 = ex * ex + ey * ey + ez * ez;
-        if (r2 < dd2) {
-          const float u = __fsqrt_rn(r2) - dd;
-          acc += u * u;
-        }
+        const float u = __fsqrt_rn(r2) - dd;
+        acc += (r2 < dd2) ? u * u : 0.0f;
       });
       rho = (double)acc;
     } else {
@@ -108,10 +106,8 @@ __global__ __launch_bounds__(BLOCK) void k_density(Consts K, const RepDesc* __re
         const double ey = min_image(pj.y - pi.y, d.len[1], d.half[1], d.per[1]);
         const double ez = min_image(pj.z - pi.z, d.len[2], d.half[2], d.per[2]);
         const double r2 = ex * ex + ey * ey + ez * ez;
-        if (r2 < K.d_sq) {
-          const double u = sqrt(r2) - K.d;
-          rho += u * u;
-        }
+        const double u = sqrt(r2) - K.d;
+        rho += (r2 < K.d_sq) ? u * u : 0.0;
       });
     }
   }
@@ -164,26 +160,27 @@ __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __rest
         const float ey = (float)min_image(pj.y - pi.y, d.len[1], d.half[1], d.per[1]);
         const float ez = (float)min_image(pj.z - pi.z, d.len[2], d.half[2], d.per[2]);
         const float r2 = ex * ex + ey * ey + ez * ez;
-        if (r2 < csq) {
-          const float rinv = __frsqrt_rn(r2);
-          const float r = r2 * rinv;
-          const float u = r - cc, t = r - rv;
-          const float p = pmin + c2 * t * t;                    // c0 + c1 r + c2 r^2, vertex form
-          float g = u * (2.0f * p + u * (2.0f * c2 * t));        // phi'(r)
-          if (r2 < dsq) g += (Fi + (float)pj.w) * (2.0f * (r - dd));
-          const float s = g * rinv;                              // F_i += g (q_j - q_i) / r
-          ax += s * ex;
-          ay += s * ey;
-          az += s * ez;
-          if (ENERGY) {
-            ep += 0.5f * u * u * p;
-            w0 -= 0.5f * s * ex * ex;
-            w1 -= 0.5f * s * ey * ey;
-            w2 -= 0.5f * s * ez * ez;
-            w3 -= 0.5f * s * ex * ey;
-            w4 -= 0.5f * s * ex * ez;
-            w5 -= 0.5f * s * ey * ez;
-          }
+        // all lanes evaluate; the cutoffs select (no branch: the whole 32-byte gather is
+        // consumed up front)
+        const bool inc = r2 < csq;
+        const float rinv = __frsqrt_rn(inc ? r2 : 1.0f);
+        const float r = r2 * rinv;
+        const float u = r - cc, t = r - rv;
+        const float p = pmin + c2 * t * t;                      // c0 + c1 r + c2 r^2, vertex form
+        float g = u * (2.0f * p + u * (2.0f * c2 * t));          // phi'(r)
+        g += (r2 < dsq) ? (Fi + (float)pj.w) * (2.0f * (r - dd)) : 0.0f;
+        const float s = inc ? g * rinv : 0.0f;                   // F_i += g (q_j - q_i) / r
+        ax += s * ex;
+        ay += s * ey;
+        az += s * ez;
+        if (ENERGY) {
+          ep += inc ? 0.5f * u * u * p : 0.0f;
+          w0 -= 0.5f * s * ex * ex;
+          w1 -= 0.5f * s * ey * ey;
+          w2 -= 0.5f * s * ez * ez;
+          w3 -= 0.5f * s * ex * ey;
+          w4 -= 0.5f * s * ex * ez;
+          w5 -= 0.5f * s * ey * ez;
         }
       });
       fx = ax;
@@ -205,26 +202,27 @@ __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __rest
         const double ey = min_image(pj.y - pi.y, d.len[1], d.half[1], d.per[1]);
         const double ez = min_image(pj.z - pi.z, d.len[2], d.half[2], d.per[2]);
         const double r2 = ex * ex + ey * ey + ez * ez;
-        if (r2 < K.c_sq) {
-          const double rinv = rsqrt(r2);
-          const double r = r2 * rinv;
-          const double u = r - K.c;
-          const double p = K.c0 + r * (K.c1 + r * K.c2);
-          double g = u * (2.0 * p + u * (K.c1 + 2.0 * K.c2 * r));   // phi'(r)
-          if (r2 < K.d_sq) g += (Fi + pj.w) * (2.0 * (r - K.d));
-          const double s = g * rinv;
-          fx += s * ex;
-          fy += s * ey;
-          fz += s * ez;
-          if (ENERGY) {
-            acc[P_PAIR] += 0.5 * u * u * p;
-            acc[P_WXX] -= 0.5 * s * ex * ex;
-            acc[P_WYY] -= 0.5 * s * ey * ey;
-            acc[P_WZZ] -= 0.5 * s * ez * ez;
-            acc[P_WXY] -= 0.5 * s * ex * ey;
-            acc[P_WXZ] -= 0.5 * s * ex * ez;
-            acc[P_WYZ] -= 0.5 * s * ey * ez;
-          }
+        // all lanes evaluate; the cutoffs select (no branch: the whole 32-byte gather is
+        // consumed up front)
+        const bool inc = r2 < K.c_sq;
+        const double rinv = rsqrt(inc ? r2 : 1.0);
+        const double r = r2 * rinv;
+        const double u = r - K.c;
+        const double p = K.c0 + r * (K.c1 + r * K.c2);
+        double g = u * (2.0 * p + u * (K.c1 + 2.0 * K.c2 * r));     // phi'(r)
+        g += (r2 < K.d_sq) ? (Fi + pj.w) * (2.0 * (r - K.d)) : 0.0;
+        const double s = inc ? g * rinv : 0.0;
+        fx += s * ex;
+        fy += s * ey;
+        fz += s * ez;
+        if (ENERGY) {
+          acc[P_PAIR] += inc ? 0.5 * u * u * p : 0.0;
+          acc[P_WXX] -= 0.5 * s * ex * ex;
+          acc[P_WYY] -= 0.5 * s * ey * ey;
+          acc[P_WZZ] -= 0.5 * s * ez * ez;
+          acc[P_WXY] -= 0.5 * s * ex * ey;
+          acc[P_WXZ] -= 0.5 * s * ex * ez;
+          acc[P_WYZ] -= 0.5 * s * ey * ez;
         }
       });
     }
