@@ -67,7 +67,7 @@ def main(argv=None):
     ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
     ap.add_argument("--energy-every", type=int, default=10)
-    ap.add_argument("--tpa", type=int, default=1, choices=[1, 2, 4, 8],
+    ap.add_argument("--tpa", type=int, default=2, choices=[1, 2, 4, 8],
                     help="lanes per atom in the density / force passes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args(argv)

@@ -416,7 +416,7 @@ MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l
   if (s->list_mix)
     k_list<true><<<(s->ncell_cr + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, BLOCK, 0, st>>>(s->K, A);
   else
-    k_list<false><<<(s->ncell_cr + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, BLOCK, 0, st>>>(s->K, A);
+    k_list_rows<<<s->ntiles, BLOCK, 0, st>>>(s->K, A);
   k_xlist<<<A.near_blocks, BLOCK, 0, st>>>(s->K, A);
   return check_launch();
 }

@@ -551,6 +551,127 @@ __global__ __launch_bounds__(BLOCK) void k_list(Consts K, BuildArgs A) {
   }
 }
 
+// One lane per sorted Cr atom (lists of replicas whose periodic axes all have >= 3 list
+// cells).  The candidates in each of the nine cell rows (y, z) around the atom's cell are
+// the atoms of x-cells cx-1 .. cx+1 of that row: one contiguous range of the sorted order,
+// or two when the row wraps around a periodic x axis.  Rows are visited z-major, then y,
+// the ranges along x, and the atoms of a cell in id order: the same candidate order as
+// the wavefront-per-run kernel above, so both give identical lists.
+__global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
+  if (rebuild_off(A)) return;
+  const int b = blockIdx.x;
+  const int r = A.tile_rep[b];
+  RepState& S = A.S[r];
+  if (!S.rebuild) return;
+  const RepDesc& d = A.R[r];
+  if (b == d.t0 && threadIdx.x == 0) {   // once per replica: the build is counted
+    S.nbuilds += 1;
+    S.ind_z_ref = S.ind_z;
+  }
+  const int lane = threadIdx.x % WAVE;
+  const int p = b * TILE + threadIdx.x;
+  const bool live = p < d.a0 + d.n;
+  double4 pi = make_double4(0.0, 0.0, 0.0, 0.0);
+  int count = 0;
+  bool near = false;
+  if (live) {
+    pi = A.tq[p];
+    const int gx = S.gd[0], gy = S.gd[1], gz = S.gd[2];
+    const int cx = cell_coord(pi.x, S.glo[0], S.ginv[0], gx);
+    const int cy = cell_coord(pi.y, S.glo[1], S.ginv[1], gy);
+    const int cz = cell_coord(pi.z, S.glo[2], S.ginv[2], gz);
+    const int sbase = d.a0 - A.start[d.g0];   // sorted slot = sbase + start[cell]
+    const double rl2 = K.rlist_sq;
+    const int cap = K.cap, T = K.lt, Ts = K.lt_shift;
+    const int row = (int)K.ntot * T;
+    const int ibase = p * T;
+    // x segments (first cell, last cell, shift), identical for the nine rows
+    int xa0 = cx - 1, xb0 = cx + 1, xa1 = 0, xb1 = -1;
+    double sh0 = 0.0, sh1 = 0.0;
+    if (d.per[0]) {
+      if (cx == 0) {
+        xa0 = gx - 1; xb0 = gx - 1; sh0 = -d.len[0];
+        xa1 = 0; xb1 = 1;
+      } else if (cx == gx - 1) {
+        xa0 = gx - 2; xb0 = gx - 1;
+        xa1 = 0; xb1 = 0; sh1 = d.len[0];
+      }
+    } else {
+      xa0 = max(xa0, 0);
+      xb0 = min(xb0, gx - 1);
+    }
+    for (int tz = 0; tz < 3; ++tz) {
+      int z = cz + tz - 1;
+      double shz = 0.0;
+      if (d.per[2]) {
+        if (z < 0) { z += gz; shz = -d.len[2]; }
+        else if (z >= gz) { z -= gz; shz = d.len[2]; }
+      } else if (z < 0 || z >= gz) {
+        continue;
+      }
+      for (int ty = 0; ty < 3; ++ty) {
+        int y = cy + ty - 1;
+        double shy = 0.0;
+        if (d.per[1]) {
+          if (y < 0) { y += gy; shy = -d.len[1]; }
+          else if (y >= gy) { y -= gy; shy = d.len[1]; }
+        } else if (y < 0 || y >= gy) {
+          continue;
+        }
+        const int crow = d.g0 + (z * gy + y) * gx;
+        for (int sg = 0; sg < 2; ++sg) {
+          const int xa = sg ? xa1 : xa0, xb = sg ? xb1 : xb0;
+          if (xb < xa) continue;
+          const double shx = sg ? sh1 : sh0;
+          const int j1 = sbase + A.start[crow + xb + 1];
+          for (int j = sbase + A.start[crow + xa]; j < j1; ++j) {
+            const double4 pj = A.tq[j];
+            const double ex = (pj.x - pi.x) + shx;
+            const double ey = (pj.y - pi.y) + shy;
+            const double ez = (pj.z - pi.z) + shz;
+            if (j != p && dist_sq_exact(ex, ey, ez) < rl2) {
+              if (count < cap) A.idx[(count >> Ts) * row + ibase + (count & (T - 1))] = j;
+              ++count;
+            }
+          }
+        }
+      }
+    }
+    // count, overflow, near flag and copy-back of the sorted state
+    A.cnt[p] = min(count, cap);
+    if (count > cap) atomicMax(&S.overflow, count);
+    if (d.nc > 0) {
+      int hx, hy, hz;
+      c_cell_coords(d, pi.x, pi.y, pi.z, hx, hy, hz);
+      near = A.hnear[d.h0 + (hz * d.hd[1] + hy) * d.hd[0] + hx] != 0;
+    }
+    A.xcnt[p] = 0;
+    A.fme[4 * (int64_t)p + 0] = 0.0;
+    A.fme[4 * (int64_t)p + 1] = 0.0;
+    A.fme[4 * (int64_t)p + 2] = 0.0;
+    A.fme[4 * (int64_t)p + 3] = 0.0;
+    A.q[p] = pi;
+    A.xref[3 * p + 0] = pi.x;
+    A.xref[3 * p + 1] = pi.y;
+    A.xref[3 * p + 2] = pi.z;
+    A.v[3 * p + 0] = A.tv[3 * p + 0];
+    A.v[3 * p + 1] = A.tv[3 * p + 1];
+    A.v[3 * p + 2] = A.tv[3 * p + 2];
+    A.f[3 * p + 0] = A.tf[3 * p + 0];
+    A.f[3 * p + 1] = A.tf[3 * p + 1];
+    A.f[3 * p + 2] = A.tf[3 * p + 2];
+    A.fixed[p] = A.tfixed[p];
+    A.id[p] = A.tid[p];
+  }
+  const unsigned long long nm = __ballot(near);
+  if (nm) {   // append this wave's near atoms (order within the near list is irrelevant)
+    int first = 0;
+    if (lane == 0) first = atomicAdd(&S.nnear, __popcll(nm));
+    first = __shfl(first, 0, WAVE);
+    if (near) A.near[d.a0 + first + __popcll(nm & ((1ull << lane) - 1ull))] = p;
+  }
+}
+
 // Cr-C list {k : |xc_k + ind_z - q_p|^2 < (rc + skin)^2}, atom-major: xidx[p * xcap + n],
 // for the atoms of the near list of each rebuilding replica.  One wavefront per near atom
 // (grid-stride), its lanes sharing the 27 carbon cells around the atom; the passing
