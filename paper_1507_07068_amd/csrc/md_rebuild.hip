@@ -61,6 +61,10 @@ struct BuildArgs {
 };
 
 constexpr int MAXC = 512;           // candidates staged per window in k_xlist
+#ifndef MD_LIST_BATCH
+#define MD_LIST_BATCH 4
+#endif
+constexpr int LIST_BATCH = MD_LIST_BATCH;   // candidate loads issued together in k_list_rows
 constexpr int SUPER_X = 4;             // cells along x handled by one wavefront
 
 // Cells per wavefront along x: SUPER_X, or 1 when a periodic x axis is too short for the
@@ -585,6 +589,8 @@ __global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
     const int cap = K.cap, T = K.lt, Ts = K.lt_shift;
     const int row = (int)K.ntot * T;
     const int ibase = p * T;
+    const double4* __restrict__ tq = A.tq;
+    int* __restrict__ idx = A.idx;
     // x segments (first cell, last cell, shift), identical for the nine rows
     int xa0 = cx - 1, xb0 = cx + 1, xa1 = 0, xb1 = -1;
     double sh0 = 0.0, sh1 = 0.0;
@@ -624,16 +630,24 @@ __global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
           if (xb < xa) continue;
           const double shx = sg ? sh1 : sh0;
           const int j1 = sbase + A.start[crow + xb + 1];
-          for (int j = sbase + A.start[crow + xa]; j < j1; ++j) {
-            const double4 pj = A.tq[j];
+          auto test = [&](const double4& pj, int j) {
             const double ex = (pj.x - pi.x) + shx;
             const double ey = (pj.y - pi.y) + shy;
             const double ez = (pj.z - pi.z) + shz;
             if (j != p && dist_sq_exact(ex, ey, ez) < rl2) {
-              if (count < cap) A.idx[(count >> Ts) * row + ibase + (count & (T - 1))] = j;
+              if (count < cap) idx[(count >> Ts) * row + ibase + (count & (T - 1))] = j;
               ++count;
             }
+          };
+          int j = sbase + A.start[crow + xa];
+          for (; j + LIST_BATCH <= j1; j += LIST_BATCH) {   // LIST_BATCH loads in flight
+            double4 pj[LIST_BATCH];
+#pragma unroll
+            for (int u = 0; u < LIST_BATCH; ++u) pj[u] = tq[j + u];
+#pragma unroll
+            for (int u = 0; u < LIST_BATCH; ++u) test(pj[u], j + u);
           }
+          for (; j < j1; ++j) test(tq[j], j);
         }
       }
     }
