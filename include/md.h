@@ -147,7 +147,7 @@ typedef struct md_status {
     int32_t xoverflow;      /* same for the Cr-C list and xcap */
     int32_t nonfinite;      /* 1 if a non-finite force or density was produced */
     int32_t nbuilds;        /* list builds so far (summed over replicas) */
-    int32_t sync_timeout;   /* reserved (always 0) */
+    int32_t sync_timeout;   /* a bounded device-side wait of a list build gave up: that build is invalid */
     int32_t nnear;          /* Cr atoms whose carbon cells are within reach of a carbon at the
                                last build (the candidates of the Cr-C lists), all replicas */
     int32_t pad[2];

@@ -22,8 +22,9 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Byte offsets of the workspace regions.
 struct Layout {
-  size_t desc, state, tile_rep, c_rep, cell_rep, misc, xref, dmax, tbox, cellid, perm, tq, tv, tf, tfixed,
-      tid, count, start, hcell, hlist, hsorted, bsum, hnear, near, fme, p_embed, p_force, p_morse, p_kin, total;
+  size_t desc, state, tile_rep, c_rep, cell_rep, misc, xref, dmax, tbox, cellid, crank, perm, skey, tq, tv,
+      tf, tfixed, tid, count, start, hcell, hrank, hlist, hsorted, scan_state, hnear, near, fme, p_embed, p_force,
+      p_morse, p_kin, total;
 };
 
 constexpr int MISC_INTS = 16;    // rebuild flag, status words
@@ -76,7 +77,9 @@ Layout make_layout(const md_system& s) {
   L.dmax = take(sizeof(double) * nt);
   L.tbox = take(sizeof(double) * 6 * nt);
   L.cellid = take(sizeof(int) * n);
+  L.crank = take(sizeof(int) * n);
   L.perm = take(sizeof(int) * n);
+  L.skey = take(sizeof(long long) * n);
   L.tq = take(sizeof(double) * 4 * n);
   L.tv = take(sizeof(double) * 3 * n);
   L.tf = take(sizeof(double) * 3 * n);
@@ -85,9 +88,10 @@ Layout make_layout(const md_system& s) {
   L.count = take(sizeof(int) * (size_t)s.ncell_all);
   L.start = take(sizeof(int) * ((size_t)s.ncell_all + 1));
   L.hcell = take(sizeof(int) * (size_t)s.ctot);
+  L.hrank = take(sizeof(int) * (size_t)s.ctot);
   L.hlist = take(sizeof(int) * (size_t)s.ctot);
   L.hsorted = take(sizeof(int) * (size_t)s.ctot);
-  L.bsum = take(sizeof(int) * (size_t)s.scan_blocks);
+  L.scan_state = take(sizeof(long long) * (size_t)s.scan_blocks);
   L.hnear = take(sizeof(int) * (size_t)s.ncell_all);
   L.near = take(sizeof(int) * n);
   L.fme = take(sizeof(double) * 4 * n);
@@ -376,7 +380,9 @@ MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l
   A.xc = a->xc;
   A.xref = at<double>(s, s->L.xref);
   A.cellid = at<int>(s, s->L.cellid);
+  A.crank = at<int>(s, s->L.crank);
   A.perm = at<int>(s, s->L.perm);
+  A.skey = at<long long>(s, s->L.skey);
   A.tq = at<double4>(s, s->L.tq);
   A.tv = at<double>(s, s->L.tv);
   A.tf = at<double>(s, s->L.tf);
@@ -385,9 +391,11 @@ MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l
   A.count = at<int>(s, s->L.count);
   A.start = at<int>(s, s->L.start);
   A.hcell = at<int>(s, s->L.hcell);
+  A.hrank = at<int>(s, s->L.hrank);
   A.hlist = at<int>(s, s->L.hlist);
   A.hsorted = at<int>(s, s->L.hsorted);
-  A.bsum = at<int>(s, s->L.bsum);
+  A.scan_state = at<long long>(s, s->L.scan_state);
+  A.scan_ticket = misc + 1;
   A.idx = l->idx;
   A.cnt = l->cnt;
   A.xidx = l->xidx;
@@ -400,6 +408,7 @@ MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l
   A.ncell_cr = s->ncell_cr;
   A.ntiles = s->ntiles;
   A.ctot = (int)s->ctot;
+  static_assert(SCAN_CHUNK == BLOCK * SCAN_PER_THREAD, "k_scan covers SCAN_CHUNK cells per block");
   A.scan_chunk = SCAN_CHUNK;
   A.scan_blocks = s->scan_blocks;
   const int cblocks = (int)((s->ctot + BLOCK - 1) / BLOCK);
@@ -408,9 +417,7 @@ MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l
   k_decide<<<1, BLOCK, 0, st>>>(s->K, A, at<double>(s, s->L.dmax), at<double>(s, s->L.tbox),
                                 (flags & MD_B_FORCE) ? 1 : 0);
   k_bin<<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A);
-  k_scan_reduce<<<s->scan_blocks, BLOCK, 0, st>>>(A);
-  k_scan_top<<<1, BLOCK, 0, st>>>(A);
-  k_scan_apply<<<s->scan_blocks, BLOCK, 0, st>>>(A);
+  k_scan<<<s->scan_blocks, BLOCK, 0, st>>>(A);
   k_scatter<<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A);
   k_sort_gather<<<(s->ncell_all + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, BLOCK, 0, st>>>(s->K, A);
   if (s->list_mix)

@@ -3,8 +3,9 @@
 //
 //   k_decide        one block: per-replica skin test (Section 2.6) -> rebuild flags
 //   k_bin           wrap periodic coordinates, cell of every atom / carbon, cell counts
-//   k_scan_*        exclusive scan of all cell counts (three short kernels)
-//   k_scatter       atom slots / carbon indices into their cells (arbitrary order)
+//   k_scan          exclusive scan of all cell counts (one pass, decoupled look-back)
+//   k_scatter       atom slots / carbon indices into their cells at the ranks k_bin took
+//                   (arbitrary order within a cell), with the (cell, id) sort keys
 //   k_sort_gather   one wavefront per cell: order the cell by atom id, gather the atom
 //                   state into sorted order (so the final order is canonical)
 //   k_list          one wavefront per Cr cell: the 27-cell candidates are loaded once into
@@ -35,8 +36,10 @@ struct BuildArgs {
   int* id;
   const double* xc;
   double* xref;
-  int* cellid;           // [ntot]
-  int* perm;             // [ntot]
+  int* cellid;           // [ntot] cell of each atom slot
+  int* crank;            // [ntot] rank of the slot among the atoms binned into its cell
+  int* perm;             // [ntot] slots by cell (cells in order, arbitrary order within one)
+  long long* skey;       // [ntot] (cell, id) sort key of perm's entries
   double4* tq;
   double* tv;
   double* tf;
@@ -45,9 +48,11 @@ struct BuildArgs {
   int* count;            // [ncell_all]
   int* start;            // [ncell_all + 1]
   int* hcell;            // [ctot]
+  int* hrank;            // [ctot] rank of the carbon among those binned into its cell
   int* hlist;            // [ctot] carbons by cell (arbitrary order within a cell)
   int* hsorted;          // [ctot] carbons by cell, ascending index within a cell
-  int* bsum;             // [scan_blocks]
+  long long* scan_state; // [scan_blocks] published chunk sums of k_scan
+  int* scan_ticket;      // chunk ticket of k_scan
   int* hnear;            // [ncell_all]: carbon cell c has a carbon in its 27-cell stencil
   int* idx;
   int* cnt;
@@ -160,34 +165,65 @@ __device__ __forceinline__ void c_cell_coords(const RepDesc& d, double x, double
   hz = cell_coord(fold(z, d.lo[2], d.len[2], d.per[2]), d.lo[2], d.hinv[2], d.hd[2]);
 }
 
+// Rank of this lane's atom among the atoms binned into cell `cid`: consecutive lanes with
+// the same cell (the common case, atoms arrive in the previous build's cell order) form a
+// run that takes its ranks with one atomic add.  Every lane of the wave calls it together.
+__device__ __forceinline__ int bin_rank(int* count, int cid, bool live) {
+  const int lane = threadIdx.x % WAVE;
+  const int key = live ? cid : -1;
+  const int prev = __shfl_up(key, 1, WAVE);
+  const bool head = live && (lane == 0 || prev != key);
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long stops = __ballot(head || !live);   // first lane of the next run
+  const unsigned long long upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+  const unsigned long long below = heads & upto;                // heads at lanes <= lane
+  const int start = below ? 63 - __builtin_clzll(below) : 0;
+  int base = 0;
+  if (head) {
+    const unsigned long long after = stops & ~upto;
+    const int end = after ? __builtin_ctzll(after) : WAVE;
+    base = atomicAdd(&count[cid], end - lane);
+  }
+  base = __shfl(base, start, WAVE);
+  return base + (lane - start);
+}
+
 // Blocks [0, ntiles): one tile of Cr atoms each.  Blocks [ntiles, ...): 256 carbons each.
 __global__ __launch_bounds__(BLOCK) void k_bin(Consts K, BuildArgs A) {
   if (rebuild_off(A)) return;
   const int b = blockIdx.x;
+  if (b == 0) {   // fresh state for this build's k_scan
+    for (int t = threadIdx.x; t < A.scan_blocks; t += BLOCK) A.scan_state[t] = 0;
+    if (threadIdx.x == 0) *A.scan_ticket = 0;
+  }
   if (b < A.ntiles) {
     const int r = A.tile_rep[b];
     if (!A.S[r].rebuild) return;
     const RepDesc& d = A.R[r];
     const int64_t i = (int64_t)b * TILE + threadIdx.x;
-    if (i >= (int64_t)d.a0 + d.n) return;
-    double4 p = A.q[i];
-    double xyz[3] = {p.x, p.y, p.z};
+    const bool live = i < (int64_t)d.a0 + d.n;
+    int cid = -1;
+    if (live) {
+      double4 p = A.q[i];
+      double xyz[3] = {p.x, p.y, p.z};
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      if (!d.per[a]) continue;
-      const double hi = d.lo[a] + d.len[a];
-      if (xyz[a] >= hi)
-        xyz[a] -= d.len[a];
-      else if (xyz[a] < d.lo[a])
-        xyz[a] += d.len[a];
+      for (int a = 0; a < 3; ++a) {
+        if (!d.per[a]) continue;
+        const double hi = d.lo[a] + d.len[a];
+        if (xyz[a] >= hi)
+          xyz[a] -= d.len[a];
+        else if (xyz[a] < d.lo[a])
+          xyz[a] += d.len[a];
+      }
+      p.x = xyz[0];
+      p.y = xyz[1];
+      p.z = xyz[2];
+      A.q[i] = p;
+      cid = cr_cell_of(d, A.S[r], p.x, p.y, p.z);
+      A.cellid[i] = cid;
     }
-    p.x = xyz[0];
-    p.y = xyz[1];
-    p.z = xyz[2];
-    A.q[i] = p;
-    const int cid = cr_cell_of(d, A.S[r], p.x, p.y, p.z);
-    A.cellid[i] = cid;
-    atomicAdd(&A.count[cid], 1);
+    const int rank = bin_rank(A.count, cid, live);
+    if (live) A.crank[i] = rank;
   } else {
     const int64_t k = (int64_t)(b - A.ntiles) * BLOCK + threadIdx.x;
     int r = -1;
@@ -202,51 +238,74 @@ __global__ __launch_bounds__(BLOCK) void k_bin(Consts K, BuildArgs A) {
       c_cell_coords(d, A.xc[3 * k + 0], A.xc[3 * k + 1], z, hx, hy, hz);
       const int hid = d.h0 + (hz * d.hd[1] + hy) * d.hd[0] + hx;
       A.hcell[k] = hid;
-      atomicAdd(&A.count[hid], 1);
+      A.hrank[k] = atomicAdd(&A.count[hid], 1);
     }
   }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_scan_reduce(BuildArgs A) {
+// Exclusive scan of all cell counts in one launch: each block scans SCAN_CHUNK cells and
+// finds the sum of the chunks before it by looking back over the published chunk states
+// (single-pass scan with decoupled look-back, Merrill and Garland 2016).  Chunks are
+// taken in ticket order, so a block only waits for blocks that are already running; the
+// wait is bounded and a timeout is reported in the status words.
+constexpr int SCAN_PER_THREAD = 8;
+constexpr long long SCAN_AGG = 1ll << 32, SCAN_INCL = 2ll << 32;
+constexpr int SCAN_SPIN_LIMIT = 1 << 22;
+
+__global__ __launch_bounds__(BLOCK) void k_scan(BuildArgs A) {
   if (rebuild_off(A)) return;
-  const int c0 = blockIdx.x * A.scan_chunk, c1 = min(c0 + A.scan_chunk, A.ncell_all);
-  int s = 0;
-  for (int c = c0 + threadIdx.x; c < c1; c += BLOCK) s += A.count[c];
+  __shared__ int chunk_sh, excl_sh;
+  if (threadIdx.x == 0) chunk_sh = atomicAdd(A.scan_ticket, 1);
+  __syncthreads();
+  const int b = chunk_sh;
+  const int c0 = b * A.scan_chunk + threadIdx.x * SCAN_PER_THREAD;
+  int v[SCAN_PER_THREAD];
+  int sum = 0;
+#pragma unroll
+  for (int u = 0; u < SCAN_PER_THREAD; ++u) {
+    v[u] = (c0 + u < A.ncell_all) ? A.count[c0 + u] : 0;
+    sum += v[u];
+  }
   int tot;
-  block_exclusive_scan(s, &tot);
-  if (threadIdx.x == 0) A.bsum[blockIdx.x] = tot;
-}
-
-__global__ __launch_bounds__(BLOCK) void k_scan_top(BuildArgs A) {
-  if (rebuild_off(A)) return;
-  int carry = 0;
-  for (int b0 = 0; b0 < A.scan_blocks; b0 += BLOCK) {
-    const int b = b0 + threadIdx.x;
-    const int v = b < A.scan_blocks ? A.bsum[b] : 0;
-    int tot;
-    const int ex = block_exclusive_scan(v, &tot);
-    if (b < A.scan_blocks) A.bsum[b] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) A.start[A.ncell_all] = carry;
-}
-
-// start[c] = exclusive prefix; count[c] = 0 (it becomes the fill cursor of k_scatter).
-__global__ __launch_bounds__(BLOCK) void k_scan_apply(BuildArgs A) {
-  if (rebuild_off(A)) return;
-  const int c0 = blockIdx.x * A.scan_chunk, c1 = min(c0 + A.scan_chunk, A.ncell_all);
-  int carry = A.bsum[blockIdx.x];
-  for (int cb = c0; cb < c1; cb += BLOCK) {
-    const int c = cb + threadIdx.x;
-    const int v = c < c1 ? A.count[c] : 0;
-    int tot;
-    const int ex = block_exclusive_scan(v, &tot);
-    if (c < c1) {
-      A.start[c] = carry + ex;
-      A.count[c] = 0;
-      A.hnear[c] = 0;
+  const int pre = block_exclusive_scan(sum, &tot);
+  if (threadIdx.x == 0) {
+    long long* st = A.scan_state;
+    int excl = 0;
+    if (b == 0) {
+      __hip_atomic_store(&st[0], SCAN_INCL | (unsigned)tot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      __hip_atomic_store(&st[b], SCAN_AGG | (unsigned)tot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      int j = b - 1, spins = 0;
+      while (j >= 0) {
+        const long long w = __hip_atomic_load(&st[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const long long flag = w & ~0xffffffffll;
+        if (flag == 0) {
+          if (++spins > SCAN_SPIN_LIMIT) {
+            A.S[0].sync_timeout = 1;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        excl += (int)(unsigned)(w & 0xffffffffll);
+        if (flag == SCAN_INCL) break;
+        --j;
+      }
+      __hip_atomic_store(&st[b], SCAN_INCL | (unsigned)(excl + tot), __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_AGENT);
     }
-    carry += tot;
+    excl_sh = excl;
+    if (b == A.scan_blocks - 1) A.start[A.ncell_all] = excl + tot;
+  }
+  __syncthreads();
+  int run = excl_sh + pre;
+#pragma unroll
+  for (int u = 0; u < SCAN_PER_THREAD; ++u) {
+    if (c0 + u < A.ncell_all) {
+      A.start[c0 + u] = run;
+      A.hnear[c0 + u] = 0;
+    }
+    run += v[u];
   }
 }
 
@@ -260,8 +319,9 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Consts K, BuildArgs A) {
     const int64_t i = (int64_t)b * TILE + threadIdx.x;
     if (i >= (int64_t)d.a0 + d.n) return;
     const int cid = A.cellid[i];
-    const int slot = atomicAdd(&A.count[cid], 1);
-    A.perm[d.a0 + (A.start[cid] - A.start[d.g0]) + slot] = (int)i;
+    const int pos = d.a0 + (A.start[cid] - A.start[d.g0]) + A.crank[i];
+    A.perm[pos] = (int)i;
+    A.skey[pos] = ((long long)cid << 32) | (unsigned)A.id[i];
   } else {
     const int64_t k = (int64_t)(b - A.ntiles) * BLOCK + threadIdx.x;
     if (k >= A.ctot) return;
@@ -269,8 +329,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Consts K, BuildArgs A) {
     if (!A.S[r].rebuild) return;
     const RepDesc& d = A.R[r];
     const int hid = A.hcell[k];
-    const int slot = atomicAdd(&A.count[hid], 1);
-    A.hlist[d.c0 + (A.start[hid] - A.start[d.h0]) + slot] = (int)k;
+    A.hlist[d.c0 + (A.start[hid] - A.start[d.h0]) + A.hrank[k]] = (int)k;
   }
 }
 
@@ -322,10 +381,10 @@ __global__ __launch_bounds__(BLOCK) void k_sort_gather(Consts K, BuildArgs A) {
       const bool have = u < m;
       const int e = have ? A.perm[base + u] : 0;
       // order by (cell, id): within the run, the rank is the atom's final position
-      const long long key = have ? (((long long)(A.cellid[e] - crow)) << 32) | (unsigned)A.id[e] : 0;
-      const int rank = segment_rank(m, key, e, have, [&](int t, long long& kk, int& tt) {
-        tt = A.perm[base + t];
-        kk = (((long long)(A.cellid[tt] - crow)) << 32) | (unsigned)A.id[tt];
+      const long long key = have ? A.skey[base + u] : 0;
+      const int rank = segment_rank(m, key, 0, have, [&](int t, long long& kk, int& tt) {
+        kk = A.skey[base + t];
+        tt = 0;
       });
       if (have) {
         const int p = base + rank;
