@@ -95,7 +95,7 @@ def main(argv=None):
 
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        sim = md.Simulation(systems, precision=precision, cap=64, xcap=160, tpa=args.tpa)
+        sim = md.Simulation(systems, precision=precision, xcap=160, tpa=args.tpa)
         sim.initial_forces()
         if args.warmup:
             sim.md_run(args.warmup)
@@ -117,7 +117,7 @@ def main(argv=None):
         if flags["overflow"] or flags["xoverflow"] or flags["nonfinite"] or flags["sync_timeout"]:
             raise SystemExit(f"invalid run: {flags}")
         k_ms = np.array([events[2 * k].elapsed_time(events[2 * k + 1]) for k in range(steps)])
-        cnt = sim.cnt.cpu().numpy()
+        cnt = sim.list_counts()
         live = np.concatenate([np.arange(o, o + s.n) for o, s in zip(sim.offsets, systems)])
         mean_list = float(cnt[live].mean()) if live.size else 0.0
         o = obs.cpu().numpy()

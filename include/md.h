@@ -106,7 +106,8 @@ typedef struct md_params {
     int32_t cap;        /* Cr-Cr list capacity per atom */
     int32_t xcap;       /* Cr-C list capacity per atom */
     int32_t tpa;        /* lanes per atom in the density / force passes: 1, 2, 4 or 8 (the
-                           Cr-Cr list is interleaved by tpa to match) */
+                           Cr-Cr list is interleaved by tpa to match; cap must be a multiple
+                           of tpa) */
     int32_t pad;
 } md_params;
 
@@ -135,7 +136,9 @@ typedef struct md_atoms {
 /* Device neighbour lists (caller-owned, written by md_build_neighbors). */
 typedef struct md_lists {
     int32_t *idx;       /* [cap * n_total]: entry k of atom i (an atom slot) at
-                           idx[(k / tpa) * n_total * tpa + i * tpa + k % tpa] */
+                           idx[(k / tpa) * n_total * tpa + i * tpa + k % tpa]; entries are
+                           ordered by the cell row (dz, dy = 0..2 around the atom's cell, dz
+                           slowest), then along x, then by slot */
     int32_t *cnt;       /* [n_total] */
     int32_t *xidx;      /* [n_total][xcap]: carbon indices (into xc) of atom i's Cr-C list */
     int32_t *xcnt;      /* [n_total] */

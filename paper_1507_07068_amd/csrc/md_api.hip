@@ -22,7 +22,7 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Byte offsets of the workspace regions.
 struct Layout {
-  size_t desc, state, tile_rep, c_rep, cell_rep, misc, xref, dmax, tbox, cellid, crank, perm, skey, tq, tv,
+  size_t desc, state, tile_rep, c_rep, cell_rep, misc, xref, dmax, tbox, cellid, crank, perm, skey, tq, tqf, tv,
       tf, tfixed, tid, count, start, hcell, hrank, hlist, hsorted, scan_state, hnear, near, fme, p_embed, p_force,
       p_morse, p_kin, total;
 };
@@ -47,7 +47,6 @@ struct md_system {
   Layout L;
   char* ws;
   int scan_blocks;
-  bool list_mix;   // some periodic axis has fewer than 3 list cells
   bool have_embed, have_force;
 };
 
@@ -81,6 +80,7 @@ Layout make_layout(const md_system& s) {
   L.perm = take(sizeof(int) * n);
   L.skey = take(sizeof(long long) * n);
   L.tq = take(sizeof(double) * 4 * n);
+  L.tqf = take(sizeof(float) * 4 * n);
   L.tv = take(sizeof(double) * 3 * n);
   L.tf = take(sizeof(double) * 3 * n);
   L.tfixed = take(n);
@@ -203,6 +203,7 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
   if (!reps || !p || nrep < 1 || nrep > MAXREP) return MD_ERR_ARG;
   if (!(p->mass > 0) || !(p->dt > 0) || !(p->skin >= 0) || p->cap < 1 || p->xcap < 1) return MD_ERR_ARG;
   if (p->tpa != 1 && p->tpa != 2 && p->tpa != 4 && p->tpa != 8) return MD_ERR_ARG;
+  if (p->cap % p->tpa != 0) return MD_ERR_ARG;
   if (!(p->eam.c > 0) || !(p->eam.d > 0) || !(p->eam.d <= p->eam.c) || !(p->morse.rc > 0) ||
       !(p->morse.alpha > 0))
     return MD_ERR_ARG;
@@ -211,7 +212,6 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
   s->p = *p;
   s->nrep = nrep;
   s->ws = nullptr;
-  s->list_mix = false;
   s->have_embed = s->have_force = false;
   const double rlist = p->eam.c + p->skin;
   const double rxlist = p->morse.rc + p->skin;
@@ -237,7 +237,6 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
       if (d.per[a] && !(rd.len[a] > 2.0 * rlist)) { delete s; return MD_ERR_ARG; }
       if (d.per[a] && rd.n_c > 0 && !(rd.len[a] > 2.0 * rxlist)) { delete s; return MD_ERR_ARG; }
       d.ginv[a] = nb / rd.len[a];
-      if (d.per[a] && nb < 3) s->list_mix = true;
       d.hinv[a] = d.hd[a] / rd.len[a];
     }
     d.a0 = (int)a0;
@@ -384,6 +383,7 @@ MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l
   A.perm = at<int>(s, s->L.perm);
   A.skey = at<long long>(s, s->L.skey);
   A.tq = at<double4>(s, s->L.tq);
+  A.tqf = at<float4>(s, s->L.tqf);
   A.tv = at<double>(s, s->L.tv);
   A.tf = at<double>(s, s->L.tf);
   A.tfixed = at<uint8_t>(s, s->L.tfixed);
@@ -420,10 +420,7 @@ MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l
   k_scan<<<s->scan_blocks, BLOCK, 0, st>>>(A);
   k_scatter<<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A);
   k_sort_gather<<<(s->ncell_all + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, BLOCK, 0, st>>>(s->K, A);
-  if (s->list_mix)
-    k_list<true><<<(s->ncell_cr + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, BLOCK, 0, st>>>(s->K, A);
-  else
-    k_list_rows<<<s->ntiles, BLOCK, 0, st>>>(s->K, A);
+  k_list_rows<<<s->ntiles, BLOCK, 0, st>>>(s->K, A);
   k_xlist<<<A.near_blocks, BLOCK, 0, st>>>(s->K, A);
   return check_launch();
 }

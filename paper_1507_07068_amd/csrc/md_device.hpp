@@ -205,6 +205,12 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Slot of entry k of atom i in the Cr-Cr list (interleave T: entries k..k+T-1 of one atom
+// are adjacent, so T lanes of one atom read consecutive words).
+__device__ __forceinline__ int list_pos(int k, int i, int ntot, int T, int Tshift) {
+  return ((k >> Tshift) * ntot + i) * T + (k & (T - 1));
+}
+
 // The 27-cell stencil, one axis at a time: offsets t = 0..stencil_n-1 map to cells
 // c-1, c, c+1 (periodic wrap, or -1 = outside an open axis).  A periodic axis with fewer
 // than 3 cells visits each of its cells once instead, so no cell is met twice.

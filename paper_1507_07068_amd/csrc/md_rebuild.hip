@@ -8,10 +8,8 @@
 //                   (arbitrary order within a cell), with the (cell, id) sort keys
 //   k_sort_gather   one wavefront per cell: order the cell by atom id, gather the atom
 //                   state into sorted order (so the final order is canonical)
-//   k_list          one wavefront per Cr cell: the 27-cell candidates are loaded once into
-//                   registers, every atom of the cell tests them together, a ballot +
-//                   popcount compacts the passing ones in candidate order; copies the
-//                   sorted state back
+//   k_list_rows     one lane per Cr atom scanning contiguous cell-row ranges of the sorted
+//                   atoms; copies the sorted state back
 //   k_xlist         Cr-C lists: one wavefront per Cr atom within reach of the carbons
 //
 // Every kernel after k_decide returns at once when no replica needs a rebuild, so a step
@@ -41,6 +39,7 @@ struct BuildArgs {
   int* perm;             // [ntot] slots by cell (cells in order, arbitrary order within one)
   long long* skey;       // [ntot] (cell, id) sort key of perm's entries
   double4* tq;
+  float4* tqf;           // [ntot] sorted positions relative to the replica's grid origin, FP32
   double* tv;
   double* tf;
   uint8_t* tfixed;
@@ -79,11 +78,6 @@ __device__ __forceinline__ int super_x(const RepDesc& d, int gx) {
 }
 constexpr int WAVES_PER_BLOCK = BLOCK / WAVE;
 
-// Slot of entry k of atom i in the Cr-Cr list (interleave T: entries k..k+T-1 of one atom
-// are adjacent, so T lanes of one atom read consecutive words).
-__device__ __forceinline__ int list_pos(int k, int i, int ntot, int T, int Tshift) {
-  return ((k >> Tshift) * ntot + i) * T + (k & (T - 1));
-}
 
 __device__ __forceinline__ bool rebuild_off(const BuildArgs& A) { return *A.any == 0; }
 
@@ -268,34 +262,46 @@ __global__ __launch_bounds__(BLOCK) void k_scan(BuildArgs A) {
   }
   int tot;
   const int pre = block_exclusive_scan(sum, &tot);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < WAVE) {   // wave 0 publishes this chunk and looks back 64 chunks at a time
+    const int lane = threadIdx.x;
     long long* st = A.scan_state;
     int excl = 0;
     if (b == 0) {
-      __hip_atomic_store(&st[0], SCAN_INCL | (unsigned)tot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (lane == 0)
+        __hip_atomic_store(&st[0], SCAN_INCL | (unsigned)tot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
-      __hip_atomic_store(&st[b], SCAN_AGG | (unsigned)tot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      int j = b - 1, spins = 0;
-      while (j >= 0) {
-        const long long w = __hip_atomic_load(&st[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      if (lane == 0)
+        __hip_atomic_store(&st[b], SCAN_AGG | (unsigned)tot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      int top = b - 1, spins = 0;
+      while (true) {
+        const int j = top - lane;   // lane 0 is the nearest predecessor; j < 0 reads as prefix 0
+        const long long w =
+            j >= 0 ? __hip_atomic_load(&st[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) : SCAN_INCL;
         const long long flag = w & ~0xffffffffll;
-        if (flag == 0) {
+        const unsigned long long incl = __ballot(flag == SCAN_INCL);
+        const unsigned long long ready = __ballot(flag != 0);
+        const int first = incl ? __builtin_ctzll(incl) : WAVE;   // nearest inclusive prefix
+        const unsigned long long need = first < WAVE ? ((2ull << first) - 1ull) : ~0ull;
+        if ((ready & need) != need) {   // some chunk in between has not published yet
           if (++spins > SCAN_SPIN_LIMIT) {
-            A.S[0].sync_timeout = 1;
+            if (lane == 0) A.S[0].sync_timeout = 1;
             break;
           }
           __builtin_amdgcn_s_sleep(1);
           continue;
         }
-        excl += (int)(unsigned)(w & 0xffffffffll);
-        if (flag == SCAN_INCL) break;
-        --j;
+        excl += wave_sum(lane <= first ? (int)(unsigned)(w & 0xffffffffll) : 0);
+        if (first < WAVE) break;
+        top -= WAVE;
       }
-      __hip_atomic_store(&st[b], SCAN_INCL | (unsigned)(excl + tot), __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
+      if (lane == 0)
+        __hip_atomic_store(&st[b], SCAN_INCL | (unsigned)(excl + tot), __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
     }
-    excl_sh = excl;
-    if (b == A.scan_blocks - 1) A.start[A.ncell_all] = excl + tot;
+    if (lane == 0) {
+      excl_sh = excl;
+      if (b == A.scan_blocks - 1) A.start[A.ncell_all] = excl + tot;
+    }
   }
   __syncthreads();
   int run = excl_sh + pre;
@@ -388,7 +394,9 @@ __global__ __launch_bounds__(BLOCK) void k_sort_gather(Consts K, BuildArgs A) {
       });
       if (have) {
         const int p = base + rank;
-        A.tq[p] = A.q[e];
+        const double4 qe = A.q[e];
+        A.tq[p] = qe;
+        A.tqf[p] = make_float4((float)(qe.x - S.glo[0]), (float)(qe.y - S.glo[1]), (float)(qe.z - S.glo[2]), 0.0f);
         A.tv[3 * p + 0] = A.v[3 * e + 0];
         A.tv[3 * p + 1] = A.v[3 * e + 1];
         A.tv[3 * p + 2] = A.v[3 * e + 2];
@@ -429,157 +437,139 @@ __global__ __launch_bounds__(BLOCK) void k_sort_gather(Consts K, BuildArgs A) {
   }
 }
 
-constexpr int LCH = 4;                 // candidate chunks of 64 held in registers at once
-
-// MIX: some replica has a periodic axis with fewer than 3 cells (the image is then taken
-// pair by pair on that axis).
-template <bool MIX>
-__global__ __launch_bounds__(BLOCK) void k_list(Consts K, BuildArgs A) {
+// Cr-Cr lists, one lane per sorted Cr atom.  The candidates of the atom are those of the
+// cells around its own: nine cell rows (y, z), each holding x-cells cx-1 .. cx+1, which are
+// one contiguous range of the sorted order (two where the row wraps around a periodic x
+// axis).  Entries are written rows in order (z-major), along x, then by slot, at the
+// interleaved positions the tpa lanes of the force passes read.  Along a periodic axis with
+// >= 3 cells the periodic image of a candidate is fixed by the cell it comes from
+// (separation + 0 or -+ length: the same rounding as the minimum image for every pair
+// inside the list radius); along a periodic axis with fewer cells each cell is visited once
+// and the minimum image is taken pair by pair.
+__global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
   if (rebuild_off(A)) return;
-  __shared__ int cand_sh[WAVES_PER_BLOCK][LCH * WAVE];    // candidate slot
-  __shared__ int code_sh[WAVES_PER_BLOCK][LCH * WAVE];    // its periodic image code
-  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
-  const int c = blockIdx.x * WAVES_PER_BLOCK + w;
-  if (c >= A.ncell_cr) return;
-  const int r = A.cell_rep[c];
-  if (!A.S[r].rebuild) return;
-  const RepDesc& d = A.R[r];
+  const int T = K.lt, Ts = K.lt_shift;
+  const int tile = blockIdx.x;
+  const int r = A.tile_rep[tile];
   RepState& S = A.S[r];
-  if (c == d.g0 && lane == 0) {   // once per replica: the build is counted
+  if (!S.rebuild) return;
+  const RepDesc& d = A.R[r];
+  if (tile == d.t0 && threadIdx.x == 0) {   // once per replica: the build is counted
     S.nbuilds += 1;
     S.ind_z_ref = S.ind_z;
   }
-  const int lc = c - d.g0;
-  const int gx = S.gd[0], gy = S.gd[1], gz = S.gd[2];
-  // one wavefront per run of sx consecutive cells along x (their atoms are contiguous)
-  const int sx = super_x(d, gx);
-  const int ngx = (gx + sx - 1) / sx;
-  if (lc >= ngx * gy * gz) return;
-  const int cx0 = (lc % ngx) * sx, cy = (lc / ngx) % gy, cz = lc / (ngx * gy);
-  const int cx1 = min(cx0 + sx, gx);
-  const int crow = d.g0 + (cz * gy + cy) * gx;
-  const int sbase = A.start[d.g0];
-  const int m = A.start[crow + cx1] - A.start[crow + cx0];
-  if (m == 0) return;
-  const int base = d.a0 + (A.start[crow + cx0] - sbase);
-  // Along a periodic axis with >= 3 cells the image of a candidate is fixed by the stencil
-  // cell it comes from (separation + 0 or -+ length: the same rounding as the minimum
-  // image for every pair inside the list radius); with fewer cells the minimum image is
-  // taken pair by pair.
-  const bool mix = MIX && d.per[0] && gx < 3, miy = MIX && d.per[1] && gy < 3,
-             miz = MIX && d.per[2] && gz < 3;
-  const double Lx = d.len[0], Ly = d.len[1], Lz = d.len[2];
-  const double Hx = d.half[0], Hy = d.half[1], Hz = d.half[2];
-
-  // Stencil cells: lane t < ns describes the t-th of up to (sx+2)*3*3 cells.
-  const int nsx = mix ? gx : (cx1 - cx0) + 2;
-  const int nsy = stencil_n(gy, d.per[1]), nsz = stencil_n(gz, d.per[2]);
-  const int ns = nsx * nsy * nsz;
-  int js = 0, jn = 0, code = 0;
-  if (lane < ns) {
-    const int tx = lane % nsx, ty = (lane / nsx) % nsy, tz = lane / (nsx * nsy);
-    int x = mix ? tx : cx0 - 1 + tx;
-    if (!mix) {
-      if (d.per[0]) x = x < 0 ? x + gx : (x >= gx ? x - gx : x);
-      else if (x < 0 || x >= gx) x = -1;
-    }
-    const int y = stencil_cell(cy, ty, gy, d.per[1]);
-    const int z = stencil_cell(cz, tz, gz, d.per[2]);
-    if (x >= 0 && y >= 0 && z >= 0) {
-      const int cid = d.g0 + (z * gy + y) * gx + x;
-      js = d.a0 + (A.start[cid] - sbase);
-      jn = A.start[cid + 1] - A.start[cid];
-      // image code per axis: 0 none, 1 subtract length, 2 add length
-      const int ux = cx0 - 1 + tx;
-      const int ix = (!mix && d.per[0]) ? (ux >= gx ? 2 : (ux < 0 ? 1 : 0)) : 0;
-      const int iy = (!miy && d.per[1]) ? (cy + ty - 1 >= gy ? 2 : (cy + ty - 1 < 0 ? 1 : 0)) : 0;
-      const int iz = (!miz && d.per[2]) ? (cz + tz - 1 >= gz ? 2 : (cz + tz - 1 < 0 ? 1 : 0)) : 0;
-      code = ix | (iy << 2) | (iz << 4);
-    }
-  }
-  int pref = jn;
-#pragma unroll
-  for (int o = 1; o < WAVE; o <<= 1) {
-    const int y = __shfl_up(pref, o, WAVE);
-    if (lane >= o) pref += y;
-  }
-  const int total = __shfl(pref, WAVE - 1, WAVE);
-  pref -= jn;
-
-  const int T = K.lt, Ts = K.lt_shift;
-  const double rl2 = K.rlist_sq;
+  const int lane = threadIdx.x % WAVE;
+  const int p = tile * TILE + threadIdx.x;
+  const bool live = p < d.a0 + d.n;
   const int cap = K.cap;
-  const int row = (int)K.ntot * T;          // words between list rows (cap * ntot < 2^31)
-  for (int a0 = 0; a0 < m; a0 += WAVE) {    // center atoms in groups of 64
-    const int ma = min(WAVE, m - a0);
-    double4 mine = make_double4(0.0, 0.0, 0.0, 0.0);   // lane a holds center atom a0 + a
-    if (lane < ma) mine = A.tq[base + a0 + lane];
-    int count = 0;                                     // lane a: list length of atom a0 + a
-    for (int w0 = 0; w0 < total; w0 += LCH * WAVE) {
-      // stage this window's candidates (slot and image code) in candidate order
-      const int lo = max(0, w0 - pref), hi = min(jn, w0 + LCH * WAVE - pref);
-      for (int e = lo; e < hi; ++e) {
-        cand_sh[w][pref + e - w0] = js + e;
-        code_sh[w][pref + e - w0] = code;
-      }
-      wave_sync();
-      const int wn = min(LCH * WAVE, total - w0);
-      const int nch = (wn + WAVE - 1) / WAVE;
-      int cj[LCH];
-      double px[LCH], py[LCH], pz[LCH], sx[LCH], sy[LCH], sz[LCH];
+  bool near = false;
+  if (live) {
+    const double4 pi = A.tq[p];
+    const int gx = S.gd[0], gy = S.gd[1], gz = S.gd[2];
+    const int cx = cell_coord(pi.x, S.glo[0], S.ginv[0], gx);
+    const int cy = cell_coord(pi.y, S.glo[1], S.ginv[1], gy);
+    const int cz = cell_coord(pi.z, S.glo[2], S.ginv[2], gz);
+    const int sbase = d.a0 - A.start[d.g0];   // sorted slot = sbase + start[cell]
+    const double rl2 = K.rlist_sq;
+    const int64_t row = K.ntot * T;   // entry k at idx[(k / T) * row + k % T]
+    const double4* __restrict__ tq = A.tq;
+    const float4* __restrict__ tqf = A.tqf;
+    int* __restrict__ idx = A.idx + (int64_t)p * T;
+    // pairwise minimum image on periodic axes with fewer than 3 cells
+    const bool mx = d.per[0] && gx < 3, my = d.per[1] && gy < 3, mz = d.per[2] && gz < 3;
+    // FP32 screen: r2f, the squared separation from FP32 coordinates relative to the grid
+    // origin, decides the pair when it lies outside [rl2 - delta, rl2 + delta); pairs inside
+    // that band get the exact FP64 test.  With u = 2^-24, coordinates within E of the origin
+    // and a periodic length L, each separation component carries an error of at most
+    // eta = u (2E + 2L + 3R) for |component| <= R = r_list + 1, so |r2f - r2| <= sum over axes
+    // of (2 R eta + eta^2) + 4 u (rl2 + R^2); delta is twice that.  Pairs farther than R
+    // apart are far outside the band.  Axes with a pairwise minimum image use FP64 only.
+    const bool screen = !(mx || my || mz);
+    float lo_f = 0.0f, hi_f = 0.0f;
+    {
+      const double u = 0x1p-24, R = K.rlist + 1.0;
+      const int g[3] = {gx, gy, gz};
+      double err = 4.0 * u * (rl2 + R * R);
 #pragma unroll
-      for (int h = 0; h < LCH; ++h) {
-        cj[h] = -1;
-        px[h] = py[h] = pz[h] = 0.0;
-        sx[h] = sy[h] = sz[h] = 0.0;
-        if (h < nch && h * WAVE + lane < wn) {
-          cj[h] = cand_sh[w][h * WAVE + lane];
-          const int cd = code_sh[w][h * WAVE + lane];
-          const double4 pj = A.tq[cj[h]];
-          px[h] = pj.x;
-          py[h] = pj.y;
-          pz[h] = pj.z;
-          sx[h] = (cd & 3) == 1 ? -Lx : ((cd & 3) == 2 ? Lx : 0.0);
-          sy[h] = ((cd >> 2) & 3) == 1 ? -Ly : (((cd >> 2) & 3) == 2 ? Ly : 0.0);
-          sz[h] = ((cd >> 4) & 3) == 1 ? -Lz : (((cd >> 4) & 3) == 2 ? Lz : 0.0);
-        }
+      for (int a = 0; a < 3; ++a) {
+        const double E = g[a] / S.ginv[a] + 2.0 * R;
+        const double eta = u * (2.0 * E + (d.per[a] ? 2.0 * d.len[a] : 0.0) + 3.0 * R);
+        err += 2.0 * R * eta + eta * eta;
       }
-      wave_sync();
-      for (int a = 0; a < ma; ++a) {
-        const int i = base + a0 + a;
-        const double pix = readlane_d(mine.x, a), piy = readlane_d(mine.y, a), piz = readlane_d(mine.z, a);
-        int na = __builtin_amdgcn_readlane(count, a);
-        const int ibase = i * T;
-#pragma unroll
-        for (int h = 0; h < LCH; ++h) {
-          if (h >= nch) break;
-          const double dx = px[h] - pix, dy = py[h] - piy, dz = pz[h] - piz;
-          double ex, ey, ez;
-          if (MIX) {
-            ex = mix ? min_image(dx, Lx, Hx, 1) : dx + sx[h];
-            ey = miy ? min_image(dy, Ly, Hy, 1) : dy + sy[h];
-            ez = miz ? min_image(dz, Lz, Hz, 1) : dz + sz[h];
-          } else {
-            ex = dx + sx[h];
-            ey = dy + sy[h];
-            ez = dz + sz[h];
+      const double delta = 2.0 * err + 1e-6;
+      lo_f = (float)(rl2 - delta);
+      hi_f = (float)(rl2 + delta);
+    }
+    const float4 pf = tqf[p];
+    // x segments (first cell, last cell, shift), the same for every row
+    int xa0 = cx - 1, xb0 = cx + 1, xa1 = 0, xb1 = -1;
+    double sh0 = 0.0, sh1 = 0.0;
+    if (mx) {
+      xa0 = 0;
+      xb0 = gx - 1;
+    } else if (d.per[0]) {
+      if (cx == 0) {
+        xa0 = gx - 1; xb0 = gx - 1; sh0 = -d.len[0];
+        xa1 = 0; xb1 = 1;
+      } else if (cx == gx - 1) {
+        xa0 = gx - 2; xb0 = gx - 1;
+        xa1 = 0; xb1 = 0; sh1 = d.len[0];
+      }
+    } else {
+      xa0 = max(xa0, 0);
+      xb0 = min(xb0, gx - 1);
+    }
+    const int nsy = stencil_n(gy, d.per[1]), nsz = stencil_n(gz, d.per[2]);
+    int count = 0;
+    for (int rr = 0; rr < 9; ++rr) {
+      const int tz = rr / 3, ty = rr % 3;
+      if (tz >= nsz || ty >= nsy) continue;
+      const int z = stencil_cell(cz, tz, gz, d.per[2]);
+      const int y = stencil_cell(cy, ty, gy, d.per[1]);
+      if (z < 0 || y < 0) continue;
+      const int uz = cz + tz - 1, uy = cy + ty - 1;   // unwrapped row (image shift)
+      const double shz = (d.per[2] && !mz) ? (uz < 0 ? -d.len[2] : (uz >= gz ? d.len[2] : 0.0)) : 0.0;
+      const double shy = (d.per[1] && !my) ? (uy < 0 ? -d.len[1] : (uy >= gy ? d.len[1] : 0.0)) : 0.0;
+      const int crow = d.g0 + (z * gy + y) * gx;
+      for (int sg = 0; sg < 2; ++sg) {
+        const int xa = sg ? xa1 : xa0, xb = sg ? xb1 : xb0;
+        if (xb < xa) continue;
+        const double shx = sg ? sh1 : sh0;
+        const float fx = (float)shx, fy = (float)shy, fz = (float)shz;
+        const int j1 = sbase + A.start[crow + xb + 1];
+        auto exact = [&](int j) {
+          const double4 pj = tq[j];
+          double ex = pj.x - pi.x, ey = pj.y - pi.y, ez = pj.z - pi.z;
+          ex = mx ? min_image(ex, d.len[0], d.half[0], 1) : ex + shx;
+          ey = my ? min_image(ey, d.len[1], d.half[1], 1) : ey + shy;
+          ez = mz ? min_image(ez, d.len[2], d.half[2], 1) : ez + shz;
+          return dist_sq_exact(ex, ey, ez) < rl2;
+        };
+        auto test = [&](const float4& cf, int j) {
+          const float ex = (cf.x - pf.x) + fx, ey = (cf.y - pf.y) + fy, ez = (cf.z - pf.z) + fz;
+          const float r2f = ex * ex + ey * ey + ez * ez;
+          bool in = screen && r2f < lo_f;
+          if (!screen || (!in && !(r2f >= hi_f))) in = exact(j);
+          if (in && j != p) {
+            if (count < cap) idx[(count >> Ts) * row + (count & (T - 1))] = j;
+            ++count;
           }
-          const bool pred = cj[h] >= 0 && cj[h] != i && dist_sq_exact(ex, ey, ez) < rl2;
-          const unsigned long long mask = __ballot(pred);
-          const int k = na + __popcll(mask & ((1ull << lane) - 1ull));
-          if (pred && k < cap) A.idx[(k >> Ts) * row + ibase + (k & (T - 1))] = cj[h];
-          na += __popcll(mask);
+        };
+        int j = sbase + A.start[crow + xa];
+        for (; j + LIST_BATCH <= j1; j += LIST_BATCH) {   // LIST_BATCH loads in flight
+          float4 cf[LIST_BATCH];
+#pragma unroll
+          for (int u = 0; u < LIST_BATCH; ++u) cf[u] = tqf[j + u];
+#pragma unroll
+          for (int u = 0; u < LIST_BATCH; ++u) test(cf[u], j + u);
         }
-        if (lane == a) count = na;
+        for (; j < j1; ++j) test(tqf[j], j);
       }
     }
-    // counts, overflow, near list and copy-back of these center atoms (one lane per atom)
-    bool near = false;
-    if (lane < ma) {
-      const int p = base + a0 + lane;
-      A.cnt[p] = min(count, K.cap);
-      if (count > K.cap) atomicMax(&S.overflow, count);
-      const double4 pi = mine;
+    A.cnt[p] = min(count, cap);
+    if (count > cap) atomicMax(&S.overflow, count);
+    {
+      // near flag and copy-back of the sorted state
       if (d.nc > 0) {
         int hx, hy, hz;
         c_cell_coords(d, pi.x, pi.y, pi.z, hx, hy, hz);
@@ -590,7 +580,6 @@ __global__ __launch_bounds__(BLOCK) void k_list(Consts K, BuildArgs A) {
       A.fme[4 * (int64_t)p + 1] = 0.0;
       A.fme[4 * (int64_t)p + 2] = 0.0;
       A.fme[4 * (int64_t)p + 3] = 0.0;
-      // copy back the sorted state; reference positions for the skin test
       A.q[p] = pi;
       A.xref[3 * p + 0] = pi.x;
       A.xref[3 * p + 1] = pi.y;
@@ -604,137 +593,6 @@ __global__ __launch_bounds__(BLOCK) void k_list(Consts K, BuildArgs A) {
       A.fixed[p] = A.tfixed[p];
       A.id[p] = A.tid[p];
     }
-    const unsigned long long nm = __ballot(near);
-    if (nm) {   // append this wave's near atoms (order within the near list is irrelevant)
-      int first = 0;
-      if (lane == 0) first = atomicAdd(&S.nnear, __popcll(nm));
-      first = __shfl(first, 0, WAVE);
-      if (near) A.near[d.a0 + first + __popcll(nm & ((1ull << lane) - 1ull))] = base + a0 + lane;
-    }
-  }
-}
-
-// One lane per sorted Cr atom (lists of replicas whose periodic axes all have >= 3 list
-// cells).  The candidates in each of the nine cell rows (y, z) around the atom's cell are
-// the atoms of x-cells cx-1 .. cx+1 of that row: one contiguous range of the sorted order,
-// or two when the row wraps around a periodic x axis.  Rows are visited z-major, then y,
-// the ranges along x, and the atoms of a cell in id order: the same candidate order as
-// the wavefront-per-run kernel above, so both give identical lists.
-__global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
-  if (rebuild_off(A)) return;
-  const int b = blockIdx.x;
-  const int r = A.tile_rep[b];
-  RepState& S = A.S[r];
-  if (!S.rebuild) return;
-  const RepDesc& d = A.R[r];
-  if (b == d.t0 && threadIdx.x == 0) {   // once per replica: the build is counted
-    S.nbuilds += 1;
-    S.ind_z_ref = S.ind_z;
-  }
-  const int lane = threadIdx.x % WAVE;
-  const int p = b * TILE + threadIdx.x;
-  const bool live = p < d.a0 + d.n;
-  double4 pi = make_double4(0.0, 0.0, 0.0, 0.0);
-  int count = 0;
-  bool near = false;
-  if (live) {
-    pi = A.tq[p];
-    const int gx = S.gd[0], gy = S.gd[1], gz = S.gd[2];
-    const int cx = cell_coord(pi.x, S.glo[0], S.ginv[0], gx);
-    const int cy = cell_coord(pi.y, S.glo[1], S.ginv[1], gy);
-    const int cz = cell_coord(pi.z, S.glo[2], S.ginv[2], gz);
-    const int sbase = d.a0 - A.start[d.g0];   // sorted slot = sbase + start[cell]
-    const double rl2 = K.rlist_sq;
-    const int cap = K.cap, T = K.lt, Ts = K.lt_shift;
-    const int row = (int)K.ntot * T;
-    const int ibase = p * T;
-    const double4* __restrict__ tq = A.tq;
-    int* __restrict__ idx = A.idx;
-    // x segments (first cell, last cell, shift), identical for the nine rows
-    int xa0 = cx - 1, xb0 = cx + 1, xa1 = 0, xb1 = -1;
-    double sh0 = 0.0, sh1 = 0.0;
-    if (d.per[0]) {
-      if (cx == 0) {
-        xa0 = gx - 1; xb0 = gx - 1; sh0 = -d.len[0];
-        xa1 = 0; xb1 = 1;
-      } else if (cx == gx - 1) {
-        xa0 = gx - 2; xb0 = gx - 1;
-        xa1 = 0; xb1 = 0; sh1 = d.len[0];
-      }
-    } else {
-      xa0 = max(xa0, 0);
-      xb0 = min(xb0, gx - 1);
-    }
-    for (int tz = 0; tz < 3; ++tz) {
-      int z = cz + tz - 1;
-      double shz = 0.0;
-      if (d.per[2]) {
-        if (z < 0) { z += gz; shz = -d.len[2]; }
-        else if (z >= gz) { z -= gz; shz = d.len[2]; }
-      } else if (z < 0 || z >= gz) {
-        continue;
-      }
-      for (int ty = 0; ty < 3; ++ty) {
-        int y = cy + ty - 1;
-        double shy = 0.0;
-        if (d.per[1]) {
-          if (y < 0) { y += gy; shy = -d.len[1]; }
-          else if (y >= gy) { y -= gy; shy = d.len[1]; }
-        } else if (y < 0 || y >= gy) {
-          continue;
-        }
-        const int crow = d.g0 + (z * gy + y) * gx;
-        for (int sg = 0; sg < 2; ++sg) {
-          const int xa = sg ? xa1 : xa0, xb = sg ? xb1 : xb0;
-          if (xb < xa) continue;
-          const double shx = sg ? sh1 : sh0;
-          const int j1 = sbase + A.start[crow + xb + 1];
-          auto test = [&](const double4& pj, int j) {
-            const double ex = (pj.x - pi.x) + shx;
-            const double ey = (pj.y - pi.y) + shy;
-            const double ez = (pj.z - pi.z) + shz;
-            if (j != p && dist_sq_exact(ex, ey, ez) < rl2) {
-              if (count < cap) idx[(count >> Ts) * row + ibase + (count & (T - 1))] = j;
-              ++count;
-            }
-          };
-          int j = sbase + A.start[crow + xa];
-          for (; j + LIST_BATCH <= j1; j += LIST_BATCH) {   // LIST_BATCH loads in flight
-            double4 pj[LIST_BATCH];
-#pragma unroll
-            for (int u = 0; u < LIST_BATCH; ++u) pj[u] = tq[j + u];
-#pragma unroll
-            for (int u = 0; u < LIST_BATCH; ++u) test(pj[u], j + u);
-          }
-          for (; j < j1; ++j) test(tq[j], j);
-        }
-      }
-    }
-    // count, overflow, near flag and copy-back of the sorted state
-    A.cnt[p] = min(count, cap);
-    if (count > cap) atomicMax(&S.overflow, count);
-    if (d.nc > 0) {
-      int hx, hy, hz;
-      c_cell_coords(d, pi.x, pi.y, pi.z, hx, hy, hz);
-      near = A.hnear[d.h0 + (hz * d.hd[1] + hy) * d.hd[0] + hx] != 0;
-    }
-    A.xcnt[p] = 0;
-    A.fme[4 * (int64_t)p + 0] = 0.0;
-    A.fme[4 * (int64_t)p + 1] = 0.0;
-    A.fme[4 * (int64_t)p + 2] = 0.0;
-    A.fme[4 * (int64_t)p + 3] = 0.0;
-    A.q[p] = pi;
-    A.xref[3 * p + 0] = pi.x;
-    A.xref[3 * p + 1] = pi.y;
-    A.xref[3 * p + 2] = pi.z;
-    A.v[3 * p + 0] = A.tv[3 * p + 0];
-    A.v[3 * p + 1] = A.tv[3 * p + 1];
-    A.v[3 * p + 2] = A.tv[3 * p + 2];
-    A.f[3 * p + 0] = A.tf[3 * p + 0];
-    A.f[3 * p + 1] = A.tf[3 * p + 1];
-    A.f[3 * p + 2] = A.tf[3 * p + 2];
-    A.fixed[p] = A.tfixed[p];
-    A.id[p] = A.tid[p];
   }
   const unsigned long long nm = __ballot(near);
   if (nm) {   // append this wave's near atoms (order within the near list is irrelevant)

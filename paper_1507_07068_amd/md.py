@@ -159,9 +159,12 @@ class Simulation:
     first).  ``precision`` is "fp64" or "mixed".
     """
 
-    def __init__(self, systems, precision: str = "fp64", cap: int = 64, xcap: int = 160,
+    def __init__(self, systems, precision: str = "fp64", cap: int | None = None, xcap: int = 160,
                  tpa: int = 1, device: str = "cuda:0"):
+        """cap: Cr-Cr list capacity per atom (a multiple of tpa)."""
         import torch
+        if cap is None:
+            cap = 64
         if not torch.cuda.is_available():
             raise MDError("no GPU visible: the MD path runs only on the GPU")
         self.torch = torch
@@ -417,3 +420,7 @@ class Simulation:
             kk = k[:cnt[p]]
             rows.append(idx[(kk // T) * n * T + p * T + kk % T])
         return rows
+
+    def list_counts(self) -> np.ndarray:
+        """Cr-Cr list length of every atom slot."""
+        return self.cnt.cpu().numpy()

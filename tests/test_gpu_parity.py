@@ -17,7 +17,7 @@ FP64_TOL = 1e-10
 MIXED_TOL = 1e-5
 
 
-def sim_of(s, precision="fp64", cap=64, xcap=128, tpa=1):
+def sim_of(s, precision="fp64", cap=None, xcap=128, tpa=1):
     print(f"[case] {s.name} n={s.n} n_c={s.n_c} precision={precision} tpa={tpa}", flush=True)
     return md.Simulation(s, precision=precision, cap=cap, xcap=xcap, tpa=tpa)
 
@@ -144,7 +144,7 @@ def test_list_overflow_is_flagged():
     st = sim.md_check()
     cnt, _ = O.neighbors(s, s.r_list, x=O.wrap(s), cap=64)
     assert st["overflow"] == int(cnt.max())
-    assert int(sim.cnt.max().item()) == 8
+    assert int(sim.list_counts().max()) == 8
     sim.md_clear_flags()
     assert sim.md_check()["overflow"] == 0
 
