@@ -47,6 +47,7 @@ struct md_system {
   Layout L;
   char* ws;
   int scan_blocks;
+  bool list_mix;   // some periodic axis has fewer than 3 list cells
   bool have_embed, have_force;
 };
 
@@ -213,6 +214,7 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
   s->nrep = nrep;
   s->ws = nullptr;
   s->have_embed = s->have_force = false;
+  s->list_mix = false;
   const double rlist = p->eam.c + p->skin;
   const double rxlist = p->morse.rc + p->skin;
   int64_t a0 = 0, c0 = 0;
@@ -232,6 +234,7 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
       // spread to about twice the given extent along open axes (beyond that cells stretch)
       const int nb = cells_along(rd.len[a], rlist);
       d.gcap[a] = d.per[a] ? nb : std::max(2 * nb, nb + 8);
+      if (d.per[a] && nb < 3) s->list_mix = true;
       d.hd[a] = rd.n_c > 0 ? cells_along(rd.len[a], rxlist) : 1;
       // the minimum image must be the only image within the list radius
       if (d.per[a] && !(rd.len[a] > 2.0 * rlist)) { delete s; return MD_ERR_ARG; }
@@ -420,7 +423,10 @@ MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l
   k_scan<<<s->scan_blocks, BLOCK, 0, st>>>(A);
   k_scatter<<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A);
   k_sort_gather<<<(s->ncell_all + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, BLOCK, 0, st>>>(s->K, A);
-  k_list_rows<<<s->ntiles, BLOCK, 0, st>>>(s->K, A);
+  if (s->list_mix)
+    k_list_rows<false><<<s->ntiles, BLOCK, 0, st>>>(s->K, A);
+  else
+    k_list_rows<true><<<s->ntiles, BLOCK, 0, st>>>(s->K, A);
   k_xlist<<<A.near_blocks, BLOCK, 0, st>>>(s->K, A);
   return check_launch();
 }

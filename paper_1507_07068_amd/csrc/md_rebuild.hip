@@ -446,9 +446,10 @@ __global__ __launch_bounds__(BLOCK) void k_sort_gather(Consts K, BuildArgs A) {
 // (separation + 0 or -+ length: the same rounding as the minimum image for every pair
 // inside the list radius); along a periodic axis with fewer cells each cell is visited once
 // and the minimum image is taken pair by pair.
+template <bool SCREEN>
 __global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
   if (rebuild_off(A)) return;
-  const int T = K.lt, Ts = K.lt_shift;
+  const int T = K.lt;
   const int tile = blockIdx.x;
   const int r = A.tile_rep[tile];
   RepState& S = A.S[r];
@@ -471,22 +472,23 @@ __global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
     const int cz = cell_coord(pi.z, S.glo[2], S.ginv[2], gz);
     const int sbase = d.a0 - A.start[d.g0];   // sorted slot = sbase + start[cell]
     const double rl2 = K.rlist_sq;
-    const int64_t row = K.ntot * T;   // entry k at idx[(k / T) * row + k % T]
     const double4* __restrict__ tq = A.tq;
     const float4* __restrict__ tqf = A.tqf;
-    int* __restrict__ idx = A.idx + (int64_t)p * T;
-    // pairwise minimum image on periodic axes with fewer than 3 cells
-    const bool mx = d.per[0] && gx < 3, my = d.per[1] && gy < 3, mz = d.per[2] && gz < 3;
+    // entry k at idx[(k / T) * row + k % T]: wp walks the slots in entry order
+    const int64_t row = K.ntot * T;
+    int* __restrict__ wp = A.idx + (int64_t)p * T;
+    // pairwise minimum image on periodic axes with fewer than 3 cells (no FP32 screen then)
+    const bool mx = !SCREEN && d.per[0] && gx < 3, my = !SCREEN && d.per[1] && gy < 3,
+               mz = !SCREEN && d.per[2] && gz < 3;
     // FP32 screen: r2f, the squared separation from FP32 coordinates relative to the grid
     // origin, decides the pair when it lies outside [rl2 - delta, rl2 + delta); pairs inside
     // that band get the exact FP64 test.  With u = 2^-24, coordinates within E of the origin
     // and a periodic length L, each separation component carries an error of at most
     // eta = u (2E + 2L + 3R) for |component| <= R = r_list + 1, so |r2f - r2| <= sum over axes
     // of (2 R eta + eta^2) + 4 u (rl2 + R^2); delta is twice that.  Pairs farther than R
-    // apart are far outside the band.  Axes with a pairwise minimum image use FP64 only.
-    const bool screen = !(mx || my || mz);
+    // apart are far outside the band.
     float lo_f = 0.0f, hi_f = 0.0f;
-    {
+    if (SCREEN) {
       const double u = 0x1p-24, R = K.rlist + 1.0;
       const int g[3] = {gx, gy, gz};
       double err = 4.0 * u * (rl2 + R * R);
@@ -500,7 +502,7 @@ __global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
       lo_f = (float)(rl2 - delta);
       hi_f = (float)(rl2 + delta);
     }
-    const float4 pf = tqf[p];
+    const float4 pf = SCREEN ? tqf[p] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     // x segments (first cell, last cell, shift), the same for every row
     int xa0 = cx - 1, xb0 = cx + 1, xa1 = 0, xb1 = -1;
     double sh0 = 0.0, sh1 = 0.0;
@@ -521,6 +523,11 @@ __global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
     }
     const int nsy = stencil_n(gy, d.per[1]), nsz = stencil_n(gz, d.per[2]);
     int count = 0;
+    auto append = [&](int j) {
+      if (count < cap) *wp = j;
+      ++count;
+      wp += (count & (T - 1)) ? 1 : row - (T - 1);
+    };
     for (int rr = 0; rr < 9; ++rr) {
       const int tz = rr / 3, ty = rr % 3;
       if (tz >= nsz || ty >= nsy) continue;
@@ -535,8 +542,7 @@ __global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
         const int xa = sg ? xa1 : xa0, xb = sg ? xb1 : xb0;
         if (xb < xa) continue;
         const double shx = sg ? sh1 : sh0;
-        const float fx = (float)shx, fy = (float)shy, fz = (float)shz;
-        const int j1 = sbase + A.start[crow + xb + 1];
+        const int j0 = sbase + A.start[crow + xa], j1 = sbase + A.start[crow + xb + 1];
         auto exact = [&](int j) {
           const double4 pj = tq[j];
           double ex = pj.x - pi.x, ey = pj.y - pi.y, ez = pj.z - pi.z;
@@ -545,25 +551,28 @@ __global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
           ez = mz ? min_image(ez, d.len[2], d.half[2], 1) : ez + shz;
           return dist_sq_exact(ex, ey, ez) < rl2;
         };
-        auto test = [&](const float4& cf, int j) {
-          const float ex = (cf.x - pf.x) + fx, ey = (cf.y - pf.y) + fy, ez = (cf.z - pf.z) + fz;
-          const float r2f = ex * ex + ey * ey + ez * ez;
-          bool in = screen && r2f < lo_f;
-          if (!screen || (!in && !(r2f >= hi_f))) in = exact(j);
-          if (in && j != p) {
-            if (count < cap) idx[(count >> Ts) * row + (count & (T - 1))] = j;
-            ++count;
+        if (SCREEN) {
+          const float fx = (float)shx, fy = (float)shy, fz = (float)shz;
+          auto test = [&](const float4& cf, int j) {
+            const float ex = (cf.x - pf.x) + fx, ey = (cf.y - pf.y) + fy, ez = (cf.z - pf.z) + fz;
+            const float r2f = ex * ex + ey * ey + ez * ez;
+            bool in = r2f < lo_f;
+            if (__builtin_expect(!in && !(r2f >= hi_f), 0)) in = exact(j);   // band (or NaN)
+            if (in && j != p) append(j);
+          };
+          int j = j0;
+          for (; j + LIST_BATCH <= j1; j += LIST_BATCH) {   // LIST_BATCH loads in flight
+            float4 cf[LIST_BATCH];
+#pragma unroll
+            for (int u = 0; u < LIST_BATCH; ++u) cf[u] = tqf[j + u];
+#pragma unroll
+            for (int u = 0; u < LIST_BATCH; ++u) test(cf[u], j + u);
           }
-        };
-        int j = sbase + A.start[crow + xa];
-        for (; j + LIST_BATCH <= j1; j += LIST_BATCH) {   // LIST_BATCH loads in flight
-          float4 cf[LIST_BATCH];
-#pragma unroll
-          for (int u = 0; u < LIST_BATCH; ++u) cf[u] = tqf[j + u];
-#pragma unroll
-          for (int u = 0; u < LIST_BATCH; ++u) test(cf[u], j + u);
+          for (; j < j1; ++j) test(tqf[j], j);
+        } else {
+          for (int j = j0; j < j1; ++j)
+            if (j != p && exact(j)) append(j);
         }
-        for (; j < j1; ++j) test(tqf[j], j);
       }
     }
     A.cnt[p] = min(count, cap);
