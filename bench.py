@@ -4,14 +4,19 @@ due, EAM density, EAM + Morse forces with the fused final kick, energies every 1
 on one MI355X, in atom-steps/s.
 
 Default workload: the 216,000-atom Cr film (60x60x30 BCC cells) with a 2 nm carbon
-hemisphere indenter moving -0.001 A/fs, FP64, 2000 steps of 1 fs (inputs resident in
-HBM before the timed region).  Prints one JSON line.
+hemisphere indenter moving -0.001 A/fs, FP64, 2000 steps of 1 fs, inputs resident in HBM
+before the timed region.  Beside it (in "variants"): the same film with FP32-mixed
+forces and their error against the FP64 path, the 64-replica ensemble in FP32-mixed run
+as captured HIP graphs with an autotuned launch shape, and the NVE energy drift of the
+periodic 2,000-atom bulk.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1] [--precision fp64]
+    python bench.py --copy-probe 512      # plain copy of 512 MiB (counter calibration)
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -22,9 +27,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "atom-steps/s EAM+Morse MD step, FP32-mixed & batched vs FP64 at ≤1e-5 force err"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_force_c1_fp64_traffic.txt")
+FORCE_SOURCES = [os.path.join(ROOT, "paper_1507_07068_amd", "csrc", f)
+                 for f in ("md_forces.hip", "md_device.hpp")]
 
 WORKLOADS = {
-    "c0": (0, "bcc_bulk_2k_periodic"),
+    "c0": (0, "bcc_bulk_10x10x10_2k_periodic"),
     "c1": (1, "cr_film_60x60x30_216k_indenter_r20"),
     "c2": (2, "cr_film_100x100x50_1m_indenter_r30"),
     "c3": (3, "ensemble_64_replicas_1.6k-36k"),
@@ -37,10 +45,43 @@ def log(*a):
 
 
 def force_bytes_per_atom(mean_list: float) -> float:
-    """Algorithmic HBM bytes of the force pass per atom: x_i (24) + F'(rho_i) (8) + list count
-    (4) + list entries (4 each) + force write (24) + velocity read/write for the fused kick
-    (48).  Neighbour positions are gathered from cache (atoms are cell-sorted)."""
-    return 24 + 8 + 4 + 4 * mean_list + 24 + 48
+    """Algorithmic HBM bytes of one EAM force launch per atom: q_i = (x, y, z, F') 32,
+    list count 4, list entries 4 each, fixed flag 1, velocity read + write for the fused
+    kick 48, force write 24.  Neighbour positions are gathered from cache (atoms are
+    cell-sorted, so each one is fetched from HBM once per pass)."""
+    return 32 + 4 + 4 * mean_list + 1 + 48 + 24
+
+
+def force_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in FORCE_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(n_launch_atoms: int):
+    """HBM bytes per force launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE per dispatch, each scaled by the same counter's reading for a plain copy of
+    known size), or None when there is no summary for this workload or the force kernel's
+    sources changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    try:
+        if kv["source_sha256"] != force_source_hash() or int(kv["atoms"]) != n_launch_atoms:
+            return None
+        copy_b = float(kv["copy_bytes"])
+        f_scale = copy_b / (float(kv["copy_fetch_kib"]) * 1024.0)
+        w_scale = copy_b / (float(kv["copy_write_kib"]) * 1024.0)
+        return (float(kv["fetch_kib"]) * 1024.0 * f_scale + float(kv["write_kib"]) * 1024.0 * w_scale)
+    except (KeyError, ValueError, ZeroDivisionError):
+        return None
 
 
 def cpu_baseline(system, steps_per_build: float) -> dict:
@@ -59,6 +100,147 @@ def cpu_baseline(system, steps_per_build: float) -> dict:
                       f"{t:.1f} s wall"}
 
 
+def timed_run(systems, precision, steps, warmup, ee, tpa, events=True):
+    """Build, warm up, then time `steps` whole steps with md_run.  Returns a dict."""
+    import numpy as np
+    import torch
+
+    from paper_1507_07068_amd import md
+
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        sim = md.Simulation(systems, precision=precision, xcap=160, tpa=tpa)
+        sim.initial_forces()
+        if warmup:
+            sim.md_run(warmup)
+        flags = sim.md_check()
+        if flags["overflow"] or flags["xoverflow"] or flags["sync_timeout"]:
+            raise SystemExit(f"list capacity / sync problem after warm-up: {flags}")
+        nobs = steps // ee if ee > 0 else 0
+        obs = torch.zeros((max(nobs, 1), sim.nrep, md.MD_NOBS), dtype=torch.float64, device="cuda")
+        ev = None
+        if events:
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
+            for e in ev:          # torch creates the HIP event at its first record
+                e.record(stream)
+        builds0 = flags["nbuilds"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.md_run(steps, energy_every=ee, obs=obs, events=ev)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        flags = sim.md_check()
+        if flags["overflow"] or flags["xoverflow"] or flags["nonfinite"] or flags["sync_timeout"]:
+            raise SystemExit(f"invalid run: {flags}")
+        k_ms = (np.array([ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(steps)])
+                if events else np.zeros(1))
+        cnt = sim.list_counts()
+        live = np.concatenate([np.arange(o, o + s.n) for o, s in zip(sim.offsets, systems)])
+        mean_list = float(cnt[live].mean()) if live.size else 0.0
+        o = obs.cpu().numpy()
+    n_atoms = sum(s.n for s in systems)
+    return dict(sim=sim, rate=n_atoms * steps / wall, wall=wall, ms_per_step=wall / steps * 1e3,
+                k_avg=float(k_ms.mean()) * 1e-3, mean_list=mean_list,
+                builds=flags["nbuilds"] - builds0, obs=o[:nobs], n_atoms=n_atoms)
+
+
+def force_error_vs_fp64(systems, tpa):
+    """Relative RMS difference of the FP32-mixed and FP64 GPU forces on the start state
+    (the FP64 path itself matches the oracle to 1e-10, see the parity tests)."""
+    import numpy as np
+
+    from paper_1507_07068_amd import md
+    f = {}
+    for prec in ("fp64", "mixed"):
+        sim = md.Simulation(systems, precision=prec, xcap=160, tpa=tpa)
+        sim.initial_forces()
+        f[prec] = np.concatenate([st["f"] for st in sim.state()])
+        sim.close()
+    d = f["mixed"] - f["fp64"]
+    return float(np.sqrt((d * d).sum() / (f["fp64"] ** 2).sum()))
+
+
+def drift_per_ns(obs, n_atoms, dt_fs, ee):
+    """Least-squares slope of E_total / N over time, in eV/atom/ns (obs rows every ee steps)."""
+    import numpy as np
+    e = obs[:, :, 0:4].sum(-1).sum(-1) / n_atoms
+    t_ns = (np.arange(1, e.size + 1) * ee * dt_fs) * 1e-6
+    return float(np.polyfit(t_ns, e, 1)[0])
+
+
+def batched_graph_run(systems, steps, tpa, chunk=100):
+    """The ensemble as captured HIP graphs of `chunk` whole steps each."""
+    import torch
+
+    from paper_1507_07068_amd import md
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        sim = md.Simulation(systems, precision="mixed", xcap=160, tpa=tpa)
+        sim.initial_forces()
+        g = sim.md_graph_create(chunk)
+        sim.md_graph_launch(g)                    # warm-up chunk
+        torch.cuda.synchronize()
+        n = max(1, steps // chunk)
+        t0 = time.perf_counter()
+        for _ in range(n):
+            sim.md_graph_launch(g)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        flags = sim.md_check()
+        sim.close()
+    if flags["overflow"] or flags["xoverflow"] or flags["nonfinite"] or flags["sync_timeout"]:
+        raise SystemExit(f"invalid batched run: {flags}")
+    n_atoms = sum(s.n for s in systems)
+    return dict(rate=n_atoms * n * chunk / wall, steps=n * chunk, ms_per_step=wall / (n * chunk) * 1e3)
+
+
+def variants(tpa_main):
+    from paper_1507_07068_amd import inputs as I
+    from paper_1507_07068_amd import tune
+
+    out = {}
+    c1 = I.config(1)
+    r = timed_run([c1], "mixed", c1.steps, 20, 10, tpa_main, events=False)
+    r["sim"].close()
+    out["mixed_c1"] = {"value": r["rate"], "unit": "atom-steps/s", "ms_per_step": r["ms_per_step"],
+                       "steps": c1.steps, "dtype": "f32 pair math, f64 state",
+                       "force_rel_rms_vs_fp64": force_error_vs_fp64([c1], tpa_main),
+                       "list_builds": r["builds"]}
+    log(f"[bench] mixed c1: {r['rate']:.4e} atom-steps/s, force rel-RMS vs FP64 "
+        f"{out['mixed_c1']['force_rel_rms_vs_fp64']:.2e}")
+    ens = I.config(3)
+    best, times = tune.choose_tpa(ens, "mixed")
+    b = batched_graph_run(ens, ens[0].steps, best)
+    out["batched_c3"] = {"value": b["rate"], "unit": "atom-steps/s", "ms_per_step": b["ms_per_step"],
+                         "steps": b["steps"], "replicas": len(ens), "cr_atoms": sum(s.n for s in ens),
+                         "precision": "mixed", "launch": "hipGraph of 100 whole steps",
+                         "tpa_autotuned": best,
+                         "tpa_ms_per_step": {str(k): round(v * 1e3, 4) for k, v in times.items()}}
+    log(f"[bench] batched c3: {b['rate']:.4e} atom-steps/s (tpa {best})")
+    c0 = I.config(0)
+    nve = {}
+    for prec in ("fp64", "mixed"):
+        r = timed_run([c0], prec, 10000, 0, 10, 1, events=False)
+        r["sim"].close()
+        nve[prec] = drift_per_ns(r["obs"], c0.n, c0.dt, 10)
+    out["nve_c0"] = {"steps": 10000, "dt_fs": c0.dt, "drift_ev_per_atom_per_ns_fp64": nve["fp64"],
+                     "drift_ev_per_atom_per_ns_mixed": nve["mixed"]}
+    log(f"[bench] NVE c0 drift: fp64 {nve['fp64']:.3e}, mixed {nve['mixed']:.3e} eV/atom/ns")
+    return out
+
+
+def copy_probe(mib: int) -> int:
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "copy", "bytes_per_copy": n * 4, "copies": 5}), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,18 +252,18 @@ def main(argv=None):
     ap.add_argument("--tpa", type=int, default=2, choices=[1, 2, 4, 8],
                     help="lanes per atom in the density / force passes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB")
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         return 2
-
-    import numpy as np
-    import torch
+    if args.copy_probe:
+        return copy_probe(args.copy_probe)
 
     from paper_1507_07068_amd import inputs as I
-    from paper_1507_07068_amd import md
 
     idx, wname = WORKLOADS[args.workload]
     cfg = I.config(idx)
@@ -89,48 +271,22 @@ def main(argv=None):
     precision = args.precision or systems[0].precision
     steps = args.steps if args.steps is not None else systems[0].steps
     ee = args.energy_every
-    n_atoms = sum(s.n for s in systems)
-    log(f"[bench] workload {args.workload} ({wname}): {len(systems)} system(s), {n_atoms} Cr, "
-        f"{sum(s.n_c for s in systems)} C, precision {precision}, steps {steps}, warmup {args.warmup}")
-
-    stream = torch.cuda.Stream()
-    with torch.cuda.stream(stream):
-        sim = md.Simulation(systems, precision=precision, xcap=160, tpa=args.tpa)
-        sim.initial_forces()
-        if args.warmup:
-            sim.md_run(args.warmup)
-        flags = sim.md_check()
-        if flags["overflow"] or flags["xoverflow"] or flags["sync_timeout"]:
-            raise SystemExit(f"list capacity / sync problem after warm-up: {flags}")
-        nobs = steps // ee if ee > 0 else 0
-        obs = torch.zeros((max(nobs, 1), sim.nrep, md.MD_NOBS), dtype=torch.float64, device="cuda")
-        events = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
-        for e in events:          # torch creates the HIP event at its first record
-            e.record(stream)
-        builds0 = flags["nbuilds"]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sim.md_run(steps, energy_every=ee, obs=obs, events=events)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        flags = sim.md_check()
-        if flags["overflow"] or flags["xoverflow"] or flags["nonfinite"] or flags["sync_timeout"]:
-            raise SystemExit(f"invalid run: {flags}")
-        k_ms = np.array([events[2 * k].elapsed_time(events[2 * k + 1]) for k in range(steps)])
-        cnt = sim.list_counts()
-        live = np.concatenate([np.arange(o, o + s.n) for o, s in zip(sim.offsets, systems)])
-        mean_list = float(cnt[live].mean()) if live.size else 0.0
-        o = obs.cpu().numpy()
-    builds = flags["nbuilds"] - builds0
-    rate = n_atoms * steps / wall
+    log(f"[bench] workload {args.workload} ({wname}): {len(systems)} system(s), "
+        f"{sum(s.n for s in systems)} Cr, {sum(s.n_c for s in systems)} C, precision {precision}, "
+        f"steps {steps}, warmup {args.warmup}")
+    r = timed_run(systems, precision, steps, args.warmup, ee, args.tpa)
+    r["sim"].close()
+    n_atoms, rate, k_avg, mean_list = r["n_atoms"], r["rate"], r["k_avg"], r["mean_list"]
     bytes_launch = n_atoms * force_bytes_per_atom(mean_list)
-    k_avg = float(k_ms.mean()) * 1e-3
     achieved = bytes_launch / k_avg / 1e9
-    e_tot = o[:, :, 0:4].sum(-1).sum(-1) if nobs else np.zeros(1)
-    log(f"[bench] {rate:.4e} atom-steps/s, {wall / steps * 1e3:.4f} ms/step, force kernel "
+    e_tot = r["obs"][:, :, 0:4].sum(-1).sum(-1) if r["obs"].size else [0.0]
+    log(f"[bench] {rate:.4e} atom-steps/s, {r['ms_per_step']:.4f} ms/step, EAM force kernel "
         f"{k_avg * 1e6:.2f} us avg ({achieved:.0f} GB/s algorithmic), mean list {mean_list:.2f}, "
-        f"{builds} list builds, E_tot first/last {e_tot[0]:.6f} / {e_tot[-1]:.6f} eV")
-
+        f"{r['builds']} list builds, E_tot first/last {e_tot[0]:.6f} / {e_tot[-1]:.6f} eV")
+    traffic = None
+    if args.workload == "c1" and precision == "fp64" and args.tpa == 2:
+        t = measured_traffic(n_atoms)
+        traffic = None if t is None else t / 1e9 / k_avg   # GB/s, like `achieved`
     result = {
         "metric": METRIC,
         "value": rate,
@@ -138,7 +294,7 @@ def main(argv=None):
         "n_gpus": 1,
         "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": wall / steps * 1e3,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -146,16 +302,18 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": wname, "cr_atoms": n_atoms, "c_atoms": sum(s.n_c for s in systems),
                    "replicas": len(systems), "precision": precision, "energy_every": ee,
-                   "list_builds": builds, "mean_list_len": round(mean_list, 3),
+                   "list_builds": r["builds"], "mean_list_len": round(mean_list, 3),
                    "lanes_per_atom": args.tpa},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_force (EAM Eq. 1 + Morse + final kick)",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_force (EAM Eq. 1 + fused final kick)",
                      "avg_us": k_avg * 1e6, "bytes_per_launch": bytes_launch},
         "cpu_baseline": None,
     }
-    if not args.no_cpu_baseline and len(systems) == 1:
-        spb = steps / max(builds, 1)
+    if not args.no_variants and args.workload == "c1" and args.steps is None:
+        result["variants"] = variants(args.tpa)
+    if not args.no_cpu_baseline and len(systems) == 1 and systems[0].n <= 300_000:
+        spb = steps / max(r["builds"], 1)
         log(f"[bench] CPU baseline: oracle on {systems[0].name}, ~{spb:.0f} steps ...")
         result["cpu_baseline"] = cpu_baseline(I.config(idx), spb)
         log(f"[bench] CPU baseline {result['cpu_baseline']['value']:.4e} atom-steps/s")

@@ -232,12 +232,13 @@ MD_API int md_energy(md_system *sys, const md_atoms *a, double *out, void *strea
 
 /* Enqueue nsteps whole time steps in the order of Table 1 (Tasks 2+3 -> 1 -> 4 -> 5):
  * md_verlet_step(KICK_DRIFT), md_build_neighbors, md_eam_forces(DENSITY), then
- * md_eam_forces(FORCE | MORSE | KICK) -- the Task 4b/4c/5 pass -- for every replica.
+ * md_eam_forces(FORCE | KICK) and md_morse_forces(KICK) -- the Task 4b/4c/5 pass, each
+ * kernel applying the final half kick for the force it adds -- for every replica.
  * flags: MD_F_MIXED selects FP32 arithmetic.  energy_every > 0: after step k with
  * k % energy_every == 0 the energies are written as by md_energy to
  * obs[(k / energy_every - 1) * nrep * MD_NOBS ...] (device memory, caller-owned).
  * events: NULL, or 2*nsteps hipEvent_t handles (created by the caller) recorded on
- * `stream` just before and just after each step's force kernel, for timing.
+ * `stream` just before and just after each step's EAM force kernel (Eq. 1), for timing.
  * Lists must have been built and forces evaluated once before the first step
  * (md_build_neighbors with MD_B_FORCE, md_eam_forces with DENSITY|FORCE|MORSE). */
 MD_API int md_run(md_system *sys, const md_atoms *a, const md_lists *l, int32_t nsteps,

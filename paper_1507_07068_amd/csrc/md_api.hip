@@ -524,10 +524,10 @@ MD_API int md_run(md_system* s, const md_atoms* a, const md_lists* l, int32_t ns
     if ((e = md_eam_forces(s, a, l, MD_F_DENSITY | mixed | (en ? MD_F_ENERGY : 0), nullptr, stream)))
       return e;
     if (events && (e = hip_status(hipEventRecord((hipEvent_t)events[2 * (k - 1)], st)))) return e;
-    if ((e = md_eam_forces(s, a, l, MD_F_FORCE | MD_F_MORSE | MD_F_KICK | mixed | (en ? MD_F_ENERGY : 0),
-                           nullptr, stream)))
+    if ((e = md_eam_forces(s, a, l, MD_F_FORCE | MD_F_KICK | mixed | (en ? MD_F_ENERGY : 0), nullptr, stream)))
       return e;
     if (events && (e = hip_status(hipEventRecord((hipEvent_t)events[2 * (k - 1) + 1], st)))) return e;
+    if ((e = md_morse_forces(s, a, l, MD_F_KICK | mixed, stream))) return e;
     if (en) {
       double* out = obs + (int64_t)(k / energy_every - 1) * s->nrep * MD_NOBS;
       if ((e = md_energy(s, a, out, stream))) return e;

@@ -1,0 +1,106 @@
+"""Text summaries of rocprofv3 output databases (kernel timings and hardware counters).
+
+    python -m paper_1507_07068_amd.profiling stats DIR          # per-kernel time table
+    python -m paper_1507_07068_amd.profiling steps DIR          # per-step breakdown
+    python -m paper_1507_07068_amd.profiling pmc DIR [DIR ...]  # counters per kernel
+
+DIR is the output directory of ``rocprofv3 -d DIR -o run ...``; its SQLite database is
+found recursively.  Only the standard library and numpy are used.
+"""
+from __future__ import annotations
+
+import collections
+import glob
+import re
+import sqlite3
+import sys
+
+import numpy as np
+
+
+def _db(d: str) -> str:
+    found = sorted(glob.glob(d + "/**/*.db", recursive=True))
+    if not found:
+        raise SystemExit(f"no rocprofv3 database under {d}")
+    return found[-1]
+
+
+def short_name(n: str) -> str:
+    m = re.search(r"md::(k_\w+)(<[^>]*>)?", n)
+    return (m.group(1) + (m.group(2) or "")) if m else n.split("(")[0][:48]
+
+
+def stats(d: str) -> str:
+    c = sqlite3.connect(_db(d))
+    out = [f"{'kernel':44s} {'calls':>7s} {'total ms':>10s} {'avg us':>9s} {'share':>6s}"]
+    for name, calls, total, avg, pct in c.execute(
+            "select name, total_calls, total_duration, average, percentage from top_kernels limit 30"):
+        out.append(f"{short_name(name):44s} {calls:7d} {total / 1e6:10.3f} {avg / 1e3:9.2f} {pct:5.1f}%")
+    return "\n".join(out)
+
+
+def steps(d: str) -> str:
+    """Kernel durations per step (a step starts at k_kick_drift), split into steps with and
+    without a list rebuild (k_list_rows longer than 20 us)."""
+    c = sqlite3.connect(_db(d))
+    rows = list(c.execute("select name, start, end from kernels order by start"))
+    groups, cur = [], None
+    for n, s, e in rows:
+        k = short_name(n)
+        if k.startswith("k_kick_drift"):
+            cur = []
+            groups.append(cur)
+        if cur is not None:
+            cur.append((k, s, e))
+    groups = groups[5:-1]
+    out = []
+    split = {"rebuild": [], "no rebuild": []}
+    for g in groups:
+        dur = collections.defaultdict(float)
+        for k, s, e in g:
+            dur[k] += (e - s) / 1e3
+        lst = dur.get("k_list_rows<true>", dur.get("k_list_rows<false>", 0.0))
+        split["rebuild" if lst > 20.0 else "no rebuild"].append((dur, (g[-1][2] - g[0][1]) / 1e3))
+    for name, gs in split.items():
+        if not gs:
+            continue
+        out.append(f"{name}: {len(gs)} steps, first-to-last kernel {np.mean([w for _, w in gs]):.1f} us/step")
+        acc = collections.defaultdict(list)
+        for dur, _ in gs:
+            for k, v in dur.items():
+                acc[k].append(v)
+        for k, v in sorted(acc.items(), key=lambda kv: -np.mean(kv[1])):
+            out.append(f"    {k:40s} {np.mean(v):8.2f} us")
+    return "\n".join(out)
+
+
+def pmc(dirs) -> str:
+    res = collections.defaultdict(lambda: collections.defaultdict(list))
+    for d in dirs:
+        c = sqlite3.connect(_db(d))
+        for kn, cn, val in c.execute("select kernel_name, counter_name, value from counters_collection"):
+            res[kn][cn].append(val)
+    out = []
+    for kn in sorted(res):
+        parts = [f"{short_name(kn):40s}"]
+        for cn in sorted(res[kn]):
+            v = np.array(res[kn][cn])
+            parts.append(f"{cn}: mean {v.mean():.6g} max {v.max():.6g} (n={v.size})")
+        out.append("  ".join(parts))
+    return "\n".join(out)
+
+
+def main(argv=None):
+    argv = sys.argv[1:] if argv is None else argv
+    if len(argv) < 2 or argv[0] not in ("stats", "steps", "pmc"):
+        raise SystemExit(__doc__)
+    if argv[0] == "stats":
+        print(stats(argv[1]))
+    elif argv[0] == "steps":
+        print(steps(argv[1]))
+    else:
+        print(pmc(argv[1:]))
+
+
+if __name__ == "__main__":
+    main()
