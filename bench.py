@@ -283,10 +283,9 @@ def main(argv=None):
     log(f"[bench] {rate:.4e} atom-steps/s, {r['ms_per_step']:.4f} ms/step, EAM force kernel "
         f"{k_avg * 1e6:.2f} us avg ({achieved:.0f} GB/s algorithmic), mean list {mean_list:.2f}, "
         f"{r['builds']} list builds, E_tot first/last {e_tot[0]:.6f} / {e_tot[-1]:.6f} eV")
-    traffic = None
+    traffic = None   # measured HBM bytes per launch (compare with bytes_per_launch)
     if args.workload == "c1" and precision == "fp64" and args.tpa == 2:
-        t = measured_traffic(n_atoms)
-        traffic = None if t is None else t / 1e9 / k_avg   # GB/s, like `achieved`
+        traffic = measured_traffic(n_atoms)
     result = {
         "metric": METRIC,
         "value": rate,

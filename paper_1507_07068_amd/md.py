@@ -391,32 +391,39 @@ class Simulation:
                             ids=ids[slots], slots=slots))
         return out
 
-    def neighbor_sets(self, r: int = 0, cross: bool = False) -> list:
-        """Neighbour sets of replica r in id space: [sorted ids of neighbours of id 0, ...]."""
+    def neighbor_sets(self, r: int = 0, cross: bool = False, only=None) -> list:
+        """Neighbour sets of replica r in id space: [sorted ids of neighbours of id 0, ...]
+        (entries for the ids in `only` alone when given, None for the others)."""
         ids = self.id.cpu().numpy()
         cnt = (self.xcnt if cross else self.cnt).cpu().numpy()
         s = self.systems[r]
         a0 = self.offsets[r]
         sets = [None] * s.n
+        slots = np.arange(a0, a0 + s.n)
+        if only is not None:
+            want = np.zeros(s.n, bool)
+            want[np.asarray(only, dtype=np.int64)] = True
+            slots = slots[want[ids[a0:a0 + s.n]]]
         if cross:
             xidx = self.xidx.cpu().numpy()
             c0 = sum(t.n_c for t in self.systems[:r])
-            for p in range(a0, a0 + s.n):
+            for p in slots:
                 sets[ids[p]] = sorted((xidx[p, :cnt[p]] - c0).tolist())
             return sets
-        lists = self.list_rows()
-        for p in range(a0, a0 + s.n):
-            sets[ids[p]] = sorted(ids[lists[p]].tolist())
+        lists = self.list_rows(slots)
+        for p, row in zip(slots, lists):
+            sets[ids[p]] = sorted(ids[row].tolist())
         return sets
 
-    def list_rows(self) -> list:
-        """Cr-Cr list of every atom slot (slots of its neighbours, in list order)."""
+    def list_rows(self, slots=None) -> list:
+        """Cr-Cr list of every atom slot, or of the given slots (slots of the neighbours, in
+        list order)."""
         T, n = self.tpa, self.ntot
         idx = self.idx.cpu().numpy()
         cnt = self.cnt.cpu().numpy()
         k = np.arange(self.cap)
         rows = []
-        for p in range(n):
+        for p in (range(n) if slots is None else slots):
             kk = k[:cnt[p]]
             rows.append(idx[(kk // T) * n * T + p * T + kk % T])
         return rows

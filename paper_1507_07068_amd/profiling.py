@@ -35,7 +35,8 @@ def stats(d: str) -> str:
     out = [f"{'kernel':44s} {'calls':>7s} {'total ms':>10s} {'avg us':>9s} {'share':>6s}"]
     for name, calls, total, avg, pct in c.execute(
             "select name, total_calls, total_duration, average, percentage from top_kernels limit 30"):
-        out.append(f"{short_name(name):44s} {calls:7d} {total / 1e6:10.3f} {avg / 1e3:9.2f} {pct:5.1f}%")
+        # the summary table holds durations in microseconds
+        out.append(f"{short_name(name):44s} {calls:7d} {total / 1e3:10.3f} {avg:9.2f} {pct:5.1f}%")
     return "\n".join(out)
 
 

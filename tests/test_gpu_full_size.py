@@ -1,0 +1,138 @@
+"""Parity at the full benchmark sizes, in the launch shape bench.py times (two lanes per
+atom): outputs the oracle can compute one atom at a time (neighbour sets and forces of
+sampled atoms, from all-atom loops), and after a stretch of whole steps the properties
+that hold at any size (list symmetry and completeness, force balance).  The sampled
+atoms come from a seeded draw plus the atoms nearest the indenter and fixed atoms."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1507_07068_amd import inputs as I
+from paper_1507_07068_amd import md
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-5
+
+
+def sample_rows(s, n_random, seed):
+    rng = np.random.default_rng(seed)
+    rows = set(rng.choice(s.n, size=min(n_random, s.n), replace=False).tolist())
+    if s.n_c:
+        # atoms nearest the lowest carbon: they carry Morse forces
+        tip = s.xc[np.argmin(s.xc[:, 2])]
+        d = s.x - tip
+        rows |= set(np.argsort(np.einsum("ij,ij->i", d, d))[:32].tolist())
+    fixed = np.flatnonzero(s.fixed)
+    if fixed.size:
+        rows |= set(fixed[:: max(1, fixed.size // 8)][:8].tolist())
+    return np.array(sorted(rows), dtype=np.int64)
+
+
+def rel_errors(f, ref):
+    diff = np.sqrt(np.sum((f - ref) ** 2, axis=1))
+    rms = np.sqrt(np.mean(np.sum(ref ** 2, axis=1)))
+    return np.sqrt(np.sum(diff ** 2) / np.sum(ref ** 2)), diff.max() / rms
+
+
+def check_sampled(sim, r, s, rows, tol, lists=True):
+    """Replica r of sim at its start state against the oracle for the sampled atoms."""
+    print(f"[case] {s.name} n={s.n} sample={rows.size} precision={sim.precision} tpa={sim.tpa}",
+          flush=True)
+    xw = O.wrap(s)
+    st = sim.state()[r]
+    assert np.array_equal(st["x"], xw), "wrapped positions differ"
+    if lists:
+        got = sim.neighbor_sets(r, only=rows)
+        cnt, idx = O.neighbors(s, s.r_list, x=xw, rows=rows, cap=256)
+        for t, i in enumerate(rows):
+            assert got[i] == idx[t, :cnt[t]].tolist(), i
+        if s.n_c:
+            got = sim.neighbor_sets(r, cross=True, only=rows)
+            cnt, idx = O.cross_neighbors(s, s.r_list_cross, x=xw, rows=rows, cap=512)
+            for t, i in enumerate(rows):
+                assert got[i] == idx[t, :cnt[t]].tolist(), i
+    f, rho, dF, fm = O.sample_forces(s, rows, x=xw)
+    rel, mx = rel_errors(st["f"][rows], f)
+    print(f"  sampled force rel-RMS {rel:.3e} max/RMS {mx:.3e}", flush=True)
+    assert rel <= tol and mx <= tol * (10 if tol > FP64_TOL else 1), (rel, mx)
+    if sim.precision == "fp64":
+        assert np.allclose(st["dF"][rows], dF, rtol=1e-12, atol=0)
+
+
+def check_properties(sim, s, r=0, n_check=256, seed=5):
+    """Right after a build: every listed pair is within the list radius, the list is
+    symmetric, sampled atoms miss no neighbour, and the forces balance the indenter load."""
+    st = sim.state()[r]
+    x, slots = st["x"], st["slots"]
+    ids = sim.id.cpu().numpy()
+    cnt = sim.list_counts()
+    lists = sim.list_rows(slots)
+    per = np.asarray(s.periodic, bool)
+    L = s.box_len
+    rl2 = s.r_list ** 2
+    nbr = [np.sort(ids[row]) for row in lists]
+    # symmetry: j in list(i) <=> i in list(j), as sorted pair keys
+    i_of = np.repeat(np.arange(s.n, dtype=np.int64), [a.size for a in nbr])
+    j_of = np.concatenate(nbr).astype(np.int64)
+    fwd = np.sort(i_of * s.n + j_of)
+    assert np.array_equal(fwd, np.sort(j_of * s.n + i_of))
+    rng = np.random.default_rng(seed)
+    for i in rng.choice(s.n, size=min(n_check, s.n), replace=False):
+        d = x - x[i]
+        d[:, per] -= L[per] * np.round(d[:, per] / L[per])
+        r2 = np.einsum("ij,ij->i", d, d)
+        listed = set(nbr[i].tolist())
+        want = np.flatnonzero(r2 < rl2 * (1 - 1e-12))
+        assert set(want[want != i].tolist()) <= listed, i
+        assert not (set(np.flatnonzero(r2 >= rl2 * (1 + 1e-12)).tolist()) & listed), i
+    assert cnt.max() <= sim.cap
+    # force balance: EAM forces sum to zero, so the Cr total is the Morse total = -load
+    obs = sim.md_energy()[r]
+    ftot = st["f"].sum(axis=0)
+    scale = np.sqrt(np.sum(st["f"] ** 2))
+    assert np.all(np.abs(ftot + obs[10:13]) <= 1e-9 * scale), (ftot, obs[10:13])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_c1_film_216k_sampled_then_run(precision):
+    s = I.config(1)
+    rows = sample_rows(s, 192, 11)
+    sim = md.Simulation(s, precision=precision, xcap=160, tpa=2)
+    sim.initial_forces()
+    check_sampled(sim, 0, s, rows, FP64_TOL if precision == "fp64" else MIXED_TOL)
+    sim.md_run(100)
+    flags = sim.md_check()
+    assert not (flags["overflow"] or flags["xoverflow"] or flags["nonfinite"] or flags["sync_timeout"]), flags
+    assert flags["nbuilds"] > 1
+    if precision == "fp64":
+        sim.md_build_neighbors(force=True)
+        sim.md_eam_forces(md.MD_F_DENSITY | md.MD_F_FORCE | md.MD_F_MORSE | md.MD_F_ENERGY)
+        check_properties(sim, s)
+
+
+def test_c3_ensemble_sampled_replicas():
+    ens = I.config(3)
+    sim = md.Simulation(ens, precision="mixed", xcap=160, tpa=2)
+    sim.initial_forces()
+    for r in (0, 31, 63):
+        check_sampled(sim, r, ens[r], sample_rows(ens[r], 48, 100 + r), MIXED_TOL, lists=(r == 0))
+    sim.md_run(50)
+    flags = sim.md_check()
+    assert not (flags["overflow"] or flags["xoverflow"] or flags["nonfinite"] or flags["sync_timeout"]), flags
+
+
+@pytest.mark.parametrize("index,n_random", [(2, 48), (4, 24)])
+def test_large_films_sampled(index, n_random):
+    s = I.config(index)
+    rows = sample_rows(s, n_random, 7 + index)
+    for precision in ("mixed", "fp64"):
+        sim = md.Simulation(s, precision=precision, xcap=160, tpa=2)
+        sim.initial_forces()
+        check_sampled(sim, 0, s, rows, FP64_TOL if precision == "fp64" else MIXED_TOL,
+                      lists=(precision == "fp64"))
+        sim.md_run(20)
+        flags = sim.md_check()
+        assert not (flags["overflow"] or flags["xoverflow"] or flags["nonfinite"] or flags["sync_timeout"]), flags
+        sim.close()
