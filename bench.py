@@ -175,7 +175,9 @@ def batched_graph_run(systems, steps, tpa, chunk=100):
     from paper_1507_07068_amd import md
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        sim = md.Simulation(systems, precision="mixed", xcap=160, tpa=tpa)
+        # small replicas can hold an indenter wider than their periodic box, whose
+        # overlapping images crowd the Cr-C lists: give those lists more room
+        sim = md.Simulation(systems, precision="mixed", xcap=256, tpa=tpa)
         sim.initial_forces()
         g = sim.md_graph_create(chunk)
         sim.md_graph_launch(g)                    # warm-up chunk

@@ -417,7 +417,7 @@ MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l
   const int cblocks = (int)((s->ctot + BLOCK - 1) / BLOCK);
   if (flags & MD_B_FORCE)
     k_tile_box<<<s->ntiles, BLOCK, 0, st>>>(A.R, A.tile_rep, A.q, at<double>(s, s->L.tbox));
-  k_decide<<<1, BLOCK, 0, st>>>(s->K, A, at<double>(s, s->L.dmax), at<double>(s, s->L.tbox),
+  k_decide<<<1, DECIDE_THREADS, 0, st>>>(s->K, A, at<double>(s, s->L.dmax), at<double>(s, s->L.tbox),
                                 (flags & MD_B_FORCE) ? 1 : 0);
   k_bin<<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A);
   k_scan<<<s->scan_blocks, BLOCK, 0, st>>>(A);

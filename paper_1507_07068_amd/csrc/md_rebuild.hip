@@ -1,7 +1,7 @@
 // Task 1 of the MD step on gfx950: skin test and Verlet-list rebuild.  Included by
 // md_kernels.hip.
 //
-//   k_decide        one block: per-replica skin test (Section 2.6) -> rebuild flags
+//   k_decide        one block, a wavefront per replica: skin test (Section 2.6) -> rebuild flags
 //   k_bin           wrap periodic coordinates, cell of every atom / carbon, cell counts
 //   k_scan          exclusive scan of all cell counts (one pass, decoupled look-back)
 //   k_scatter       atom slots / carbon indices into their cells at the ranks k_bin took
@@ -81,58 +81,81 @@ constexpr int WAVES_PER_BLOCK = BLOCK / WAVE;
 
 __device__ __forceinline__ bool rebuild_off(const BuildArgs& A) { return *A.any == 0; }
 
-__global__ __launch_bounds__(BLOCK) void k_decide(Consts K, BuildArgs A, const double* __restrict__ dmax_tile,
-                                                  const double* __restrict__ tile_box, int force) {
-  __shared__ int any_sh, need_sh;
+// One block of DECIDE_THREADS decides every replica (skin test, then the cell grid of the
+// build) and ORs the outcomes into the launch-wide flag: the whole block per replica when
+// there are few, else one wavefront per replica (wavefront w takes replicas w, w + 16, ...).
+constexpr int DECIDE_THREADS = 1024;
+constexpr int DECIDE_BLOCKWIDE = 4;   // replicas up to which the whole block takes each one
+
+// Per-replica part of k_decide.  Reduce(v, op) reduces over the threads that share the
+// replica (a wavefront or the block); `lead` marks the thread that writes.
+template <class MaxReduce>
+__device__ __forceinline__ bool decide_replica(const Consts& K, BuildArgs& A, int r, const double* dmax_tile,
+                                               const double* tile_box, int force, int t0, int tstep,
+                                               bool lead, MaxReduce maxr) {
+  const RepDesc& d = A.R[r];
+  RepState& s = A.S[r];
+  double m = 0.0;
+  for (int t = t0; t < d.nt; t += tstep) m = fmax(m, dmax_tile[d.t0 + t]);
+  m = maxr(m);
+  const int need = force || (m > K.half_skin_sq) || (fabs(s.ind_z - s.ind_z_ref) > K.half_skin);
+  if (lead) {
+    s.rebuild = need;
+    if (need) s.nnear = 0;
+  }
+  if (!need) return false;   // uniform over the threads of the replica
+  // cell grid of this build: the box along periodic axes, the atoms' extent along open ones
+  for (int a = 0; a < 3; ++a) {
+    if (d.per[a]) {
+      if (lead) {
+        s.glo[a] = d.lo[a];
+        s.ginv[a] = d.ginv[a];
+        s.gd[a] = d.gcap[a];
+      }
+      continue;
+    }
+    double mn = INFINITY, mx = -INFINITY;
+    for (int t = t0; t < d.nt; t += tstep) {
+      mn = fmin(mn, tile_box[6 * (int64_t)(d.t0 + t) + a]);
+      mx = fmax(mx, tile_box[6 * (int64_t)(d.t0 + t) + 3 + a]);
+    }
+    mn = -maxr(-mn);
+    mx = maxr(mx);
+    if (lead) {
+      if (!(mn <= mx)) {   // no atoms (or non-finite positions): fall back to the box
+        mn = d.lo[a];
+        mx = d.lo[a] + d.len[a];
+      }
+      const double edge = K.rlist * (1.0 + 1e-9);
+      const double ext = fmax(mx - mn, edge);
+      const int g = (int)fmin(fmax(floor(ext / edge), 1.0), (double)d.gcap[a]);
+      s.glo[a] = mn;
+      s.ginv[a] = g / ext;
+      s.gd[a] = g;
+    }
+  }
+  return true;
+}
+
+__global__ __launch_bounds__(DECIDE_THREADS) void k_decide(Consts K, BuildArgs A,
+                                                           const double* __restrict__ dmax_tile,
+                                                           const double* __restrict__ tile_box, int force) {
+  __shared__ int any_sh;
   if (threadIdx.x == 0) any_sh = 0;
   __syncthreads();
-  for (int r = 0; r < K.nrep; ++r) {
-    const RepDesc& d = A.R[r];
-    double m = 0.0;
-    for (int t = threadIdx.x; t < d.nt; t += BLOCK) m = fmax(m, dmax_tile[d.t0 + t]);
-    m = block_max<BLOCK>(m);
-    if (threadIdx.x == 0) {
-      RepState& s = A.S[r];
-      const int need = force || (m > K.half_skin_sq) || (fabs(s.ind_z - s.ind_z_ref) > K.half_skin);
-      s.rebuild = need;
-      need_sh = need;
-      if (need) {
-        s.nnear = 0;
-        any_sh = 1;
-      }
+  if (K.nrep <= DECIDE_BLOCKWIDE) {
+    for (int r = 0; r < K.nrep; ++r) {
+      const bool need = decide_replica(K, A, r, dmax_tile, tile_box, force, threadIdx.x, DECIDE_THREADS,
+                                       threadIdx.x == 0, [](double v) { return block_max<DECIDE_THREADS>(v); });
+      if (need && threadIdx.x == 0) any_sh = 1;
     }
-    __syncthreads();
-    if (!need_sh) continue;   // uniform: read after the barrier
-    // cell grid of this build: the box along periodic axes, the atoms' extent along open ones
-    for (int a = 0; a < 3; ++a) {
-      RepState& s = A.S[r];
-      if (d.per[a]) {
-        if (threadIdx.x == 0) {
-          s.glo[a] = d.lo[a];
-          s.ginv[a] = d.ginv[a];
-          s.gd[a] = d.gcap[a];
-        }
-        continue;
-      }
-      double mn = INFINITY, mx = -INFINITY;
-      for (int t = threadIdx.x; t < d.nt; t += BLOCK) {
-        mn = fmin(mn, tile_box[6 * (int64_t)(d.t0 + t) + a]);
-        mx = fmax(mx, tile_box[6 * (int64_t)(d.t0 + t) + 3 + a]);
-      }
-      mn = -block_max<BLOCK>(-mn);
-      mx = block_max<BLOCK>(mx);
-      if (threadIdx.x == 0) {
-        if (!(mn <= mx)) {   // no atoms (or non-finite positions): fall back to the box
-          mn = d.lo[a];
-          mx = d.lo[a] + d.len[a];
-        }
-        const double edge = K.rlist * (1.0 + 1e-9);
-        const double ext = fmax(mx - mn, edge);
-        const int g = (int)fmin(fmax(floor(ext / edge), 1.0), (double)d.gcap[a]);
-        s.glo[a] = mn;
-        s.ginv[a] = g / ext;
-        s.gd[a] = g;
-      }
+  } else {
+    const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+    constexpr int NW = DECIDE_THREADS / WAVE;
+    for (int r = w; r < K.nrep; r += NW) {
+      const bool need = decide_replica(K, A, r, dmax_tile, tile_box, force, lane, WAVE, lane == 0,
+                                       [](double v) { return wave_max(v); });
+      if (need && lane == 0) atomicOr(&any_sh, 1);
     }
   }
   __syncthreads();

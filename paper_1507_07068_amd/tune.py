@@ -34,7 +34,7 @@ def choose_tpa(systems, precision: str, candidates=(1, 2, 4, 8), steps: int = 40
     st = stream or torch.cuda.current_stream()
     with torch.cuda.stream(st):
         for t in candidates:
-            sim = md.Simulation(systems, precision=precision, tpa=t)
+            sim = md.Simulation(systems, precision=precision, xcap=256, tpa=t)
             sim.initial_forces(energy=False)
             sim.md_run(warmup)
             torch.cuda.synchronize()
