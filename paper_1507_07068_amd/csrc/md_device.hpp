@@ -205,6 +205,40 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Work items spread over replicas (e.g. each replica's near atoms), flattened into one index
+// space so that every wavefront of a launch gets the same share whatever the replica sizes:
+// pre[r] = items of replicas before r (a block-wide scan into shared memory, called by the
+// whole block), and item g belongs to the replica r with pre[r] <= g < pre[r + 1].
+constexpr int FLAT_MAXREP = 2048;
+
+template <class Count>
+__device__ int flat_prefix(int nrep, int* pre, Count count) {
+  int carry = 0;
+  for (int r0 = 0; r0 < nrep; r0 += BLOCK) {
+    const int r = r0 + threadIdx.x;
+    const int c = r < nrep ? count(r) : 0;
+    int tot;
+    const int ex = block_exclusive_scan(c, &tot);
+    if (r < nrep) pre[r] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) pre[nrep] = carry;
+  __syncthreads();
+  return carry;
+}
+
+__device__ __forceinline__ int flat_replica(const int* pre, int nrep, int g) {
+  int lo = 0, hi = nrep - 1;   // the largest r with pre[r] <= g (empty replicas are skipped)
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= g)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
 // Slot of entry k of atom i in the Cr-Cr list (interleave T: entries k..k+T-1 of one atom
 // are adjacent, so T lanes of one atom read consecutive words).
 __device__ __forceinline__ int list_pos(int k, int i, int ntot, int T, int Tshift) {

@@ -247,8 +247,8 @@ __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __rest
 }
 
 // Task 4c: Cr-C Morse forces, F_i += -phiM'(r) (q_i - q_k)/r over atom i's Cr-C list,
-// added into f (and, with KICK, their half kick into v).  One wavefront per atom of each
-// replica's near list (grid-stride); the 64 lanes share that atom's carbons and combine
+// added into f (and, with KICK, their half kick into v).  One wavefront per atom of the
+// replicas' near lists (grid-stride over all of them); the 64 lanes share that atom's carbons and combine
 // their sums with a fixed butterfly.  fme[i] receives (F_i, E_i) of the atom for the
 // energy pass, which sums it in atom order.
 template <bool MIXED, bool KICK>
@@ -264,11 +264,10 @@ __global__ __launch_bounds__(BLOCK) void k_morse(Consts K, const RepDesc* __rest
                                                  double* __restrict__ fme) {
   const int lane = threadIdx.x % WAVE;
   const int gw = blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE, nw = gridDim.x * (BLOCK / WAVE);
-  for (int r = 0; r < K.nrep; ++r) {
+  auto one = [&](int r, int item) {   // near atom `item` of replica r, on this wavefront
     const RepDesc& d = R[r];
-    const int nnear = S[r].nnear;
     const double iz = S[r].ind_z;
-    for (int item = gw; item < nnear; item += nw) {
+    {
       const int64_t pa = near[d.a0 + item];
       const int na = xcnt[pa];
       const double4 pi = q[pa];
@@ -326,6 +325,17 @@ __global__ __launch_bounds__(BLOCK) void k_morse(Consts K, const RepDesc* __rest
         fme[4 * pa + 3] = em;
       }
     }
+  };
+  __shared__ int pre[FLAT_MAXREP + 1];
+  if (K.nrep <= FLAT_MAXREP) {
+    const int total = flat_prefix(K.nrep, pre, [&](int r) { return S[r].nnear; });
+    for (int g = gw; g < total; g += nw) {
+      const int r = flat_replica(pre, K.nrep, g);
+      one(r, g - pre[r]);
+    }
+  } else {
+    for (int r = 0; r < K.nrep; ++r)
+      for (int item = gw; item < S[r].nnear; item += nw) one(r, item);
   }
 }
 

@@ -637,75 +637,84 @@ __global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
 
 // Cr-C list {k : |xc_k + ind_z - q_p|^2 < (rc + skin)^2}, atom-major: xidx[p * xcap + n],
 // for the atoms of the near list of each rebuilding replica.  One wavefront per near atom
-// (grid-stride), its lanes sharing the 27 carbon cells around the atom; the passing
-// carbons are compacted in candidate order with a ballot.
+// (grid-stride over those of all rebuilding replicas), its lanes sharing the 27 carbon cells
+// around the atom; the passing carbons are compacted in candidate order with a ballot.
 __global__ __launch_bounds__(BLOCK) void k_xlist(Consts K, BuildArgs A) {
   if (rebuild_off(A)) return;
   __shared__ int cand_sh[WAVES_PER_BLOCK][MAXC];
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
   const int gw = blockIdx.x * WAVES_PER_BLOCK + w, nw = gridDim.x * WAVES_PER_BLOCK;
-  for (int r = 0; r < K.nrep; ++r) {
+  auto one = [&](int r, int item) {   // near atom `item` of replica r, on this wavefront
     RepState& S = A.S[r];
-    if (!S.rebuild) continue;
     const RepDesc& d = A.R[r];
-    const int nnear = S.nnear;
     const double iz = S.ind_z;
     const int hbase = A.start[d.h0];
     const int msx = stencil_n(d.hd[0], d.per[0]), msy = stencil_n(d.hd[1], d.per[1]),
               msz = stencil_n(d.hd[2], d.per[2]);
     const int ms = msx * msy * msz;
-    for (int item = gw; item < nnear; item += nw) {
-      const int64_t pa = A.near[d.a0 + item];
-      const double4 pi = A.q[pa];
-      int hx, hy, hz;
-      c_cell_coords(d, pi.x, pi.y, pi.z, hx, hy, hz);
-      int ks = 0, kn = 0;
-      if (lane < ms) {
-        const int tx = lane % msx, ty = (lane / msx) % msy, tz = lane / (msx * msy);
-        const int x = stencil_cell(hx, tx, d.hd[0], d.per[0]);
-        const int y = stencil_cell(hy, ty, d.hd[1], d.per[1]);
-        const int z = stencil_cell(hz, tz, d.hd[2], d.per[2]);
-        if (x >= 0 && y >= 0 && z >= 0) {
-          const int hid = d.h0 + (z * d.hd[1] + y) * d.hd[0] + x;
-          ks = d.c0 + (A.start[hid] - hbase);
-          kn = A.start[hid + 1] - A.start[hid];
-        }
+    const int64_t pa = A.near[d.a0 + item];
+    const double4 pi = A.q[pa];
+    int hx, hy, hz;
+    c_cell_coords(d, pi.x, pi.y, pi.z, hx, hy, hz);
+    int ks = 0, kn = 0;
+    if (lane < ms) {
+      const int tx = lane % msx, ty = (lane / msx) % msy, tz = lane / (msx * msy);
+      const int x = stencil_cell(hx, tx, d.hd[0], d.per[0]);
+      const int y = stencil_cell(hy, ty, d.hd[1], d.per[1]);
+      const int z = stencil_cell(hz, tz, d.hd[2], d.per[2]);
+      if (x >= 0 && y >= 0 && z >= 0) {
+        const int hid = d.h0 + (z * d.hd[1] + y) * d.hd[0] + x;
+        ks = d.c0 + (A.start[hid] - hbase);
+        kn = A.start[hid + 1] - A.start[hid];
       }
-      int pref = kn;
+    }
+    int pref = kn;
 #pragma unroll
-      for (int o = 1; o < WAVE; o <<= 1) {
-        const int y = __shfl_up(pref, o, WAVE);
-        if (lane >= o) pref += y;
-      }
-      const int total = __shfl(pref, WAVE - 1, WAVE);
-      pref -= kn;
-      int n = 0;
-      for (int w0 = 0; w0 < total; w0 += MAXC) {
-        const int lo = max(0, w0 - pref), hi = min(kn, w0 + MAXC - pref);
-        for (int e = lo; e < hi; ++e) cand_sh[w][pref + e - w0] = A.hsorted[ks + e];
-        wave_sync();
-        const int wn = min(MAXC, total - w0);
-        for (int k0 = 0; k0 < wn; k0 += WAVE) {
-          bool pred = false;
-          int k = 0;
-          if (k0 + lane < wn) {
-            k = cand_sh[w][k0 + lane];
-            const double ex = min_image(A.xc[3 * k + 0] - pi.x, d.len[0], d.half[0], d.per[0]);
-            const double ey = min_image(A.xc[3 * k + 1] - pi.y, d.len[1], d.half[1], d.per[1]);
-            const double ez = min_image((A.xc[3 * k + 2] + iz) - pi.z, d.len[2], d.half[2], d.per[2]);
-            pred = dist_sq_exact(ex, ey, ez) < K.rxlist_sq;
-          }
-          const unsigned long long m2 = __ballot(pred);
-          const int below = __popcll(m2 & ((1ull << lane) - 1ull));
-          if (pred && n + below < K.xcap) A.xidx[pa * K.xcap + n + below] = k;
-          n += __popcll(m2);
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const int y = __shfl_up(pref, o, WAVE);
+      if (lane >= o) pref += y;
+    }
+    const int total = __shfl(pref, WAVE - 1, WAVE);
+    pref -= kn;
+    int n = 0;
+    for (int w0 = 0; w0 < total; w0 += MAXC) {
+      const int lo = max(0, w0 - pref), hi = min(kn, w0 + MAXC - pref);
+      for (int e = lo; e < hi; ++e) cand_sh[w][pref + e - w0] = A.hsorted[ks + e];
+      wave_sync();
+      const int wn = min(MAXC, total - w0);
+      for (int k0 = 0; k0 < wn; k0 += WAVE) {
+        bool pred = false;
+        int k = 0;
+        if (k0 + lane < wn) {
+          k = cand_sh[w][k0 + lane];
+          const double ex = min_image(A.xc[3 * k + 0] - pi.x, d.len[0], d.half[0], d.per[0]);
+          const double ey = min_image(A.xc[3 * k + 1] - pi.y, d.len[1], d.half[1], d.per[1]);
+          const double ez = min_image((A.xc[3 * k + 2] + iz) - pi.z, d.len[2], d.half[2], d.per[2]);
+          pred = dist_sq_exact(ex, ey, ez) < K.rxlist_sq;
         }
-        wave_sync();
+        const unsigned long long m2 = __ballot(pred);
+        const int below = __popcll(m2 & ((1ull << lane) - 1ull));
+        if (pred && n + below < K.xcap) A.xidx[pa * K.xcap + n + below] = k;
+        n += __popcll(m2);
       }
-      if (lane == 0) {
-        A.xcnt[pa] = min(n, K.xcap);
-        if (n > K.xcap) atomicMax(&S.xoverflow, n);
-      }
+      wave_sync();
+    }
+    if (lane == 0) {
+      A.xcnt[pa] = min(n, K.xcap);
+      if (n > K.xcap) atomicMax(&S.xoverflow, n);
+    }
+  };
+  __shared__ int pre[FLAT_MAXREP + 1];
+  if (K.nrep <= FLAT_MAXREP) {   // near atoms of all rebuilding replicas as one index space
+    const int total = flat_prefix(K.nrep, pre, [&](int r) { return A.S[r].rebuild ? A.S[r].nnear : 0; });
+    for (int g = gw; g < total; g += nw) {
+      const int r = flat_replica(pre, K.nrep, g);
+      one(r, g - pre[r]);
+    }
+  } else {
+    for (int r = 0; r < K.nrep; ++r) {
+      if (!A.S[r].rebuild) continue;
+      for (int item = gw; item < A.S[r].nnear; item += nw) one(r, item);
     }
   }
 }
