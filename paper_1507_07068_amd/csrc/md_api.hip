@@ -22,7 +22,7 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Byte offsets of the workspace regions.
 struct Layout {
-  size_t desc, state, tile_rep, c_rep, cell_rep, misc, xref, dmax, tbox, cellid, crank, perm, skey, tq, tqf, tv,
+  size_t desc, state, tile_rep, c_rep, misc, xref, dmax, tbox, cellid, crank, perm, skey, tq, tqf, tv,
       tf, tfixed, tid, count, start, hcell, hrank, hlist, hsorted, scan_state, hnear, near, fme, p_embed, p_force,
       p_morse, p_kin, total;
 };
@@ -39,7 +39,6 @@ struct md_system {
   std::vector<RepDesc> desc;
   std::vector<int> tile_rep;
   std::vector<int> c_rep;
-  std::vector<int> cell_rep;
   int64_t ntot, ctot;
   int ntiles;
   int ncell_cr, ncell_all;
@@ -71,7 +70,6 @@ Layout make_layout(const md_system& s) {
   L.state = take(sizeof(RepState) * s.nrep);
   L.tile_rep = take(sizeof(int) * nt);
   L.c_rep = take(sizeof(int) * (size_t)s.ctot);
-  L.cell_rep = take(sizeof(int) * (size_t)s.ncell_all);
   L.misc = take(sizeof(int) * MISC_INTS);
   L.xref = take(sizeof(double) * 3 * n);
   L.dmax = take(sizeof(double) * nt);
@@ -263,14 +261,12 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
     s->desc.push_back(d);
     for (int t = 0; t < ntile; ++t) s->tile_rep.push_back(r);
     for (int k = 0; k < rd.n_c; ++k) s->c_rep.push_back(r);
-    for (int64_t c = 0; c < ncr; ++c) s->cell_rep.push_back(r);
   }
   s->ncell_cr = g0;
   int h = g0;
   for (int r = 0; r < nrep; ++r) {
     s->desc[r].h0 = h;
     h += hcells[r];
-    for (int c = 0; c < hcells[r]; ++c) s->cell_rep.push_back(r);
   }
   s->ncell_all = h;
   // list offsets are 32-bit
@@ -354,9 +350,6 @@ MD_API int md_workspace_bind(md_system* s, void* ws, size_t bytes, void* stream)
       (e = hip_status(hipMemcpyAsync(at<int>(s, s->L.c_rep), s->c_rep.data(), sizeof(int) * s->ctot,
                                      hipMemcpyHostToDevice, st))))
     return e;
-  if ((e = hip_status(hipMemcpyAsync(at<int>(s, s->L.cell_rep), s->cell_rep.data(),
-                                     sizeof(int) * s->ncell_all, hipMemcpyHostToDevice, st))))
-    return e;
   s->have_embed = s->have_force = false;
   return hip_status(hipStreamSynchronize(st));
 }
@@ -372,7 +365,6 @@ MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l
   A.S = at<RepState>(s, s->L.state);
   A.tile_rep = at<int>(s, s->L.tile_rep);
   A.c_rep = at<int>(s, s->L.c_rep);
-  A.cell_rep = at<int>(s, s->L.cell_rep);
   A.any = misc + 0;
   A.q = reinterpret_cast<double4*>(a->q);
   A.v = a->v;
@@ -422,7 +414,7 @@ MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l
   k_bin<<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A);
   k_scan<<<s->scan_blocks, BLOCK, 0, st>>>(A);
   k_scatter<<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A);
-  k_sort_gather<<<(s->ncell_all + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, BLOCK, 0, st>>>(s->K, A);
+  k_sort_gather<<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A);
   if (s->list_mix)
     k_list_rows<false><<<s->ntiles, BLOCK, 0, st>>>(s->K, A);
   else

@@ -6,7 +6,7 @@
 //   k_scan          exclusive scan of all cell counts (one pass, decoupled look-back)
 //   k_scatter       atom slots / carbon indices into their cells at the ranks k_bin took
 //                   (arbitrary order within a cell), with the (cell, id) sort keys
-//   k_sort_gather   one wavefront per cell: order the cell by atom id, gather the atom
+//   k_sort_gather   one lane per slot: rank within its cell by (cell, id), gather the atom
 //                   state into sorted order (so the final order is canonical)
 //   k_list_rows     one lane per Cr atom scanning contiguous cell-row ranges of the sorted
 //                   atoms; copies the sorted state back
@@ -25,7 +25,6 @@ struct BuildArgs {
   RepState* S;
   const int* tile_rep;   // [ntiles]
   const int* c_rep;      // [ctot] replica of each carbon
-  const int* cell_rep;   // [ncell_all] replica of each cell (Cr cells, then carbon cells)
   int* any;              // 1 if some replica rebuilds in this step
   double4* q;
   double* v;
@@ -69,13 +68,6 @@ constexpr int MAXC = 512;           // candidates staged per window in k_xlist
 #define MD_LIST_BATCH 4
 #endif
 constexpr int LIST_BATCH = MD_LIST_BATCH;   // candidate loads issued together in k_list_rows
-constexpr int SUPER_X = 4;             // cells along x handled by one wavefront
-
-// Cells per wavefront along x: SUPER_X, or 1 when a periodic x axis is too short for the
-// widened stencil to stay free of repeated cells.
-__device__ __forceinline__ int super_x(const RepDesc& d, int gx) {
-  return (d.per[0] && gx < SUPER_X + 2) ? 1 : SUPER_X;
-}
 constexpr int WAVES_PER_BLOCK = BLOCK / WAVE;
 
 
@@ -362,100 +354,68 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Consts K, BuildArgs A) {
   }
 }
 
-// Rank of element u among the m elements of a segment, by (key, tie) ascending.  Each lane
-// holds one element; keys of all elements are visited 64 at a time through shuffles.
-template <class LoadKey>
-__device__ __forceinline__ int segment_rank(int m, long long my_key, int my_tie, bool have, LoadKey load) {
-  const int lane = threadIdx.x % WAVE;
-  int rank = 0;
-  for (int t0 = 0; t0 < m; t0 += WAVE) {
-    long long kk = 0;
-    int tt = 0;
-    if (t0 + lane < m) load(t0 + lane, kk, tt);
-    const int nt = min(WAVE, m - t0);
-    for (int s = 0; s < nt; ++s) {
-      const long long ks = __shfl(kk, s, WAVE);
-      const int ts = __shfl(tt, s, WAVE);
-      rank += (have && (ks < my_key || (ks == my_key && ts < my_tie))) ? 1 : 0;
-    }
-  }
-  return rank;
-}
-
+// One lane per slot in cell order.  Blocks [0, ntiles): Cr slots, one tile each; blocks
+// [ntiles, ...): 256 carbon slots each.  A slot's final position is the start of its cell
+// plus the number of atoms of that cell with a smaller (cell, id) key (cells hold a few
+// atoms), so the final order is canonical; the atom's state is gathered there.
 __global__ __launch_bounds__(BLOCK) void k_sort_gather(Consts K, BuildArgs A) {
   if (rebuild_off(A)) return;
-  const int lane = threadIdx.x % WAVE;
-  const int c = blockIdx.x * WAVES_PER_BLOCK + threadIdx.x / WAVE;
-  if (c >= A.ncell_all) return;
-  const int r = A.cell_rep[c];
-  if (!A.S[r].rebuild) return;
-  const RepDesc& d = A.R[r];
-  if (c < A.ncell_cr) {
-    // the run of sx consecutive cells along x that k_list also takes together
+  const int b = blockIdx.x;
+  if (b < A.ntiles) {
+    const int r = A.tile_rep[b];
     const RepState& S = A.S[r];
-    const int lc = c - d.g0;
-    const int gx = S.gd[0], gy = S.gd[1], gz = S.gd[2];
-    const int sx = super_x(d, gx);
-    const int ngx = (gx + sx - 1) / sx;
-    if (lc >= ngx * gy * gz) return;
-    const int cx0 = (lc % ngx) * sx, cy = (lc / ngx) % gy, cz = lc / (ngx * gy);
-    const int cx1 = min(cx0 + sx, gx);
-    const int crow = d.g0 + (cz * gy + cy) * gx;
-    if (lane < cx1 - cx0) A.count[crow + cx0 + lane] = 0;   // zero again for the next rebuild
-    const int s0 = A.start[crow + cx0], m = A.start[crow + cx1] - s0;
-    if (m == 0) return;
-    const int base = d.a0 + (s0 - A.start[d.g0]);
-    for (int u0 = 0; u0 < m; u0 += WAVE) {
-      const int u = u0 + lane;
-      const bool have = u < m;
-      const int e = have ? A.perm[base + u] : 0;
-      // order by (cell, id): within the run, the rank is the atom's final position
-      const long long key = have ? A.skey[base + u] : 0;
-      const int rank = segment_rank(m, key, 0, have, [&](int t, long long& kk, int& tt) {
-        kk = A.skey[base + t];
-        tt = 0;
-      });
-      if (have) {
-        const int p = base + rank;
-        const double4 qe = A.q[e];
-        A.tq[p] = qe;
-        A.tqf[p] = make_float4((float)(qe.x - S.glo[0]), (float)(qe.y - S.glo[1]), (float)(qe.z - S.glo[2]), 0.0f);
-        A.tv[3 * p + 0] = A.v[3 * e + 0];
-        A.tv[3 * p + 1] = A.v[3 * e + 1];
-        A.tv[3 * p + 2] = A.v[3 * e + 2];
-        A.tf[3 * p + 0] = A.f[3 * e + 0];
-        A.tf[3 * p + 1] = A.f[3 * e + 1];
-        A.tf[3 * p + 2] = A.f[3 * e + 2];
-        A.tfixed[p] = A.fixed[e];
-        A.tid[p] = A.id[e];
-      }
-    }
+    if (!S.rebuild) return;
+    const RepDesc& d = A.R[r];
+    const int u = b * TILE + threadIdx.x;
+    if (u >= d.a0 + d.n) return;
+    const long long key = A.skey[u];
+    const int c = (int)(key >> 32);
+    const int sbase = d.a0 - A.start[d.g0];
+    const int s0 = sbase + A.start[c], s1 = sbase + A.start[c + 1];
+    int rank = 0;
+    for (int t = s0; t < s1; ++t) rank += A.skey[t] < key ? 1 : 0;
+    if (u == s0) A.count[c] = 0;   // zero again for the next rebuild
+    const int e = A.perm[u];
+    const int p = s0 + rank;
+    const double4 qe = A.q[e];
+    A.tq[p] = qe;
+    A.tqf[p] = make_float4((float)(qe.x - S.glo[0]), (float)(qe.y - S.glo[1]), (float)(qe.z - S.glo[2]), 0.0f);
+    A.tv[3 * p + 0] = A.v[3 * e + 0];
+    A.tv[3 * p + 1] = A.v[3 * e + 1];
+    A.tv[3 * p + 2] = A.v[3 * e + 2];
+    A.tf[3 * p + 0] = A.f[3 * e + 0];
+    A.tf[3 * p + 1] = A.f[3 * e + 1];
+    A.tf[3 * p + 2] = A.f[3 * e + 2];
+    A.tfixed[p] = A.fixed[e];
+    A.tid[p] = A.id[e];
   } else {
-    const int s0 = A.start[c], m = A.start[c + 1] - s0;
-    if (lane == 0) A.count[c] = 0;   // zero again for the next rebuild
-    if (m == 0) return;
-    // every cell of this carbon cell's stencil can hold Cr atoms within reach of a carbon
-    const int lc = c - d.h0;
-    const int hx = lc % d.hd[0], hy = (lc / d.hd[0]) % d.hd[1], hz = lc / (d.hd[0] * d.hd[1]);
-    const int msx = stencil_n(d.hd[0], d.per[0]), msy = stencil_n(d.hd[1], d.per[1]),
-              msz = stencil_n(d.hd[2], d.per[2]);
-    if (lane < msx * msy * msz) {
-      const int tx = lane % msx, ty = (lane / msx) % msy, tz = lane / (msx * msy);
-      const int x = stencil_cell(hx, tx, d.hd[0], d.per[0]);
-      const int y = stencil_cell(hy, ty, d.hd[1], d.per[1]);
-      const int z = stencil_cell(hz, tz, d.hd[2], d.per[2]);
-      if (x >= 0 && y >= 0 && z >= 0) A.hnear[d.h0 + (z * d.hd[1] + y) * d.hd[0] + x] = 1;
-    }
-    const int base = d.c0 + (s0 - A.start[d.h0]);
-    for (int u0 = 0; u0 < m; u0 += WAVE) {
-      const int u = u0 + lane;
-      const bool have = u < m;
-      const int e = have ? A.hlist[base + u] : 0;
-      const int rank = segment_rank(m, (long long)e, 0, have, [&](int t, long long& kk, int& tt) {
-        kk = A.hlist[base + t];
-        tt = 0;
-      });
-      if (have) A.hsorted[base + rank] = e;
+    const int64_t u = (int64_t)(b - A.ntiles) * BLOCK + threadIdx.x;
+    if (u >= A.ctot) return;
+    const int r = A.c_rep[u];   // carbon slots of a replica are its carbon index range
+    if (!A.S[r].rebuild) return;
+    const RepDesc& d = A.R[r];
+    const int e = A.hlist[u];
+    const int c = A.hcell[e];
+    const int hb = d.c0 - A.start[d.h0];
+    const int s0 = hb + A.start[c], s1 = hb + A.start[c + 1];
+    int rank = 0;
+    for (int t = s0; t < s1; ++t) rank += A.hlist[t] < e ? 1 : 0;
+    A.hsorted[s0 + rank] = e;
+    if (u == s0) {
+      A.count[c] = 0;   // zero again for the next rebuild
+      // every cell of this carbon cell's stencil can hold Cr atoms within reach of a carbon
+      const int lc = c - d.h0;
+      const int hx = lc % d.hd[0], hy = (lc / d.hd[0]) % d.hd[1], hz = lc / (d.hd[0] * d.hd[1]);
+      const int msx = stencil_n(d.hd[0], d.per[0]), msy = stencil_n(d.hd[1], d.per[1]),
+                msz = stencil_n(d.hd[2], d.per[2]);
+      for (int tz = 0; tz < msz; ++tz)
+        for (int ty = 0; ty < msy; ++ty)
+          for (int tx = 0; tx < msx; ++tx) {
+            const int x = stencil_cell(hx, tx, d.hd[0], d.per[0]);
+            const int y = stencil_cell(hy, ty, d.hd[1], d.per[1]);
+            const int z = stencil_cell(hz, tz, d.hd[2], d.per[2]);
+            if (x >= 0 && y >= 0 && z >= 0) A.hnear[d.h0 + (z * d.hd[1] + y) * d.hd[0] + x] = 1;
+          }
     }
   }
 }
