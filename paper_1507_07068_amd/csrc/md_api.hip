@@ -22,7 +22,7 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Byte offsets of the workspace regions.
 struct Layout {
-  size_t desc, state, tile_rep, c_rep, misc, xref, dmax, tbox, cellid, crank, perm, skey, tq, tqf, tv,
+  size_t desc, state, tile_rep, lblk_rep, c_rep, misc, xref, dmax, tbox, cellid, crank, perm, skey, tq, tqf, tv,
       tf, tfixed, tid, count, start, hcell, hrank, hlist, hsorted, scan_state, hnear, near, fme, p_embed, p_force,
       p_morse, p_kin, total;
 };
@@ -38,9 +38,11 @@ struct md_system {
   int nrep;
   std::vector<RepDesc> desc;
   std::vector<int> tile_rep;
+  std::vector<int> lblk_rep;   // replica of each block of the list build
   std::vector<int> c_rep;
   int64_t ntot, ctot;
   int ntiles;
+  int nlblk;     // blocks of the list build
   int ncell_cr, ncell_all;
   Consts K;
   Layout L;
@@ -69,6 +71,7 @@ Layout make_layout(const md_system& s) {
   L.desc = take(sizeof(RepDesc) * s.nrep);
   L.state = take(sizeof(RepState) * s.nrep);
   L.tile_rep = take(sizeof(int) * nt);
+  L.lblk_rep = take(sizeof(int) * (size_t)s.nlblk);
   L.c_rep = take(sizeof(int) * (size_t)s.ctot);
   L.misc = take(sizeof(int) * MISC_INTS);
   L.xref = take(sizeof(double) * 3 * n);
@@ -260,6 +263,12 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
     if (a0 > (int64_t)INT32_MAX / 2 || c0 > (int64_t)INT32_MAX / 2) { delete s; return MD_ERR_ARG; }
     s->desc.push_back(d);
     for (int t = 0; t < ntile; ++t) s->tile_rep.push_back(r);
+    // list build: one block per run of up to LIST_SEG cells of a cell row, at capacity
+    s->desc.back().lb0 = (int)s->lblk_rep.size();
+    s->desc.back().nseg = (d.gcap[0] + LIST_SEG - 1) / LIST_SEG;
+    const int64_t nlb = (int64_t)s->desc.back().nseg * d.gcap[1] * d.gcap[2];
+    if ((int64_t)s->lblk_rep.size() + nlb > (int64_t)INT32_MAX / 2) { delete s; return MD_ERR_ARG; }
+    s->lblk_rep.insert(s->lblk_rep.end(), (size_t)nlb, r);
     for (int k = 0; k < rd.n_c; ++k) s->c_rep.push_back(r);
   }
   s->ncell_cr = g0;
@@ -278,6 +287,7 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
   s->ntot = a0;
   s->ctot = c0;
   s->ntiles = t0;
+  s->nlblk = (int)s->lblk_rep.size();
 
   Consts& K = s->K;
   std::memset(&K, 0, sizeof K);
@@ -343,6 +353,9 @@ MD_API int md_workspace_bind(md_system* s, void* ws, size_t bytes, void* stream)
   if ((e = hip_status(hipMemcpyAsync(at<RepDesc>(s, s->L.desc), s->desc.data(),
                                      sizeof(RepDesc) * s->nrep, hipMemcpyHostToDevice, st))))
     return e;
+  if ((e = hip_status(hipMemcpyAsync(at<int>(s, s->L.lblk_rep), s->lblk_rep.data(),
+                                     sizeof(int) * s->nlblk, hipMemcpyHostToDevice, st))))
+    return e;
   if ((e = hip_status(hipMemcpyAsync(at<int>(s, s->L.tile_rep), s->tile_rep.data(),
                                      sizeof(int) * s->ntiles, hipMemcpyHostToDevice, st))))
     return e;
@@ -364,6 +377,7 @@ MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l
   A.R = at<RepDesc>(s, s->L.desc);
   A.S = at<RepState>(s, s->L.state);
   A.tile_rep = at<int>(s, s->L.tile_rep);
+  A.lblk_rep = at<int>(s, s->L.lblk_rep);
   A.c_rep = at<int>(s, s->L.c_rep);
   A.any = misc + 0;
   A.q = reinterpret_cast<double4*>(a->q);
@@ -418,7 +432,7 @@ MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l
   if (s->list_mix)
     k_list_rows<false><<<s->ntiles, BLOCK, 0, st>>>(s->K, A);
   else
-    k_list_rows<true><<<s->ntiles, BLOCK, 0, st>>>(s->K, A);
+    k_list_tiles<<<s->nlblk, BLOCK, 0, st>>>(s->K, A);
   k_xlist<<<A.near_blocks, BLOCK, 0, st>>>(s->K, A);
   return check_launch();
 }

@@ -8,8 +8,10 @@
 //                   (arbitrary order within a cell), with the (cell, id) sort keys
 //   k_sort_gather   one lane per slot: rank within its cell by (cell, id), gather the atom
 //                   state into sorted order (so the final order is canonical)
-//   k_list_rows     one lane per Cr atom scanning contiguous cell-row ranges of the sorted
-//                   atoms; copies the sorted state back
+//   k_list_tiles    one block per run of cells of a cell row: the neighbouring rows are
+//                   staged in LDS, each atom scans its window of them; copies the sorted
+//                   state back (k_list_rows: one lane per atom from global memory, for
+//                   periodic axes with fewer than 3 cells)
 //   k_xlist         Cr-C lists: one wavefront per Cr atom within reach of the carbons
 //
 // Every kernel after k_decide returns at once when no replica needs a rebuild, so a step
@@ -24,6 +26,7 @@ struct BuildArgs {
   const RepDesc* R;
   RepState* S;
   const int* tile_rep;   // [ntiles]
+  const int* lblk_rep;   // [list-build blocks] replica of each
   const int* c_rep;      // [ctot] replica of each carbon
   int* any;              // 1 if some replica rebuilds in this step
   double4* q;
@@ -69,6 +72,12 @@ constexpr int MAXC = 512;           // candidates staged per window in k_xlist
 #endif
 constexpr int LIST_BATCH = MD_LIST_BATCH;   // candidate loads issued together in k_list_rows
 constexpr int WAVES_PER_BLOCK = BLOCK / WAVE;
+constexpr int LIST_SEG = 42;      // cells of one cell row per block of k_list_tiles
+constexpr int LIST_STAGE = 1024;  // candidates staged in LDS at a time by k_list_tiles
+#ifndef MD_LIST_GROUP
+#define MD_LIST_GROUP 4
+#endif
+constexpr int LIST_GROUP = MD_LIST_GROUP;   // candidates screened together per atom in k_list_tiles
 
 
 __device__ __forceinline__ bool rebuild_off(const BuildArgs& A) { return *A.any == 0; }
@@ -592,6 +601,207 @@ __global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
     if (lane == 0) first = atomicAdd(&S.nnear, __popcll(nm));
     first = __shfl(first, 0, WAVE);
     if (near) A.near[d.a0 + first + __popcll(nm & ((1ull << lane) - 1ull))] = p;
+  }
+}
+
+// Cr-Cr lists with LDS-staged candidates (replicas whose periodic axes all have >= 3 list
+// cells).  One block per run of up to LIST_SEG cells of one cell row; its atoms are the
+// centers, one per thread.  For each of the nine neighbouring cell rows (z-major, then y)
+// the block stages that row's atoms of x-cells x0-1 .. x1+1 -- with the cell seen across a
+// periodic x face placed at the end it is seen from -- into LDS as FP32 coordinates
+// relative to the grid origin plus the row's image shift, together with their slots.  A
+// center's candidates in that row, x-cells cx-1 .. cx+1, are then one contiguous window of
+// the staged row, so the candidate order (rows, along x, by slot) is the same as in
+// k_list_rows and the lists are identical.  Rows longer than LIST_STAGE are staged in
+// chunks.  The FP32 screen and its exact FP64 band are those of k_list_rows.
+__global__ __launch_bounds__(BLOCK) void k_list_tiles(Consts K, BuildArgs A) {
+  if (rebuild_off(A)) return;
+  __shared__ float4 sq[LIST_STAGE];
+  __shared__ int sj[LIST_STAGE];
+  __shared__ int toff[LIST_SEG + 4];   // staged offset of unwrapped cells x0-1 .. x1+2
+  const int b = blockIdx.x;
+  const int r = A.lblk_rep[b];
+  RepState& S = A.S[r];
+  if (!S.rebuild) return;
+  const RepDesc& d = A.R[r];
+  const int gx = S.gd[0], gy = S.gd[1], gz = S.gd[2];
+  const int nseg = (gx + LIST_SEG - 1) / LIST_SEG;
+  const int l = b - d.lb0;
+  if (l >= nseg * gy * gz) return;
+  if (l == 0 && threadIdx.x == 0) {   // once per replica: the build is counted
+    S.nbuilds += 1;
+    S.ind_z_ref = S.ind_z;
+  }
+  const int sx = l % nseg, cy = (l / nseg) % gy, cz = l / (nseg * gy);
+  const int x0 = sx * gx / nseg, x1 = (sx + 1) * gx / nseg - 1;   // this block's cells
+  const int crow = d.g0 + (cz * gy + cy) * gx;
+  const int sbase = d.a0 - A.start[d.g0];   // sorted slot = sbase + start[cell]
+  const int cbeg = sbase + A.start[crow + x0];
+  const int m = A.start[crow + x1 + 1] - A.start[crow + x0];
+  if (m == 0) return;
+  const int lane = threadIdx.x % WAVE;
+  const double rl2 = K.rlist_sq;
+  const int cap = K.cap, T = K.lt;
+  const int64_t row = K.ntot * T;   // entry k of atom p at idx[(k / T) * row + p * T + k % T]
+  const double4* __restrict__ tq = A.tq;
+  const float4* __restrict__ tqf = A.tqf;
+  // FP32 screen bounds (see k_list_rows); the staged coordinate already includes the image
+  // shift, which the error bound covers
+  float lo_f, hi_f;
+  {
+    const double u = 0x1p-24, R = K.rlist + 1.0;
+    const int gg[3] = {gx, gy, gz};
+    double err = 4.0 * u * (rl2 + R * R);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double E = gg[a] / S.ginv[a] + 2.0 * R;
+      const double eta = u * (3.0 * E + (d.per[a] ? 2.0 * d.len[a] : 0.0) + 3.0 * R);
+      err += 2.0 * R * eta + eta * eta;
+    }
+    const double delta = 2.0 * err + 1e-6;
+    lo_f = (float)(rl2 - delta);
+    hi_f = (float)(rl2 + delta);
+  }
+  const int xa = max(x0 - 1, 0), xb = min(x1 + 1, gx - 1);   // main piece of a staged row
+  const bool wl = d.per[0] && x0 == 0, wr = d.per[0] && x1 == gx - 1;   // wrapped end cells
+  for (int c0 = 0; c0 < m; c0 += BLOCK) {
+    const int c = c0 + threadIdx.x;
+    const bool live = c < m;
+    const int p = cbeg + (live ? c : 0);
+    const double4 pi = tq[p];
+    const float4 pf = tqf[p];
+    const int cx = cell_coord(pi.x, S.glo[0], S.ginv[0], gx);
+    int count = 0;
+    int* __restrict__ wp = A.idx + (int64_t)p * T;
+    auto append = [&](int j) {
+      if (count < cap) *wp = j;
+      ++count;
+      wp += (count & (T - 1)) ? 1 : row - (T - 1);
+    };
+    for (int rr = 0; rr < 9; ++rr) {   // uniform over the block
+      const int tz = rr / 3, ty = rr % 3;
+      const int z = stencil_cell(cz, tz, gz, d.per[2]);
+      const int y = stencil_cell(cy, ty, gy, d.per[1]);
+      if (z < 0 || y < 0) continue;
+      const int uz = cz + tz - 1, uy = cy + ty - 1;
+      const double shz = d.per[2] ? (uz < 0 ? -d.len[2] : (uz >= gz ? d.len[2] : 0.0)) : 0.0;
+      const double shy = d.per[1] ? (uy < 0 ? -d.len[1] : (uy >= gy ? d.len[1] : 0.0)) : 0.0;
+      const float fy = (float)shy, fz = (float)shz, fxl = (float)(-d.len[0]), fxr = (float)d.len[0];
+      const int rw = d.g0 + (z * gy + y) * gx;
+      const int L0 = sbase + A.start[rw + gx - 1], nl = wl ? A.start[rw + gx] - A.start[rw + gx - 1] : 0;
+      const int M0 = sbase + A.start[rw + xa], nm = A.start[rw + xb + 1] - A.start[rw + xa];
+      const int R0 = sbase + A.start[rw], nr = wr ? A.start[rw + 1] - A.start[rw] : 0;
+      const int total = nl + nm + nr;
+      __syncthreads();   // the previous row's table and stage are no longer read
+      for (int t = threadIdx.x; t <= x1 - x0 + 3; t += BLOCK) {
+        const int u = x0 - 1 + t;   // unwrapped cell
+        toff[t] = u < xa ? 0 : (u <= xb + 1 ? nl + (A.start[rw + u] - A.start[rw + xa]) : total);
+      }
+      __syncthreads();
+      // this center's window: unwrapped cells cx-1 .. cx+1
+      const int w0 = toff[cx - 1 - (x0 - 1)], w1 = toff[cx + 2 - (x0 - 1)];
+      for (int ch = 0; ch < total; ch += LIST_STAGE) {
+        const int nch = min(LIST_STAGE, total - ch);
+        if (ch > 0) __syncthreads();
+        for (int s = threadIdx.x; s < nch; s += BLOCK) {
+          const int g = ch + s;
+          int j;
+          float fx;
+          if (g < nl) {
+            j = L0 + g;
+            fx = fxl;
+          } else if (g < nl + nm) {
+            j = M0 + (g - nl);
+            fx = 0.0f;
+          } else {
+            j = R0 + (g - nl - nm);
+            fx = fxr;
+          }
+          const float4 cf = tqf[j];
+          sq[s] = make_float4(cf.x + fx, cf.y + fy, cf.z + fz, 0.0f);
+          sj[s] = j;
+        }
+        __syncthreads();
+        if (live) {
+          const int e0 = max(w0, ch) - ch, e1 = min(w1, ch + nch) - ch;
+          // exact FP64 test of staged candidate s (band or NaN)
+          auto exact = [&](int s) {
+            const int g = ch + s;
+            const double shx = g < nl ? -d.len[0] : (g < nl + nm ? 0.0 : d.len[0]);
+            const double4 pj = tq[sj[s]];
+            return dist_sq_exact((pj.x - pi.x) + shx, (pj.y - pi.y) + shy, (pj.z - pi.z) + shz) < rl2;
+          };
+          // LIST_GROUP candidates at a time: the FP32 screen gives in / band bit masks, the
+          // rare band candidates get the exact test, then the passing ones are appended in
+          // order
+          int s = e0;
+          for (; s + LIST_GROUP <= e1; s += LIST_GROUP) {
+            unsigned in = 0, band = 0;
+#pragma unroll
+            for (int u = 0; u < LIST_GROUP; ++u) {
+              const float4 cf = sq[s + u];
+              const float ex = cf.x - pf.x, ey = cf.y - pf.y, ez = cf.z - pf.z;
+              const float r2f = ex * ex + ey * ey + ez * ez;
+              in |= (r2f < lo_f ? 1u : 0u) << u;
+              band |= (!(r2f < lo_f) && !(r2f >= hi_f) ? 1u : 0u) << u;
+            }
+            if (__builtin_expect(band != 0, 0)) {
+              for (unsigned bm = band; bm; bm &= bm - 1) {
+                const int u = __builtin_ctz(bm);
+                if (exact(s + u)) in |= 1u << u;
+              }
+            }
+            for (; in; in &= in - 1) {
+              const int j = sj[s + __builtin_ctz(in)];
+              if (j != p) append(j);
+            }
+          }
+          for (; s < e1; ++s) {
+            const float4 cf = sq[s];
+            const float ex = cf.x - pf.x, ey = cf.y - pf.y, ez = cf.z - pf.z;
+            const float r2f = ex * ex + ey * ey + ez * ez;
+            bool ok = r2f < lo_f;
+            if (__builtin_expect(!ok && !(r2f >= hi_f), 0)) ok = exact(s);
+            const int j = sj[s];
+            if (ok && j != p) append(j);
+          }
+        }
+      }
+    }
+    bool near = false;
+    if (live) {
+      A.cnt[p] = min(count, cap);
+      if (count > cap) atomicMax(&S.overflow, count);
+      if (d.nc > 0) {
+        int hx, hy, hz;
+        c_cell_coords(d, pi.x, pi.y, pi.z, hx, hy, hz);
+        near = A.hnear[d.h0 + (hz * d.hd[1] + hy) * d.hd[0] + hx] != 0;
+      }
+      A.xcnt[p] = 0;
+      A.fme[4 * (int64_t)p + 0] = 0.0;
+      A.fme[4 * (int64_t)p + 1] = 0.0;
+      A.fme[4 * (int64_t)p + 2] = 0.0;
+      A.fme[4 * (int64_t)p + 3] = 0.0;
+      A.q[p] = pi;
+      A.xref[3 * p + 0] = pi.x;
+      A.xref[3 * p + 1] = pi.y;
+      A.xref[3 * p + 2] = pi.z;
+      A.v[3 * p + 0] = A.tv[3 * p + 0];
+      A.v[3 * p + 1] = A.tv[3 * p + 1];
+      A.v[3 * p + 2] = A.tv[3 * p + 2];
+      A.f[3 * p + 0] = A.tf[3 * p + 0];
+      A.f[3 * p + 1] = A.tf[3 * p + 1];
+      A.f[3 * p + 2] = A.tf[3 * p + 2];
+      A.fixed[p] = A.tfixed[p];
+      A.id[p] = A.tid[p];
+    }
+    const unsigned long long nm_ = __ballot(near);
+    if (nm_) {   // append this wave's near atoms (order within the near list is irrelevant)
+      int first = 0;
+      if (lane == 0) first = atomicAdd(&S.nnear, __popcll(nm_));
+      first = __shfl(first, 0, WAVE);
+      if (near) A.near[d.a0 + first + __popcll(nm_ & ((1ull << lane) - 1ull))] = p;
+    }
   }
 }
 
