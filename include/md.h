@@ -108,7 +108,10 @@ typedef struct md_params {
     int32_t tpa;        /* lanes per atom in the density / force passes: 1, 2, 4 or 8 (the
                            Cr-Cr list is interleaved by tpa to match; cap must be a multiple
                            of tpa) */
-    int32_t pad;
+    int32_t shadow;     /* 1: keep an FP32 copy of the positions relative to each atom's cell
+                           (updated by the list build and md_verlet_step), from which the
+                           MD_F_MIXED passes take their separations; 0: those passes round FP64
+                           separations instead */
 } md_params;
 
 /* One system (replica). */
@@ -135,10 +138,13 @@ typedef struct md_atoms {
 
 /* Device neighbour lists (caller-owned, written by md_build_neighbors). */
 typedef struct md_lists {
-    int32_t *idx;       /* [cap * n_total]: entry k of atom i (an atom slot) at
-                           idx[(k / tpa) * n_total * tpa + i * tpa + k % tpa]; entries are
-                           ordered by the cell row (dz, dy = 0..2 around the atom's cell, dz
-                           slowest), then along x, then by slot */
+    int32_t *idx;       /* [cap * n_total]: entry k of atom i at
+                           idx[(k / tpa) * n_total * tpa + i * tpa + k % tpa]; its low 27 bits
+                           are the neighbour's atom slot, the bits above 9 (dz + 1) + 3 (dy + 1)
+                           + (dx + 1) for the neighbour's cell relative to atom i's at the build
+                           when shadow is set (else 0, as when a periodic axis has fewer than 3
+                           cells); entries are ordered
+                           by the cell row (dz, then dy), then along x, then by slot */
     int32_t *cnt;       /* [n_total] */
     int32_t *xidx;      /* [n_total][xcap]: carbon indices (into xc) of atom i's Cr-C list */
     int32_t *xcnt;      /* [n_total] */

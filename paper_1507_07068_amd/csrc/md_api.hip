@@ -22,7 +22,7 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Byte offsets of the workspace regions.
 struct Layout {
-  size_t desc, state, tile_rep, lblk_rep, c_rep, misc, xref, dmax, tbox, cellid, crank, perm, skey, tq, tqf, tv,
+  size_t desc, state, tile_rep, lblk_rep, c_rep, misc, xref, dmax, tbox, cellid, crank, perm, skey, tq, tqf, qs, bcell, tv,
       tf, tfixed, tid, count, start, hcell, hrank, hlist, hsorted, scan_state, hnear, near, fme, p_embed, p_force,
       p_morse, p_kin, total;
 };
@@ -83,6 +83,8 @@ Layout make_layout(const md_system& s) {
   L.skey = take(sizeof(long long) * n);
   L.tq = take(sizeof(double) * 4 * n);
   L.tqf = take(sizeof(float) * 4 * n);
+  L.qs = take(sizeof(float) * 4 * n);
+  L.bcell = take(sizeof(long long) * n);
   L.tv = take(sizeof(double) * 3 * n);
   L.tf = take(sizeof(double) * 3 * n);
   L.tfixed = take(n);
@@ -142,9 +144,12 @@ void launch_density(md_system* s, const md_atoms* a, const md_lists* l, bool mix
   double4* q = reinterpret_cast<double4*>(a->q);
   double* pe = at<double>(s, s->L.p_embed);
   const int nb = s->ntiles * T;
-#define DENS(M, E) k_density<T, M, E><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, l->idx, l->cnt, rho_out, pe)
-  if (mixed) { if (energy) DENS(true, true); else DENS(true, false); }
-  else { if (energy) DENS(false, true); else DENS(false, false); }
+  float4* qs = at<float4>(s, s->L.qs);
+#define DENS(M, SH, E) \
+  k_density<T, M, SH, E><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, qs, l->idx, l->cnt, rho_out, pe)
+  if (mixed && s->K.shadow && !s->list_mix) { if (energy) DENS(true, true, true); else DENS(true, true, false); }
+  else if (mixed) { if (energy) DENS(true, false, true); else DENS(true, false, false); }
+  else { if (energy) DENS(false, false, true); else DENS(false, false, false); }
 #undef DENS
 }
 
@@ -157,13 +162,16 @@ void launch_force(md_system* s, const md_atoms* a, const md_lists* l, bool mixed
   const double4* q = reinterpret_cast<const double4*>(a->q);
   double* pf = at<double>(s, s->L.p_force);
   const int nb = s->ntiles * T;
-#define FORCE(M, KI, E) \
-  k_force<T, M, KI, E><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, a->v, a->f, a->fixed, l->idx, l->cnt, pf)
-#define FORCE_E(M, KI) \
-  if (energy) FORCE(M, KI, true); else FORCE(M, KI, false)
-#define FORCE_K(M) \
-  if (kick) { FORCE_E(M, true); } else { FORCE_E(M, false); }
-  if (mixed) { FORCE_K(true); } else { FORCE_K(false); }
+  const float4* qs = at<float4>(s, s->L.qs);
+#define FORCE(M, SH, KI, E) \
+  k_force<T, M, SH, KI, E><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, qs, a->v, a->f, a->fixed, l->idx, l->cnt, pf)
+#define FORCE_E(M, SH, KI) \
+  if (energy) FORCE(M, SH, KI, true); else FORCE(M, SH, KI, false)
+#define FORCE_K(M, SH) \
+  if (kick) { FORCE_E(M, SH, true); } else { FORCE_E(M, SH, false); }
+  if (mixed && s->K.shadow && !s->list_mix) { FORCE_K(true, true); }
+  else if (mixed) { FORCE_K(true, false); }
+  else { FORCE_K(false, false); }
 #undef FORCE_K
 #undef FORCE_E
 #undef FORCE
@@ -278,7 +286,8 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
     h += hcells[r];
   }
   s->ncell_all = h;
-  // list offsets are 32-bit
+  // list entries keep the slot in 27 bits; list offsets are 32-bit
+  if (a0 >= ((int64_t)1 << 27)) { delete s; return MD_ERR_ARG; }
   if ((int64_t)p->cap * a0 >= (int64_t)INT32_MAX || (int64_t)p->xcap * a0 >= (int64_t)INT32_MAX) {
     delete s;
     return MD_ERR_ARG;
@@ -326,6 +335,7 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
   K.nrep = nrep;
   K.lt = p->tpa;
   K.lt_shift = p->tpa == 1 ? 0 : (p->tpa == 2 ? 1 : (p->tpa == 4 ? 2 : 3));
+  K.shadow = p->shadow ? 1 : 0;
   K.ntot = s->ntot;
   s->L = make_layout(*s);
   *out = s;
@@ -393,6 +403,8 @@ MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l
   A.skey = at<long long>(s, s->L.skey);
   A.tq = at<double4>(s, s->L.tq);
   A.tqf = at<float4>(s, s->L.tqf);
+  A.qs = at<float4>(s, s->L.qs);
+  A.bcell = at<long long>(s, s->L.bcell);
   A.tv = at<double>(s, s->L.tv);
   A.tf = at<double>(s, s->L.tf);
   A.tfixed = at<uint8_t>(s, s->L.tfixed);
@@ -493,7 +505,8 @@ MD_API int md_verlet_step(md_system* s, int32_t phase, const md_atoms* a, void* 
     k_kick_drift<<<nb, BLOCK, 0, st>>>(s->K, R, at<RepState>(s, s->L.state), tr,
                                        reinterpret_cast<double4*>(a->q), a->v, a->f, a->fixed,
                                        at<double>(s, s->L.xref), at<double>(s, s->L.dmax),
-                                       at<double>(s, s->L.tbox));
+                                       at<double>(s, s->L.tbox), at<float4>(s, s->L.qs),
+                                       at<long long>(s, s->L.bcell));
   else
     k_kick<<<nb, BLOCK, 0, st>>>(s->K, R, tr, a->v, a->f, a->fixed);
   return check_launch();

@@ -46,8 +46,29 @@ struct alignas(64) RepState {
   // Cr cell grid of the current build: origin, cells per Angstrom, dims (<= gcap).  Along
   // periodic axes it is the box; along open axes it spans the atoms' current extent.
   double glo[3], ginv[3];
+  double gedge[3];        // cell edge of that grid (1 / ginv)
   int gd[3];
 };
+
+// A Cr-Cr list entry holds the neighbour's slot in its low LIST_IDX_BITS bits and, above
+// them, the neighbour's cell relative to the atom's cell at the build: code = 9 (dz + 1) +
+// 3 (dy + 1) + (dx + 1) with dx, dy, dz in {-1, 0, 1}, counted across periodic faces.
+constexpr int LIST_IDX_BITS = 27;
+constexpr int LIST_IDX_MASK = (1 << LIST_IDX_BITS) - 1;
+__device__ __forceinline__ int list_slot(int e) { return e & LIST_IDX_MASK; }
+__device__ __forceinline__ int list_code(int e) { return (int)((unsigned)e >> LIST_IDX_BITS); }
+
+// Build cell of an atom, packed 21 bits per axis.
+__device__ __forceinline__ long long pack_cell(int cx, int cy, int cz) {
+  return (long long)cx | ((long long)cy << 21) | ((long long)cz << 42);
+}
+// FP32 position of an atom relative to the corner of its build cell (the shadow used by the
+// FP32-mixed passes): small numbers, so FP32 keeps ~1e-7 A of the separation.
+__device__ __forceinline__ float4 cell_local(const RepState& s, long long bc, double x, double y, double z, float w) {
+  const int cx = (int)(bc & 0x1FFFFF), cy = (int)((bc >> 21) & 0x1FFFFF), cz = (int)((bc >> 42) & 0x1FFFFF);
+  return make_float4((float)(x - (s.glo[0] + cx * s.gedge[0])), (float)(y - (s.glo[1] + cy * s.gedge[1])),
+                     (float)(z - (s.glo[2] + cz * s.gedge[2])), w);
+}
 
 // Constants of the potential and the integrator (passed by value).
 struct Consts {
@@ -68,6 +89,7 @@ struct Consts {
   int nrep;
   int lt;                 // list interleave: entries k..k+lt-1 of an atom are adjacent
   int lt_shift;           // log2(lt)
+  int shadow;             // 1: keep the FP32 cell-local shadow of the positions
   int64_t ntot;           // atom slots (all replicas)
 };
 

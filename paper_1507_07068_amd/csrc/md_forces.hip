@@ -1,6 +1,7 @@
 // Task 4 (and the fused Task 5 kick) of the MD step on gfx950.  Included by md_kernels.hip.
 //
 //   k_density<T>   rho_i = sum_j f(r_ij), F'(rho_i) -> q[i].w   (Section 3.3.1.2)
+//                  (FP32-mixed: separations from the FP32 cell-local shadow of q)
 //   k_force<T>     Eq. (1): F_i = -sum_j [(F'_i + F'_j) f'(r) + phi'(r)] (q_i - q_j) / r
 //   k_morse        Cr-C Morse forces: one wavefront per Cr atom that has carbons in range
 //   k_kick         Task 5 on its own
@@ -24,28 +25,42 @@ __device__ __forceinline__ V group_sum(V v) {
 }
 
 // Visit the entries k = sub, sub + T, ... (< n) of atom i's list in order, calling
-// body(q[j]) for each neighbour j.  Entries are fetched U at a time so that U independent
-// index loads, then U independent position gathers, are in flight together.
+// body(fetch(e), e) for each entry e (the neighbour's slot and relative cell, see
+// list_slot / list_code).  Entries are fetched U at a time so that U independent index
+// loads, then U independent gathers, are in flight together.
 #ifndef MD_UNROLL
 #define MD_UNROLL 1
 #endif
 constexpr int UNROLL = MD_UNROLL;
 
-template <int T, int U, class Q, class Body>
-__device__ __forceinline__ void for_neighbors(const int* __restrict__ idx, const Q* q, int i, int n,
-                                              int sub, int ntot, int shift, Body body) {
+template <int T, int U, class Fetch, class Body>
+__device__ __forceinline__ void for_entries(const int* __restrict__ idx, int i, int n, int sub, int ntot,
+                                            int shift, Fetch fetch, Body body) {
   int k = sub;
   for (; k + (U - 1) * T < n; k += U * T) {
-    int j[U];
+    int e[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) j[u] = idx[list_pos(k + u * T, i, ntot, T, shift)];
-    double4 p[U];
+    for (int u = 0; u < U; ++u) e[u] = idx[list_pos(k + u * T, i, ntot, T, shift)];
+    decltype(fetch(0)) p[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) p[u] = q[j[u]];
+    for (int u = 0; u < U; ++u) p[u] = fetch(e[u]);
 #pragma unroll
-    for (int u = 0; u < U; ++u) body(p[u]);
+    for (int u = 0; u < U; ++u) body(p[u], e[u]);
   }
-  for (; k < n; k += T) body(q[idx[list_pos(k, i, ntot, T, shift)]]);
+  for (; k < n; k += T) {
+    const int e = idx[list_pos(k, i, ntot, T, shift)];
+    body(fetch(e), e);
+  }
+}
+
+// Offsets of the 27 relative cells of a list entry in the block's replica, FP32: the
+// separation of two atoms is (shadow_j - shadow_i) + offset[code].
+__device__ __forceinline__ void fill_cell_offsets(float4* tab, const RepState& s) {
+  const int t = threadIdx.x;
+  if (t < 27)
+    tab[t] = make_float4((float)((t % 3 - 1) * s.gedge[0]), (float)((t / 3 % 3 - 1) * s.gedge[1]),
+                         (float)((t / 9 - 1) * s.gedge[2]), 0.0f);
+  __syncthreads();
 }
 
 // Atom of this thread in a launch with T lanes per atom and one block per 256/T atoms.
@@ -71,27 +86,47 @@ __device__ __forceinline__ AtomCtx atom_ctx(const int* tile_rep, const RepDesc* 
   return c;
 }
 
-template <int T, bool MIXED, bool ENERGY>
+// SHADOW (with MIXED): separations from the FP32 cell-local shadow qs and the entries'
+// relative cells; otherwise FP64 positions (rounded to FP32 for the MIXED arithmetic).
+template <int T, bool MIXED, bool SHADOW, bool ENERGY>
 __global__ __launch_bounds__(BLOCK) void k_density(Consts K, const RepDesc* __restrict__ R,
                                                    RepState* __restrict__ S,
                                                    const int* __restrict__ tile_rep,
                                                    double4* __restrict__ q,
+                                                   float4* __restrict__ qs,
                                                    const int* __restrict__ idx,
                                                    const int* __restrict__ cnt,
                                                    double* __restrict__ rho_out,
                                                    double* __restrict__ part) {
   const AtomCtx c = atom_ctx<T>(tile_rep, R);
   const RepDesc& d = R[c.r];
+  __shared__ float4 ctab[27];
+  if (SHADOW) fill_cell_offsets(ctab, S[c.r]);
   double rho = 0.0;
-  double4 pi = make_double4(0.0, 0.0, 0.0, 0.0);
   if (c.live) {
     const int64_t i = c.i;
-    pi = q[i];
     const int n = cnt[i];
-    if (MIXED) {
+    if (MIXED && SHADOW) {
+      const float4 ps = qs[i];
       float acc = 0.0f;
       const float dd = (float)K.d, dd2 = (float)K.d_sq;
-      for_neighbors<T, UNROLL>(idx, q, (int)i, n, c.sub, (int)K.ntot, K.lt_shift, [&](const double4& pj) {
+      for_entries<T, UNROLL>(idx, (int)i, n, c.sub, (int)K.ntot, K.lt_shift,
+                             [&](int e) { return qs[list_slot(e)]; },
+                             [&](const float4& pj, int e) {
+        const float4 o = ctab[list_code(e)];
+        const float ex = (pj.x - ps.x) + o.x, ey = (pj.y - ps.y) + o.y, ez = (pj.z - ps.z) + o.z;
+        const float r2 = ex * ex + ey * ey + ez * ez;
+        const float u = __fsqrt_rn(r2) - dd;
+        acc += (r2 < dd2) ? u * u : 0.0f;
+      });
+      rho = (double)acc;
+    } else if (MIXED) {
+      const double4 pi = q[i];
+      float acc = 0.0f;
+      const float dd = (float)K.d, dd2 = (float)K.d_sq;
+      for_entries<T, UNROLL>(idx, (int)i, n, c.sub, (int)K.ntot, K.lt_shift,
+                             [&](int e) { return q[list_slot(e)]; },
+                             [&](const double4& pj, int) {
         const float ex = (float)min_image(pj.x - pi.x, d.len[0], d.half[0], d.per[0]);
         const float ey = (float)min_image(pj.y - pi.y, d.len[1], d.half[1], d.per[1]);
         const float ez = (float)min_image(pj.z - pi.z, d.len[2], d.half[2], d.per[2]);
@@ -101,7 +136,10 @@ __global__ __launch_bounds__(BLOCK) void k_density(Consts K, const RepDesc* __re
       });
       rho = (double)acc;
     } else {
-      for_neighbors<T, UNROLL>(idx, q, (int)i, n, c.sub, (int)K.ntot, K.lt_shift, [&](const double4& pj) {
+      const double4 pi = q[i];
+      for_entries<T, UNROLL>(idx, (int)i, n, c.sub, (int)K.ntot, K.lt_shift,
+                             [&](int e) { return q[list_slot(e)]; },
+                             [&](const double4& pj, int) {
         const double ex = min_image(pj.x - pi.x, d.len[0], d.half[0], d.per[0]);
         const double ey = min_image(pj.y - pi.y, d.len[1], d.half[1], d.per[1]);
         const double ez = min_image(pj.z - pi.z, d.len[2], d.half[2], d.per[2]);
@@ -115,7 +153,9 @@ __global__ __launch_bounds__(BLOCK) void k_density(Consts K, const RepDesc* __re
   double e_embed = 0.0;
   if (c.live && c.sub == 0) {
     const double sr = sqrt(rho);
-    q[c.i].w = rho > 0.0 ? -K.A / (2.0 * sr) : 0.0;
+    const double dF = rho > 0.0 ? -K.A / (2.0 * sr) : 0.0;
+    q[c.i].w = dF;
+    if (SHADOW) qs[c.i].w = (float)dF;
     if (rho_out) rho_out[c.i] = rho;
     if (ENERGY) e_embed = -K.A * sr;
     if (!(rho == rho)) S[c.r].nonfinite = 1;
@@ -129,11 +169,12 @@ __global__ __launch_bounds__(BLOCK) void k_density(Consts K, const RepDesc* __re
 // Partial sums written per block by k_force.
 enum { P_PAIR = 0, P_WXX, P_WYY, P_WZZ, P_WXY, P_WXZ, P_WYZ, NP_FORCE };
 
-template <int T, bool MIXED, bool KICK, bool ENERGY>
+template <int T, bool MIXED, bool SHADOW, bool KICK, bool ENERGY>
 __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __restrict__ R,
                                                  RepState* __restrict__ S,
                                                  const int* __restrict__ tile_rep,
                                                  const double4* __restrict__ q,
+                                                 const float4* __restrict__ qs,
                                                  double* __restrict__ v, double* __restrict__ f,
                                                  const uint8_t* __restrict__ fixed,
                                                  const int* __restrict__ idx,
@@ -141,34 +182,31 @@ __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __rest
                                                  double* __restrict__ part) {
   const AtomCtx c = atom_ctx<T>(tile_rep, R);
   const RepDesc& d = R[c.r];
+  __shared__ float4 ctab[27];
+  if (SHADOW) fill_cell_offsets(ctab, S[c.r]);
   double acc[NP_FORCE];
 #pragma unroll
   for (int k = 0; k < NP_FORCE; ++k) acc[k] = 0.0;
   double fx = 0.0, fy = 0.0, fz = 0.0;
   if (c.live) {
     const int64_t i = c.i;
-    const double4 pi = q[i];
     const int n = cnt[i];
     if (MIXED) {
       const float cc = (float)K.c, dd = (float)K.d, c2 = (float)K.c2, rv = (float)K.rv,
                   pmin = (float)K.pmin, csq = (float)K.c_sq, dsq = (float)K.d_sq;
-      const float Fi = (float)pi.w;
       float ax = 0.f, ay = 0.f, az = 0.f;
       float ep = 0.f, w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f, w4 = 0.f, w5 = 0.f;
-      for_neighbors<T, UNROLL>(idx, q, (int)i, n, c.sub, (int)K.ntot, K.lt_shift, [&](const double4& pj) {
-        const float ex = (float)min_image(pj.x - pi.x, d.len[0], d.half[0], d.per[0]);
-        const float ey = (float)min_image(pj.y - pi.y, d.len[1], d.half[1], d.per[1]);
-        const float ez = (float)min_image(pj.z - pi.z, d.len[2], d.half[2], d.per[2]);
+      // pair term for separation (ex, ey, ez) and neighbour F' fj
+      auto pair = [&](float ex, float ey, float ez, float Fi, float fj) {
         const float r2 = ex * ex + ey * ey + ez * ez;
-        // all lanes evaluate; the cutoffs select (no branch: the whole 32-byte gather is
-        // consumed up front)
+        // all lanes evaluate; the cutoffs select (no branch)
         const bool inc = r2 < csq;
         const float rinv = __frsqrt_rn(inc ? r2 : 1.0f);
         const float r = r2 * rinv;
         const float u = r - cc, t = r - rv;
         const float p = pmin + c2 * t * t;                      // c0 + c1 r + c2 r^2, vertex form
         float g = u * (2.0f * p + u * (2.0f * c2 * t));          // phi'(r)
-        g += (r2 < dsq) ? (Fi + (float)pj.w) * (2.0f * (r - dd)) : 0.0f;
+        g += (r2 < dsq) ? (Fi + fj) * (2.0f * (r - dd)) : 0.0f;
         const float s = inc ? g * rinv : 0.0f;                   // F_i += g (q_j - q_i) / r
         ax += s * ex;
         ay += s * ey;
@@ -182,7 +220,26 @@ __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __rest
           w4 -= 0.5f * s * ex * ez;
           w5 -= 0.5f * s * ey * ez;
         }
-      });
+      };
+      if (SHADOW) {
+        const float4 ps = qs[i];
+        for_entries<T, UNROLL>(idx, (int)i, n, c.sub, (int)K.ntot, K.lt_shift,
+                               [&](int e) { return qs[list_slot(e)]; },
+                               [&](const float4& pj, int e) {
+          const float4 o = ctab[list_code(e)];
+          pair((pj.x - ps.x) + o.x, (pj.y - ps.y) + o.y, (pj.z - ps.z) + o.z, ps.w, pj.w);
+        });
+      } else {
+        const double4 pi = q[i];
+        const float Fi = (float)pi.w;
+        for_entries<T, UNROLL>(idx, (int)i, n, c.sub, (int)K.ntot, K.lt_shift,
+                               [&](int e) { return q[list_slot(e)]; },
+                               [&](const double4& pj, int) {
+          pair((float)min_image(pj.x - pi.x, d.len[0], d.half[0], d.per[0]),
+               (float)min_image(pj.y - pi.y, d.len[1], d.half[1], d.per[1]),
+               (float)min_image(pj.z - pi.z, d.len[2], d.half[2], d.per[2]), Fi, (float)pj.w);
+        });
+      }
       fx = ax;
       fy = ay;
       fz = az;
@@ -196,8 +253,11 @@ __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __rest
         acc[P_WYZ] = w5;
       }
     } else {
+      const double4 pi = q[i];
       const double Fi = pi.w;
-      for_neighbors<T, UNROLL>(idx, q, (int)i, n, c.sub, (int)K.ntot, K.lt_shift, [&](const double4& pj) {
+      for_entries<T, UNROLL>(idx, (int)i, n, c.sub, (int)K.ntot, K.lt_shift,
+                             [&](int e) { return q[list_slot(e)]; },
+                             [&](const double4& pj, int) {
         const double ex = min_image(pj.x - pi.x, d.len[0], d.half[0], d.per[0]);
         const double ey = min_image(pj.y - pi.y, d.len[1], d.half[1], d.per[1]);
         const double ez = min_image(pj.z - pi.z, d.len[2], d.half[2], d.per[2]);

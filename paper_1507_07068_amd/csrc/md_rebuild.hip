@@ -42,6 +42,8 @@ struct BuildArgs {
   long long* skey;       // [ntot] (cell, id) sort key of perm's entries
   double4* tq;
   float4* tqf;           // [ntot] sorted positions relative to the replica's grid origin, FP32
+  float4* qs;            // [ntot] FP32 cell-local shadow of q (x, y, z, F')
+  long long* bcell;      // [ntot] build cell of each atom slot (pack_cell)
   double* tv;
   double* tf;
   uint8_t* tfixed;
@@ -73,7 +75,7 @@ constexpr int MAXC = 512;           // candidates staged per window in k_xlist
 constexpr int LIST_BATCH = MD_LIST_BATCH;   // candidate loads issued together in k_list_rows
 constexpr int WAVES_PER_BLOCK = BLOCK / WAVE;
 constexpr int LIST_SEG = 42;      // cells of one cell row per block of k_list_tiles
-constexpr int LIST_STAGE = 1024;  // candidates staged in LDS at a time by k_list_tiles
+constexpr int LIST_STAGE = 768;   // candidates staged in LDS at a time by k_list_tiles
 #ifndef MD_LIST_GROUP
 #define MD_LIST_GROUP 4
 #endif
@@ -111,6 +113,7 @@ __device__ __forceinline__ bool decide_replica(const Consts& K, BuildArgs& A, in
       if (lead) {
         s.glo[a] = d.lo[a];
         s.ginv[a] = d.ginv[a];
+        s.gedge[a] = d.len[a] / d.gcap[a];
         s.gd[a] = d.gcap[a];
       }
       continue;
@@ -132,6 +135,7 @@ __device__ __forceinline__ bool decide_replica(const Consts& K, BuildArgs& A, in
       const int g = (int)fmin(fmax(floor(ext / edge), 1.0), (double)d.gcap[a]);
       s.glo[a] = mn;
       s.ginv[a] = g / ext;
+      s.gedge[a] = ext / g;
       s.gd[a] = g;
     }
   }
@@ -582,6 +586,11 @@ __global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
       A.fme[4 * (int64_t)p + 2] = 0.0;
       A.fme[4 * (int64_t)p + 3] = 0.0;
       A.q[p] = pi;
+      if (K.shadow) {
+        const long long bc = pack_cell(cx, cy, cz);
+        A.bcell[p] = bc;
+        A.qs[p] = cell_local(S, bc, pi.x, pi.y, pi.z, (float)pi.w);
+      }
       A.xref[3 * p + 0] = pi.x;
       A.xref[3 * p + 1] = pi.y;
       A.xref[3 * p + 2] = pi.z;
@@ -614,7 +623,12 @@ __global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
 // the staged row, so the candidate order (rows, along x, by slot) is the same as in
 // k_list_rows and the lists are identical.  Rows longer than LIST_STAGE are staged in
 // chunks.  The FP32 screen and its exact FP64 band are those of k_list_rows.
-__global__ __launch_bounds__(BLOCK) void k_list_tiles(Consts K, BuildArgs A) {
+#ifndef MD_LIST_WAVES
+#define MD_LIST_WAVES 6
+#endif
+// Occupancy floor: this kernel hides the latency of its LDS and global reads with waves, so
+// its registers are held to what MD_LIST_WAVES wavefronts per SIMD can share.
+__global__ __launch_bounds__(BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts K, BuildArgs A) {
   if (rebuild_off(A)) return;
   __shared__ float4 sq[LIST_STAGE];
   __shared__ int sj[LIST_STAGE];
@@ -662,6 +676,7 @@ __global__ __launch_bounds__(BLOCK) void k_list_tiles(Consts K, BuildArgs A) {
     lo_f = (float)(rl2 - delta);
     hi_f = (float)(rl2 + delta);
   }
+  const bool shadow = K.shadow;   // entries carry relative cells only for the FP32 shadow
   const int xa = max(x0 - 1, 0), xb = min(x1 + 1, gx - 1);   // main piece of a staged row
   const bool wl = d.per[0] && x0 == 0, wr = d.per[0] && x1 == gx - 1;   // wrapped end cells
   for (int c0 = 0; c0 < m; c0 += BLOCK) {
@@ -698,8 +713,11 @@ __global__ __launch_bounds__(BLOCK) void k_list_tiles(Consts K, BuildArgs A) {
         toff[t] = u < xa ? 0 : (u <= xb + 1 ? nl + (A.start[rw + u] - A.start[rw + xa]) : total);
       }
       __syncthreads();
-      // this center's window: unwrapped cells cx-1 .. cx+1
+      // this center's window: unwrapped cells cx-1 .. cx+1 (staged offsets w0, b1, b2, w1);
+      // relative-cell code of the row, the x offset added per candidate
       const int w0 = toff[cx - 1 - (x0 - 1)], w1 = toff[cx + 2 - (x0 - 1)];
+      const int b1 = toff[cx - (x0 - 1)], b2 = toff[cx + 1 - (x0 - 1)];
+      const int rcode = 9 * tz + 3 * ty;
       for (int ch = 0; ch < total; ch += LIST_STAGE) {
         const int nch = min(LIST_STAGE, total - ch);
         if (ch > 0) __syncthreads();
@@ -752,8 +770,9 @@ __global__ __launch_bounds__(BLOCK) void k_list_tiles(Consts K, BuildArgs A) {
               }
             }
             for (; in; in &= in - 1) {
-              const int j = sj[s + __builtin_ctz(in)];
-              if (j != p) append(j);
+              const int su = s + __builtin_ctz(in);
+              const int j = sj[su];
+              if (j != p) append(shadow ? j | ((rcode + (su + ch >= b1) + (su + ch >= b2)) << LIST_IDX_BITS) : j);
             }
           }
           for (; s < e1; ++s) {
@@ -763,7 +782,7 @@ __global__ __launch_bounds__(BLOCK) void k_list_tiles(Consts K, BuildArgs A) {
             bool ok = r2f < lo_f;
             if (__builtin_expect(!ok && !(r2f >= hi_f), 0)) ok = exact(s);
             const int j = sj[s];
-            if (ok && j != p) append(j);
+            if (ok && j != p) append(shadow ? j | ((rcode + (s + ch >= b1) + (s + ch >= b2)) << LIST_IDX_BITS) : j);
           }
         }
       }
@@ -783,6 +802,11 @@ __global__ __launch_bounds__(BLOCK) void k_list_tiles(Consts K, BuildArgs A) {
       A.fme[4 * (int64_t)p + 2] = 0.0;
       A.fme[4 * (int64_t)p + 3] = 0.0;
       A.q[p] = pi;
+      if (K.shadow) {
+        const long long bc = pack_cell(cx, cy, cz);
+        A.bcell[p] = bc;
+        A.qs[p] = cell_local(S, bc, pi.x, pi.y, pi.z, (float)pi.w);
+      }
       A.xref[3 * p + 0] = pi.x;
       A.xref[3 * p + 1] = pi.y;
       A.xref[3 * p + 2] = pi.z;

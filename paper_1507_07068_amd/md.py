@@ -47,7 +47,7 @@ class MorseParams(C.Structure):
 class Params(C.Structure):
     _fields_ = [("eam", EamParams), ("morse", MorseParams), ("mass", C.c_double),
                 ("dt", C.c_double), ("v_ind", C.c_double), ("skin", C.c_double),
-                ("cap", C.c_int32), ("xcap", C.c_int32), ("tpa", C.c_int32), ("pad", C.c_int32)]
+                ("cap", C.c_int32), ("xcap", C.c_int32), ("tpa", C.c_int32), ("shadow", C.c_int32)]
 
 
 class ReplicaDesc(C.Structure):
@@ -69,6 +69,11 @@ class Status(C.Structure):
     _fields_ = [("overflow", C.c_int32), ("xoverflow", C.c_int32), ("nonfinite", C.c_int32),
                 ("nbuilds", C.c_int32), ("sync_timeout", C.c_int32), ("nnear", C.c_int32),
                 ("pad", C.c_int32 * 2)]
+
+
+# A Cr-Cr list entry keeps the neighbour's slot in its low 27 bits (the bits above give the
+# neighbour's cell relative to the atom's cell at the build).
+LIST_IDX_MASK = (1 << 27) - 1
 
 
 class MDError(RuntimeError):
@@ -127,7 +132,7 @@ def _ok(code: int, what: str):
         raise MDError(f"{what}: {msg} ({code})")
 
 
-def make_params(s, cap: int = 64, xcap: int = 64, tpa: int = 1) -> Params:
+def make_params(s, cap: int = 64, xcap: int = 64, tpa: int = 1, shadow: bool = False) -> Params:
     p = Params()
     p.eam = EamParams(**{k: float(s.eam[k]) for k in ("A", "c", "d", "c0", "c1", "c2")})
     p.morse = MorseParams(**{k: float(s.morse[k]) for k in ("D", "alpha", "r0", "rc")})
@@ -138,6 +143,7 @@ def make_params(s, cap: int = 64, xcap: int = 64, tpa: int = 1) -> Params:
     p.cap = int(cap)
     p.xcap = int(xcap)
     p.tpa = int(tpa)
+    p.shadow = int(bool(shadow))
     return p
 
 
@@ -160,8 +166,9 @@ class Simulation:
     """
 
     def __init__(self, systems, precision: str = "fp64", cap: int | None = None, xcap: int = 160,
-                 tpa: int = 1, device: str = "cuda:0"):
-        """cap: Cr-Cr list capacity per atom (a multiple of tpa)."""
+                 tpa: int = 1, device: str = "cuda:0", shadow: bool | None = None):
+        """cap: Cr-Cr list capacity per atom (a multiple of tpa).  shadow: keep the FP32
+        cell-local positions for the FP32-mixed passes (default: when precision is mixed)."""
         import torch
         if cap is None:
             cap = 64
@@ -175,7 +182,9 @@ class Simulation:
         self.mixed = precision == "mixed"
         self.device = torch.device(device)
         s0 = self.systems[0]
-        self.params = make_params(s0, cap, xcap, tpa)
+        # the FP32 cell-local shadow serves the FP32-mixed passes only
+        self.params = make_params(s0, cap, xcap, tpa,
+                                  shadow=(precision == "mixed") if shadow is None else shadow)
         self.tpa = tpa
         descs = (ReplicaDesc * self.nrep)(*[make_replica_desc(s) for s in self.systems])
         h = C.c_void_p()
@@ -425,7 +434,7 @@ class Simulation:
         rows = []
         for p in (range(n) if slots is None else slots):
             kk = k[:cnt[p]]
-            rows.append(idx[(kk // T) * n * T + p * T + kk % T])
+            rows.append(idx[(kk // T) * n * T + p * T + kk % T] & LIST_IDX_MASK)
         return rows
 
     def list_counts(self) -> np.ndarray:

@@ -213,9 +213,13 @@ def test_morse_standalone_equals_fused():
     assert np.allclose(oa[[2, 10, 11, 12]], ob[[2, 10, 11, 12]], rtol=1e-12, atol=1e-14)
 
 
-def test_mixed_precision_force_error():
+@pytest.mark.parametrize("shadow", [True, False])
+def test_mixed_precision_force_error(shadow):
+    """FP32-mixed forces within 1e-5 of the oracle, with separations from the FP32
+    cell-local shadow or from rounded FP64 separations."""
     for s in (I.config(0), I.small_film(nx=8, ny=8, nz=6, radius=8.0, gap=-1.0, seed=4, noise=0.05)):
-        sim = sim_of(s, precision="mixed")
+        print(f"[case] {s.name} mixed shadow={shadow}", flush=True)
+        sim = md.Simulation(s, precision="mixed", xcap=128, shadow=shadow)
         obs, st = _initial(sim)
         ref = O.evaluate(s, O.wrap(s))
         rel, mx = force_errors(st["f"], ref["f"])
