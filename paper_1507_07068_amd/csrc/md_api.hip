@@ -83,7 +83,7 @@ Layout make_layout(const md_system& s) {
   L.skey = take(sizeof(long long) * n);
   L.tq = take(sizeof(double) * 4 * n);
   L.tqf = take(sizeof(float) * 4 * n);
-  L.qs = take(sizeof(float) * 4 * n);
+  L.qs = take(sizeof(int) * 4 * n);
   L.bcell = take(sizeof(long long) * n);
   L.tv = take(sizeof(double) * 3 * n);
   L.tf = take(sizeof(double) * 3 * n);
@@ -144,7 +144,7 @@ void launch_density(md_system* s, const md_atoms* a, const md_lists* l, bool mix
   double4* q = reinterpret_cast<double4*>(a->q);
   double* pe = at<double>(s, s->L.p_embed);
   const int nb = s->ntiles * T;
-  float4* qs = at<float4>(s, s->L.qs);
+  int4* qs = at<int4>(s, s->L.qs);
 #define DENS(M, SH, E) \
   k_density<T, M, SH, E><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, qs, l->idx, l->cnt, rho_out, pe)
   if (mixed && s->K.shadow && !s->list_mix) { if (energy) DENS(true, true, true); else DENS(true, true, false); }
@@ -162,7 +162,7 @@ void launch_force(md_system* s, const md_atoms* a, const md_lists* l, bool mixed
   const double4* q = reinterpret_cast<const double4*>(a->q);
   double* pf = at<double>(s, s->L.p_force);
   const int nb = s->ntiles * T;
-  const float4* qs = at<float4>(s, s->L.qs);
+  const int4* qs = at<int4>(s, s->L.qs);
 #define FORCE(M, SH, KI, E) \
   k_force<T, M, SH, KI, E><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, qs, a->v, a->f, a->fixed, l->idx, l->cnt, pf)
 #define FORCE_E(M, SH, KI) \
@@ -403,7 +403,7 @@ MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l
   A.skey = at<long long>(s, s->L.skey);
   A.tq = at<double4>(s, s->L.tq);
   A.tqf = at<float4>(s, s->L.tqf);
-  A.qs = at<float4>(s, s->L.qs);
+  A.qs = at<int4>(s, s->L.qs);
   A.bcell = at<long long>(s, s->L.bcell);
   A.tv = at<double>(s, s->L.tv);
   A.tf = at<double>(s, s->L.tf);
@@ -505,7 +505,7 @@ MD_API int md_verlet_step(md_system* s, int32_t phase, const md_atoms* a, void* 
     k_kick_drift<<<nb, BLOCK, 0, st>>>(s->K, R, at<RepState>(s, s->L.state), tr,
                                        reinterpret_cast<double4*>(a->q), a->v, a->f, a->fixed,
                                        at<double>(s, s->L.xref), at<double>(s, s->L.dmax),
-                                       at<double>(s, s->L.tbox), at<float4>(s, s->L.qs),
+                                       at<double>(s, s->L.tbox), at<int4>(s, s->L.qs),
                                        at<long long>(s, s->L.bcell));
   else
     k_kick<<<nb, BLOCK, 0, st>>>(s->K, R, tr, a->v, a->f, a->fixed);

@@ -47,6 +47,7 @@ struct alignas(64) RepState {
   // periodic axes it is the box; along open axes it spans the atoms' current extent.
   double glo[3], ginv[3];
   double gedge[3];        // cell edge of that grid (1 / ginv)
+  double qscale;          // fixed-point scale of the shadow positions (a power of two)
   int gd[3];
 };
 
@@ -62,12 +63,16 @@ __device__ __forceinline__ int list_code(int e) { return (int)((unsigned)e >> LI
 __device__ __forceinline__ long long pack_cell(int cx, int cy, int cz) {
   return (long long)cx | ((long long)cy << 21) | ((long long)cz << 42);
 }
-// FP32 position of an atom relative to the corner of its build cell (the shadow used by the
-// FP32-mixed passes): small numbers, so FP32 keeps ~1e-7 A of the separation.
-__device__ __forceinline__ float4 cell_local(const RepState& s, long long bc, double x, double y, double z, float w) {
+// Shadow position of an atom for the FP32-mixed passes: its offset from the centre of its
+// build cell in fixed point (units of 1 / qscale, with qscale chosen so a cell edge is at
+// most 2^29 units), and F' as FP32 bits in w.  The separation of two atoms is then an exact
+// integer sum -- shadow_j - shadow_i + (relative cell) x edge -- rounded once to FP32, the
+// same rounding as an FP64 separation converted to FP32.
+__device__ __forceinline__ int4 cell_local(const RepState& s, long long bc, double x, double y, double z, float w) {
   const int cx = (int)(bc & 0x1FFFFF), cy = (int)((bc >> 21) & 0x1FFFFF), cz = (int)((bc >> 42) & 0x1FFFFF);
-  return make_float4((float)(x - (s.glo[0] + cx * s.gedge[0])), (float)(y - (s.glo[1] + cy * s.gedge[1])),
-                     (float)(z - (s.glo[2] + cz * s.gedge[2])), w);
+  return make_int4((int)rint((x - (s.glo[0] + (cx + 0.5) * s.gedge[0])) * s.qscale),
+                   (int)rint((y - (s.glo[1] + (cy + 0.5) * s.gedge[1])) * s.qscale),
+                   (int)rint((z - (s.glo[2] + (cz + 0.5) * s.gedge[2])) * s.qscale), __float_as_int(w));
 }
 
 // Constants of the potential and the integrator (passed by value).

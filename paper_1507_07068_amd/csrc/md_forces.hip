@@ -1,7 +1,7 @@
 // Task 4 (and the fused Task 5 kick) of the MD step on gfx950.  Included by md_kernels.hip.
 //
 //   k_density<T>   rho_i = sum_j f(r_ij), F'(rho_i) -> q[i].w   (Section 3.3.1.2)
-//                  (FP32-mixed: separations from the FP32 cell-local shadow of q)
+//                  (FP32-mixed: separations from the fixed-point cell-local shadow of q)
 //   k_force<T>     Eq. (1): F_i = -sum_j [(F'_i + F'_j) f'(r) + phi'(r)] (q_i - q_j) / r
 //   k_morse        Cr-C Morse forces: one wavefront per Cr atom that has carbons in range
 //   k_kick         Task 5 on its own
@@ -53,13 +53,15 @@ __device__ __forceinline__ void for_entries(const int* __restrict__ idx, int i, 
   }
 }
 
-// Offsets of the 27 relative cells of a list entry in the block's replica, FP32: the
-// separation of two atoms is (shadow_j - shadow_i) + offset[code].
-__device__ __forceinline__ void fill_cell_offsets(float4* tab, const RepState& s) {
+// Offsets of the 27 relative cells of a list entry in the block's replica, in shadow units:
+// the separation of two atoms is (shadow_j - shadow_i + offset[code]) / qscale.
+__device__ __forceinline__ void fill_cell_offsets(int4* tab, const RepState& s) {
   const int t = threadIdx.x;
-  if (t < 27)
-    tab[t] = make_float4((float)((t % 3 - 1) * s.gedge[0]), (float)((t / 3 % 3 - 1) * s.gedge[1]),
-                         (float)((t / 9 - 1) * s.gedge[2]), 0.0f);
+  if (t < 27) {
+    const double q = s.qscale;
+    tab[t] = make_int4((t % 3 - 1) * (int)rint(s.gedge[0] * q), (t / 3 % 3 - 1) * (int)rint(s.gedge[1] * q),
+                       (t / 9 - 1) * (int)rint(s.gedge[2] * q), 0);
+  }
   __syncthreads();
 }
 
@@ -86,35 +88,37 @@ __device__ __forceinline__ AtomCtx atom_ctx(const int* tile_rep, const RepDesc* 
   return c;
 }
 
-// SHADOW (with MIXED): separations from the FP32 cell-local shadow qs and the entries'
+// SHADOW (with MIXED): separations from the fixed-point cell-local shadow qs and the entries'
 // relative cells; otherwise FP64 positions (rounded to FP32 for the MIXED arithmetic).
 template <int T, bool MIXED, bool SHADOW, bool ENERGY>
 __global__ __launch_bounds__(BLOCK) void k_density(Consts K, const RepDesc* __restrict__ R,
                                                    RepState* __restrict__ S,
                                                    const int* __restrict__ tile_rep,
                                                    double4* __restrict__ q,
-                                                   float4* __restrict__ qs,
+                                                   int4* __restrict__ qs,
                                                    const int* __restrict__ idx,
                                                    const int* __restrict__ cnt,
                                                    double* __restrict__ rho_out,
                                                    double* __restrict__ part) {
   const AtomCtx c = atom_ctx<T>(tile_rep, R);
   const RepDesc& d = R[c.r];
-  __shared__ float4 ctab[27];
+  __shared__ int4 ctab[27];
   if (SHADOW) fill_cell_offsets(ctab, S[c.r]);
   double rho = 0.0;
   if (c.live) {
     const int64_t i = c.i;
     const int n = cnt[i];
     if (MIXED && SHADOW) {
-      const float4 ps = qs[i];
+      const int4 ps = qs[i];
+      const float qi = (float)(1.0 / S[c.r].qscale);
       float acc = 0.0f;
       const float dd = (float)K.d, dd2 = (float)K.d_sq;
       for_entries<T, UNROLL>(idx, (int)i, n, c.sub, (int)K.ntot, K.lt_shift,
                              [&](int e) { return qs[list_slot(e)]; },
-                             [&](const float4& pj, int e) {
-        const float4 o = ctab[list_code(e)];
-        const float ex = (pj.x - ps.x) + o.x, ey = (pj.y - ps.y) + o.y, ez = (pj.z - ps.z) + o.z;
+                             [&](const int4& pj, int e) {
+        const int4 o = ctab[list_code(e)];
+        const float ex = (float)(pj.x - ps.x + o.x) * qi, ey = (float)(pj.y - ps.y + o.y) * qi,
+                    ez = (float)(pj.z - ps.z + o.z) * qi;
         const float r2 = ex * ex + ey * ey + ez * ez;
         const float u = __fsqrt_rn(r2) - dd;
         acc += (r2 < dd2) ? u * u : 0.0f;
@@ -155,7 +159,7 @@ __global__ __launch_bounds__(BLOCK) void k_density(Consts K, const RepDesc* __re
     const double sr = sqrt(rho);
     const double dF = rho > 0.0 ? -K.A / (2.0 * sr) : 0.0;
     q[c.i].w = dF;
-    if (SHADOW) qs[c.i].w = (float)dF;
+    if (SHADOW) qs[c.i].w = __float_as_int((float)dF);
     if (rho_out) rho_out[c.i] = rho;
     if (ENERGY) e_embed = -K.A * sr;
     if (!(rho == rho)) S[c.r].nonfinite = 1;
@@ -174,7 +178,7 @@ __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __rest
                                                  RepState* __restrict__ S,
                                                  const int* __restrict__ tile_rep,
                                                  const double4* __restrict__ q,
-                                                 const float4* __restrict__ qs,
+                                                 const int4* __restrict__ qs,
                                                  double* __restrict__ v, double* __restrict__ f,
                                                  const uint8_t* __restrict__ fixed,
                                                  const int* __restrict__ idx,
@@ -182,7 +186,7 @@ __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __rest
                                                  double* __restrict__ part) {
   const AtomCtx c = atom_ctx<T>(tile_rep, R);
   const RepDesc& d = R[c.r];
-  __shared__ float4 ctab[27];
+  __shared__ int4 ctab[27];
   if (SHADOW) fill_cell_offsets(ctab, S[c.r]);
   double acc[NP_FORCE];
 #pragma unroll
@@ -222,12 +226,15 @@ __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __rest
         }
       };
       if (SHADOW) {
-        const float4 ps = qs[i];
+        const int4 ps = qs[i];
+        const float qi = (float)(1.0 / S[c.r].qscale);
+        const float Fi = __int_as_float(ps.w);
         for_entries<T, UNROLL>(idx, (int)i, n, c.sub, (int)K.ntot, K.lt_shift,
                                [&](int e) { return qs[list_slot(e)]; },
-                               [&](const float4& pj, int e) {
-          const float4 o = ctab[list_code(e)];
-          pair((pj.x - ps.x) + o.x, (pj.y - ps.y) + o.y, (pj.z - ps.z) + o.z, ps.w, pj.w);
+                               [&](const int4& pj, int e) {
+          const int4 o = ctab[list_code(e)];
+          pair((float)(pj.x - ps.x + o.x) * qi, (float)(pj.y - ps.y + o.y) * qi,
+               (float)(pj.z - ps.z + o.z) * qi, Fi, __int_as_float(pj.w));
         });
       } else {
         const double4 pi = q[i];

@@ -52,7 +52,7 @@ __device__ __forceinline__ void tile_box_store(const RepDesc& d, bool live, doub
 }
 
 // v(t + dt/2) = v + a dt / 2 and r(t + dt) = r + v(t + dt/2) dt (algebraically Eq. A11) for
-// mobile atoms, and their FP32 cell-local shadow; the indenter moves by v_ind dt.  Writes
+// mobile atoms, and their cell-local shadow; the indenter moves by v_ind dt.  Writes
 // max |r - r_ref|^2 of each tile and the tile's bounding box along open axes.
 __global__ __launch_bounds__(BLOCK) void k_kick_drift(Consts K, const RepDesc* __restrict__ R,
                                                       RepState* __restrict__ S,
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(Consts K, const RepDesc* _
                                                       const double* __restrict__ xref,
                                                       double* __restrict__ dmax_tile,
                                                       double* __restrict__ tile_box,
-                                                      float4* __restrict__ qs,
+                                                      int4* __restrict__ qs,
                                                       const long long* __restrict__ bcell) {
   TileCtx c = tile_ctx(tile_rep, R);
   double d2 = 0.0;
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(Consts K, const RepDesc* _
       v[3 * i + 1] = vy;
       v[3 * i + 2] = vz;
       q[i] = p;
-      if (K.shadow) qs[i] = cell_local(S[c.r], bcell[i], p.x, p.y, p.z, (float)p.w);   // FP32 shadow
+      if (K.shadow) qs[i] = cell_local(S[c.r], bcell[i], p.x, p.y, p.z, (float)p.w);   // shadow
     }
     double ex = p.x - xref[3 * i + 0];
     double ey = p.y - xref[3 * i + 1];

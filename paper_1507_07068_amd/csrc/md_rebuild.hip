@@ -42,7 +42,7 @@ struct BuildArgs {
   long long* skey;       // [ntot] (cell, id) sort key of perm's entries
   double4* tq;
   float4* tqf;           // [ntot] sorted positions relative to the replica's grid origin, FP32
-  float4* qs;            // [ntot] FP32 cell-local shadow of q (x, y, z, F')
+  int4* qs;              // [ntot] fixed-point cell-local shadow of q (x, y, z, F' bits)
   long long* bcell;      // [ntot] build cell of each atom slot (pack_cell)
   double* tv;
   double* tf;
@@ -138,6 +138,10 @@ __device__ __forceinline__ bool decide_replica(const Consts& K, BuildArgs& A, in
       s.gedge[a] = ext / g;
       s.gd[a] = g;
     }
+  }
+  if (lead) {   // shadow scale: the longest cell edge spans at most 2^29 units
+    const double emax = fmax(s.gedge[0], fmax(s.gedge[1], s.gedge[2]));
+    s.qscale = ldexp(1.0, 29 - (int)ceil(log2(emax)));
   }
   return true;
 }
