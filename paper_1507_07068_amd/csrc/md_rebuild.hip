@@ -68,11 +68,11 @@ struct BuildArgs {
   int scan_chunk, scan_blocks;
 };
 
-constexpr int MAXC = 512;           // candidates staged per window in k_xlist
 #ifndef MD_LIST_BATCH
 #define MD_LIST_BATCH 4
 #endif
 constexpr int LIST_BATCH = MD_LIST_BATCH;   // candidate loads issued together in k_list_rows
+constexpr int MAXC = 512;           // candidates staged per window in k_xlist
 constexpr int WAVES_PER_BLOCK = BLOCK / WAVE;
 constexpr int LIST_SEG = 42;      // cells of one cell row per block of k_list_tiles
 constexpr int LIST_STAGE = 768;   // candidates staged in LDS at a time by k_list_tiles
@@ -389,10 +389,15 @@ __global__ __launch_bounds__(BLOCK) void k_sort_gather(Consts K, BuildArgs A) {
     const int c = (int)(key >> 32);
     const int sbase = d.a0 - A.start[d.g0];
     const int s0 = sbase + A.start[c], s1 = sbase + A.start[c + 1];
-    int rank = 0;
-    for (int t = s0; t < s1; ++t) rank += A.skey[t] < key ? 1 : 0;
-    if (u == s0) A.count[c] = 0;   // zero again for the next rebuild
     const int e = A.perm[u];
+    int rank = 0;
+    int t = s0;
+    for (; t + 4 <= s1; t += 4) {   // four independent key loads at a time
+      const long long k0 = A.skey[t], k1 = A.skey[t + 1], k2 = A.skey[t + 2], k3 = A.skey[t + 3];
+      rank += (k0 < key) + (k1 < key) + (k2 < key) + (k3 < key);
+    }
+    for (; t < s1; ++t) rank += A.skey[t] < key ? 1 : 0;
+    if (u == s0) A.count[c] = 0;   // zero again for the next rebuild
     const int p = s0 + rank;
     const double4 qe = A.q[e];
     A.tq[p] = qe;
