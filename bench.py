@@ -27,9 +27,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "atom-steps/s EAM+Morse MD step, FP32-mixed & batched vs FP64 at ≤1e-5 force err"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_force_c1_fp64_traffic.txt")
-FORCE_SOURCES = [os.path.join(ROOT, "paper_1507_07068_amd", "csrc", f)
-                 for f in ("md_forces.hip", "md_device.hpp")]
+TIME_EVERY = 8   # kernel timing events on every TIME_EVERY-th step
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c1_fp64_hbm_traffic.txt")
+SOURCES = {k: [os.path.join(ROOT, "paper_1507_07068_amd", "csrc", f) for f in v]
+           for k, v in (("force", ("md_forces.hip", "md_device.hpp")),
+                        ("list", ("md_rebuild.hip", "md_device.hpp")))}
 
 WORKLOADS = {
     "c0": (0, "bcc_bulk_10x10x10_2k_periodic"),
@@ -52,19 +54,29 @@ def force_bytes_per_atom(mean_list: float) -> float:
     return 32 + 4 + 4 * mean_list + 1 + 48 + 24
 
 
-def force_source_hash() -> str:
+def list_bytes_per_atom(mean_list: float) -> float:
+    """Algorithmic HBM bytes of one Cr-Cr list-build launch per rebuilt atom: read the
+    cell-sorted state (q 32, FP32 copy 16, v 24, f 24, fixed 1, id 4) = 101; write it back
+    (q 32, reference position 24, v 24, f 24, fixed 1, id 4) plus the list count 4, list
+    entries 4 each, Cr-C count 4 and the cleared Morse record 32 = 149 + 4 L.  Candidate
+    positions come from cache (each cell row is staged once per block)."""
+    return 101 + 149 + 4 * mean_list
+
+
+def source_hash(kind: str) -> str:
     h = hashlib.sha256()
-    for f in FORCE_SOURCES:
+    for f in SOURCES[kind]:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(n_launch_atoms: int):
-    """HBM bytes per force launch from the committed counter summary (FETCH_SIZE and
-    WRITE_SIZE per dispatch, each scaled by the same counter's reading for a plain copy of
-    known size), or None when there is no summary for this workload or the force kernel's
-    sources changed since the counters were taken."""
+def measured_traffic(kind: str, n_launch_atoms: int):
+    """HBM bytes per launch of the force ("force") or list-build ("list") kernel from the
+    committed counter summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by the
+    same counter's reading for a plain copy of known size), or None when there is no
+    summary for this workload or the kernel's sources changed since the counters were
+    taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -74,12 +86,13 @@ def measured_traffic(n_launch_atoms: int):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
     try:
-        if kv["source_sha256"] != force_source_hash() or int(kv["atoms"]) != n_launch_atoms:
+        if kv[kind + "_source_sha256"] != source_hash(kind) or int(kv["atoms"]) != n_launch_atoms:
             return None
         copy_b = float(kv["copy_bytes"])
         f_scale = copy_b / (float(kv["copy_fetch_kib"]) * 1024.0)
         w_scale = copy_b / (float(kv["copy_write_kib"]) * 1024.0)
-        return (float(kv["fetch_kib"]) * 1024.0 * f_scale + float(kv["write_kib"]) * 1024.0 * w_scale)
+        return (float(kv[kind + "_fetch_kib"]) * 1024.0 * f_scale
+                + float(kv[kind + "_write_kib"]) * 1024.0 * w_scale)
     except (KeyError, ValueError, ZeroDivisionError):
         return None
 
@@ -119,10 +132,15 @@ def timed_run(systems, precision, steps, warmup, ee, tpa, events=True):
         nobs = steps // ee if ee > 0 else 0
         obs = torch.zeros((max(nobs, 1), sim.nrep, md.MD_NOBS), dtype=torch.float64, device="cuda")
         ev = None
+        timed = list(range(0, steps, TIME_EVERY)) if events else []
         if events:
-            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
-            for e in ev:          # torch creates the HIP event at its first record
-                e.record(stream)
+            # events around the force and list kernels of every TIME_EVERY-th step (recording
+            # them at every step would add their own cost to the step time)
+            ev = [None] * (4 * steps)
+            for k in timed:
+                for u in range(4):
+                    ev[4 * k + u] = torch.cuda.Event(enable_timing=True)
+                    ev[4 * k + u].record(stream)   # torch creates the HIP event at its first record
         builds0 = flags["nbuilds"]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -132,16 +150,34 @@ def timed_run(systems, precision, steps, warmup, ee, tpa, events=True):
         flags = sim.md_check()
         if flags["overflow"] or flags["xoverflow"] or flags["nonfinite"] or flags["sync_timeout"]:
             raise SystemExit(f"invalid run: {flags}")
-        k_ms = (np.array([ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(steps)])
+        k_ms = (np.array([ev[4 * k].elapsed_time(ev[4 * k + 1]) for k in timed])
+                if events else np.zeros(1))
+        l_ms = (np.array([ev[4 * k + 2].elapsed_time(ev[4 * k + 3]) for k in timed])
                 if events else np.zeros(1))
         cnt = sim.list_counts()
         live = np.concatenate([np.arange(o, o + s.n) for o, s in zip(sim.offsets, systems)])
         mean_list = float(cnt[live].mean()) if live.size else 0.0
         o = obs.cpu().numpy()
     n_atoms = sum(s.n for s in systems)
+    builds = flags["nbuilds"] - builds0
+    # sampled list-kernel launches: those that rebuilt are far longer than those that return
+    # at once, so they are told apart by the geometric mean of the extremes; totals are
+    # the per-kind averages times the whole run's counts
+    l_avg = l_idle = 0.0
+    if events and builds:
+        cut = np.sqrt(max(l_ms.min(), 1e-6) * l_ms.max())
+        reb = l_ms[l_ms > cut]
+        if reb.size and reb.size < l_ms.size:
+            l_avg, l_idle = float(reb.mean()) * 1e-3, float(l_ms[l_ms <= cut].mean()) * 1e-3
+        else:   # every sampled launch of one kind: rebuilt at each sampled step or at none
+            l_avg = float(l_ms.mean()) * 1e-3 if builds * 2 > steps else 0.0
+    elif events:
+        l_idle = float(l_ms.mean()) * 1e-3
+    l_total = l_avg * builds + l_idle * (steps - builds)
     return dict(sim=sim, rate=n_atoms * steps / wall, wall=wall, ms_per_step=wall / steps * 1e3,
-                k_avg=float(k_ms.mean()) * 1e-3, mean_list=mean_list,
-                builds=flags["nbuilds"] - builds0, obs=o[:nobs], n_atoms=n_atoms)
+                k_avg=float(k_ms.mean()) * 1e-3, l_avg=l_avg, l_total=l_total,
+                k_total=float(k_ms.mean()) * 1e-3 * steps, mean_list=mean_list,
+                builds=builds, obs=o[:nobs], n_atoms=n_atoms)
 
 
 def force_error_vs_fp64(systems, tpa):
@@ -285,9 +321,17 @@ def main(argv=None):
     log(f"[bench] {rate:.4e} atom-steps/s, {r['ms_per_step']:.4f} ms/step, EAM force kernel "
         f"{k_avg * 1e6:.2f} us avg ({achieved:.0f} GB/s algorithmic), mean list {mean_list:.2f}, "
         f"{r['builds']} list builds, E_tot first/last {e_tot[0]:.6f} / {e_tot[-1]:.6f} eV")
-    traffic = None   # measured HBM bytes per launch (compare with bytes_per_launch)
+    # (+24 B per atom for the fixed-point shadow and build cell written in mixed runs)
+    lbytes = (n_atoms * (list_bytes_per_atom(mean_list) + (24 if precision == "mixed" else 0))
+              if len(systems) == 1 else None)
+    l_achieved = lbytes / r["l_avg"] / 1e9 if (lbytes and r["l_avg"] > 0) else None
+    traffic = ltraffic = None   # measured HBM bytes per launch (compare with bytes_per_launch)
     if args.workload == "c1" and precision == "fp64" and args.tpa == 2:
-        traffic = measured_traffic(n_atoms)
+        traffic = measured_traffic("force", n_atoms)
+        ltraffic = measured_traffic("list", n_atoms)
+    log(f"[bench] list kernel {r['l_avg'] * 1e6:.2f} us per rebuild launch"
+        + (f" ({l_achieved:.0f} GB/s algorithmic)" if l_achieved else "")
+        + f"; GPU time in list / force kernels {r['l_total'] * 1e3:.1f} / {r['k_total'] * 1e3:.1f} ms")
     result = {
         "metric": METRIC,
         "value": rate,
@@ -305,12 +349,24 @@ def main(argv=None):
                    "replicas": len(systems), "precision": precision, "energy_every": ee,
                    "list_builds": r["builds"], "mean_list_len": round(mean_list, 3),
                    "lanes_per_atom": args.tpa},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_force (EAM Eq. 1 + fused final kick)",
-                     "avg_us": k_avg * 1e6, "bytes_per_launch": bytes_launch},
+        "roofline": None,
+        "roofline_force": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                           "kernel": "k_force (EAM Eq. 1 + fused final kick)",
+                           "avg_us": k_avg * 1e6, "bytes_per_launch": bytes_launch,
+                           "gpu_ms_total": r["k_total"] * 1e3},
         "cpu_baseline": None,
     }
+    if l_achieved:
+        result["roofline_list"] = {"bound": "hbm", "achieved": l_achieved, "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": l_achieved / HBM_PEAK_GBS, "traffic": ltraffic,
+                                   "kernel": "k_list_tiles (Cr-Cr Verlet list build, rebuild launches)",
+                                   "avg_us": r["l_avg"] * 1e6, "bytes_per_launch": lbytes,
+                                   "gpu_ms_total": r["l_total"] * 1e3}
+    # the dominant kernel: the one with the most GPU time over the timed steps
+    dom = ("roofline_list" if ("roofline_list" in result
+                               and r["l_total"] > r["k_total"]) else "roofline_force")
+    result["roofline"] = dict(result[dom], dominant_of=["k_force", "k_list_tiles"])
     if not args.no_variants and args.workload == "c1" and args.steps is None:
         result["variants"] = variants(args.tpa)
     if not args.no_cpu_baseline and len(systems) == 1 and systems[0].n <= 300_000:

@@ -243,8 +243,11 @@ MD_API int md_energy(md_system *sys, const md_atoms *a, double *out, void *strea
  * flags: MD_F_MIXED selects FP32 arithmetic.  energy_every > 0: after step k with
  * k % energy_every == 0 the energies are written as by md_energy to
  * obs[(k / energy_every - 1) * nrep * MD_NOBS ...] (device memory, caller-owned).
- * events: NULL, or 2*nsteps hipEvent_t handles (created by the caller) recorded on
- * `stream` just before and just after each step's EAM force kernel (Eq. 1), for timing.
+ * events: NULL, or 4*nsteps hipEvent_t handles (created by the caller) recorded on
+ * `stream`, for timing: events[4k], events[4k+1] just before and after step k's EAM force
+ * kernel (Eq. 1), events[4k+2], events[4k+3] just before and after its Cr-Cr list kernel
+ * (which returns at once when no rebuild is due); NULL entries are not recorded (to time a
+ * sample of the steps).
  * Lists must have been built and forces evaluated once before the first step
  * (md_build_neighbors with MD_B_FORCE, md_eam_forces with DENSITY|FORCE|MORSE). */
 MD_API int md_run(md_system *sys, const md_atoms *a, const md_lists *l, int32_t nsteps,

@@ -377,11 +377,12 @@ MD_API int md_workspace_bind(md_system* s, void* ws, size_t bytes, void* stream)
   return hip_status(hipStreamSynchronize(st));
 }
 
-MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l, uint32_t flags,
-                              void* stream) {
-  if (!s || !atoms_ok(a) || !lists_ok(l) || (s->ctot > 0 && !a->xc)) return MD_ERR_ARG;
-  if (!s->ws) return MD_ERR_STATE;
-  hipStream_t st = (hipStream_t)stream;
+namespace {
+
+// The list build; ev0 / ev1 (or null) are recorded just before and after the Cr-Cr list
+// kernel.
+int build_chain(md_system* s, const md_atoms* a, const md_lists* l, uint32_t flags, hipStream_t st,
+                hipEvent_t ev0, hipEvent_t ev1) {
   int* misc = at<int>(s, s->L.misc);
   BuildArgs A;
   A.R = at<RepDesc>(s, s->L.desc);
@@ -441,12 +442,24 @@ MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l
   k_scan<<<s->scan_blocks, BLOCK, 0, st>>>(A);
   k_scatter<<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A);
   k_sort_gather<<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A);
+  int e;
+  if (ev0 && (e = hip_status(hipEventRecord(ev0, st)))) return e;
   if (s->list_mix)
     k_list_rows<false><<<s->ntiles, BLOCK, 0, st>>>(s->K, A);
   else
     k_list_tiles<<<s->nlblk, BLOCK, 0, st>>>(s->K, A);
+  if (ev1 && (e = hip_status(hipEventRecord(ev1, st)))) return e;
   k_xlist<<<A.near_blocks, BLOCK, 0, st>>>(s->K, A);
   return check_launch();
+}
+
+}  // namespace
+
+MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l, uint32_t flags,
+                              void* stream) {
+  if (!s || !atoms_ok(a) || !lists_ok(l) || (s->ctot > 0 && !a->xc)) return MD_ERR_ARG;
+  if (!s->ws) return MD_ERR_STATE;
+  return build_chain(s, a, l, flags, (hipStream_t)stream, nullptr, nullptr);
 }
 
 MD_API int md_eam_forces(md_system* s, const md_atoms* a, const md_lists* l, uint32_t flags,
@@ -539,13 +552,16 @@ MD_API int md_run(md_system* s, const md_atoms* a, const md_lists* l, int32_t ns
   for (int k = 1; k <= nsteps; ++k) {
     const bool en = energy_every > 0 && k % energy_every == 0;
     if ((e = md_verlet_step(s, MD_PHASE_KICK_DRIFT, a, stream))) return e;
-    if ((e = md_build_neighbors(s, a, l, 0, stream))) return e;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (events)
+      for (int u = 0; u < 4; ++u) ev[u] = (hipEvent_t)events[4 * (k - 1) + u];
+    if ((e = build_chain(s, a, l, 0, st, ev[2], ev[3]))) return e;
     if ((e = md_eam_forces(s, a, l, MD_F_DENSITY | mixed | (en ? MD_F_ENERGY : 0), nullptr, stream)))
       return e;
-    if (events && (e = hip_status(hipEventRecord((hipEvent_t)events[2 * (k - 1)], st)))) return e;
+    if (ev[0] && (e = hip_status(hipEventRecord(ev[0], st)))) return e;
     if ((e = md_eam_forces(s, a, l, MD_F_FORCE | MD_F_KICK | mixed | (en ? MD_F_ENERGY : 0), nullptr, stream)))
       return e;
-    if (events && (e = hip_status(hipEventRecord((hipEvent_t)events[2 * (k - 1) + 1], st)))) return e;
+    if (ev[1] && (e = hip_status(hipEventRecord(ev[1], st)))) return e;
     if ((e = md_morse_forces(s, a, l, MD_F_KICK | mixed, stream))) return e;
     if (en) {
       double* out = obs + (int64_t)(k / energy_every - 1) * s->nrep * MD_NOBS;

@@ -321,14 +321,17 @@ class Simulation:
 
     def md_run(self, nsteps: int, energy_every: int = 0, obs=None, events=None):
         """Enqueue nsteps whole steps in C.  obs: device float64 tensor with room for
-        nsteps // energy_every rows of (nrep, MD_NOBS); events: list of 2*nsteps
-        torch.cuda.Event recorded around each force kernel (each recorded once before, so
-        that its HIP event exists)."""
+        nsteps // energy_every rows of (nrep, MD_NOBS); events: list of 4*nsteps
+        torch.cuda.Event or None, per step two around the EAM force kernel and two around the
+        Cr-Cr list kernel (each event recorded once before, so that its HIP event exists;
+        None: not recorded)."""
         flags = MD_F_MIXED if self.mixed else 0
         ev = None
         if events is not None:
-            handles = [e.cuda_event for e in events]
-            if not all(handles):
+            if len(events) != 4 * nsteps:
+                raise MDError("md_run: give 4 timing events (or None) per step")
+            handles = [None if e is None else e.cuda_event for e in events]
+            if not all(h is None or h for h in handles):
                 raise MDError("md_run: record each timing event once before passing it")
             ev = (C.c_void_p * len(events))(*handles)
         _ok(self.lib.md_run(self.handle, C.byref(self._atoms()), C.byref(self._lists()), int(nsteps),

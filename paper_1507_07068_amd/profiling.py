@@ -42,7 +42,7 @@ def stats(d: str) -> str:
 
 def steps(d: str) -> str:
     """Kernel durations per step (a step starts at k_kick_drift), split into steps with and
-    without a list rebuild (k_list_rows longer than 20 us)."""
+    without a list rebuild (Cr-Cr list kernel longer than 20 us)."""
     c = sqlite3.connect(_db(d))
     rows = list(c.execute("select name, start, end from kernels order by start"))
     groups, cur = [], None
@@ -60,7 +60,7 @@ def steps(d: str) -> str:
         dur = collections.defaultdict(float)
         for k, s, e in g:
             dur[k] += (e - s) / 1e3
-        lst = dur.get("k_list_rows<true>", dur.get("k_list_rows<false>", 0.0))
+        lst = sum(v for k, v in dur.items() if k.startswith(("k_list_tiles", "k_list_rows")))
         split["rebuild" if lst > 20.0 else "no rebuild"].append((dur, (g[-1][2] - g[0][1]) / 1e3))
     for name, gs in split.items():
         if not gs:
