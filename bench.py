@@ -113,6 +113,38 @@ def cpu_baseline(system, steps_per_build: float) -> dict:
                       f"{t:.1f} s wall"}
 
 
+class TimingEvent:
+    """A HIP event for kernel timing, created with hipEventDisableSystemFence: recording it
+    skips the system-scope cache write-back and invalidation that a default event does,
+    which would otherwise slow the kernel that follows it.  Uses the HIP runtime that torch
+    has already loaded."""
+    _hip = None
+
+    def __init__(self):
+        import ctypes as C
+        if TimingEvent._hip is None:
+            hip = C.CDLL("libamdhip64.so.7", mode=os.RTLD_NOLOAD | C.RTLD_GLOBAL)
+            hip.hipEventCreateWithFlags.argtypes = [C.POINTER(C.c_void_p), C.c_uint]
+            hip.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+            hip.hipEventDestroy.argtypes = [C.c_void_p]
+            TimingEvent._hip = hip
+        h = C.c_void_p()
+        if TimingEvent._hip.hipEventCreateWithFlags(C.byref(h), 0x20000000) != 0:
+            raise RuntimeError("hipEventCreateWithFlags failed")
+        self.cuda_event = h.value
+
+    def elapsed_time(self, end) -> float:
+        import ctypes as C
+        ms = C.c_float()
+        if TimingEvent._hip.hipEventElapsedTime(C.byref(ms), self.cuda_event, end.cuda_event) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return ms.value
+
+    def __del__(self):
+        if self.cuda_event and TimingEvent._hip is not None:
+            TimingEvent._hip.hipEventDestroy(self.cuda_event)
+
+
 def timed_run(systems, precision, steps, warmup, ee, tpa, events=True):
     """Build, warm up, then time `steps` whole steps with md_run.  Returns a dict."""
     import numpy as np
@@ -139,8 +171,7 @@ def timed_run(systems, precision, steps, warmup, ee, tpa, events=True):
             ev = [None] * (4 * steps)
             for k in timed:
                 for u in range(4):
-                    ev[4 * k + u] = torch.cuda.Event(enable_timing=True)
-                    ev[4 * k + u].record(stream)   # torch creates the HIP event at its first record
+                    ev[4 * k + u] = TimingEvent()
         builds0 = flags["nbuilds"]
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -271,9 +271,10 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
     if (a0 > (int64_t)INT32_MAX / 2 || c0 > (int64_t)INT32_MAX / 2) { delete s; return MD_ERR_ARG; }
     s->desc.push_back(d);
     for (int t = 0; t < ntile; ++t) s->tile_rep.push_back(r);
-    // list build: one block per run of up to LIST_SEG cells of a cell row, at capacity
+    // list build: one block per run of cells of a cell row, at capacity, up to nseg runs
+    // per row (twice the runs of LIST_SEG cells, so that dense rows can be cut finer)
     s->desc.back().lb0 = (int)s->lblk_rep.size();
-    s->desc.back().nseg = (d.gcap[0] + LIST_SEG - 1) / LIST_SEG;
+    s->desc.back().nseg = 2 * ((d.gcap[0] + LIST_SEG - 1) / LIST_SEG);
     const int64_t nlb = (int64_t)s->desc.back().nseg * d.gcap[1] * d.gcap[2];
     if ((int64_t)s->lblk_rep.size() + nlb > (int64_t)INT32_MAX / 2) { delete s; return MD_ERR_ARG; }
     s->lblk_rep.insert(s->lblk_rep.end(), (size_t)nlb, r);

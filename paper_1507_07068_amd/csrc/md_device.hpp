@@ -27,7 +27,7 @@ struct RepDesc {
   int g0, gcap[3];      // Cr-Cr cell grid: first cell (global), allocated dims (the dims in
                         // use along open axes follow the atoms, see RepState)
   int h0, hd[3];        // Cr-C cell grid: first cell (global, after all Cr grids), dims
-  int lb0, nseg;        // list build: first block, blocks per cell row (x-segments at capacity)
+  int lb0, nseg;        // list build: first work item, items per cell row (most runs of cells)
   double ginv[3];       // cells per Angstrom of the Cr grid along periodic axes
   double hinv[3];       // cells per Angstrom of the carbon grid
 };
@@ -271,6 +271,18 @@ __device__ __forceinline__ int flat_replica(const int* pre, int nrep, int g) {
 // are adjacent, so T lanes of one atom read consecutive words).
 __device__ __forceinline__ int list_pos(int k, int i, int ntot, int T, int Tshift) {
   return ((k >> Tshift) * ntot + i) * T + (k & (T - 1));
+}
+
+// Values the same on every lane of a wavefront, moved to scalar registers (the compiler
+// keeps loads through pointers it cannot prove read-only in vector registers).
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uniform(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uniform(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)b), hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
 // The 27-cell stencil, one axis at a time: offsets t = 0..stencil_n-1 map to cells

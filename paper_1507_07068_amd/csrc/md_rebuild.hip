@@ -74,8 +74,11 @@ struct BuildArgs {
 constexpr int LIST_BATCH = MD_LIST_BATCH;   // candidate loads issued together in k_list_rows
 constexpr int MAXC = 512;           // candidates staged per window in k_xlist
 constexpr int WAVES_PER_BLOCK = BLOCK / WAVE;
-constexpr int LIST_SEG = 42;      // cells of one cell row per block of k_list_tiles
-constexpr int LIST_STAGE = 768;   // candidates staged in LDS at a time by k_list_tiles
+constexpr int LIST_SEG = 42;      // most cells of one work item of k_list_tiles
+#ifndef MD_LIST_STAGE
+#define MD_LIST_STAGE 1280
+#endif
+constexpr int LIST_STAGE = MD_LIST_STAGE;   // candidates k_list_tiles stages in LDS at a time
 #ifndef MD_LIST_GROUP
 #define MD_LIST_GROUP 4
 #endif
@@ -623,44 +626,71 @@ __global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
 }
 
 // Cr-Cr lists with LDS-staged candidates (replicas whose periodic axes all have >= 3 list
-// cells).  One block per run of up to LIST_SEG cells of one cell row; its atoms are the
-// centers, one per thread.  For each of the nine neighbouring cell rows (z-major, then y)
-// the block stages that row's atoms of x-cells x0-1 .. x1+1 -- with the cell seen across a
-// periodic x face placed at the end it is seen from -- into LDS as FP32 coordinates
-// relative to the grid origin plus the row's image shift, together with their slots.  A
-// center's candidates in that row, x-cells cx-1 .. cx+1, are then one contiguous window of
-// the staged row, so the candidate order (rows, along x, by slot) is the same as in
-// k_list_rows and the lists are identical.  Rows longer than LIST_STAGE are staged in
-// chunks.  The FP32 screen and its exact FP64 band are those of k_list_rows.
+// cells).  A work item is a run of cells of one cell row: each row is cut into as many
+// runs as keep a run's atoms near LIST_TGT (and no run longer than LIST_SEG cells), so
+// that one pass of a block's threads covers a run's atoms, one center per thread; one
+// block per item.  For each of the nine neighbouring cell rows (z-major, then y) the block
+// stages that row's atoms of x-cells x0-1 .. x1+1 -- with the cell seen across a periodic
+// x face placed at the end it is seen from -- into LDS as FP32 coordinates relative to the
+// grid origin plus the row's image shift, with the slot in the fourth word.  The nine
+// staged rows are laid end to end; a center's candidates in one row, x-cells cx-1 .. cx+1,
+// are a contiguous window of it, so the candidate order (rows, along x, by slot) is the
+// same as in k_list_rows and the lists are identical.  All nine rows are staged with one
+// round of loads when they fit LIST_STAGE candidates (else in pieces of that size), so a
+// block waits on few dependent memory round trips.  The FP32 screen and its exact FP64
+// band are those of k_list_rows.
 #ifndef MD_LIST_WAVES
 #define MD_LIST_WAVES 6
 #endif
+constexpr int LIST_TGT = 224;                  // atoms per work item aimed at
+constexpr int LIST_PT = LIST_STAGE / BLOCK;    // candidates each thread stages per piece
+static_assert(LIST_STAGE % BLOCK == 0, "a piece is a whole number of candidates per thread");
+
+// Image shift (FP64) of neighbouring row rr (z-major, then y) of the row (cy, cz).
+__device__ __forceinline__ void row_shift(int rr, int cy, int cz, int gy, int gz, int per1, int per2,
+                                          double len1, double len2, double& shy, double& shz) {
+  const int uz = cz + rr / 3 - 1, uy = cy + rr % 3 - 1;
+  shz = per2 ? (uz < 0 ? -len2 : (uz >= gz ? len2 : 0.0)) : 0.0;
+  shy = per1 ? (uy < 0 ? -len1 : (uy >= gy ? len1 : 0.0)) : 0.0;
+}
+
 // Occupancy floor: this kernel hides the latency of its LDS and global reads with waves, so
 // its registers are held to what MD_LIST_WAVES wavefronts per SIMD can share.
 __global__ __launch_bounds__(BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts K, BuildArgs A) {
   if (rebuild_off(A)) return;
-  __shared__ float4 sq[LIST_STAGE];
-  __shared__ int sj[LIST_STAGE];
-  __shared__ int toff[LIST_SEG + 4];   // staged offset of unwrapped cells x0-1 .. x1+2
+  __shared__ float4 sq[LIST_STAGE];        // staged candidates: x, y, z, slot bits
+  __shared__ int toff[9][LIST_SEG + 4];    // per row: row-local staged offset of cells x0-1 .. x1+2
+  __shared__ int rinfo[9][6];   // per row: first slots of the left, main and right pieces;
+                                // row-local ends of the left and main pieces; staged total
+  __shared__ int4 rslot[9];     // per row: slot of row-local candidate g is g + .x (g < .w),
+                                // g + .y (g < end of the main piece), else g + .z
+  __shared__ float2 rsh[9];     // per row: FP32 image shift along y and z
   const int b = blockIdx.x;
-  const int r = A.lblk_rep[b];
+  const int r = uniform(A.lblk_rep[b]);
   RepState& S = A.S[r];
   if (!S.rebuild) return;
   const RepDesc& d = A.R[r];
-  const int gx = S.gd[0], gy = S.gd[1], gz = S.gd[2];
-  const int nseg = (gx + LIST_SEG - 1) / LIST_SEG;
-  const int l = b - d.lb0;
-  if (l >= nseg * gy * gz) return;
+  const int gx = uniform(S.gd[0]), gy = uniform(S.gd[1]), gz = uniform(S.gd[2]);
+  // descriptor values used in the loops, held in scalar registers
+  const int per0 = uniform(d.per[0]), per1 = uniform(d.per[1]), per2 = uniform(d.per[2]);
+  const double len0 = uniform(d.len[0]), len1 = uniform(d.len[1]), len2 = uniform(d.len[2]);
+  const int dseg = uniform(d.nseg);
+  const int l = b - uniform(d.lb0);
   if (l == 0 && threadIdx.x == 0) {   // once per replica: the build is counted
     S.nbuilds += 1;
     S.ind_z_ref = S.ind_z;
   }
-  const int sx = l % nseg, cy = (l / nseg) % gy, cz = l / (nseg * gy);
-  const int x0 = sx * gx / nseg, x1 = (sx + 1) * gx / nseg - 1;   // this block's cells
-  const int crow = d.g0 + (cz * gy + cy) * gx;
-  const int sbase = d.a0 - A.start[d.g0];   // sorted slot = sbase + start[cell]
-  const int cbeg = sbase + A.start[crow + x0];
-  const int m = A.start[crow + x1 + 1] - A.start[crow + x0];
+  const int sx = l % dseg, cy = (l / dseg) % gy, cz = (l / dseg) / gy;
+  if (cz >= gz) return;
+  const int g0 = uniform(d.g0);
+  const int crow = g0 + (cz * gy + cy) * gx;
+  const int nseg = min(min(dseg, gx), max((gx + LIST_SEG - 1) / LIST_SEG,
+                                          (uniform(A.start[crow + gx] - A.start[crow]) + LIST_TGT - 1) / LIST_TGT));
+  if (sx >= nseg) return;
+  const int x0 = sx * gx / nseg, x1 = (sx + 1) * gx / nseg - 1;   // this item's cells
+  const int sbase = uniform(d.a0 - A.start[g0]);   // sorted slot = sbase + start[cell]
+  const int cbeg = sbase + uniform(A.start[crow + x0]);
+  const int m = uniform(A.start[crow + x1 + 1]) - (cbeg - sbase);
   if (m == 0) return;
   const int lane = threadIdx.x % WAVE;
   const double rl2 = K.rlist_sq;
@@ -668,6 +698,7 @@ __global__ __launch_bounds__(BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts K, B
   const int64_t row = K.ntot * T;   // entry k of atom p at idx[(k / T) * row + p * T + k % T]
   const double4* __restrict__ tq = A.tq;
   const float4* __restrict__ tqf = A.tqf;
+  const bool shadow = K.shadow;   // entries carry relative cells only for the FP32 shadow
   // FP32 screen bounds (see k_list_rows); the staged coordinate already includes the image
   // shift, which the error bound covers
   float lo_f, hi_f;
@@ -682,19 +713,55 @@ __global__ __launch_bounds__(BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts K, B
       err += 2.0 * R * eta + eta * eta;
     }
     const double delta = 2.0 * err + 1e-6;
-    lo_f = (float)(rl2 - delta);
-    hi_f = (float)(rl2 + delta);
+    lo_f = uniform((float)(rl2 - delta));
+    hi_f = uniform((float)(rl2 + delta));
   }
-  const bool shadow = K.shadow;   // entries carry relative cells only for the FP32 shadow
   const int xa = max(x0 - 1, 0), xb = min(x1 + 1, gx - 1);   // main piece of a staged row
-  const bool wl = d.per[0] && x0 == 0, wr = d.per[0] && x1 == gx - 1;   // wrapped end cells
+  const bool wl = per0 && x0 == 0, wr = per0 && x1 == gx - 1;   // wrapped end cells
+  const int nt = x1 - x0 + 4;
+  const float fxl = (float)(-len0), fxr = (float)len0;
+  for (int t = threadIdx.x; t < 9 * nt; t += BLOCK) {   // the nine rows' tables
+    const int rr = t / nt, k = t % nt;
+    const int z = stencil_cell(cz, rr / 3, gz, per2), y = stencil_cell(cy, rr % 3, gy, per1);
+    int v = 0;
+    if (z >= 0 && y >= 0) {
+      const int rw = g0 + (z * gy + y) * gx;
+      const int sa = A.start[rw + xa];
+      const int nl = wl ? A.start[rw + gx] - A.start[rw + gx - 1] : 0;
+      const int nm = A.start[rw + xb + 1] - sa;
+      const int nr = wr ? A.start[rw + 1] - A.start[rw] : 0;
+      const int u = x0 - 1 + k;   // unwrapped cell
+      v = u < xa ? 0 : (u <= xb + 1 ? nl + (A.start[rw + u] - sa) : nl + nm + nr);
+      if (k == 0) {
+        rinfo[rr][0] = sbase + A.start[rw + gx - 1];
+        rinfo[rr][1] = sbase + sa;
+        rinfo[rr][2] = sbase + A.start[rw];
+        rinfo[rr][3] = nl;
+        rinfo[rr][4] = nl + nm;
+        rinfo[rr][5] = nl + nm + nr;
+        rslot[rr] = make_int4(sbase + A.start[rw + gx - 1], sbase + sa - nl, sbase + A.start[rw] - (nl + nm), nl);
+        double shy, shz;
+        row_shift(rr, cy, cz, gy, gz, per1, per2, len1, len2, shy, shz);
+        rsh[rr] = make_float2((float)shy, (float)shz);
+      }
+    } else if (k == 0) {
+      rinfo[rr][5] = 0;
+    }
+    toff[rr][k] = v;
+  }
+  __syncthreads();
+  // start of each row in the staged sequence (scalar registers)
+  int roff[10];
+  roff[0] = 0;
+#pragma unroll
+  for (int rr = 0; rr < 9; ++rr) roff[rr + 1] = roff[rr] + uniform(rinfo[rr][5]);
+  const int tot = roff[9];
   for (int c0 = 0; c0 < m; c0 += BLOCK) {
     const int c = c0 + threadIdx.x;
     const bool live = c < m;
     const int p = cbeg + (live ? c : 0);
-    const double4 pi = tq[p];
     const float4 pf = tqf[p];
-    const int cx = cell_coord(pi.x, S.glo[0], S.ginv[0], gx);
+    const int cx = cell_coord(tq[p].x, uniform(S.glo[0]), uniform(S.ginv[0]), gx);
     int count = 0;
     int* __restrict__ wp = A.idx + (int64_t)p * T;
     auto append = [&](int j) {
@@ -702,61 +769,61 @@ __global__ __launch_bounds__(BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts K, B
       ++count;
       wp += (count & (T - 1)) ? 1 : row - (T - 1);
     };
-    for (int rr = 0; rr < 9; ++rr) {   // uniform over the block
-      const int tz = rr / 3, ty = rr % 3;
-      const int z = stencil_cell(cz, tz, gz, d.per[2]);
-      const int y = stencil_cell(cy, ty, gy, d.per[1]);
-      if (z < 0 || y < 0) continue;
-      const int uz = cz + tz - 1, uy = cy + ty - 1;
-      const double shz = d.per[2] ? (uz < 0 ? -d.len[2] : (uz >= gz ? d.len[2] : 0.0)) : 0.0;
-      const double shy = d.per[1] ? (uy < 0 ? -d.len[1] : (uy >= gy ? d.len[1] : 0.0)) : 0.0;
-      const float fy = (float)shy, fz = (float)shz, fxl = (float)(-d.len[0]), fxr = (float)d.len[0];
-      const int rw = d.g0 + (z * gy + y) * gx;
-      const int L0 = sbase + A.start[rw + gx - 1], nl = wl ? A.start[rw + gx] - A.start[rw + gx - 1] : 0;
-      const int M0 = sbase + A.start[rw + xa], nm = A.start[rw + xb + 1] - A.start[rw + xa];
-      const int R0 = sbase + A.start[rw], nr = wr ? A.start[rw + 1] - A.start[rw] : 0;
-      const int total = nl + nm + nr;
-      __syncthreads();   // the previous row's table and stage are no longer read
-      for (int t = threadIdx.x; t <= x1 - x0 + 3; t += BLOCK) {
-        const int u = x0 - 1 + t;   // unwrapped cell
-        toff[t] = u < xa ? 0 : (u <= xb + 1 ? nl + (A.start[rw + u] - A.start[rw + xa]) : total);
+    for (int G0 = 0; G0 < tot; G0 += LIST_STAGE) {   // uniform over the block
+      const int nch = min(LIST_STAGE, tot - G0);
+      if (c0 > 0 || G0 > 0) __syncthreads();   // the previous piece is no longer read
+      {
+        float3 pc[LIST_PT];
+        int pj[LIST_PT], pk[LIST_PT];   // slot; 4 * row + piece (0 left, 1 main, 2 right)
+#pragma unroll
+        for (int u = 0; u < LIST_PT; ++u) {   // slots, shifts and loads first, all in flight
+          const int s = threadIdx.x + u * BLOCK;
+          pj[u] = -1;
+          if (s < nch) {
+            const int G = G0 + s;
+            int rr = 0, g = G;   // the row of staged position G and its row-local index
+#pragma unroll
+            for (int k = 1; k < 9; ++k)
+              if (G >= roff[k]) {
+                rr = k;
+                g = G - roff[k];
+              }
+            const int4 rs = rslot[rr];
+            const int nlm = rinfo[rr][4];
+            const int j = g + (g < rs.w ? rs.x : (g < nlm ? rs.y : rs.z));
+            pk[u] = 4 * rr + (g < rs.w ? 0 : (g < nlm ? 1 : 2));
+            const float4* c4 = tqf + j;
+            pc[u] = make_float3(c4->x, c4->y, c4->z);
+            pj[u] = j;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < LIST_PT; ++u)   // then the image shifts and the LDS writes
+          if (pj[u] >= 0) {
+            const float2 yz = rsh[pk[u] >> 2];
+            const int pc_ = pk[u] & 3;
+            const float fx = pc_ == 0 ? fxl : (pc_ == 1 ? 0.0f : fxr);
+            sq[threadIdx.x + u * BLOCK] = make_float4(pc[u].x + fx, pc[u].y + yz.x, pc[u].z + yz.y, __int_as_float(pj[u]));
+          }
       }
       __syncthreads();
-      // this center's window: unwrapped cells cx-1 .. cx+1 (staged offsets w0, b1, b2, w1);
-      // relative-cell code of the row, the x offset added per candidate
-      const int w0 = toff[cx - 1 - (x0 - 1)], w1 = toff[cx + 2 - (x0 - 1)];
-      const int b1 = toff[cx - (x0 - 1)], b2 = toff[cx + 1 - (x0 - 1)];
-      const int rcode = 9 * tz + 3 * ty;
-      for (int ch = 0; ch < total; ch += LIST_STAGE) {
-        const int nch = min(LIST_STAGE, total - ch);
-        if (ch > 0) __syncthreads();
-        for (int s = threadIdx.x; s < nch; s += BLOCK) {
-          const int g = ch + s;
-          int j;
-          float fx;
-          if (g < nl) {
-            j = L0 + g;
-            fx = fxl;
-          } else if (g < nl + nm) {
-            j = M0 + (g - nl);
-            fx = 0.0f;
-          } else {
-            j = R0 + (g - nl - nm);
-            fx = fxr;
-          }
-          const float4 cf = tqf[j];
-          sq[s] = make_float4(cf.x + fx, cf.y + fy, cf.z + fz, 0.0f);
-          sj[s] = j;
-        }
-        __syncthreads();
-        if (live) {
-          const int e0 = max(w0, ch) - ch, e1 = min(w1, ch + nch) - ch;
+      if (live) {
+#pragma unroll 1
+        for (int rr = 0; rr < 9; ++rr) {   // this center's window in each row
+          const int* to = toff[rr] + (cx - x0);
+          const int w0 = roff[rr] + to[0], w1 = roff[rr] + to[3];
+          const int e0 = max(w0, G0) - G0, e1 = min(w1, G0 + nch) - G0;
+          if (e0 >= e1) continue;
+          const int b1 = roff[rr] + to[1], b2 = roff[rr] + to[2];
+          const int rcode = 9 * (rr / 3) + 3 * (rr % 3);
           // exact FP64 test of staged candidate s (band or NaN)
           auto exact = [&](int s) {
-            const int g = ch + s;
-            const double shx = g < nl ? -d.len[0] : (g < nl + nm ? 0.0 : d.len[0]);
-            const double4 pj = tq[sj[s]];
-            return dist_sq_exact((pj.x - pi.x) + shx, (pj.y - pi.y) + shy, (pj.z - pi.z) + shz) < rl2;
+            double shy, shz;
+            row_shift(rr, cy, cz, gy, gz, per1, per2, len1, len2, shy, shz);
+            const int g = G0 + s - roff[rr];
+            const double shx = g < rinfo[rr][3] ? -len0 : (g < rinfo[rr][4] ? 0.0 : len0);
+            const double4 pi = tq[p], pj4 = tq[__float_as_int(sq[s].w)];
+            return dist_sq_exact((pj4.x - pi.x) + shx, (pj4.y - pi.y) + shy, (pj4.z - pi.z) + shz) < rl2;
           };
           // LIST_GROUP candidates at a time: the FP32 screen gives in / band bit masks, the
           // rare band candidates get the exact test, then the passing ones are appended in
@@ -780,8 +847,8 @@ __global__ __launch_bounds__(BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts K, B
             }
             for (; in; in &= in - 1) {
               const int su = s + __builtin_ctz(in);
-              const int j = sj[su];
-              if (j != p) append(shadow ? j | ((rcode + (su + ch >= b1) + (su + ch >= b2)) << LIST_IDX_BITS) : j);
+              const int j = __float_as_int(sq[su].w);
+              if (j != p) append(shadow ? j | ((rcode + (su + G0 >= b1) + (su + G0 >= b2)) << LIST_IDX_BITS) : j);
             }
           }
           for (; s < e1; ++s) {
@@ -790,14 +857,15 @@ __global__ __launch_bounds__(BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts K, B
             const float r2f = ex * ex + ey * ey + ez * ez;
             bool ok = r2f < lo_f;
             if (__builtin_expect(!ok && !(r2f >= hi_f), 0)) ok = exact(s);
-            const int j = sj[s];
-            if (ok && j != p) append(shadow ? j | ((rcode + (s + ch >= b1) + (s + ch >= b2)) << LIST_IDX_BITS) : j);
+            const int j = __float_as_int(cf.w);
+            if (ok && j != p) append(shadow ? j | ((rcode + (s + G0 >= b1) + (s + G0 >= b2)) << LIST_IDX_BITS) : j);
           }
         }
       }
     }
     bool near = false;
     if (live) {
+      const double4 pi = tq[p];
       A.cnt[p] = min(count, cap);
       if (count > cap) atomicMax(&S.overflow, count);
       if (d.nc > 0) {

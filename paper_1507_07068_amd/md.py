@@ -322,9 +322,9 @@ class Simulation:
     def md_run(self, nsteps: int, energy_every: int = 0, obs=None, events=None):
         """Enqueue nsteps whole steps in C.  obs: device float64 tensor with room for
         nsteps // energy_every rows of (nrep, MD_NOBS); events: list of 4*nsteps
-        torch.cuda.Event or None, per step two around the EAM force kernel and two around the
-        Cr-Cr list kernel (each event recorded once before, so that its HIP event exists;
-        None: not recorded)."""
+        events (any object whose ``cuda_event`` is a HIP event handle, e.g. torch.cuda.Event
+        recorded once before so that its HIP event exists) or None, per step two around the
+        EAM force kernel and two around the Cr-Cr list kernel (None: not recorded)."""
         flags = MD_F_MIXED if self.mixed else 0
         ev = None
         if events is not None:

@@ -62,6 +62,13 @@ def steps(d: str) -> str:
             dur[k] += (e - s) / 1e3
         lst = sum(v for k, v in dur.items() if k.startswith(("k_list_tiles", "k_list_rows")))
         split["rebuild" if lst > 20.0 else "no rebuild"].append((dur, (g[-1][2] - g[0][1]) / 1e3))
+    # the rebuilding steps' list-kernel time over the run, in quarters
+    reb = [sum(v for k, v in dur.items() if k.startswith(("k_list_tiles", "k_list_rows")))
+           for dur, _ in split["rebuild"]]
+    if len(reb) >= 4:
+        q = np.array_split(np.array(reb), 4)
+        out.append("list kernel of rebuilding steps by quarter of the run: "
+                   + ", ".join(f"{x.mean():.1f}" for x in q) + " us")
     for name, gs in split.items():
         if not gs:
             continue
