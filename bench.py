@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "atom-steps/s EAM+Morse MD step, FP32-mixed & batched vs FP64 at ≤1e-5 force err"
 HBM_PEAK_GBS = 8000.0
-TIME_EVERY = 8   # kernel timing events on every TIME_EVERY-th step
+TIME_EVERY = 8   # kernel timing events on one step in TIME_EVERY (--time-every)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c1_fp64_hbm_traffic.txt")
 SOURCES = {k: [os.path.join(ROOT, "paper_1507_07068_amd", "csrc", f) for f in v]
            for k, v in (("force", ("md_forces.hip", "md_device.hpp")),
@@ -145,7 +145,7 @@ class TimingEvent:
             TimingEvent._hip.hipEventDestroy(self.cuda_event)
 
 
-def timed_run(systems, precision, steps, warmup, ee, tpa, events=True):
+def timed_run(systems, precision, steps, warmup, ee, tpa, events=True, time_every=TIME_EVERY):
     """Build, warm up, then time `steps` whole steps with md_run.  Returns a dict."""
     import numpy as np
     import torch
@@ -164,10 +164,14 @@ def timed_run(systems, precision, steps, warmup, ee, tpa, events=True):
         nobs = steps // ee if ee > 0 else 0
         obs = torch.zeros((max(nobs, 1), sim.nrep, md.MD_NOBS), dtype=torch.float64, device="cuda")
         ev = None
-        timed = list(range(0, steps, TIME_EVERY)) if events else []
+        timed = []
+        if events:   # a seeded random sample of the steps (a stride could alias with the
+                     # rebuild pattern, which is nearly periodic)
+            rng = np.random.default_rng(12345)
+            timed = sorted(rng.choice(steps, size=max(1, steps // max(time_every, 1)), replace=False).tolist())
         if events:
-            # events around the force and list kernels of every TIME_EVERY-th step (recording
-            # them at every step would add their own cost to the step time)
+            # events around the force and list kernels of the sampled steps (on every step
+            # they would add several per cent to the step time)
             ev = [None] * (4 * steps)
             for k in timed:
                 for u in range(4):
@@ -320,6 +324,8 @@ def main(argv=None):
     ap.add_argument("--energy-every", type=int, default=10)
     ap.add_argument("--tpa", type=int, default=2, choices=[1, 2, 4, 8],
                     help="lanes per atom in the density / force passes")
+    ap.add_argument("--time-every", type=int, default=TIME_EVERY, metavar="K",
+                    help="record the kernel timing events on a random one in K steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB")
@@ -343,7 +349,7 @@ def main(argv=None):
     log(f"[bench] workload {args.workload} ({wname}): {len(systems)} system(s), "
         f"{sum(s.n for s in systems)} Cr, {sum(s.n_c for s in systems)} C, precision {precision}, "
         f"steps {steps}, warmup {args.warmup}")
-    r = timed_run(systems, precision, steps, args.warmup, ee, args.tpa)
+    r = timed_run(systems, precision, steps, args.warmup, ee, args.tpa, time_every=args.time_every)
     r["sim"].close()
     n_atoms, rate, k_avg, mean_list = r["n_atoms"], r["rate"], r["k_avg"], r["mean_list"]
     bytes_launch = n_atoms * force_bytes_per_atom(mean_list)

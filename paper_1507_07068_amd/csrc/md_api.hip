@@ -274,7 +274,7 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
     // list build: one block per run of cells of a cell row, at capacity, up to nseg runs
     // per row (twice the runs of LIST_SEG cells, so that dense rows can be cut finer)
     s->desc.back().lb0 = (int)s->lblk_rep.size();
-    s->desc.back().nseg = 2 * ((d.gcap[0] + LIST_SEG - 1) / LIST_SEG);
+    s->desc.back().nseg = 2 * ((d.gcap[0] + LIST_SEG - 1) / LIST_SEG) * ((224 + LIST_TGT - 1) / LIST_TGT);
     const int64_t nlb = (int64_t)s->desc.back().nseg * d.gcap[1] * d.gcap[2];
     if ((int64_t)s->lblk_rep.size() + nlb > (int64_t)INT32_MAX / 2) { delete s; return MD_ERR_ARG; }
     s->lblk_rep.insert(s->lblk_rep.end(), (size_t)nlb, r);
@@ -448,7 +448,7 @@ int build_chain(md_system* s, const md_atoms* a, const md_lists* l, uint32_t fla
   if (s->list_mix)
     k_list_rows<false><<<s->ntiles, BLOCK, 0, st>>>(s->K, A);
   else
-    k_list_tiles<<<s->nlblk, BLOCK, 0, st>>>(s->K, A);
+    k_list_tiles<<<s->nlblk, LIST_BLOCK, 0, st>>>(s->K, A);
   if (ev1 && (e = hip_status(hipEventRecord(ev1, st)))) return e;
   k_xlist<<<A.near_blocks, BLOCK, 0, st>>>(s->K, A);
   return check_launch();

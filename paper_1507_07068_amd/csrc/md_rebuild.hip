@@ -76,7 +76,7 @@ constexpr int MAXC = 512;           // candidates staged per window in k_xlist
 constexpr int WAVES_PER_BLOCK = BLOCK / WAVE;
 constexpr int LIST_SEG = 42;      // most cells of one work item of k_list_tiles
 #ifndef MD_LIST_STAGE
-#define MD_LIST_STAGE 1280
+#define MD_LIST_STAGE 1024
 #endif
 constexpr int LIST_STAGE = MD_LIST_STAGE;   // candidates k_list_tiles stages in LDS at a time
 #ifndef MD_LIST_GROUP
@@ -640,11 +640,19 @@ __global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
 // block waits on few dependent memory round trips.  The FP32 screen and its exact FP64
 // band are those of k_list_rows.
 #ifndef MD_LIST_WAVES
-#define MD_LIST_WAVES 6
+#define MD_LIST_WAVES 7
 #endif
-constexpr int LIST_TGT = 224;                  // atoms per work item aimed at
-constexpr int LIST_PT = LIST_STAGE / BLOCK;    // candidates each thread stages per piece
-static_assert(LIST_STAGE % BLOCK == 0, "a piece is a whole number of candidates per thread");
+#ifndef MD_LIST_BLOCK
+#define MD_LIST_BLOCK 256
+#endif
+#ifndef MD_LIST_TGT
+#define MD_LIST_TGT 224
+#endif
+constexpr int LIST_BLOCK = MD_LIST_BLOCK;           // threads of k_list_tiles
+constexpr int LIST_TGT = MD_LIST_TGT;               // atoms per work item aimed at
+constexpr int LIST_PT = LIST_STAGE / LIST_BLOCK;    // candidates each thread stages per piece
+static_assert(LIST_STAGE % LIST_BLOCK == 0, "a piece is a whole number of candidates per thread");
+static_assert(LIST_TGT <= LIST_BLOCK, "a work item's atoms aimed at fit one pass of the threads");
 
 // Image shift (FP64) of neighbouring row rr (z-major, then y) of the row (cy, cz).
 __device__ __forceinline__ void row_shift(int rr, int cy, int cz, int gy, int gz, int per1, int per2,
@@ -656,12 +664,11 @@ __device__ __forceinline__ void row_shift(int rr, int cy, int cz, int gy, int gz
 
 // Occupancy floor: this kernel hides the latency of its LDS and global reads with waves, so
 // its registers are held to what MD_LIST_WAVES wavefronts per SIMD can share.
-__global__ __launch_bounds__(BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts K, BuildArgs A) {
+__global__ __launch_bounds__(LIST_BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts K, BuildArgs A) {
   if (rebuild_off(A)) return;
   __shared__ float4 sq[LIST_STAGE];        // staged candidates: x, y, z, slot bits
   __shared__ int toff[9][LIST_SEG + 4];    // per row: row-local staged offset of cells x0-1 .. x1+2
-  __shared__ int rinfo[9][6];   // per row: first slots of the left, main and right pieces;
-                                // row-local ends of the left and main pieces; staged total
+  __shared__ int rinfo[9][2];   // per row: row-local end of the main piece; staged total
   __shared__ int4 rslot[9];     // per row: slot of row-local candidate g is g + .x (g < .w),
                                 // g + .y (g < end of the main piece), else g + .z
   __shared__ float2 rsh[9];     // per row: FP32 image shift along y and z
@@ -720,48 +727,72 @@ __global__ __launch_bounds__(BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts K, B
   const bool wl = per0 && x0 == 0, wr = per0 && x1 == gx - 1;   // wrapped end cells
   const int nt = x1 - x0 + 4;
   const float fxl = (float)(-len0), fxr = (float)len0;
-  for (int t = threadIdx.x; t < 9 * nt; t += BLOCK) {   // the nine rows' tables
-    const int rr = t / nt, k = t % nt;
-    const int z = stencil_cell(cz, rr / 3, gz, per2), y = stencil_cell(cy, rr % 3, gy, per1);
-    int v = 0;
-    if (z >= 0 && y >= 0) {
-      const int rw = g0 + (z * gy + y) * gx;
-      const int sa = A.start[rw + xa];
-      const int nl = wl ? A.start[rw + gx] - A.start[rw + gx - 1] : 0;
-      const int nm = A.start[rw + xb + 1] - sa;
-      const int nr = wr ? A.start[rw + 1] - A.start[rw] : 0;
-      const int u = x0 - 1 + k;   // unwrapped cell
-      v = u < xa ? 0 : (u <= xb + 1 ? nl + (A.start[rw + u] - sa) : nl + nm + nr);
-      if (k == 0) {
-        rinfo[rr][0] = sbase + A.start[rw + gx - 1];
-        rinfo[rr][1] = sbase + sa;
-        rinfo[rr][2] = sbase + A.start[rw];
-        rinfo[rr][3] = nl;
-        rinfo[rr][4] = nl + nm;
-        rinfo[rr][5] = nl + nm + nr;
-        rslot[rr] = make_int4(sbase + A.start[rw + gx - 1], sbase + sa - nl, sbase + A.start[rw] - (nl + nm), nl);
-        double shy, shz;
-        row_shift(rr, cy, cz, gy, gz, per1, per2, len1, len2, shy, shz);
-        rsh[rr] = make_float2((float)shy, (float)shz);
+  // the first pass's centers: their loads go out before the tables' round of loads
+  const int cfirst = min((int)threadIdx.x, m - 1);
+  const float4 pf_first = tqf[cbeg + cfirst];
+  const double px_first = tq[cbeg + cfirst].x;
+  {   // the nine rows' tables: all loads first (one round), then the LDS writes
+    constexpr int NIT = (9 * (LIST_SEG + 4) + LIST_BLOCK - 1) / LIST_BLOCK;
+    int tv[NIT], ts[NIT], tl[NIT], tm[NIT], tr[NIT], tL[NIT], tR[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int t = threadIdx.x + it * LIST_BLOCK;
+      const int rr = t / nt, k = t % nt;
+      tv[it] = -1;
+      if (t < 9 * nt) {
+        const int z = stencil_cell(cz, rr / 3, gz, per2), y = stencil_cell(cy, rr % 3, gy, per1);
+        if (z >= 0 && y >= 0) {
+          const int rw = g0 + (z * gy + y) * gx;
+          const int u = min(max(x0 - 1 + k, xa), xb + 1);   // unwrapped cell, clamped
+          ts[it] = A.start[rw + xa];
+          tl[it] = wl ? A.start[rw + gx] - A.start[rw + gx - 1] : 0;
+          tm[it] = A.start[rw + xb + 1];
+          tr[it] = wr ? A.start[rw + 1] - A.start[rw] : 0;
+          tv[it] = A.start[rw + u];
+          tL[it] = k == 0 ? A.start[rw + gx - 1] : 0;
+          tR[it] = k == 0 ? A.start[rw] : 0;
+        } else {
+          tv[it] = -2;
+        }
       }
-    } else if (k == 0) {
-      rinfo[rr][5] = 0;
     }
-    toff[rr][k] = v;
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int t = threadIdx.x + it * LIST_BLOCK;
+      if (tv[it] == -1) continue;
+      const int rr = t / nt, k = t % nt;
+      int v = 0;
+      if (tv[it] != -2) {
+        const int sa = ts[it], nl = tl[it], nm = tm[it] - sa, nr = tr[it];
+        const int u = x0 - 1 + k;   // unwrapped cell
+        v = u < xa ? 0 : (u <= xb + 1 ? nl + (tv[it] - sa) : nl + nm + nr);
+        if (k == 0) {
+          rinfo[rr][0] = nl + nm;
+          rinfo[rr][1] = nl + nm + nr;
+          rslot[rr] = make_int4(sbase + tL[it], sbase + sa - nl, sbase + tR[it] - (nl + nm), nl);
+          double shy, shz;
+          row_shift(rr, cy, cz, gy, gz, per1, per2, len1, len2, shy, shz);
+          rsh[rr] = make_float2((float)shy, (float)shz);
+        }
+      } else if (k == 0) {
+        rinfo[rr][1] = 0;
+      }
+      toff[rr][k] = v;
+    }
   }
   __syncthreads();
   // start of each row in the staged sequence (scalar registers)
   int roff[10];
   roff[0] = 0;
 #pragma unroll
-  for (int rr = 0; rr < 9; ++rr) roff[rr + 1] = roff[rr] + uniform(rinfo[rr][5]);
+  for (int rr = 0; rr < 9; ++rr) roff[rr + 1] = roff[rr] + uniform(rinfo[rr][1]);
   const int tot = roff[9];
-  for (int c0 = 0; c0 < m; c0 += BLOCK) {
+  for (int c0 = 0; c0 < m; c0 += LIST_BLOCK) {
     const int c = c0 + threadIdx.x;
     const bool live = c < m;
     const int p = cbeg + (live ? c : 0);
-    const float4 pf = tqf[p];
-    const int cx = cell_coord(tq[p].x, uniform(S.glo[0]), uniform(S.ginv[0]), gx);
+    const float4 pf = c0 == 0 ? pf_first : tqf[p];
+    const int cx = cell_coord(c0 == 0 ? px_first : tq[p].x, uniform(S.glo[0]), uniform(S.ginv[0]), gx);
     int count = 0;
     int* __restrict__ wp = A.idx + (int64_t)p * T;
     auto append = [&](int j) {
@@ -773,12 +804,12 @@ __global__ __launch_bounds__(BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts K, B
       const int nch = min(LIST_STAGE, tot - G0);
       if (c0 > 0 || G0 > 0) __syncthreads();   // the previous piece is no longer read
       {
+        // slot and image shift of each staged position into LDS at once, the coordinate
+        // loads in flight meanwhile; then the coordinates are added in
         float3 pc[LIST_PT];
-        int pj[LIST_PT], pk[LIST_PT];   // slot; 4 * row + piece (0 left, 1 main, 2 right)
 #pragma unroll
-        for (int u = 0; u < LIST_PT; ++u) {   // slots, shifts and loads first, all in flight
-          const int s = threadIdx.x + u * BLOCK;
-          pj[u] = -1;
+        for (int u = 0; u < LIST_PT; ++u) {
+          const int s = threadIdx.x + u * LIST_BLOCK;
           if (s < nch) {
             const int G = G0 + s;
             int rr = 0, g = G;   // the row of staged position G and its row-local index
@@ -789,22 +820,25 @@ __global__ __launch_bounds__(BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts K, B
                 g = G - roff[k];
               }
             const int4 rs = rslot[rr];
-            const int nlm = rinfo[rr][4];
+            const int nlm = rinfo[rr][0];
             const int j = g + (g < rs.w ? rs.x : (g < nlm ? rs.y : rs.z));
-            pk[u] = 4 * rr + (g < rs.w ? 0 : (g < nlm ? 1 : 2));
             const float4* c4 = tqf + j;
             pc[u] = make_float3(c4->x, c4->y, c4->z);
-            pj[u] = j;
+            const float2 yz = rsh[rr];
+            sq[s] = make_float4(g < rs.w ? fxl : (g < nlm ? 0.0f : fxr), yz.x, yz.y, __int_as_float(j));
           }
         }
 #pragma unroll
-        for (int u = 0; u < LIST_PT; ++u)   // then the image shifts and the LDS writes
-          if (pj[u] >= 0) {
-            const float2 yz = rsh[pk[u] >> 2];
-            const int pc_ = pk[u] & 3;
-            const float fx = pc_ == 0 ? fxl : (pc_ == 1 ? 0.0f : fxr);
-            sq[threadIdx.x + u * BLOCK] = make_float4(pc[u].x + fx, pc[u].y + yz.x, pc[u].z + yz.y, __int_as_float(pj[u]));
+        for (int u = 0; u < LIST_PT; ++u) {
+          const int s = threadIdx.x + u * LIST_BLOCK;
+          if (s < nch) {
+            float4 e = sq[s];
+            e.x += pc[u].x;
+            e.y += pc[u].y;
+            e.z += pc[u].z;
+            sq[s] = e;
           }
+        }
       }
       __syncthreads();
       if (live) {
@@ -821,7 +855,7 @@ __global__ __launch_bounds__(BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts K, B
             double shy, shz;
             row_shift(rr, cy, cz, gy, gz, per1, per2, len1, len2, shy, shz);
             const int g = G0 + s - roff[rr];
-            const double shx = g < rinfo[rr][3] ? -len0 : (g < rinfo[rr][4] ? 0.0 : len0);
+            const double shx = g < rslot[rr].w ? -len0 : (g < rinfo[rr][0] ? 0.0 : len0);
             const double4 pi = tq[p], pj4 = tq[__float_as_int(sq[s].w)];
             return dist_sq_exact((pj4.x - pi.x) + shx, (pj4.y - pi.y) + shy, (pj4.z - pi.z) + shz) < rl2;
           };
