@@ -207,9 +207,12 @@ MD_API int md_build_neighbors(md_system *sys, const md_atoms *a, const md_lists 
  * per atom slot); MD_F_FORCE computes
  *   F_i = - sum_j [(F'(rho_i) + F'(rho_j)) f'(r_ij) + phi'(r_ij)] (q_i - q_j) / r_ij
  * into f over the Cr-Cr list (each atom gathers over its full list: no atomics).  With
- * MD_F_MORSE the Cr-C Morse forces of md_morse_forces are added in the same pass; with
- * MD_F_KICK the Task 5 half kick v += F/m dt/2 follows (mobile atoms).  MD_F_MIXED selects
- * FP32 arithmetic.  Lists must be current (md_build_neighbors in the same step). */
+ * MD_F_MORSE (and MD_F_FORCE) the Cr-C Morse forces of md_morse_forces are included in f:
+ * they are computed by extra blocks of the density launch when MD_F_DENSITY is also set
+ * (Task 4c does not depend on the density), else by a launch of their own before the force
+ * pass.  With MD_F_KICK the Task 5 half kick v += F/m dt/2 of the whole force follows
+ * (mobile atoms).  MD_F_MIXED selects FP32 arithmetic.  Lists must be current
+ * (md_build_neighbors in the same step). */
 MD_API int md_eam_forces(md_system *sys, const md_atoms *a, const md_lists *l, uint32_t flags,
                          double *rho_out, void *stream);
 

@@ -130,23 +130,28 @@ int grid_tiles(const md_system* s) { return s->ntiles; }
 
 // Grid of the kernels that walk the near-indenter atoms (one wavefront per atom, grid-stride).
 int near_blocks(const md_system* s) { return std::max(1, std::min(2048, s->ntiles)); }
+constexpr int MORSE_FUSED_BLOCKS = 256;   // most blocks of the Cr-C pass inside a density launch
 
 }  // namespace
 
 namespace {
 
 template <int T>
+// morse: the leading blocks of the launch also run the Cr-C pass into fme (for a force
+// pass that adds it)
 void launch_density(md_system* s, const md_atoms* a, const md_lists* l, bool mixed, bool energy,
-                    double* rho_out, hipStream_t st) {
+                    double* rho_out, bool morse, hipStream_t st) {
   const RepDesc* R = at<RepDesc>(s, s->L.desc);
   RepState* S = at<RepState>(s, s->L.state);
   const int* tr = at<int>(s, s->L.tile_rep);
   double4* q = reinterpret_cast<double4*>(a->q);
   double* pe = at<double>(s, s->L.p_embed);
-  const int nb = s->ntiles * T;
+  const MorseIn M{a->xc, l->xidx, l->xcnt, at<int>(s, s->L.near), at<double>(s, s->L.fme),
+                  morse ? std::min(near_blocks(s), MORSE_FUSED_BLOCKS) : 0};
+  const int nb = s->ntiles * T + M.nblocks;
   int4* qs = at<int4>(s, s->L.qs);
-#define DENS(M, SH, E) \
-  k_density<T, M, SH, E><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, qs, l->idx, l->cnt, rho_out, pe)
+#define DENS(M_, SH, E) \
+  k_density<T, M_, SH, E><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, qs, l->idx, l->cnt, rho_out, pe, M)
   if (mixed && s->K.shadow && !s->list_mix) { if (energy) DENS(true, true, true); else DENS(true, true, false); }
   else if (mixed) { if (energy) DENS(true, false, true); else DENS(true, false, false); }
   else { if (energy) DENS(false, false, true); else DENS(false, false, false); }
@@ -154,8 +159,9 @@ void launch_density(md_system* s, const md_atoms* a, const md_lists* l, bool mix
 }
 
 template <int T>
+// add_fme: the force includes the Cr-C force of this step from fme
 void launch_force(md_system* s, const md_atoms* a, const md_lists* l, bool mixed, bool kick, bool energy,
-                  hipStream_t st) {
+                  bool add_fme, hipStream_t st) {
   const RepDesc* R = at<RepDesc>(s, s->L.desc);
   RepState* S = at<RepState>(s, s->L.state);
   const int* tr = at<int>(s, s->L.tile_rep);
@@ -164,7 +170,8 @@ void launch_force(md_system* s, const md_atoms* a, const md_lists* l, bool mixed
   const int nb = s->ntiles * T;
   const int4* qs = at<int4>(s, s->L.qs);
 #define FORCE(M, SH, KI, E) \
-  k_force<T, M, SH, KI, E><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, qs, a->v, a->f, a->fixed, l->idx, l->cnt, pf)
+  k_force<T, M, SH, KI, E><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, qs, a->v, a->f, a->fixed, l->idx, l->cnt, pf, \
+                                                  l->xcnt, add_fme ? at<double>(s, s->L.fme) : nullptr)
 #define FORCE_E(M, SH, KI) \
   if (energy) FORCE(M, SH, KI, true); else FORCE(M, SH, KI, false)
 #define FORCE_K(M, SH) \
@@ -177,7 +184,8 @@ void launch_force(md_system* s, const md_atoms* a, const md_lists* l, bool mixed
 #undef FORCE
 }
 
-void launch_morse(md_system* s, const md_atoms* a, const md_lists* l, bool mixed, bool kick,
+// add_f: the Cr-C forces are added into f (else only recorded in fme)
+void launch_morse(md_system* s, const md_atoms* a, const md_lists* l, bool mixed, bool kick, bool add_f,
                   hipStream_t st) {
   const RepDesc* R = at<RepDesc>(s, s->L.desc);
   const RepState* S = at<RepState>(s, s->L.state);
@@ -185,10 +193,11 @@ void launch_morse(md_system* s, const md_atoms* a, const md_lists* l, bool mixed
   const int* nr = at<int>(s, s->L.near);
   double* fme = at<double>(s, s->L.fme);
   const int nb = near_blocks(s);
-#define MORSE(M, KI) \
-  k_morse<M, KI><<<nb, BLOCK, 0, st>>>(s->K, R, S, q, a->v, a->f, a->fixed, a->xc, l->xidx, l->xcnt, nr, fme)
-  if (mixed) { if (kick) MORSE(true, true); else MORSE(true, false); }
-  else { if (kick) MORSE(false, true); else MORSE(false, false); }
+#define MORSE(M, KI, AF) \
+  k_morse<M, KI, AF><<<nb, BLOCK, 0, st>>>(s->K, R, S, q, a->v, a->f, a->fixed, a->xc, l->xidx, l->xcnt, nr, fme)
+  if (!add_f) { if (mixed) MORSE(true, false, false); else MORSE(false, false, false); }
+  else if (mixed) { if (kick) MORSE(true, true, true); else MORSE(true, false, true); }
+  else { if (kick) MORSE(false, true, true); else MORSE(false, false, true); }
 #undef MORSE
 }
 
@@ -463,6 +472,37 @@ MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l
   return build_chain(s, a, l, flags, (hipStream_t)stream, nullptr, nullptr);
 }
 
+namespace {
+
+// The density pass (morse: with the Cr-C pass in the same launch).
+int eam_density(md_system* s, const md_atoms* a, const md_lists* l, uint32_t flags, double* rho_out, bool morse,
+                hipStream_t st) {
+  const bool mixed = flags & MD_F_MIXED, energy = flags & MD_F_ENERGY;
+  switch (s->K.lt) {
+    case 1: launch_density<1>(s, a, l, mixed, energy, rho_out, morse, st); break;
+    case 2: launch_density<2>(s, a, l, mixed, energy, rho_out, morse, st); break;
+    case 4: launch_density<4>(s, a, l, mixed, energy, rho_out, morse, st); break;
+    default: launch_density<8>(s, a, l, mixed, energy, rho_out, morse, st); break;
+  }
+  s->have_embed = energy;
+  return check_launch();
+}
+
+// The force pass (add_fme: the Cr-C forces recorded in fme this step are included).
+int eam_force(md_system* s, const md_atoms* a, const md_lists* l, uint32_t flags, bool add_fme, hipStream_t st) {
+  const bool mixed = flags & MD_F_MIXED, energy = flags & MD_F_ENERGY, kick = flags & MD_F_KICK;
+  switch (s->K.lt) {
+    case 1: launch_force<1>(s, a, l, mixed, kick, energy, add_fme, st); break;
+    case 2: launch_force<2>(s, a, l, mixed, kick, energy, add_fme, st); break;
+    case 4: launch_force<4>(s, a, l, mixed, kick, energy, add_fme, st); break;
+    default: launch_force<8>(s, a, l, mixed, kick, energy, add_fme, st); break;
+  }
+  s->have_force = energy;
+  return check_launch();
+}
+
+}  // namespace
+
 MD_API int md_eam_forces(md_system* s, const md_atoms* a, const md_lists* l, uint32_t flags,
                          double* rho_out, void* stream) {
   if (!s || !atoms_ok(a) || !lists_ok(l)) return MD_ERR_ARG;
@@ -470,30 +510,15 @@ MD_API int md_eam_forces(md_system* s, const md_atoms* a, const md_lists* l, uin
   if ((flags & MD_F_MIXED) && s->p.eam.c2 == 0.0) return MD_ERR_ARG;
   if (!s->ws) return MD_ERR_STATE;
   hipStream_t st = (hipStream_t)stream;
-  const bool mixed = flags & MD_F_MIXED, energy = flags & MD_F_ENERGY, kick = flags & MD_F_KICK;
-  const int T = s->K.lt;
-  if (flags & MD_F_DENSITY) {
-    switch (T) {
-      case 1: launch_density<1>(s, a, l, mixed, energy, rho_out, st); break;
-      case 2: launch_density<2>(s, a, l, mixed, energy, rho_out, st); break;
-      case 4: launch_density<4>(s, a, l, mixed, energy, rho_out, st); break;
-      default: launch_density<8>(s, a, l, mixed, energy, rho_out, st); break;
-    }
-    s->have_embed = energy;
-    int e = check_launch();
-    if (e) return e;
-  }
+  // With a force pass, the Cr-C forces go in with the Eq. 1 forces: computed into fme by
+  // extra blocks of the density launch when there is one, else by their own launch first.
+  const bool morse = (flags & MD_F_MORSE) && (flags & MD_F_FORCE) && s->ctot > 0;
+  const bool fused = morse && (flags & MD_F_DENSITY);
+  int e;
+  if ((flags & MD_F_DENSITY) && (e = eam_density(s, a, l, flags, rho_out, fused, st))) return e;
   if (flags & MD_F_FORCE) {
-    switch (T) {
-      case 1: launch_force<1>(s, a, l, mixed, kick, energy, st); break;
-      case 2: launch_force<2>(s, a, l, mixed, kick, energy, st); break;
-      case 4: launch_force<4>(s, a, l, mixed, kick, energy, st); break;
-      default: launch_force<8>(s, a, l, mixed, kick, energy, st); break;
-    }
-    s->have_force = energy;
-    if ((flags & MD_F_MORSE) && s->ctot > 0) launch_morse(s, a, l, mixed, kick, st);
-    int e = check_launch();
-    if (e) return e;
+    if (morse && !fused) launch_morse(s, a, l, flags & MD_F_MIXED, false, false, st);
+    if ((e = eam_force(s, a, l, flags, morse, st))) return e;
   }
   return MD_OK;
 }
@@ -503,7 +528,7 @@ MD_API int md_morse_forces(md_system* s, const md_atoms* a, const md_lists* l, u
   if (!s || !atoms_ok(a) || !lists_ok(l)) return MD_ERR_ARG;
   if (s->ctot > 0 && !a->xc) return MD_ERR_ARG;
   if (!s->ws) return MD_ERR_STATE;
-  if (s->ctot > 0) launch_morse(s, a, l, flags & MD_F_MIXED, flags & MD_F_KICK, (hipStream_t)stream);
+  if (s->ctot > 0) launch_morse(s, a, l, flags & MD_F_MIXED, flags & MD_F_KICK, true, (hipStream_t)stream);
   return check_launch();
 }
 
@@ -557,13 +582,13 @@ MD_API int md_run(md_system* s, const md_atoms* a, const md_lists* l, int32_t ns
     if (events)
       for (int u = 0; u < 4; ++u) ev[u] = (hipEvent_t)events[4 * (k - 1) + u];
     if ((e = build_chain(s, a, l, 0, st, ev[2], ev[3]))) return e;
-    if ((e = md_eam_forces(s, a, l, MD_F_DENSITY | mixed | (en ? MD_F_ENERGY : 0), nullptr, stream)))
-      return e;
+    // Task 4c runs in the density launch; the force pass includes it and gives the kick
+    const bool morse = s->ctot > 0;
+    const uint32_t ef = mixed | (en ? MD_F_ENERGY : 0);
+    if ((e = eam_density(s, a, l, MD_F_DENSITY | ef, nullptr, morse, st))) return e;
     if (ev[0] && (e = hip_status(hipEventRecord(ev[0], st)))) return e;
-    if ((e = md_eam_forces(s, a, l, MD_F_FORCE | MD_F_KICK | mixed | (en ? MD_F_ENERGY : 0), nullptr, stream)))
-      return e;
+    if ((e = eam_force(s, a, l, MD_F_FORCE | MD_F_KICK | ef, morse, st))) return e;
     if (ev[1] && (e = hip_status(hipEventRecord(ev[1], st)))) return e;
-    if ((e = md_morse_forces(s, a, l, MD_F_KICK | mixed, stream))) return e;
     if (en) {
       double* out = obs + (int64_t)(k / energy_every - 1) * s->nrep * MD_NOBS;
       if ((e = md_energy(s, a, out, stream))) return e;

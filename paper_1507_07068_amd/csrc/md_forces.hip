@@ -75,10 +75,10 @@ struct AtomCtx {
 };
 
 template <int T>
-__device__ __forceinline__ AtomCtx atom_ctx(const int* tile_rep, const RepDesc* R) {
+__device__ __forceinline__ AtomCtx atom_ctx(const int* tile_rep, const RepDesc* R, int bid, int nb) {
   constexpr int APB = BLOCK / T;
   AtomCtx c;
-  c.blk = xcd_block(blockIdx.x, gridDim.x);
+  c.blk = xcd_block(bid, nb);
   const int tile = c.blk / T;
   c.r = tile_rep[tile];
   c.sub = threadIdx.x % T;
@@ -87,6 +87,127 @@ __device__ __forceinline__ AtomCtx atom_ctx(const int* tile_rep, const RepDesc* 
   c.live = c.i < (int64_t)d.a0 + d.n;
   return c;
 }
+
+// Task 4c: Cr-C Morse forces, F_i += -phiM'(r) (q_i - q_k)/r over atom i's Cr-C list.
+// One wavefront per atom of the replicas' near lists (grid-stride over all of them); the
+// 64 lanes share that atom's carbons and combine their sums with a fixed butterfly.
+// fme[i] receives (F_i, E_i) of the atom, which the energy pass sums in atom order; with
+// ADD_F the force is also added into f (and, with KICK, its half kick into v).  Without
+// ADD_F the pass runs in extra blocks of the density launch and the force pass adds fme.
+template <bool MIXED, bool KICK, bool ADD_F>
+__device__ __forceinline__ void morse_pass(const Consts& K, const RepDesc* __restrict__ R,
+                                           const RepState* __restrict__ S,
+                                           const double4* __restrict__ q,
+                                           double* __restrict__ v, double* __restrict__ f,
+                                           const uint8_t* __restrict__ fixed,
+                                           const double* __restrict__ xc,
+                                           const int* __restrict__ xidx,
+                                           const int* __restrict__ xcnt,
+                                           const int* __restrict__ near,
+                                           double* __restrict__ fme, int bid, int nb) {
+  const int lane = threadIdx.x % WAVE;
+  const int gw = bid * (BLOCK / WAVE) + threadIdx.x / WAVE, nw = nb * (BLOCK / WAVE);
+  auto one = [&](int r, int item) {   // near atom `item` of replica r, on this wavefront
+    const RepDesc& d = R[r];
+    const double iz = S[r].ind_z;
+    {
+      const int64_t pa = near[d.a0 + item];
+      const int na = xcnt[pa];
+      const double4 pi = q[pa];
+      double fm0 = 0.0, fm1 = 0.0, fm2 = 0.0, em = 0.0;
+      for (int k = lane; k < na; k += WAVE) {
+        const int kk = xidx[pa * K.xcap + k];
+        const double ex = min_image(xc[3 * kk + 0] - pi.x, d.len[0], d.half[0], d.per[0]);
+        const double ey = min_image(xc[3 * kk + 1] - pi.y, d.len[1], d.half[1], d.per[1]);
+        const double ez = min_image((xc[3 * kk + 2] + iz) - pi.z, d.len[2], d.half[2], d.per[2]);
+        if (MIXED) {
+          const float fx = (float)ex, fy = (float)ey, fz = (float)ez;
+          const float r2 = fx * fx + fy * fy + fz * fz;
+          if (r2 < (float)K.mrc_sq) {
+            const float rinv = __frsqrt_rn(r2);
+            const float rr = r2 * rinv;
+            const float e = __expf(-(float)K.alpha * (rr - (float)K.r0));
+            const float g = 2.0f * (float)(K.alpha * K.D) * (e - e * e);   // phiM'(r)
+            const float s = g * rinv;                                     // F_i += g (q_k - q_i)/r
+            fm0 += s * fx;
+            fm1 += s * fy;
+            fm2 += s * fz;
+            em += (double)((float)K.D * (e * e - 2.0f * e)) - K.mshift;
+          }
+        } else {
+          const double r2 = ex * ex + ey * ey + ez * ez;
+          if (r2 < K.mrc_sq) {
+            const double rr = sqrt(r2);
+            const double e = exp(-K.alpha * (rr - K.r0));
+            const double g = 2.0 * K.alpha * K.D * (e - e * e);
+            const double s = g / rr;
+            fm0 += s * ex;
+            fm1 += s * ey;
+            fm2 += s * ez;
+            em += K.D * (e * e - 2.0 * e) - K.mshift;
+          }
+        }
+      }
+      fm0 = wave_sum(fm0);
+      fm1 = wave_sum(fm1);
+      fm2 = wave_sum(fm2);
+      em = wave_sum(em);
+      if (lane == 0) {
+        if (ADD_F) {
+          f[3 * pa + 0] += fm0;
+          f[3 * pa + 1] += fm1;
+          f[3 * pa + 2] += fm2;
+        }
+        if (KICK && !fixed[pa]) {
+          const double h = 0.5 * K.dt * K.acc;
+          v[3 * pa + 0] += h * fm0;
+          v[3 * pa + 1] += h * fm1;
+          v[3 * pa + 2] += h * fm2;
+        }
+        fme[4 * pa + 0] = fm0;
+        fme[4 * pa + 1] = fm1;
+        fme[4 * pa + 2] = fm2;
+        fme[4 * pa + 3] = em;
+      }
+    }
+  };
+  __shared__ int pre[FLAT_MAXREP + 1];
+  if (K.nrep <= FLAT_MAXREP) {
+    const int total = flat_prefix(K.nrep, pre, [&](int r) { return S[r].nnear; });
+    for (int g = gw; g < total; g += nw) {
+      const int r = flat_replica(pre, K.nrep, g);
+      one(r, g - pre[r]);
+    }
+  } else {
+    for (int r = 0; r < K.nrep; ++r)
+      for (int item = gw; item < S[r].nnear; item += nw) one(r, item);
+  }
+}
+
+template <bool MIXED, bool KICK, bool ADD_F>
+__global__ __launch_bounds__(BLOCK) void k_morse(Consts K, const RepDesc* __restrict__ R,
+                                                 const RepState* __restrict__ S,
+                                                 const double4* __restrict__ q,
+                                                 double* __restrict__ v, double* __restrict__ f,
+                                                 const uint8_t* __restrict__ fixed,
+                                                 const double* __restrict__ xc,
+                                                 const int* __restrict__ xidx,
+                                                 const int* __restrict__ xcnt,
+                                                 const int* __restrict__ near,
+                                                 double* __restrict__ fme) {
+  morse_pass<MIXED, KICK, ADD_F>(K, R, S, q, v, f, fixed, xc, xidx, xcnt, near, fme, blockIdx.x, gridDim.x);
+}
+
+// The Cr-C pass that the leading M.nblocks blocks of a density launch run (Task 4c does
+// not depend on the density, so it overlaps with it).
+struct MorseIn {
+  const double* xc;
+  const int* xidx;
+  const int* xcnt;
+  const int* near;
+  double* fme;
+  int nblocks;
+};
 
 // SHADOW (with MIXED): separations from the fixed-point cell-local shadow qs and the entries'
 // relative cells; otherwise FP64 positions (rounded to FP32 for the MIXED arithmetic).
@@ -99,8 +220,13 @@ __global__ __launch_bounds__(BLOCK) void k_density(Consts K, const RepDesc* __re
                                                    const int* __restrict__ idx,
                                                    const int* __restrict__ cnt,
                                                    double* __restrict__ rho_out,
-                                                   double* __restrict__ part) {
-  const AtomCtx c = atom_ctx<T>(tile_rep, R);
+                                                   double* __restrict__ part, MorseIn M) {
+  if ((int)blockIdx.x < M.nblocks) {   // uniform over the block
+    morse_pass<MIXED, false, false>(K, R, S, q, nullptr, nullptr, nullptr, M.xc, M.xidx, M.xcnt, M.near, M.fme,
+                                    blockIdx.x, M.nblocks);
+    return;
+  }
+  const AtomCtx c = atom_ctx<T>(tile_rep, R, (int)blockIdx.x - M.nblocks, (int)gridDim.x - M.nblocks);
   const RepDesc& d = R[c.r];
   __shared__ int4 ctab[27];
   if (SHADOW) fill_cell_offsets(ctab, S[c.r]);
@@ -183,8 +309,10 @@ __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __rest
                                                  const uint8_t* __restrict__ fixed,
                                                  const int* __restrict__ idx,
                                                  const int* __restrict__ cnt,
-                                                 double* __restrict__ part) {
-  const AtomCtx c = atom_ctx<T>(tile_rep, R);
+                                                 double* __restrict__ part,
+                                                 const int* __restrict__ xcnt,
+                                                 const double* __restrict__ fme) {
+  const AtomCtx c = atom_ctx<T>(tile_rep, R, blockIdx.x, gridDim.x);
   const RepDesc& d = R[c.r];
   __shared__ int4 ctab[27];
   if (SHADOW) fill_cell_offsets(ctab, S[c.r]);
@@ -299,6 +427,11 @@ __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __rest
   fz = group_sum<T>(fz);
   if (c.live && c.sub == 0) {
     const int64_t i = c.i;
+    if (fme && xcnt[i] > 0) {   // the Cr-C force of this step (atoms with carbons in range)
+      fx += fme[4 * i + 0];
+      fy += fme[4 * i + 1];
+      fz += fme[4 * i + 2];
+    }
     f[3 * i + 0] = fx;
     f[3 * i + 1] = fy;
     f[3 * i + 2] = fz;
@@ -311,99 +444,6 @@ __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __rest
     }
   }
   if (ENERGY) block_sum_store<NP_FORCE, BLOCK>(acc, part + (int64_t)c.blk * NP_FORCE);
-}
-
-// Task 4c: Cr-C Morse forces, F_i += -phiM'(r) (q_i - q_k)/r over atom i's Cr-C list,
-// added into f (and, with KICK, their half kick into v).  One wavefront per atom of the
-// replicas' near lists (grid-stride over all of them); the 64 lanes share that atom's carbons and combine
-// their sums with a fixed butterfly.  fme[i] receives (F_i, E_i) of the atom for the
-// energy pass, which sums it in atom order.
-template <bool MIXED, bool KICK>
-__global__ __launch_bounds__(BLOCK) void k_morse(Consts K, const RepDesc* __restrict__ R,
-                                                 const RepState* __restrict__ S,
-                                                 const double4* __restrict__ q,
-                                                 double* __restrict__ v, double* __restrict__ f,
-                                                 const uint8_t* __restrict__ fixed,
-                                                 const double* __restrict__ xc,
-                                                 const int* __restrict__ xidx,
-                                                 const int* __restrict__ xcnt,
-                                                 const int* __restrict__ near,
-                                                 double* __restrict__ fme) {
-  const int lane = threadIdx.x % WAVE;
-  const int gw = blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE, nw = gridDim.x * (BLOCK / WAVE);
-  auto one = [&](int r, int item) {   // near atom `item` of replica r, on this wavefront
-    const RepDesc& d = R[r];
-    const double iz = S[r].ind_z;
-    {
-      const int64_t pa = near[d.a0 + item];
-      const int na = xcnt[pa];
-      const double4 pi = q[pa];
-      double fm0 = 0.0, fm1 = 0.0, fm2 = 0.0, em = 0.0;
-      for (int k = lane; k < na; k += WAVE) {
-        const int kk = xidx[pa * K.xcap + k];
-        const double ex = min_image(xc[3 * kk + 0] - pi.x, d.len[0], d.half[0], d.per[0]);
-        const double ey = min_image(xc[3 * kk + 1] - pi.y, d.len[1], d.half[1], d.per[1]);
-        const double ez = min_image((xc[3 * kk + 2] + iz) - pi.z, d.len[2], d.half[2], d.per[2]);
-        if (MIXED) {
-          const float fx = (float)ex, fy = (float)ey, fz = (float)ez;
-          const float r2 = fx * fx + fy * fy + fz * fz;
-          if (r2 < (float)K.mrc_sq) {
-            const float rinv = __frsqrt_rn(r2);
-            const float rr = r2 * rinv;
-            const float e = __expf(-(float)K.alpha * (rr - (float)K.r0));
-            const float g = 2.0f * (float)(K.alpha * K.D) * (e - e * e);   // phiM'(r)
-            const float s = g * rinv;                                     // F_i += g (q_k - q_i)/r
-            fm0 += s * fx;
-            fm1 += s * fy;
-            fm2 += s * fz;
-            em += (double)((float)K.D * (e * e - 2.0f * e)) - K.mshift;
-          }
-        } else {
-          const double r2 = ex * ex + ey * ey + ez * ez;
-          if (r2 < K.mrc_sq) {
-            const double rr = sqrt(r2);
-            const double e = exp(-K.alpha * (rr - K.r0));
-            const double g = 2.0 * K.alpha * K.D * (e - e * e);
-            const double s = g / rr;
-            fm0 += s * ex;
-            fm1 += s * ey;
-            fm2 += s * ez;
-            em += K.D * (e * e - 2.0 * e) - K.mshift;
-          }
-        }
-      }
-      fm0 = wave_sum(fm0);
-      fm1 = wave_sum(fm1);
-      fm2 = wave_sum(fm2);
-      em = wave_sum(em);
-      if (lane == 0) {
-        f[3 * pa + 0] += fm0;
-        f[3 * pa + 1] += fm1;
-        f[3 * pa + 2] += fm2;
-        if (KICK && !fixed[pa]) {
-          const double h = 0.5 * K.dt * K.acc;
-          v[3 * pa + 0] += h * fm0;
-          v[3 * pa + 1] += h * fm1;
-          v[3 * pa + 2] += h * fm2;
-        }
-        fme[4 * pa + 0] = fm0;
-        fme[4 * pa + 1] = fm1;
-        fme[4 * pa + 2] = fm2;
-        fme[4 * pa + 3] = em;
-      }
-    }
-  };
-  __shared__ int pre[FLAT_MAXREP + 1];
-  if (K.nrep <= FLAT_MAXREP) {
-    const int total = flat_prefix(K.nrep, pre, [&](int r) { return S[r].nnear; });
-    for (int g = gw; g < total; g += nw) {
-      const int r = flat_replica(pre, K.nrep, g);
-      one(r, g - pre[r]);
-    }
-  } else {
-    for (int r = 0; r < K.nrep; ++r)
-      for (int item = gw; item < S[r].nnear; item += nw) one(r, item);
-  }
 }
 
 // Task 5 alone.
