@@ -48,10 +48,11 @@ def log(*a):
 
 def force_bytes_per_atom(mean_list: float) -> float:
     """Algorithmic HBM bytes of one EAM force launch per atom: q_i = (x, y, z, F') 32,
-    list count 4, list entries 4 each, fixed flag 1, velocity read + write for the fused
+    list count 4, list entries 4 each, Cr-C count 4 (the few atoms with carbons in range
+    also read their 32-byte Cr-C record), fixed flag 1, velocity read + write for the fused
     kick 48, force write 24.  Neighbour positions are gathered from cache (atoms are
     cell-sorted, so each one is fetched from HBM once per pass)."""
-    return 32 + 4 + 4 * mean_list + 1 + 48 + 24
+    return 32 + 4 + 4 * mean_list + 4 + 1 + 48 + 24
 
 
 def list_bytes_per_atom(mean_list: float) -> float:

@@ -83,17 +83,25 @@ def steps(d: str) -> str:
 
 
 def pmc(dirs) -> str:
-    res = collections.defaultdict(lambda: collections.defaultdict(list))
+    """Counters per kernel: the mean over its dispatches, and the mean over its busy
+    dispatches (those above the geometric mean of the smallest and largest reading; for the
+    build kernels, which return at once in steps without a rebuild, these are the rebuilds)."""
+    res = collections.defaultdict(lambda: collections.defaultdict(lambda: collections.defaultdict(float)))
     for d in dirs:
         c = sqlite3.connect(_db(d))
-        for kn, cn, val in c.execute("select kernel_name, counter_name, value from counters_collection"):
-            res[kn][cn].append(val)
+        cols = [r[1] for r in c.execute("pragma table_info(counters_collection)")]
+        key = "dispatch_id" if "dispatch_id" in cols else "rowid"
+        for kn, cn, val, did in c.execute(
+                f"select kernel_name, counter_name, value, {key} from counters_collection"):
+            res[kn][cn][(d, did)] += val
     out = []
     for kn in sorted(res):
         parts = [f"{short_name(kn):40s}"]
         for cn in sorted(res[kn]):
-            v = np.array(res[kn][cn])
-            parts.append(f"{cn}: mean {v.mean():.6g} max {v.max():.6g} (n={v.size})")
+            v = np.array(list(res[kn][cn].values()))
+            lo, hi = max(v.min(), 1e-9), max(v.max(), 1e-9)
+            busy = v[v > np.sqrt(lo * hi)] if hi > 4 * lo else v
+            parts.append(f"{cn}: mean {v.mean():.6g} busy {busy.mean():.6g} (n={v.size}, busy {busy.size})")
         out.append("  ".join(parts))
     return "\n".join(out)
 
