@@ -22,7 +22,7 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Byte offsets of the workspace regions.
 struct Layout {
-  size_t desc, state, tile_rep, lblk_rep, c_rep, misc, xref, dmax, tbox, cellid, crank, perm, skey, tq, tqf, qs, bcell, tv,
+  size_t desc, state, tile_rep, row_rep, items, c_rep, misc, xref, dmax, tbox, cellid, crank, perm, skey, tq, tqf, qs, bcell, tv,
       tf, tfixed, tid, count, start, hcell, hrank, hlist, hsorted, scan_state, hnear, near, fme, p_embed, p_force,
       p_morse, p_kin, total;
 };
@@ -38,11 +38,12 @@ struct md_system {
   int nrep;
   std::vector<RepDesc> desc;
   std::vector<int> tile_rep;
-  std::vector<int> lblk_rep;   // replica of each block of the list build
+  std::vector<int> row_rep;    // replica of each cell row at capacity
   std::vector<int> c_rep;
   int64_t ntot, ctot;
   int ntiles;
-  int nlblk;     // blocks of the list build
+  int nlblk;     // blocks of the list build (most work items)
+  int nrows;     // cell rows at capacity, all replicas
   int ncell_cr, ncell_all;
   Consts K;
   Layout L;
@@ -71,7 +72,8 @@ Layout make_layout(const md_system& s) {
   L.desc = take(sizeof(RepDesc) * s.nrep);
   L.state = take(sizeof(RepState) * s.nrep);
   L.tile_rep = take(sizeof(int) * nt);
-  L.lblk_rep = take(sizeof(int) * (size_t)s.nlblk);
+  L.row_rep = take(sizeof(int) * (size_t)s.nrows);
+  L.items = take(sizeof(int2) * (size_t)s.nlblk);
   L.c_rep = take(sizeof(int) * (size_t)s.ctot);
   L.misc = take(sizeof(int) * MISC_INTS);
   L.xref = take(sizeof(double) * 3 * n);
@@ -130,7 +132,11 @@ int grid_tiles(const md_system* s) { return s->ntiles; }
 
 // Grid of the kernels that walk the near-indenter atoms (one wavefront per atom, grid-stride).
 int near_blocks(const md_system* s) { return std::max(1, std::min(2048, s->ntiles)); }
-constexpr int MORSE_FUSED_BLOCKS = 256;   // most blocks of the Cr-C pass inside a density launch
+// Blocks of the Cr-C pass inside a density launch: about one wavefront per three carbons'
+// worth of near atoms (their count is known only on the device), 64 .. 2048.
+int morse_fused_blocks(const md_system* s) {
+  return (int)std::min<int64_t>(2048, std::max<int64_t>(64, (s->ctot + 11) / 12));
+}
 
 }  // namespace
 
@@ -147,7 +153,7 @@ void launch_density(md_system* s, const md_atoms* a, const md_lists* l, bool mix
   double4* q = reinterpret_cast<double4*>(a->q);
   double* pe = at<double>(s, s->L.p_embed);
   const MorseIn M{a->xc, l->xidx, l->xcnt, at<int>(s, s->L.near), at<double>(s, s->L.fme),
-                  morse ? std::min(near_blocks(s), MORSE_FUSED_BLOCKS) : 0};
+                  morse ? morse_fused_blocks(s) : 0};
   const int nb = s->ntiles * T + M.nblocks;
   int4* qs = at<int4>(s, s->L.qs);
 #define DENS(M_, SH, E) \
@@ -235,7 +241,7 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
   s->list_mix = false;
   const double rlist = p->eam.c + p->skin;
   const double rxlist = p->morse.rc + p->skin;
-  int64_t a0 = 0, c0 = 0;
+  int64_t a0 = 0, c0 = 0, nlblk = 0;
   int t0 = 0, g0 = 0;
   std::vector<int> hcells(nrep);
   for (int r = 0; r < nrep; ++r) {
@@ -280,13 +286,17 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
     if (a0 > (int64_t)INT32_MAX / 2 || c0 > (int64_t)INT32_MAX / 2) { delete s; return MD_ERR_ARG; }
     s->desc.push_back(d);
     for (int t = 0; t < ntile; ++t) s->tile_rep.push_back(r);
-    // list build: one block per run of cells of a cell row, at capacity, up to nseg runs
-    // per row (twice the runs of LIST_SEG cells, so that dense rows can be cut finer)
-    s->desc.back().lb0 = (int)s->lblk_rep.size();
+    // list build: rows at capacity, each cut into at most nseg runs of cells (twice the
+    // runs of LIST_SEG cells, so that dense rows can be cut finer); one block per run
+    s->desc.back().rb0 = (int)s->row_rep.size();
     s->desc.back().nseg = 2 * ((d.gcap[0] + LIST_SEG - 1) / LIST_SEG) * ((224 + LIST_TGT - 1) / LIST_TGT);
-    const int64_t nlb = (int64_t)s->desc.back().nseg * d.gcap[1] * d.gcap[2];
-    if ((int64_t)s->lblk_rep.size() + nlb > (int64_t)INT32_MAX / 2) { delete s; return MD_ERR_ARG; }
-    s->lblk_rep.insert(s->lblk_rep.end(), (size_t)nlb, r);
+    const int64_t nrw = (int64_t)d.gcap[1] * d.gcap[2];
+    nlblk += (int64_t)s->desc.back().nseg * nrw;
+    if ((int64_t)s->row_rep.size() + nrw > (int64_t)INT32_MAX / 2 || nlblk > (int64_t)INT32_MAX / 2) {
+      delete s;
+      return MD_ERR_ARG;
+    }
+    s->row_rep.insert(s->row_rep.end(), (size_t)nrw, r);
     for (int k = 0; k < rd.n_c; ++k) s->c_rep.push_back(r);
   }
   s->ncell_cr = g0;
@@ -306,7 +316,8 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
   s->ntot = a0;
   s->ctot = c0;
   s->ntiles = t0;
-  s->nlblk = (int)s->lblk_rep.size();
+  s->nlblk = (int)nlblk;
+  s->nrows = (int)s->row_rep.size();
 
   Consts& K = s->K;
   std::memset(&K, 0, sizeof K);
@@ -373,8 +384,8 @@ MD_API int md_workspace_bind(md_system* s, void* ws, size_t bytes, void* stream)
   if ((e = hip_status(hipMemcpyAsync(at<RepDesc>(s, s->L.desc), s->desc.data(),
                                      sizeof(RepDesc) * s->nrep, hipMemcpyHostToDevice, st))))
     return e;
-  if ((e = hip_status(hipMemcpyAsync(at<int>(s, s->L.lblk_rep), s->lblk_rep.data(),
-                                     sizeof(int) * s->nlblk, hipMemcpyHostToDevice, st))))
+  if ((e = hip_status(hipMemcpyAsync(at<int>(s, s->L.row_rep), s->row_rep.data(),
+                                     sizeof(int) * s->nrows, hipMemcpyHostToDevice, st))))
     return e;
   if ((e = hip_status(hipMemcpyAsync(at<int>(s, s->L.tile_rep), s->tile_rep.data(),
                                      sizeof(int) * s->ntiles, hipMemcpyHostToDevice, st))))
@@ -398,7 +409,11 @@ int build_chain(md_system* s, const md_atoms* a, const md_lists* l, uint32_t fla
   A.R = at<RepDesc>(s, s->L.desc);
   A.S = at<RepState>(s, s->L.state);
   A.tile_rep = at<int>(s, s->L.tile_rep);
-  A.lblk_rep = at<int>(s, s->L.lblk_rep);
+  A.row_rep = at<int>(s, s->L.row_rep);
+  A.items = at<int2>(s, s->L.items);
+  A.nitems = misc + 2;
+  A.nrows = s->nrows;
+  A.nlblk = s->nlblk;
   A.c_rep = at<int>(s, s->L.c_rep);
   A.any = misc + 0;
   A.q = reinterpret_cast<double4*>(a->q);

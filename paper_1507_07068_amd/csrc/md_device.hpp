@@ -27,7 +27,7 @@ struct RepDesc {
   int g0, gcap[3];      // Cr-Cr cell grid: first cell (global), allocated dims (the dims in
                         // use along open axes follow the atoms, see RepState)
   int h0, hd[3];        // Cr-C cell grid: first cell (global, after all Cr grids), dims
-  int lb0, nseg;        // list build: first work item, items per cell row (most runs of cells)
+  int rb0, nseg;        // list build: first cell row at capacity (global numbering), most runs per row
   double ginv[3];       // cells per Angstrom of the Cr grid along periodic axes
   double hinv[3];       // cells per Angstrom of the carbon grid
 };

@@ -26,7 +26,9 @@ struct BuildArgs {
   const RepDesc* R;
   RepState* S;
   const int* tile_rep;   // [ntiles]
-  const int* lblk_rep;   // [list-build blocks] replica of each
+  const int* row_rep;    // [nrows] replica of each cell row at capacity
+  int2* items;           // [list-build blocks] work items of k_list_tiles: (row, run | runs << 16)
+  int* nitems;           // work items of this build
   const int* c_rep;      // [ctot] replica of each carbon
   int* any;              // 1 if some replica rebuilds in this step
   double4* q;
@@ -66,6 +68,7 @@ struct BuildArgs {
   int ncell_all, ncell_cr, ntiles, ctot;
   int near_blocks;       // grid of k_xlist
   int scan_chunk, scan_blocks;
+  int nrows, nlblk;      // cell rows at capacity; capacity of the work-item table
 };
 
 #ifndef MD_LIST_BATCH
@@ -79,6 +82,20 @@ constexpr int LIST_SEG = 42;      // most cells of one work item of k_list_tiles
 #define MD_LIST_STAGE 1024
 #endif
 constexpr int LIST_STAGE = MD_LIST_STAGE;   // candidates k_list_tiles stages in LDS at a time
+#ifndef MD_LIST_WAVES
+#define MD_LIST_WAVES 7
+#endif
+#ifndef MD_LIST_BLOCK
+#define MD_LIST_BLOCK 256
+#endif
+#ifndef MD_LIST_TGT
+#define MD_LIST_TGT 224
+#endif
+constexpr int LIST_BLOCK = MD_LIST_BLOCK;           // threads of k_list_tiles
+constexpr int LIST_TGT = MD_LIST_TGT;               // atoms per work item aimed at
+constexpr int LIST_PT = LIST_STAGE / LIST_BLOCK;    // candidates each thread stages per piece
+static_assert(LIST_STAGE % LIST_BLOCK == 0, "a piece is a whole number of candidates per thread");
+static_assert(LIST_TGT <= LIST_BLOCK, "a work item's atoms aimed at fit one pass of the threads");
 #ifndef MD_LIST_GROUP
 #define MD_LIST_GROUP 4
 #endif
@@ -171,7 +188,17 @@ __global__ __launch_bounds__(DECIDE_THREADS) void k_decide(Consts K, BuildArgs A
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) *A.any = any_sh;
+  if (threadIdx.x == 0) {
+    *A.any = any_sh;
+    *A.nitems = 0;   // k_scatter lists the list-build work items of a rebuild
+  }
+  for (int r = threadIdx.x; r < K.nrep; r += DECIDE_THREADS) {   // builds are counted here
+    RepState& s = A.S[r];
+    if (s.rebuild) {
+      s.nbuilds += 1;
+      s.ind_z_ref = s.ind_z;
+    }
+  }
 }
 
 __device__ __forceinline__ int cr_cell_of(const RepDesc& d, const RepState& s, double x, double y, double z) {
@@ -350,8 +377,44 @@ __global__ __launch_bounds__(BLOCK) void k_scan(BuildArgs A) {
   }
 }
 
+// Work items of k_list_tiles for cell row g (capacity numbering) of a rebuilding replica:
+// the row is cut into as many runs of cells as keep a run's atoms near LIST_TGT (and no run
+// longer than LIST_SEG cells); empty rows get none.  Returns the number of runs.
+__device__ __forceinline__ int row_runs(const BuildArgs& A, int64_t g) {
+  if (g >= A.nrows) return 0;
+  const int r = A.row_rep[g];
+  const RepState& S = A.S[r];
+  if (!S.rebuild) return 0;
+  const RepDesc& d = A.R[r];
+  const int gx = S.gd[0], gy = S.gd[1], gz = S.gd[2];
+  const int l = (int)(g - d.rb0), cy = l % gy, cz = l / gy;
+  if (cz >= gz) return 0;
+  const int crow = d.g0 + (cz * gy + cy) * gx;
+  const int n = A.start[crow + gx] - A.start[crow];
+  if (n == 0) return 0;
+  return min(min(d.nseg, gx), max((gx + LIST_SEG - 1) / LIST_SEG, (n + LIST_TGT - 1) / LIST_TGT));
+}
+
 __global__ __launch_bounds__(BLOCK) void k_scatter(Consts K, BuildArgs A) {
   if (rebuild_off(A)) return;
+  // list-build work items, one cell row per thread, appended with one atomic per wavefront
+  // (their order is immaterial: each item writes only its own atoms' lists)
+  const int lane = threadIdx.x % WAVE;
+  for (int64_t g0 = (int64_t)blockIdx.x * BLOCK; g0 < A.nrows; g0 += (int64_t)gridDim.x * BLOCK) {
+    const int64_t g = g0 + threadIdx.x;
+    const int nr = row_runs(A, g);
+    int incl = nr;   // inclusive prefix over the wavefront
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const int t = __shfl_up(incl, o, WAVE);
+      if (lane >= o) incl += t;
+    }
+    int base = 0;
+    if (lane == WAVE - 1 && incl > 0) base = atomicAdd(A.nitems, incl);
+    base = __shfl(base, WAVE - 1, WAVE);
+    for (int k = 0, at = base + incl - nr; k < nr; ++k, ++at)
+      if (at < A.nlblk) A.items[at] = make_int2((int)g, k | (nr << 16));
+  }
   const int b = blockIdx.x;
   if (b < A.ntiles) {
     const int r = A.tile_rep[b];
@@ -463,10 +526,6 @@ __global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
   RepState& S = A.S[r];
   if (!S.rebuild) return;
   const RepDesc& d = A.R[r];
-  if (tile == d.t0 && threadIdx.x == 0) {   // once per replica: the build is counted
-    S.nbuilds += 1;
-    S.ind_z_ref = S.ind_z;
-  }
   const int lane = threadIdx.x % WAVE;
   const int p = tile * TILE + threadIdx.x;
   const bool live = p < d.a0 + d.n;
@@ -626,10 +685,9 @@ __global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
 }
 
 // Cr-Cr lists with LDS-staged candidates (replicas whose periodic axes all have >= 3 list
-// cells).  A work item is a run of cells of one cell row: each row is cut into as many
-// runs as keep a run's atoms near LIST_TGT (and no run longer than LIST_SEG cells), so
-// that one pass of a block's threads covers a run's atoms, one center per thread; one
-// block per item.  For each of the nine neighbouring cell rows (z-major, then y) the block
+// cells).  A work item is a run of cells of one cell row (listed by k_scatter, see
+// row_runs), sized so that one pass of a block's threads covers a run's atoms, one center
+// per thread; one block per item, the blocks beyond the items return at once.  For each of the nine neighbouring cell rows (z-major, then y) the block
 // stages that row's atoms of x-cells x0-1 .. x1+1 -- with the cell seen across a periodic
 // x face placed at the end it is seen from -- into LDS as FP32 coordinates relative to the
 // grid origin plus the row's image shift, with the slot in the fourth word.  The nine
@@ -639,20 +697,6 @@ __global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
 // round of loads when they fit LIST_STAGE candidates (else in pieces of that size), so a
 // block waits on few dependent memory round trips.  The FP32 screen and its exact FP64
 // band are those of k_list_rows.
-#ifndef MD_LIST_WAVES
-#define MD_LIST_WAVES 7
-#endif
-#ifndef MD_LIST_BLOCK
-#define MD_LIST_BLOCK 256
-#endif
-#ifndef MD_LIST_TGT
-#define MD_LIST_TGT 224
-#endif
-constexpr int LIST_BLOCK = MD_LIST_BLOCK;           // threads of k_list_tiles
-constexpr int LIST_TGT = MD_LIST_TGT;               // atoms per work item aimed at
-constexpr int LIST_PT = LIST_STAGE / LIST_BLOCK;    // candidates each thread stages per piece
-static_assert(LIST_STAGE % LIST_BLOCK == 0, "a piece is a whole number of candidates per thread");
-static_assert(LIST_TGT <= LIST_BLOCK, "a work item's atoms aimed at fit one pass of the threads");
 
 // Image shift (FP64) of neighbouring row rr (z-major, then y) of the row (cy, cz).
 __device__ __forceinline__ void row_shift(int rr, int cy, int cz, int gy, int gz, int per1, int per2,
@@ -673,27 +717,20 @@ __global__ __launch_bounds__(LIST_BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts
                                 // g + .y (g < end of the main piece), else g + .z
   __shared__ float2 rsh[9];     // per row: FP32 image shift along y and z
   const int b = blockIdx.x;
-  const int r = uniform(A.lblk_rep[b]);
+  if (b >= uniform(*A.nitems)) return;   // zero in a step without a rebuild
+  const int2 it = A.items[b];
+  const int grow = uniform(it.x), sx = uniform(it.y & 0xFFFF), nseg = uniform(it.y >> 16);
+  const int r = uniform(A.row_rep[grow]);
   RepState& S = A.S[r];
-  if (!S.rebuild) return;
   const RepDesc& d = A.R[r];
   const int gx = uniform(S.gd[0]), gy = uniform(S.gd[1]), gz = uniform(S.gd[2]);
   // descriptor values used in the loops, held in scalar registers
   const int per0 = uniform(d.per[0]), per1 = uniform(d.per[1]), per2 = uniform(d.per[2]);
   const double len0 = uniform(d.len[0]), len1 = uniform(d.len[1]), len2 = uniform(d.len[2]);
-  const int dseg = uniform(d.nseg);
-  const int l = b - uniform(d.lb0);
-  if (l == 0 && threadIdx.x == 0) {   // once per replica: the build is counted
-    S.nbuilds += 1;
-    S.ind_z_ref = S.ind_z;
-  }
-  const int sx = l % dseg, cy = (l / dseg) % gy, cz = (l / dseg) / gy;
-  if (cz >= gz) return;
+  const int l = grow - uniform(d.rb0);
+  const int cy = l % gy, cz = l / gy;
   const int g0 = uniform(d.g0);
   const int crow = g0 + (cz * gy + cy) * gx;
-  const int nseg = min(min(dseg, gx), max((gx + LIST_SEG - 1) / LIST_SEG,
-                                          (uniform(A.start[crow + gx] - A.start[crow]) + LIST_TGT - 1) / LIST_TGT));
-  if (sx >= nseg) return;
   const int x0 = sx * gx / nseg, x1 = (sx + 1) * gx / nseg - 1;   // this item's cells
   const int sbase = uniform(d.a0 - A.start[g0]);   // sorted slot = sbase + start[cell]
   const int cbeg = sbase + uniform(A.start[crow + x0]);
