@@ -197,19 +197,14 @@ def timed_run(systems, precision, steps, warmup, ee, tpa, events=True, time_ever
     n_atoms = sum(s.n for s in systems)
     builds = flags["nbuilds"] - builds0
     # sampled list-kernel launches: those that rebuilt are far longer than those that return
-    # at once, so they are told apart by the geometric mean of the extremes; totals are
-    # the per-kind averages times the whole run's counts
-    l_avg = l_idle = 0.0
+    # at once, so they are told apart by the geometric mean of the extremes (when the two
+    # kinds differ); the sample is random, so the run's list-kernel time is its mean x steps
+    l_avg = 0.0
     if events and builds:
-        cut = np.sqrt(max(l_ms.min(), 1e-6) * l_ms.max())
-        reb = l_ms[l_ms > cut]
-        if reb.size and reb.size < l_ms.size:
-            l_avg, l_idle = float(reb.mean()) * 1e-3, float(l_ms[l_ms <= cut].mean()) * 1e-3
-        else:   # every sampled launch of one kind: rebuilt at each sampled step or at none
-            l_avg = float(l_ms.mean()) * 1e-3 if builds * 2 > steps else 0.0
-    elif events:
-        l_idle = float(l_ms.mean()) * 1e-3
-    l_total = l_avg * builds + l_idle * (steps - builds)
+        lo, hi = max(float(l_ms.min()), 1e-6), float(l_ms.max())
+        reb = l_ms[l_ms > np.sqrt(lo * hi)] if hi > 4 * lo else l_ms
+        l_avg = float(reb.mean()) * 1e-3
+    l_total = float(l_ms.mean()) * 1e-3 * steps if events else 0.0
     return dict(sim=sim, rate=n_atoms * steps / wall, wall=wall, ms_per_step=wall / steps * 1e3,
                 k_avg=float(k_ms.mean()) * 1e-3, l_avg=l_avg, l_total=l_total,
                 k_total=float(k_ms.mean()) * 1e-3 * steps, mean_list=mean_list,

@@ -29,7 +29,7 @@ __device__ __forceinline__ V group_sum(V v) {
 // list_slot / list_code).  Entries are fetched U at a time so that U independent index
 // loads, then U independent gathers, are in flight together.
 #ifndef MD_UNROLL
-#define MD_UNROLL 1
+#define MD_UNROLL 2
 #endif
 constexpr int UNROLL = MD_UNROLL;
 
