@@ -26,8 +26,8 @@ __device__ __forceinline__ V group_sum(V v) {
 
 // Visit the entries k = sub, sub + T, ... (< n) of atom i's list in order, calling
 // body(fetch(e), e) for each entry e (the neighbour's slot and relative cell, see
-// list_slot / list_code).  Entries are fetched U at a time so that U independent index
-// loads, then U independent gathers, are in flight together.
+// list_slot / list_code).  Entries go U at a time: the U gathers of one group are in
+// flight together with the U index loads of the next.
 #ifndef MD_UNROLL
 #define MD_UNROLL 2
 #endif
@@ -37,20 +37,26 @@ template <int T, int U, class Fetch, class Body>
 __device__ __forceinline__ void for_entries(const int* __restrict__ idx, int i, int n, int sub, int ntot,
                                             int shift, Fetch fetch, Body body) {
   int k = sub;
-  for (; k + (U - 1) * T < n; k += U * T) {
-    int e[U];
+  int e[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) e[u] = idx[list_pos(k + u * T, i, ntot, T, shift)];
+  for (int u = 0; u < U; ++u) e[u] = (k + u * T < n) ? idx[list_pos(k + u * T, i, ntot, T, shift)] : 0;
+  for (; k + (U - 1) * T < n; k += U * T) {
     decltype(fetch(0)) p[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) p[u] = fetch(e[u]);
+    int en[U];
+    const int kn = k + U * T;
+#pragma unroll
+    for (int u = 0; u < U; ++u) en[u] = (kn + u * T < n) ? idx[list_pos(kn + u * T, i, ntot, T, shift)] : 0;
 #pragma unroll
     for (int u = 0; u < U; ++u) body(p[u], e[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) e[u] = en[u];
   }
-  for (; k < n; k += T) {
-    const int e = idx[list_pos(k, i, ntot, T, shift)];
-    body(fetch(e), e);
-  }
+  // k < n <= k + (U - 1) T: the remaining entries' indices are in e[0 ..]
+#pragma unroll
+  for (int u = 0; u < U - 1; ++u)
+    if (k + u * T < n) body(fetch(e[u]), e[u]);
 }
 
 // Offsets of the 27 relative cells of a list entry in the block's replica, in shadow units:
