@@ -53,7 +53,7 @@ __device__ __forceinline__ void for_entries(const int* __restrict__ idx, int i, 
 #pragma unroll
     for (int u = 0; u < U; ++u) e[u] = en[u];
   }
-  // k < n <= k + (U - 1) T: the remaining entries' indices are in e[0 ..]
+  // fewer than U entries remain (k + (U - 1) T >= n); their indices are already in e[]
 #pragma unroll
   for (int u = 0; u < U - 1; ++u)
     if (k + u * T < n) body(fetch(e[u]), e[u]);
