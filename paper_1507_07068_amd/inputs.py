@@ -260,16 +260,18 @@ def small_film(nx=8, ny=8, nz=6, radius=6.0, gap=1.0, seed=11, noise=0.02, steps
     return film(nx, ny, nz, radius, gap, seed, noise=noise, steps=steps, name="small_film")
 
 
-def random_gas(n: int, box: float, seed: int, periodic=(True, True, True)) -> System:
-    """Uniform random atoms in a cube (list-build edge cases: irregular counts,
-    close pairs, atoms slightly outside the box on periodic axes)."""
+def random_gas(n: int, box: float, seed: int, periodic=(True, True, True), lengths=None) -> System:
+    """Uniform random atoms in a cube of edge `box`, or a box of the given `lengths`
+    (list-build edge cases: irregular counts, close pairs, atoms slightly outside the box on
+    periodic axes, long and crowded cell rows)."""
     rng = np.random.default_rng(seed)
-    x = rng.uniform(-0.1 * box, 1.1 * box, size=(n, 3))
+    L = np.full(3, float(box)) if lengths is None else np.asarray(lengths, float)
+    x = rng.uniform(-0.1 * L, 1.1 * L, size=(n, 3))
     per = np.array(periodic, bool)
     for ax in range(3):
         if not per[ax]:
-            x[:, ax] = np.clip(x[:, ax], 0.0, box)
+            x[:, ax] = np.clip(x[:, ax], 0.0, L[ax])
     v = np.zeros((n, 3))
     return System(name="gas", x=x, v=v, fixed=np.zeros(n, np.uint8),
                   ids=np.arange(n, dtype=np.int32), xc=np.zeros((0, 3)),
-                  box_lo=np.zeros(3), box_len=np.full(3, float(box)), periodic=per, steps=0)
+                  box_lo=np.zeros(3), box_len=L, periodic=per, steps=0)

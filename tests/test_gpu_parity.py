@@ -42,7 +42,7 @@ def assert_forces(f, ref, tol):
     assert rel <= tol and mx <= tol * (10 if tol > FP64_TOL else 1), (rel, mx)
 
 
-def check_lists(sim, s, cross=False, ind_z=0.0, rows=None):
+def check_lists(sim, s, cross=False, ind_z=0.0, rows=None, cap=256):
     """GPU neighbour sets (id space) vs the oracle's brute force on its own wrap."""
     xw = O.wrap(s)
     st = sim.state()[0]
@@ -51,7 +51,7 @@ def check_lists(sim, s, cross=False, ind_z=0.0, rows=None):
     if cross:
         cnt, idx = O.cross_neighbors(s, s.r_list_cross, x=xw, ind_z=ind_z, rows=rows, cap=256)
     else:
-        cnt, idx = O.neighbors(s, s.r_list, x=xw, rows=rows, cap=256)
+        cnt, idx = O.neighbors(s, s.r_list, x=xw, rows=rows, cap=cap)
     ref = O.neighbor_sets(cnt, idx)
     ids = range(s.n) if rows is None else rows
     for t, i in enumerate(ids):
@@ -83,6 +83,23 @@ def test_lists_random_gas_ragged(n, per):
     sim.md_build_neighbors(force=True)
     assert sim.md_check()["overflow"] == 0
     check_lists(sim, s)
+
+
+@pytest.mark.parametrize("n,density,per", [(4000, 0.08, (1, 1, 1)), (3000, 0.08, (0, 1, 0)),
+                                           (15000, 0.3, (1, 1, 1))])
+def test_lists_long_crowded_rows(n, density, per):
+    """Cell rows longer than one list-build run (more than 42 cells along x) and holding
+    more atoms than one block pass: each row is cut into several runs of cells; at the
+    highest density the runs per row are capped, so a run's atoms take several passes of
+    the block's threads.  The runs at either end of a periodic row stage the wrapped cell."""
+    ly = lz = 13.0
+    lx = n / (density * ly * lz)
+    s = I.random_gas(n, lx, seed=500 + n, periodic=per, lengths=(lx, ly, lz))
+    sim = sim_of(s, cap=384)   # up to ~270 neighbours where wrapped margins overlap at 0.3/A^3
+    sim.md_build_neighbors(force=True)
+    st = sim.md_check()
+    assert st["overflow"] == 0 and st["sync_timeout"] == 0
+    assert check_lists(sim, s, cap=384) > 0
 
 
 def test_lists_small_periodic_box_fewer_than_three_cells():
