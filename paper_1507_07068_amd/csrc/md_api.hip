@@ -96,7 +96,7 @@ Layout make_layout(const md_system& s) {
   L.hcell = take(sizeof(int) * (size_t)s.ctot);
   L.hrank = take(sizeof(int) * (size_t)s.ctot);
   L.hlist = take(sizeof(int) * (size_t)s.ctot);
-  L.hsorted = take(sizeof(int) * (size_t)s.ctot);
+  L.hsorted = take(sizeof(double4) * (size_t)s.ctot);
   L.scan_state = take(sizeof(long long) * (size_t)s.scan_blocks);
   L.hnear = take(sizeof(int) * (size_t)s.ncell_all);
   L.near = take(sizeof(int) * n);
@@ -440,7 +440,7 @@ int build_chain(md_system* s, const md_atoms* a, const md_lists* l, uint32_t fla
   A.hcell = at<int>(s, s->L.hcell);
   A.hrank = at<int>(s, s->L.hrank);
   A.hlist = at<int>(s, s->L.hlist);
-  A.hsorted = at<int>(s, s->L.hsorted);
+  A.hsorted = at<double4>(s, s->L.hsorted);
   A.scan_state = at<long long>(s, s->L.scan_state);
   A.scan_ticket = misc + 1;
   A.idx = l->idx;

@@ -55,7 +55,8 @@ struct BuildArgs {
   int* hcell;            // [ctot]
   int* hrank;            // [ctot] rank of the carbon among those binned into its cell
   int* hlist;            // [ctot] carbons by cell (arbitrary order within a cell)
-  int* hsorted;          // [ctot] carbons by cell, ascending index within a cell
+  double4* hsorted;      // [ctot] carbons by cell, ascending index within a cell: position at
+                         // zero indenter displacement, the carbon's index (as bits) in .w
   long long* scan_state; // [scan_blocks] published chunk sums of k_scan
   int* scan_ticket;      // chunk ticket of k_scan
   int* hnear;            // [ncell_all]: carbon cell c has a carbon in its 27-cell stencil
@@ -488,7 +489,8 @@ __global__ __launch_bounds__(BLOCK) void k_sort_gather(Consts K, BuildArgs A) {
     const int s0 = hb + A.start[c], s1 = hb + A.start[c + 1];
     int rank = 0;
     for (int t = s0; t < s1; ++t) rank += A.hlist[t] < e ? 1 : 0;
-    A.hsorted[s0 + rank] = e;
+    A.hsorted[s0 + rank] = make_double4(A.xc[3 * e + 0], A.xc[3 * e + 1], A.xc[3 * e + 2],
+                                        __longlong_as_double((long long)e));
     if (u == s0) {
       A.count[c] = 0;   // zero again for the next rebuild
       // every cell of this carbon cell's stencil can hold Cr atoms within reach of a carbon
@@ -1021,17 +1023,18 @@ __global__ __launch_bounds__(BLOCK) void k_xlist(Consts K, BuildArgs A) {
     int n = 0;
     for (int w0 = 0; w0 < total; w0 += MAXC) {
       const int lo = max(0, w0 - pref), hi = min(kn, w0 + MAXC - pref);
-      for (int e = lo; e < hi; ++e) cand_sh[w][pref + e - w0] = A.hsorted[ks + e];
+      for (int e = lo; e < hi; ++e) cand_sh[w][pref + e - w0] = ks + e;   // sorted carbon slots
       wave_sync();
       const int wn = min(MAXC, total - w0);
       for (int k0 = 0; k0 < wn; k0 += WAVE) {
         bool pred = false;
         int k = 0;
         if (k0 + lane < wn) {
-          k = cand_sh[w][k0 + lane];
-          const double ex = min_image(A.xc[3 * k + 0] - pi.x, d.len[0], d.half[0], d.per[0]);
-          const double ey = min_image(A.xc[3 * k + 1] - pi.y, d.len[1], d.half[1], d.per[1]);
-          const double ez = min_image((A.xc[3 * k + 2] + iz) - pi.z, d.len[2], d.half[2], d.per[2]);
+          const double4 c4 = A.hsorted[cand_sh[w][k0 + lane]];
+          k = (int)__double_as_longlong(c4.w);
+          const double ex = min_image(c4.x - pi.x, d.len[0], d.half[0], d.per[0]);
+          const double ey = min_image(c4.y - pi.y, d.len[1], d.half[1], d.per[1]);
+          const double ez = min_image((c4.z + iz) - pi.z, d.len[2], d.half[2], d.per[2]);
           pred = dist_sq_exact(ex, ey, ez) < K.rxlist_sq;
         }
         const unsigned long long m2 = __ballot(pred);
