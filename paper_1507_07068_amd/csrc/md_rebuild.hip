@@ -77,6 +77,10 @@ struct BuildArgs {
 #endif
 constexpr int LIST_BATCH = MD_LIST_BATCH;   // candidate loads issued together in k_list_rows
 constexpr int MAXC = 512;           // candidates staged per window in k_xlist
+#ifndef MD_SG_KEYS
+#define MD_SG_KEYS 8
+#endif
+constexpr int SG_KEYS = MD_SG_KEYS;   // keys of a cell k_sort_gather loads at a time
 constexpr int WAVES_PER_BLOCK = BLOCK / WAVE;
 constexpr int LIST_SEG = 42;      // most cells of one work item of k_list_tiles
 #ifndef MD_LIST_STAGE
@@ -458,12 +462,13 @@ __global__ __launch_bounds__(BLOCK) void k_sort_gather(Consts K, BuildArgs A) {
     const int s0 = sbase + A.start[c], s1 = sbase + A.start[c + 1];
     const int e = A.perm[u];
     int rank = 0;
-    int t = s0;
-    for (; t + 4 <= s1; t += 4) {   // four independent key loads at a time
-      const long long k0 = A.skey[t], k1 = A.skey[t + 1], k2 = A.skey[t + 2], k3 = A.skey[t + 3];
-      rank += (k0 < key) + (k1 < key) + (k2 < key) + (k3 < key);
+    for (int t = s0; t < s1; t += SG_KEYS) {   // SG_KEYS independent key loads at a time
+      long long kk[SG_KEYS];
+#pragma unroll
+      for (int u = 0; u < SG_KEYS; ++u) kk[u] = t + u < s1 ? A.skey[t + u] : key;
+#pragma unroll
+      for (int u = 0; u < SG_KEYS; ++u) rank += kk[u] < key ? 1 : 0;
     }
-    for (; t < s1; ++t) rank += A.skey[t] < key ? 1 : 0;
     if (u == s0) A.count[c] = 0;   // zero again for the next rebuild
     const int p = s0 + rank;
     const double4 qe = A.q[e];
@@ -488,7 +493,13 @@ __global__ __launch_bounds__(BLOCK) void k_sort_gather(Consts K, BuildArgs A) {
     const int hb = d.c0 - A.start[d.h0];
     const int s0 = hb + A.start[c], s1 = hb + A.start[c + 1];
     int rank = 0;
-    for (int t = s0; t < s1; ++t) rank += A.hlist[t] < e ? 1 : 0;
+    for (int t = s0; t < s1; t += SG_KEYS) {   // SG_KEYS independent loads at a time
+      int hh[SG_KEYS];
+#pragma unroll
+      for (int u = 0; u < SG_KEYS; ++u) hh[u] = t + u < s1 ? A.hlist[t + u] : e;
+#pragma unroll
+      for (int u = 0; u < SG_KEYS; ++u) rank += hh[u] < e ? 1 : 0;
+    }
     A.hsorted[s0 + rank] = make_double4(A.xc[3 * e + 0], A.xc[3 * e + 1], A.xc[3 * e + 2],
                                         __longlong_as_double((long long)e));
     if (u == s0) {
