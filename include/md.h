@@ -239,10 +239,14 @@ MD_API int md_energy(md_system *sys, const md_atoms *a, double *out, void *strea
 /* Whole steps                                                                          */
 /* ---------------------------------------------------------------------------------- */
 
-/* Enqueue nsteps whole time steps in the order of Table 1 (Tasks 2+3 -> 1 -> 4 -> 5):
- * md_verlet_step(KICK_DRIFT), md_build_neighbors, md_eam_forces(DENSITY), then
- * md_eam_forces(FORCE | KICK) and md_morse_forces(KICK) -- the Task 4b/4c/5 pass, each
- * kernel applying the final half kick for the force it adds -- for every replica.
+/* Enqueue nsteps whole time steps in the order of Table 1 (Tasks 2+3 -> 1 -> 4 -> 5) for
+ * every replica: md_verlet_step(KICK_DRIFT), md_build_neighbors, then the Task 4 passes
+ * with the Cr-C forces included in the Eq. 1 pass and the final half kick applied by it
+ * (as md_eam_forces(DENSITY | FORCE | MORSE | KICK)).  Where a step's end velocities are
+ * not observed (no energies after it, not the last step), its final half kick and the next
+ * step's first one are given together (a full kick of the same force) and the next Task 3
+ * only drifts: the same velocity Verlet steps, rounded once per kick pair instead of twice.
+ * After md_run the velocities are at the last whole step.
  * flags: MD_F_MIXED selects FP32 arithmetic.  energy_every > 0: after step k with
  * k % energy_every == 0 the energies are written as by md_energy to
  * obs[(k / energy_every - 1) * nrep * MD_NOBS ...] (device memory, caller-owned).

@@ -165,9 +165,11 @@ void launch_density(md_system* s, const md_atoms* a, const md_lists* l, bool mix
 }
 
 template <int T>
-// add_fme: the force includes the Cr-C force of this step from fme
+// add_fme: the force includes the Cr-C force of this step from fme; full_kick: the kick is
+// dt a (the two half kicks of Task 5 and the next step's Task 3 at once), else dt a / 2
 void launch_force(md_system* s, const md_atoms* a, const md_lists* l, bool mixed, bool kick, bool energy,
-                  bool add_fme, hipStream_t st) {
+                  bool add_fme, hipStream_t st, bool full_kick = false) {
+  const double kick_h = (full_kick ? 1.0 : 0.5) * s->K.dt * s->K.acc;
   const RepDesc* R = at<RepDesc>(s, s->L.desc);
   RepState* S = at<RepState>(s, s->L.state);
   const int* tr = at<int>(s, s->L.tile_rep);
@@ -177,7 +179,7 @@ void launch_force(md_system* s, const md_atoms* a, const md_lists* l, bool mixed
   const int4* qs = at<int4>(s, s->L.qs);
 #define FORCE(M, SH, KI, E) \
   k_force<T, M, SH, KI, E><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, qs, a->v, a->f, a->fixed, l->idx, l->cnt, pf, \
-                                                  l->xcnt, add_fme ? at<double>(s, s->L.fme) : nullptr)
+                                                  l->xcnt, add_fme ? at<double>(s, s->L.fme) : nullptr, kick_h)
 #define FORCE_E(M, SH, KI) \
   if (energy) FORCE(M, SH, KI, true); else FORCE(M, SH, KI, false)
 #define FORCE_K(M, SH) \
@@ -503,14 +505,16 @@ int eam_density(md_system* s, const md_atoms* a, const md_lists* l, uint32_t fla
   return check_launch();
 }
 
-// The force pass (add_fme: the Cr-C forces recorded in fme this step are included).
-int eam_force(md_system* s, const md_atoms* a, const md_lists* l, uint32_t flags, bool add_fme, hipStream_t st) {
+// The force pass (add_fme: the Cr-C forces recorded in fme this step are included;
+// full_kick: see launch_force).
+int eam_force(md_system* s, const md_atoms* a, const md_lists* l, uint32_t flags, bool add_fme, hipStream_t st,
+              bool full_kick = false) {
   const bool mixed = flags & MD_F_MIXED, energy = flags & MD_F_ENERGY, kick = flags & MD_F_KICK;
   switch (s->K.lt) {
-    case 1: launch_force<1>(s, a, l, mixed, kick, energy, add_fme, st); break;
-    case 2: launch_force<2>(s, a, l, mixed, kick, energy, add_fme, st); break;
-    case 4: launch_force<4>(s, a, l, mixed, kick, energy, add_fme, st); break;
-    default: launch_force<8>(s, a, l, mixed, kick, energy, add_fme, st); break;
+    case 1: launch_force<1>(s, a, l, mixed, kick, energy, add_fme, st, full_kick); break;
+    case 2: launch_force<2>(s, a, l, mixed, kick, energy, add_fme, st, full_kick); break;
+    case 4: launch_force<4>(s, a, l, mixed, kick, energy, add_fme, st, full_kick); break;
+    default: launch_force<8>(s, a, l, mixed, kick, energy, add_fme, st, full_kick); break;
   }
   s->have_force = energy;
   return check_launch();
@@ -547,6 +551,21 @@ MD_API int md_morse_forces(md_system* s, const md_atoms* a, const md_lists* l, u
   return check_launch();
 }
 
+namespace {
+
+// Tasks 2 + 3 (kick: the half kick first; else the velocities are at the half step already).
+void launch_kick_drift(md_system* s, const md_atoms* a, hipStream_t st, bool kick) {
+#define KD(KI)                                                                                                  \
+  k_kick_drift<KI><<<grid_tiles(s), BLOCK, 0, st>>>(                                                           \
+      s->K, at<RepDesc>(s, s->L.desc), at<RepState>(s, s->L.state), at<int>(s, s->L.tile_rep),                 \
+      reinterpret_cast<double4*>(a->q), a->v, a->f, a->fixed, at<double>(s, s->L.xref), at<double>(s, s->L.dmax), \
+      at<double>(s, s->L.tbox), at<int4>(s, s->L.qs), at<long long>(s, s->L.bcell))
+  if (kick) KD(true); else KD(false);
+#undef KD
+}
+
+}  // namespace
+
 MD_API int md_verlet_step(md_system* s, int32_t phase, const md_atoms* a, void* stream) {
   if (!s || !atoms_ok(a)) return MD_ERR_ARG;
   if (phase != MD_PHASE_KICK_DRIFT && phase != MD_PHASE_KICK) return MD_ERR_ARG;
@@ -556,11 +575,7 @@ MD_API int md_verlet_step(md_system* s, int32_t phase, const md_atoms* a, void* 
   const int* tr = at<int>(s, s->L.tile_rep);
   const int nb = grid_tiles(s);
   if (phase == MD_PHASE_KICK_DRIFT)
-    k_kick_drift<<<nb, BLOCK, 0, st>>>(s->K, R, at<RepState>(s, s->L.state), tr,
-                                       reinterpret_cast<double4*>(a->q), a->v, a->f, a->fixed,
-                                       at<double>(s, s->L.xref), at<double>(s, s->L.dmax),
-                                       at<double>(s, s->L.tbox), at<int4>(s, s->L.qs),
-                                       at<long long>(s, s->L.bcell));
+    launch_kick_drift(s, a, st, true);
   else
     k_kick<<<nb, BLOCK, 0, st>>>(s->K, R, tr, a->v, a->f, a->fixed);
   return check_launch();
@@ -590,9 +605,15 @@ MD_API int md_run(md_system* s, const md_atoms* a, const md_lists* l, int32_t ns
   hipStream_t st = (hipStream_t)stream;
   const uint32_t mixed = flags & MD_F_MIXED;
   int e;
+  // Velocity Verlet (Eqs. A11-A13, Task 5).  Where the velocities at the end of a step are
+  // not observed (no energies, not the last step), its final half kick and the next step's
+  // first one are given together by the force pass (a full kick of the same force), and
+  // the next Task 3 only drifts.
+  bool half_kicked = true;   // the velocities are at a whole step
   for (int k = 1; k <= nsteps; ++k) {
     const bool en = energy_every > 0 && k % energy_every == 0;
-    if ((e = md_verlet_step(s, MD_PHASE_KICK_DRIFT, a, stream))) return e;
+    const bool full = k < nsteps && !en;
+    launch_kick_drift(s, a, st, half_kicked);
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     if (events)
       for (int u = 0; u < 4; ++u) ev[u] = (hipEvent_t)events[4 * (k - 1) + u];
@@ -602,8 +623,9 @@ MD_API int md_run(md_system* s, const md_atoms* a, const md_lists* l, int32_t ns
     const uint32_t ef = mixed | (en ? MD_F_ENERGY : 0);
     if ((e = eam_density(s, a, l, MD_F_DENSITY | ef, nullptr, morse, st))) return e;
     if (ev[0] && (e = hip_status(hipEventRecord(ev[0], st)))) return e;
-    if ((e = eam_force(s, a, l, MD_F_FORCE | MD_F_KICK | ef, morse, st))) return e;
+    if ((e = eam_force(s, a, l, MD_F_FORCE | MD_F_KICK | ef, morse, st, full))) return e;
     if (ev[1] && (e = hip_status(hipEventRecord(ev[1], st)))) return e;
+    half_kicked = !full;
     if (en) {
       double* out = obs + (int64_t)(k / energy_every - 1) * s->nrep * MD_NOBS;
       if ((e = md_energy(s, a, out, stream))) return e;

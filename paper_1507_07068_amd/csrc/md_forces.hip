@@ -317,7 +317,7 @@ __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __rest
                                                  const int* __restrict__ cnt,
                                                  double* __restrict__ part,
                                                  const int* __restrict__ xcnt,
-                                                 const double* __restrict__ fme) {
+                                                 const double* __restrict__ fme, double kick_h) {
   const AtomCtx c = atom_ctx<T>(tile_rep, R, blockIdx.x, gridDim.x);
   const RepDesc& d = R[c.r];
   __shared__ int4 ctab[27];
@@ -442,11 +442,10 @@ __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __rest
     f[3 * i + 1] = fy;
     f[3 * i + 2] = fz;
     if (!(fabs(fx) + fabs(fy) + fabs(fz) < INFINITY)) S[c.r].nonfinite = 1;
-    if (KICK && !fixed[i]) {
-      const double h = 0.5 * K.dt * K.acc;
-      v[3 * i + 0] += h * fx;
-      v[3 * i + 1] += h * fy;
-      v[3 * i + 2] += h * fz;
+    if (KICK && !fixed[i]) {   // kick_h = dt a / 2 (Task 5), or dt a (with the next Task 3's)
+      v[3 * i + 0] += kick_h * fx;
+      v[3 * i + 1] += kick_h * fy;
+      v[3 * i + 2] += kick_h * fz;
     }
   }
   if (ENERGY) block_sum_store<NP_FORCE, BLOCK>(acc, part + (int64_t)c.blk * NP_FORCE);

@@ -53,7 +53,10 @@ __device__ __forceinline__ void tile_box_store(const RepDesc& d, bool live, doub
 
 // v(t + dt/2) = v + a dt / 2 and r(t + dt) = r + v(t + dt/2) dt (algebraically Eq. A11) for
 // mobile atoms, and their cell-local shadow; the indenter moves by v_ind dt.  Writes
-// max |r - r_ref|^2 of each tile and the tile's bounding box along open axes.
+// max |r - r_ref|^2 of each tile and the tile's bounding box along open axes.  Without
+// KICK the velocity is already v(t + dt/2) (the previous force pass gave a full kick) and
+// only the drift is done.
+template <bool KICK>
 __global__ __launch_bounds__(BLOCK) void k_kick_drift(Consts K, const RepDesc* __restrict__ R,
                                                       RepState* __restrict__ S,
                                                       const int* __restrict__ tile_rep,
@@ -72,16 +75,19 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(Consts K, const RepDesc* _
     const int64_t i = c.i;
     p = q[i];
     if (!fixed[i]) {
-      const double h = 0.5 * K.dt * K.acc;
-      double vx = v[3 * i + 0] + h * f[3 * i + 0];
-      double vy = v[3 * i + 1] + h * f[3 * i + 1];
-      double vz = v[3 * i + 2] + h * f[3 * i + 2];
+      double vx = v[3 * i + 0], vy = v[3 * i + 1], vz = v[3 * i + 2];
+      if (KICK) {
+        const double h = 0.5 * K.dt * K.acc;
+        vx += h * f[3 * i + 0];
+        vy += h * f[3 * i + 1];
+        vz += h * f[3 * i + 2];
+        v[3 * i + 0] = vx;
+        v[3 * i + 1] = vy;
+        v[3 * i + 2] = vz;
+      }
       p.x += vx * K.dt;
       p.y += vy * K.dt;
       p.z += vz * K.dt;
-      v[3 * i + 0] = vx;
-      v[3 * i + 1] = vy;
-      v[3 * i + 2] = vz;
       q[i] = p;
       if (K.shadow) qs[i] = cell_local(S[c.r], bcell[i], p.x, p.y, p.z, (float)p.w);   // shadow
     }
