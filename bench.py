@@ -46,13 +46,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def force_bytes_per_atom(mean_list: float) -> float:
+def force_bytes_per_atom(mean_list: float, drift: bool = False) -> float:
     """Algorithmic HBM bytes of one EAM force launch per atom: q_i = (x, y, z, F') 32,
     list count 4, list entries 4 each, Cr-C count 4 (the few atoms with carbons in range
     also read their 32-byte Cr-C record), fixed flag 1, velocity read + write for the fused
-    kick 48, force write 24.  Neighbour positions are gathered from cache (atoms are
-    cell-sorted, so each one is fetched from HBM once per pass)."""
-    return 32 + 4 + 4 * mean_list + 4 + 1 + 48 + 24
+    kick 48, force write 24; with the next step's drift in the same launch (FP64 steps
+    whose velocities are not observed: all but the energy steps and the last) also the new
+    position 32 and the reference position 24.  Neighbour positions are gathered from
+    cache (atoms are cell-sorted, so each one is fetched from HBM once per pass)."""
+    return 32 + 4 + 4 * mean_list + 4 + 1 + 48 + 24 + (56 if drift else 0)
 
 
 def list_bytes_per_atom(mean_list: float) -> float:
@@ -348,7 +350,8 @@ def main(argv=None):
     r = timed_run(systems, precision, steps, args.warmup, ee, args.tpa, time_every=args.time_every)
     r["sim"].close()
     n_atoms, rate, k_avg, mean_list = r["n_atoms"], r["rate"], r["k_avg"], r["mean_list"]
-    bytes_launch = n_atoms * force_bytes_per_atom(mean_list)
+    # FP64 runs (no shadow) drift the atoms in the force pass of most steps
+    bytes_launch = n_atoms * force_bytes_per_atom(mean_list, drift=precision == "fp64")
     achieved = bytes_launch / k_avg / 1e9
     e_tot = r["obs"][:, :, 0:4].sum(-1).sum(-1) if r["obs"].size else [0.0]
     log(f"[bench] {rate:.4e} atom-steps/s, {r['ms_per_step']:.4f} ms/step, EAM force kernel "
@@ -385,7 +388,8 @@ def main(argv=None):
         "roofline": None,
         "roofline_force": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                           "kernel": "k_force (EAM Eq. 1 + fused final kick)",
+                           "kernel": ("k_force (EAM Eq. 1 with the Cr-C forces, fused kicks"
+                                      + (" and next drift)" if precision == "fp64" else ")")),
                            "avg_us": k_avg * 1e6, "bytes_per_launch": bytes_launch,
                            "gpu_ms_total": r["k_total"] * 1e3},
         "cpu_baseline": None,

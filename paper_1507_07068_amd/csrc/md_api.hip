@@ -22,7 +22,7 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Byte offsets of the workspace regions.
 struct Layout {
-  size_t desc, state, tile_rep, row_rep, items, c_rep, misc, xref, dmax, tbox, cellid, crank, perm, skey, tq, tqf, qs, bcell, tv,
+  size_t desc, state, tile_rep, row_rep, items, c_rep, misc, xref, dmax, tbox, cellid, crank, perm, skey, tq, tqf, qs, q2, qs2, bcell, tv,
       tf, tfixed, tid, count, start, hcell, hrank, hlist, hsorted, scan_state, hnear, near, fme, p_embed, p_force,
       p_morse, p_kin, total;
 };
@@ -51,6 +51,11 @@ struct md_system {
   int scan_blocks;
   bool list_mix;   // some periodic axis has fewer than 3 list cells
   bool have_embed, have_force;
+  // Inside md_run the positions alternate between the caller's q (with the workspace
+  // shadow qs) and the workspace pair q2, qs2: cur says which holds the current ones
+  // (outside md_run always the caller's).  ppt: parts per tile of the last displacement
+  // maxima and boxes (1 from the kick-drift pass, T from a force pass with the drift).
+  int cur = 0, ppt = 1;
 };
 
 namespace {
@@ -77,8 +82,8 @@ Layout make_layout(const md_system& s) {
   L.c_rep = take(sizeof(int) * (size_t)s.ctot);
   L.misc = take(sizeof(int) * MISC_INTS);
   L.xref = take(sizeof(double) * 3 * n);
-  L.dmax = take(sizeof(double) * nt);
-  L.tbox = take(sizeof(double) * 6 * nt);
+  L.dmax = take(sizeof(double) * nt * 8);       // per tile, or per part of a tile (up to 8)
+  L.tbox = take(sizeof(double) * 6 * nt * 8);
   L.cellid = take(sizeof(int) * n);
   L.crank = take(sizeof(int) * n);
   L.perm = take(sizeof(int) * n);
@@ -86,6 +91,8 @@ Layout make_layout(const md_system& s) {
   L.tq = take(sizeof(double) * 4 * n);
   L.tqf = take(sizeof(float) * 4 * n);
   L.qs = take(sizeof(int) * 4 * n);
+  L.q2 = take(sizeof(double) * 4 * n);   // md_run's second position buffer
+  L.qs2 = take(sizeof(int) * 4 * n);
   L.bcell = take(sizeof(long long) * n);
   L.tv = take(sizeof(double) * 3 * n);
   L.tf = take(sizeof(double) * 3 * n);
@@ -130,6 +137,16 @@ bool lists_ok(const md_lists* l) { return l && l->idx && l->cnt && l->xidx && l-
 
 int grid_tiles(const md_system* s) { return s->ntiles; }
 
+// Current and next position buffers (see md_system::cur).
+double4* qcur(md_system* s, const md_atoms* a) {
+  return s->cur ? at<double4>(s, s->L.q2) : reinterpret_cast<double4*>(a->q);
+}
+double4* qnext(md_system* s, const md_atoms* a) {
+  return s->cur ? reinterpret_cast<double4*>(a->q) : at<double4>(s, s->L.q2);
+}
+int4* qscur(md_system* s) { return at<int4>(s, s->cur ? s->L.qs2 : s->L.qs); }
+int4* qsnext(md_system* s) { return at<int4>(s, s->cur ? s->L.qs : s->L.qs2); }
+
 // Grid of the kernels that walk the near-indenter atoms (one wavefront per atom, grid-stride).
 int near_blocks(const md_system* s) { return std::max(1, std::min(2048, s->ntiles)); }
 // Blocks of the Cr-C pass inside a density launch: about one wavefront per three carbons'
@@ -150,12 +167,12 @@ void launch_density(md_system* s, const md_atoms* a, const md_lists* l, bool mix
   const RepDesc* R = at<RepDesc>(s, s->L.desc);
   RepState* S = at<RepState>(s, s->L.state);
   const int* tr = at<int>(s, s->L.tile_rep);
-  double4* q = reinterpret_cast<double4*>(a->q);
+  double4* q = qcur(s, a);
   double* pe = at<double>(s, s->L.p_embed);
   const MorseIn M{a->xc, l->xidx, l->xcnt, at<int>(s, s->L.near), at<double>(s, s->L.fme),
                   morse ? morse_fused_blocks(s) : 0};
   const int nb = s->ntiles * T + M.nblocks;
-  int4* qs = at<int4>(s, s->L.qs);
+  int4* qs = qscur(s);
 #define DENS(M_, SH, E) \
   k_density<T, M_, SH, E><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, qs, l->idx, l->cnt, rho_out, pe, M)
   if (mixed && s->K.shadow && !s->list_mix) { if (energy) DENS(true, true, true); else DENS(true, true, false); }
@@ -166,27 +183,39 @@ void launch_density(md_system* s, const md_atoms* a, const md_lists* l, bool mix
 
 template <int T>
 // add_fme: the force includes the Cr-C force of this step from fme; full_kick: the kick is
-// dt a (the two half kicks of Task 5 and the next step's Task 3 at once), else dt a / 2
+// dt a (the two half kicks of Task 5 and the next step's Task 3 at once), else dt a / 2;
+// drift (with full_kick): the pass also drifts the atoms into the next position buffer.
 void launch_force(md_system* s, const md_atoms* a, const md_lists* l, bool mixed, bool kick, bool energy,
-                  bool add_fme, hipStream_t st, bool full_kick = false) {
+                  bool add_fme, hipStream_t st, bool full_kick = false, bool drift = false) {
   const double kick_h = (full_kick ? 1.0 : 0.5) * s->K.dt * s->K.acc;
+  const DriftOut D{qnext(s, a), qsnext(s), at<double>(s, s->L.xref), at<long long>(s, s->L.bcell),
+                   at<double>(s, s->L.dmax), at<double>(s, s->L.tbox)};
   const RepDesc* R = at<RepDesc>(s, s->L.desc);
   RepState* S = at<RepState>(s, s->L.state);
   const int* tr = at<int>(s, s->L.tile_rep);
-  const double4* q = reinterpret_cast<const double4*>(a->q);
+  const double4* q = qcur(s, a);
   double* pf = at<double>(s, s->L.p_force);
   const int nb = s->ntiles * T;
-  const int4* qs = at<int4>(s, s->L.qs);
+  const int4* qs = qscur(s);
 #define FORCE(M, SH, KI, E) \
   k_force<T, M, SH, KI, E><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, qs, a->v, a->f, a->fixed, l->idx, l->cnt, pf, \
-                                                  l->xcnt, add_fme ? at<double>(s, s->L.fme) : nullptr, kick_h)
+                                                  l->xcnt, add_fme ? at<double>(s, s->L.fme) : nullptr, kick_h, D)
+#define FORCE_DRIFT(M, SH)                                                                                       \
+  k_force<T, M, SH, true, false, true><<<nb, BLOCK, 0, st>>>(                                                    \
+      s->K, R, S, tr, q, qs, a->v, a->f, a->fixed, l->idx, l->cnt, pf, l->xcnt,                                  \
+      add_fme ? at<double>(s, s->L.fme) : nullptr, kick_h, D)
 #define FORCE_E(M, SH, KI) \
   if (energy) FORCE(M, SH, KI, true); else FORCE(M, SH, KI, false)
 #define FORCE_K(M, SH) \
   if (kick) { FORCE_E(M, SH, true); } else { FORCE_E(M, SH, false); }
-  if (mixed && s->K.shadow && !s->list_mix) { FORCE_K(true, true); }
+  if (drift) {
+    if (mixed && s->K.shadow && !s->list_mix) { FORCE_DRIFT(true, true); }
+    else if (mixed) { FORCE_DRIFT(true, false); }
+    else { FORCE_DRIFT(false, false); }
+  } else if (mixed && s->K.shadow && !s->list_mix) { FORCE_K(true, true); }
   else if (mixed) { FORCE_K(true, false); }
   else { FORCE_K(false, false); }
+#undef FORCE_DRIFT
 #undef FORCE_K
 #undef FORCE_E
 #undef FORCE
@@ -197,7 +226,7 @@ void launch_morse(md_system* s, const md_atoms* a, const md_lists* l, bool mixed
                   hipStream_t st) {
   const RepDesc* R = at<RepDesc>(s, s->L.desc);
   const RepState* S = at<RepState>(s, s->L.state);
-  const double4* q = reinterpret_cast<const double4*>(a->q);
+  const double4* q = qcur(s, a);
   const int* nr = at<int>(s, s->L.near);
   double* fme = at<double>(s, s->L.fme);
   const int nb = near_blocks(s);
@@ -418,7 +447,7 @@ int build_chain(md_system* s, const md_atoms* a, const md_lists* l, uint32_t fla
   A.nlblk = s->nlblk;
   A.c_rep = at<int>(s, s->L.c_rep);
   A.any = misc + 0;
-  A.q = reinterpret_cast<double4*>(a->q);
+  A.q = qcur(s, a);
   A.v = a->v;
   A.f = a->f;
   A.fixed = a->fixed;
@@ -431,7 +460,7 @@ int build_chain(md_system* s, const md_atoms* a, const md_lists* l, uint32_t fla
   A.skey = at<long long>(s, s->L.skey);
   A.tq = at<double4>(s, s->L.tq);
   A.tqf = at<float4>(s, s->L.tqf);
-  A.qs = at<int4>(s, s->L.qs);
+  A.qs = qscur(s);
   A.bcell = at<long long>(s, s->L.bcell);
   A.tv = at<double>(s, s->L.tv);
   A.tf = at<double>(s, s->L.tf);
@@ -464,7 +493,7 @@ int build_chain(md_system* s, const md_atoms* a, const md_lists* l, uint32_t fla
   if (flags & MD_B_FORCE)
     k_tile_box<<<s->ntiles, BLOCK, 0, st>>>(A.R, A.tile_rep, A.q, at<double>(s, s->L.tbox));
   k_decide<<<1, DECIDE_THREADS, 0, st>>>(s->K, A, at<double>(s, s->L.dmax), at<double>(s, s->L.tbox),
-                                (flags & MD_B_FORCE) ? 1 : 0);
+                                (flags & MD_B_FORCE) ? 1 : 0, (flags & MD_B_FORCE) ? 1 : s->ppt);
   k_bin<<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A);
   k_scan<<<s->scan_blocks, BLOCK, 0, st>>>(A);
   k_scatter<<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A);
@@ -508,13 +537,13 @@ int eam_density(md_system* s, const md_atoms* a, const md_lists* l, uint32_t fla
 // The force pass (add_fme: the Cr-C forces recorded in fme this step are included;
 // full_kick: see launch_force).
 int eam_force(md_system* s, const md_atoms* a, const md_lists* l, uint32_t flags, bool add_fme, hipStream_t st,
-              bool full_kick = false) {
+              bool full_kick = false, bool drift = false) {
   const bool mixed = flags & MD_F_MIXED, energy = flags & MD_F_ENERGY, kick = flags & MD_F_KICK;
   switch (s->K.lt) {
-    case 1: launch_force<1>(s, a, l, mixed, kick, energy, add_fme, st, full_kick); break;
-    case 2: launch_force<2>(s, a, l, mixed, kick, energy, add_fme, st, full_kick); break;
-    case 4: launch_force<4>(s, a, l, mixed, kick, energy, add_fme, st, full_kick); break;
-    default: launch_force<8>(s, a, l, mixed, kick, energy, add_fme, st, full_kick); break;
+    case 1: launch_force<1>(s, a, l, mixed, kick, energy, add_fme, st, full_kick, drift); break;
+    case 2: launch_force<2>(s, a, l, mixed, kick, energy, add_fme, st, full_kick, drift); break;
+    case 4: launch_force<4>(s, a, l, mixed, kick, energy, add_fme, st, full_kick, drift); break;
+    default: launch_force<8>(s, a, l, mixed, kick, energy, add_fme, st, full_kick, drift); break;
   }
   s->have_force = energy;
   return check_launch();
@@ -558,10 +587,11 @@ void launch_kick_drift(md_system* s, const md_atoms* a, hipStream_t st, bool kic
 #define KD(KI)                                                                                                  \
   k_kick_drift<KI><<<grid_tiles(s), BLOCK, 0, st>>>(                                                           \
       s->K, at<RepDesc>(s, s->L.desc), at<RepState>(s, s->L.state), at<int>(s, s->L.tile_rep),                 \
-      reinterpret_cast<double4*>(a->q), a->v, a->f, a->fixed, at<double>(s, s->L.xref), at<double>(s, s->L.dmax), \
-      at<double>(s, s->L.tbox), at<int4>(s, s->L.qs), at<long long>(s, s->L.bcell))
+      qcur(s, a), a->v, a->f, a->fixed, at<double>(s, s->L.xref), at<double>(s, s->L.dmax),                    \
+      at<double>(s, s->L.tbox), qscur(s), at<long long>(s, s->L.bcell))
   if (kick) KD(true); else KD(false);
 #undef KD
+  s->ppt = 1;
 }
 
 }  // namespace
@@ -609,11 +639,16 @@ MD_API int md_run(md_system* s, const md_atoms* a, const md_lists* l, int32_t ns
   // not observed (no energies, not the last step), its final half kick and the next step's
   // first one are given together by the force pass (a full kick of the same force), and
   // the next Task 3 only drifts.
-  bool half_kicked = true;   // the velocities are at a whole step
+  // Without the FP32 shadow, the force pass of such a step also does the next step's drift
+  // (into the other position buffer; the positions come back to the caller's q at the end).
+  // With it, the shadow's update made that slower than the drift pass of its own.
+  bool drifted = false;   // this step's Task 2 + 3 was done by the previous force pass
+  bool whole = true;      // the velocities are at a whole step
   for (int k = 1; k <= nsteps; ++k) {
     const bool en = energy_every > 0 && k % energy_every == 0;
     const bool full = k < nsteps && !en;
-    launch_kick_drift(s, a, st, half_kicked);
+    const bool drift = full && !s->K.shadow;
+    if (!drifted) launch_kick_drift(s, a, st, whole);
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     if (events)
       for (int u = 0; u < 4; ++u) ev[u] = (hipEvent_t)events[4 * (k - 1) + u];
@@ -623,13 +658,25 @@ MD_API int md_run(md_system* s, const md_atoms* a, const md_lists* l, int32_t ns
     const uint32_t ef = mixed | (en ? MD_F_ENERGY : 0);
     if ((e = eam_density(s, a, l, MD_F_DENSITY | ef, nullptr, morse, st))) return e;
     if (ev[0] && (e = hip_status(hipEventRecord(ev[0], st)))) return e;
-    if ((e = eam_force(s, a, l, MD_F_FORCE | MD_F_KICK | ef, morse, st, full))) return e;
+    if ((e = eam_force(s, a, l, MD_F_FORCE | MD_F_KICK | ef, morse, st, full, drift))) return e;
     if (ev[1] && (e = hip_status(hipEventRecord(ev[1], st)))) return e;
-    half_kicked = !full;
+    if (drift) {
+      s->cur ^= 1;
+      s->ppt = s->K.lt;
+    }
+    drifted = drift;
+    whole = !full;
     if (en) {
       double* out = obs + (int64_t)(k / energy_every - 1) * s->nrep * MD_NOBS;
       if ((e = md_energy(s, a, out, stream))) return e;
     }
+  }
+  if (s->cur) {   // the positions back into the caller's q
+    k_copy_positions<<<(int)((s->ntot + BLOCK - 1) / BLOCK), BLOCK, 0, st>>>(
+        s->ntot, at<double4>(s, s->L.q2), reinterpret_cast<double4*>(a->q), at<int4>(s, s->L.qs2),
+        at<int4>(s, s->L.qs), s->K.shadow);
+    s->cur = 0;
+    if ((e = check_launch())) return e;
   }
   return MD_OK;
 }

@@ -151,6 +151,25 @@ __device__ __forceinline__ void block_sum_store(double (&v)[K], double* out) {
   __syncthreads();
 }
 
+// Maxima over the block of N values per thread, delivered to thread 0 only (one barrier;
+// call once per block).
+template <int NT, int N>
+__device__ __forceinline__ void block_max_to0(double (&v)[N]) {
+  constexpr int NW = NT / WAVE;
+  __shared__ double sh[NW][N];
+  const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = wave_max(v[k]);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < N; ++k) sh[w][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+      for (int i = 1; i < NW; ++i) v[k] = fmax(v[k], sh[i][k]);
+}
+
 template <int NT>
 __device__ __forceinline__ double block_max(double v) {
   constexpr int NW = NT / WAVE;

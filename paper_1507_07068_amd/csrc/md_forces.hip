@@ -305,7 +305,20 @@ __global__ __launch_bounds__(BLOCK) void k_density(Consts K, const RepDesc* __re
 // Partial sums written per block by k_force.
 enum { P_PAIR = 0, P_WXX, P_WYY, P_WZZ, P_WXY, P_WXZ, P_WYZ, NP_FORCE };
 
-template <int T, bool MIXED, bool SHADOW, bool KICK, bool ENERGY>
+// With DRIFT (and a full kick) the pass also does the next step's Task 2 + 3: the new
+// positions (and their fixed-point shadow) go to the other position buffer, with the
+// displacement maxima and open-axis boxes of each block's atoms (T parts per tile) for the
+// next rebuild decision, and the indenter moves.
+struct DriftOut {
+  double4* q;             // next step's positions (the other buffer)
+  int4* qs;               // and their shadow
+  const double* xref;
+  const long long* bcell;
+  double* dmax;           // [tile * T + part]
+  double* tbox;           // [6 (tile * T + part) + ...]
+};
+
+template <int T, bool MIXED, bool SHADOW, bool KICK, bool ENERGY, bool DRIFT = false>
 __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __restrict__ R,
                                                  RepState* __restrict__ S,
                                                  const int* __restrict__ tile_rep,
@@ -317,7 +330,8 @@ __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __rest
                                                  const int* __restrict__ cnt,
                                                  double* __restrict__ part,
                                                  const int* __restrict__ xcnt,
-                                                 const double* __restrict__ fme, double kick_h) {
+                                                 const double* __restrict__ fme, double kick_h,
+                                                 DriftOut D) {
   const AtomCtx c = atom_ctx<T>(tile_rep, R, blockIdx.x, gridDim.x);
   const RepDesc& d = R[c.r];
   __shared__ int4 ctab[27];
@@ -443,9 +457,46 @@ __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __rest
     f[3 * i + 2] = fz;
     if (!(fabs(fx) + fabs(fy) + fabs(fz) < INFINITY)) S[c.r].nonfinite = 1;
     if (KICK && !fixed[i]) {   // kick_h = dt a / 2 (Task 5), or dt a (with the next Task 3's)
-      v[3 * i + 0] += kick_h * fx;
-      v[3 * i + 1] += kick_h * fy;
-      v[3 * i + 2] += kick_h * fz;
+      const double vx = v[3 * i + 0] + kick_h * fx, vy = v[3 * i + 1] + kick_h * fy,
+                   vz = v[3 * i + 2] + kick_h * fz;
+      v[3 * i + 0] = vx;
+      v[3 * i + 1] = vy;
+      v[3 * i + 2] = vz;
+      if (DRIFT) {   // x(t + dt) = x + v(t + dt/2) dt into the other buffer
+        double4 p = q[i];
+        p.x += vx * K.dt;
+        p.y += vy * K.dt;
+        p.z += vz * K.dt;
+        D.q[i] = p;
+      }
+    } else if (DRIFT) {
+      D.q[i] = q[i];
+    }
+  }
+  if (DRIFT) {
+    const bool own = c.live && c.sub == 0;
+    double4 p = make_double4(0.0, 0.0, 0.0, 0.0);
+    double d2 = 0.0;
+    if (own) {
+      const int64_t i = c.i;
+      p = D.q[i];
+      if (K.shadow) D.qs[i] = cell_local(S[c.r], D.bcell[i], p.x, p.y, p.z, (float)p.w);
+      const double ex = p.x - D.xref[3 * i + 0], ey = p.y - D.xref[3 * i + 1], ez = p.z - D.xref[3 * i + 2];
+      d2 = (ex * ex + ey * ey) + ez * ez;
+      if (!(d2 == d2)) d2 = INFINITY;   // NaN positions force a rebuild (and get flagged there)
+    }
+    // the part's displacement maximum and box (minima as maxima of the negated coordinates)
+    double m[7] = {d2, own ? -p.x : -INFINITY, own ? -p.y : -INFINITY, own ? -p.z : -INFINITY,
+                   own ? p.x : -INFINITY, own ? p.y : -INFINITY, own ? p.z : -INFINITY};
+    block_max_to0<BLOCK, 7>(m);
+    if (threadIdx.x == 0) {
+      D.dmax[c.blk] = m[0];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        D.tbox[6 * (int64_t)c.blk + a] = -m[1 + a];
+        D.tbox[6 * (int64_t)c.blk + 3 + a] = m[4 + a];
+      }
+      if (c.blk == d.t0 * T) S[c.r].ind_z += K.v_ind * K.dt;   // Task 2, once per replica
     }
   }
   if (ENERGY) block_sum_store<NP_FORCE, BLOCK>(acc, part + (int64_t)c.blk * NP_FORCE);

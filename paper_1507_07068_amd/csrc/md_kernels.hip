@@ -105,6 +105,16 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(Consts K, const RepDesc* _
   tile_box_store(R[c.r], c.live, p, tile_box + 6 * (int64_t)c.tile);
 }
 
+// Positions (and their shadow) from the second buffer back into the caller's arrays.
+__global__ __launch_bounds__(BLOCK) void k_copy_positions(int64_t n, const double4* __restrict__ q2,
+                                                          double4* __restrict__ q, const int4* __restrict__ qs2,
+                                                          int4* __restrict__ qs, int shadow) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= n) return;
+  q[i] = q2[i];
+  if (shadow) qs[i] = qs2[i];
+}
+
 // Tile bounding boxes of the current positions (before a forced build).
 __global__ __launch_bounds__(BLOCK) void k_tile_box(const RepDesc* __restrict__ R,
                                                     const int* __restrict__ tile_rep,

@@ -119,12 +119,12 @@ constexpr int DECIDE_BLOCKWIDE = 4;   // replicas up to which the whole block ta
 // replica (a wavefront or the block); `lead` marks the thread that writes.
 template <class MaxReduce>
 __device__ __forceinline__ bool decide_replica(const Consts& K, BuildArgs& A, int r, const double* dmax_tile,
-                                               const double* tile_box, int force, int t0, int tstep,
+                                               const double* tile_box, int force, int ppt, int t0, int tstep,
                                                bool lead, MaxReduce maxr) {
   const RepDesc& d = A.R[r];
   RepState& s = A.S[r];
   double m = 0.0;
-  for (int t = t0; t < d.nt; t += tstep) m = fmax(m, dmax_tile[d.t0 + t]);
+  for (int t = t0; t < d.nt * ppt; t += tstep) m = fmax(m, dmax_tile[d.t0 * ppt + t]);
   m = maxr(m);
   const int need = force || (m > K.half_skin_sq) || (fabs(s.ind_z - s.ind_z_ref) > K.half_skin);
   if (lead) {
@@ -144,9 +144,9 @@ __device__ __forceinline__ bool decide_replica(const Consts& K, BuildArgs& A, in
       continue;
     }
     double mn = INFINITY, mx = -INFINITY;
-    for (int t = t0; t < d.nt; t += tstep) {
-      mn = fmin(mn, tile_box[6 * (int64_t)(d.t0 + t) + a]);
-      mx = fmax(mx, tile_box[6 * (int64_t)(d.t0 + t) + 3 + a]);
+    for (int t = t0; t < d.nt * ppt; t += tstep) {
+      mn = fmin(mn, tile_box[6 * (int64_t)(d.t0 * ppt + t) + a]);
+      mx = fmax(mx, tile_box[6 * (int64_t)(d.t0 * ppt + t) + 3 + a]);
     }
     mn = -maxr(-mn);
     mx = maxr(mx);
@@ -173,13 +173,14 @@ __device__ __forceinline__ bool decide_replica(const Consts& K, BuildArgs& A, in
 
 __global__ __launch_bounds__(DECIDE_THREADS) void k_decide(Consts K, BuildArgs A,
                                                            const double* __restrict__ dmax_tile,
-                                                           const double* __restrict__ tile_box, int force) {
+                                                           const double* __restrict__ tile_box, int force,
+                                                           int ppt) {
   __shared__ int any_sh;
   if (threadIdx.x == 0) any_sh = 0;
   __syncthreads();
   if (K.nrep <= DECIDE_BLOCKWIDE) {
     for (int r = 0; r < K.nrep; ++r) {
-      const bool need = decide_replica(K, A, r, dmax_tile, tile_box, force, threadIdx.x, DECIDE_THREADS,
+      const bool need = decide_replica(K, A, r, dmax_tile, tile_box, force, ppt, threadIdx.x, DECIDE_THREADS,
                                        threadIdx.x == 0, [](double v) { return block_max<DECIDE_THREADS>(v); });
       if (need && threadIdx.x == 0) any_sh = 1;
     }
@@ -187,7 +188,7 @@ __global__ __launch_bounds__(DECIDE_THREADS) void k_decide(Consts K, BuildArgs A
     const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
     constexpr int NW = DECIDE_THREADS / WAVE;
     for (int r = w; r < K.nrep; r += NW) {
-      const bool need = decide_replica(K, A, r, dmax_tile, tile_box, force, lane, WAVE, lane == 0,
+      const bool need = decide_replica(K, A, r, dmax_tile, tile_box, force, ppt, lane, WAVE, lane == 0,
                                        [](double v) { return wave_max(v); });
       if (need && lane == 0) atomicOr(&any_sh, 1);
     }
