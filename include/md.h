@@ -246,7 +246,9 @@ MD_API int md_energy(md_system *sys, const md_atoms *a, double *out, void *strea
  * not observed (no energies after it, not the last step), its final half kick and the next
  * step's first one are given together (a full kick of the same force) and the next Task 3
  * only drifts: the same velocity Verlet steps, rounded once per kick pair instead of twice.
- * After md_run the velocities are at the last whole step.
+ * Without the FP32 shadow that drift is done by the force pass itself, into a second
+ * position buffer in the workspace.  After md_run the velocities are at the last whole step
+ * and the positions are back in a->q.
  * flags: MD_F_MIXED selects FP32 arithmetic.  energy_every > 0: after step k with
  * k % energy_every == 0 the energies are written as by md_energy to
  * obs[(k / energy_every - 1) * nrep * MD_NOBS ...] (device memory, caller-owned).
