@@ -500,12 +500,14 @@ int build_chain(md_system* s, const md_atoms* a, const md_lists* l, uint32_t fla
   k_sort_gather<<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A);
   int e;
   if (ev0 && (e = hip_status(hipEventRecord(ev0, st)))) return e;
+  // the Cr-C lists: leading blocks of the staged Cr-Cr list launch, else a launch of their own
+  A.xblocks = (s->list_mix || s->ctot == 0) ? 0 : morse_fused_blocks(s);
   if (s->list_mix)
     k_list_rows<false><<<s->ntiles, BLOCK, 0, st>>>(s->K, A);
   else
-    k_list_tiles<<<s->nlblk, LIST_BLOCK, 0, st>>>(s->K, A);
+    k_list_tiles<<<A.xblocks + s->nlblk, LIST_BLOCK, 0, st>>>(s->K, A);
   if (ev1 && (e = hip_status(hipEventRecord(ev1, st)))) return e;
-  k_xlist<<<A.near_blocks, BLOCK, 0, st>>>(s->K, A);
+  if (s->list_mix && s->ctot > 0) k_xlist<<<A.near_blocks, BLOCK, 0, st>>>(s->K, A);
   return check_launch();
 }
 

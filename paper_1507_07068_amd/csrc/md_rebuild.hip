@@ -68,6 +68,7 @@ struct BuildArgs {
   double* fme;           // [ntot][4]: last Morse force and energy per atom (0 if none)
   int ncell_all, ncell_cr, ntiles, ctot;
   int near_blocks;       // grid of k_xlist
+  int xblocks;           // leading blocks of k_list_tiles that build the Cr-C lists (0: none)
   int scan_chunk, scan_blocks;
   int nrows, nlblk;      // cell rows at capacity; capacity of the work-item table
 };
@@ -439,7 +440,24 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Consts K, BuildArgs A) {
     if (!A.S[r].rebuild) return;
     const RepDesc& d = A.R[r];
     const int hid = A.hcell[k];
-    A.hlist[d.c0 + (A.start[hid] - A.start[d.h0]) + A.hrank[k]] = (int)k;
+    const int rank = A.hrank[k];
+    A.hlist[d.c0 + (A.start[hid] - A.start[d.h0]) + rank] = (int)k;
+    if (rank == 0) {
+      // one carbon per occupied carbon cell: every cell of its stencil can hold Cr atoms
+      // within reach of a carbon (k_scan cleared the marks)
+      const int lc = hid - d.h0;
+      const int hx = lc % d.hd[0], hy = (lc / d.hd[0]) % d.hd[1], hz = lc / (d.hd[0] * d.hd[1]);
+      const int msx = stencil_n(d.hd[0], d.per[0]), msy = stencil_n(d.hd[1], d.per[1]),
+                msz = stencil_n(d.hd[2], d.per[2]);
+      for (int tz = 0; tz < msz; ++tz)
+        for (int ty = 0; ty < msy; ++ty)
+          for (int tx = 0; tx < msx; ++tx) {
+            const int x = stencil_cell(hx, tx, d.hd[0], d.per[0]);
+            const int y = stencil_cell(hy, ty, d.hd[1], d.per[1]);
+            const int z = stencil_cell(hz, tz, d.hd[2], d.per[2]);
+            if (x >= 0 && y >= 0 && z >= 0) A.hnear[d.h0 + (z * d.hd[1] + y) * d.hd[0] + x] = 1;
+          }
+    }
   }
 }
 
@@ -452,37 +470,60 @@ __global__ __launch_bounds__(BLOCK) void k_sort_gather(Consts K, BuildArgs A) {
   const int b = blockIdx.x;
   if (b < A.ntiles) {
     const int r = A.tile_rep[b];
-    const RepState& S = A.S[r];
+    RepState& S = A.S[r];
     if (!S.rebuild) return;
     const RepDesc& d = A.R[r];
     const int u = b * TILE + threadIdx.x;
-    if (u >= d.a0 + d.n) return;
-    const long long key = A.skey[u];
-    const int c = (int)(key >> 32);
-    const int sbase = d.a0 - A.start[d.g0];
-    const int s0 = sbase + A.start[c], s1 = sbase + A.start[c + 1];
-    const int e = A.perm[u];
-    int rank = 0;
-    for (int t = s0; t < s1; t += SG_KEYS) {   // SG_KEYS independent key loads at a time
-      long long kk[SG_KEYS];
+    bool near = false;
+    int p = 0;
+    if (u < d.a0 + d.n) {
+      const long long key = A.skey[u];
+      const int c = (int)(key >> 32);
+      const int sbase = d.a0 - A.start[d.g0];
+      const int s0 = sbase + A.start[c], s1 = sbase + A.start[c + 1];
+      const int e = A.perm[u];
+      int rank = 0;
+      for (int t = s0; t < s1; t += SG_KEYS) {   // SG_KEYS independent key loads at a time
+        long long kk[SG_KEYS];
 #pragma unroll
-      for (int u = 0; u < SG_KEYS; ++u) kk[u] = t + u < s1 ? A.skey[t + u] : key;
+        for (int u = 0; u < SG_KEYS; ++u) kk[u] = t + u < s1 ? A.skey[t + u] : key;
 #pragma unroll
-      for (int u = 0; u < SG_KEYS; ++u) rank += kk[u] < key ? 1 : 0;
+        for (int u = 0; u < SG_KEYS; ++u) rank += kk[u] < key ? 1 : 0;
+      }
+      if (u == s0) A.count[c] = 0;   // zero again for the next rebuild
+      p = s0 + rank;
+      const double4 qe = A.q[e];
+      A.tq[p] = qe;
+      A.tqf[p] = make_float4((float)(qe.x - S.glo[0]), (float)(qe.y - S.glo[1]), (float)(qe.z - S.glo[2]), 0.0f);
+      A.tv[3 * p + 0] = A.v[3 * e + 0];
+      A.tv[3 * p + 1] = A.v[3 * e + 1];
+      A.tv[3 * p + 2] = A.v[3 * e + 2];
+      A.tf[3 * p + 0] = A.f[3 * e + 0];
+      A.tf[3 * p + 1] = A.f[3 * e + 1];
+      A.tf[3 * p + 2] = A.f[3 * e + 2];
+      A.tfixed[p] = A.fixed[e];
+      A.tid[p] = A.id[e];
+      // no Cr-C force or list until the Cr-C list build of this rebuild says otherwise
+      A.xcnt[p] = 0;
+      A.fme[4 * (int64_t)p + 0] = 0.0;
+      A.fme[4 * (int64_t)p + 1] = 0.0;
+      A.fme[4 * (int64_t)p + 2] = 0.0;
+      A.fme[4 * (int64_t)p + 3] = 0.0;
+      if (d.nc > 0) {   // in the stencil of an occupied carbon cell: the atom gets a Cr-C list
+        int hx, hy, hz;
+        c_cell_coords(d, qe.x, qe.y, qe.z, hx, hy, hz);
+        near = A.hnear[d.h0 + (hz * d.hd[1] + hy) * d.hd[0] + hx] != 0;
+      }
     }
-    if (u == s0) A.count[c] = 0;   // zero again for the next rebuild
-    const int p = s0 + rank;
-    const double4 qe = A.q[e];
-    A.tq[p] = qe;
-    A.tqf[p] = make_float4((float)(qe.x - S.glo[0]), (float)(qe.y - S.glo[1]), (float)(qe.z - S.glo[2]), 0.0f);
-    A.tv[3 * p + 0] = A.v[3 * e + 0];
-    A.tv[3 * p + 1] = A.v[3 * e + 1];
-    A.tv[3 * p + 2] = A.v[3 * e + 2];
-    A.tf[3 * p + 0] = A.f[3 * e + 0];
-    A.tf[3 * p + 1] = A.f[3 * e + 1];
-    A.tf[3 * p + 2] = A.f[3 * e + 2];
-    A.tfixed[p] = A.fixed[e];
-    A.tid[p] = A.id[e];
+    const int lane = threadIdx.x % WAVE;
+    const unsigned long long nm = __ballot(near);
+    if (nm) {   // append this wave's near atoms (order within the near list is irrelevant)
+      const int lead = __builtin_ctzll(nm);
+      int first = 0;
+      if (lane == lead) first = atomicAdd(&S.nnear, __popcll(nm));
+      first = __shfl(first, lead, WAVE);
+      if (near) A.near[d.a0 + first + __popcll(nm & ((1ull << lane) - 1ull))] = p;
+    }
   } else {
     const int64_t u = (int64_t)(b - A.ntiles) * BLOCK + threadIdx.x;
     if (u >= A.ctot) return;
@@ -503,22 +544,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_gather(Consts K, BuildArgs A) {
     }
     A.hsorted[s0 + rank] = make_double4(A.xc[3 * e + 0], A.xc[3 * e + 1], A.xc[3 * e + 2],
                                         __longlong_as_double((long long)e));
-    if (u == s0) {
-      A.count[c] = 0;   // zero again for the next rebuild
-      // every cell of this carbon cell's stencil can hold Cr atoms within reach of a carbon
-      const int lc = c - d.h0;
-      const int hx = lc % d.hd[0], hy = (lc / d.hd[0]) % d.hd[1], hz = lc / (d.hd[0] * d.hd[1]);
-      const int msx = stencil_n(d.hd[0], d.per[0]), msy = stencil_n(d.hd[1], d.per[1]),
-                msz = stencil_n(d.hd[2], d.per[2]);
-      for (int tz = 0; tz < msz; ++tz)
-        for (int ty = 0; ty < msy; ++ty)
-          for (int tx = 0; tx < msx; ++tx) {
-            const int x = stencil_cell(hx, tx, d.hd[0], d.per[0]);
-            const int y = stencil_cell(hy, ty, d.hd[1], d.per[1]);
-            const int z = stencil_cell(hz, tz, d.hd[2], d.per[2]);
-            if (x >= 0 && y >= 0 && z >= 0) A.hnear[d.h0 + (z * d.hd[1] + y) * d.hd[0] + x] = 1;
-          }
-    }
+    if (u == s0) A.count[c] = 0;   // zero again for the next rebuild
   }
 }
 
@@ -540,11 +566,9 @@ __global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
   RepState& S = A.S[r];
   if (!S.rebuild) return;
   const RepDesc& d = A.R[r];
-  const int lane = threadIdx.x % WAVE;
   const int p = tile * TILE + threadIdx.x;
   const bool live = p < d.a0 + d.n;
   const int cap = K.cap;
-  bool near = false;
   if (live) {
     const double4 pi = A.tq[p];
     const int gx = S.gd[0], gy = S.gd[1], gz = S.gd[2];
@@ -659,17 +683,7 @@ __global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
     A.cnt[p] = min(count, cap);
     if (count > cap) atomicMax(&S.overflow, count);
     {
-      // near flag and copy-back of the sorted state
-      if (d.nc > 0) {
-        int hx, hy, hz;
-        c_cell_coords(d, pi.x, pi.y, pi.z, hx, hy, hz);
-        near = A.hnear[d.h0 + (hz * d.hd[1] + hy) * d.hd[0] + hx] != 0;
-      }
-      A.xcnt[p] = 0;
-      A.fme[4 * (int64_t)p + 0] = 0.0;
-      A.fme[4 * (int64_t)p + 1] = 0.0;
-      A.fme[4 * (int64_t)p + 2] = 0.0;
-      A.fme[4 * (int64_t)p + 3] = 0.0;
+      // copy-back of the sorted state
       A.q[p] = pi;
       if (K.shadow) {
         const long long bc = pack_cell(cx, cy, cz);
@@ -689,12 +703,92 @@ __global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
       A.id[p] = A.tid[p];
     }
   }
-  const unsigned long long nm = __ballot(near);
-  if (nm) {   // append this wave's near atoms (order within the near list is irrelevant)
-    int first = 0;
-    if (lane == 0) first = atomicAdd(&S.nnear, __popcll(nm));
-    first = __shfl(first, 0, WAVE);
-    if (near) A.near[d.a0 + first + __popcll(nm & ((1ull << lane) - 1ull))] = p;
+}
+
+// Cr-C list {k : |xc_k + ind_z - q_p|^2 < (rc + skin)^2}, atom-major: xidx[p * xcap + n],
+// for the atoms of the near list of each rebuilding replica.  One wavefront per near atom
+// (stride over those of all rebuilding replicas), its lanes sharing the 27 carbon cells
+// around the atom; the passing carbons are compacted in candidate order with a ballot.  Runs
+// in blocks bid of nb blocks of BLOCK threads; cand and pre are the block's LDS scratch
+// (WAVES_PER_BLOCK x MAXC slots, XL_FLAT_MAXREP + 1 prefixes).  Reads the sorted positions
+// (tq) and the near list written by k_sort_gather, so it may run beside the Cr-Cr list build.
+constexpr int XL_FLAT_MAXREP = FLAT_MAXREP - 1;   // replicas of the flattened index space
+__device__ __forceinline__ void xlist_pass(const Consts& K, const BuildArgs& A, int (*cand_sh)[MAXC], int* pre,
+                                           int bid, int nb) {
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int gw = bid * WAVES_PER_BLOCK + w, nw = nb * WAVES_PER_BLOCK;
+  auto one = [&](int r, int item) {   // near atom `item` of replica r, on this wavefront
+    RepState& S = A.S[r];
+    const RepDesc& d = A.R[r];
+    const double iz = S.ind_z;
+    const int hbase = A.start[d.h0];
+    const int msx = stencil_n(d.hd[0], d.per[0]), msy = stencil_n(d.hd[1], d.per[1]),
+              msz = stencil_n(d.hd[2], d.per[2]);
+    const int ms = msx * msy * msz;
+    const int64_t pa = A.near[d.a0 + item];
+    const double4 pi = A.tq[pa];
+    int hx, hy, hz;
+    c_cell_coords(d, pi.x, pi.y, pi.z, hx, hy, hz);
+    int ks = 0, kn = 0;
+    if (lane < ms) {
+      const int tx = lane % msx, ty = (lane / msx) % msy, tz = lane / (msx * msy);
+      const int x = stencil_cell(hx, tx, d.hd[0], d.per[0]);
+      const int y = stencil_cell(hy, ty, d.hd[1], d.per[1]);
+      const int z = stencil_cell(hz, tz, d.hd[2], d.per[2]);
+      if (x >= 0 && y >= 0 && z >= 0) {
+        const int hid = d.h0 + (z * d.hd[1] + y) * d.hd[0] + x;
+        ks = d.c0 + (A.start[hid] - hbase);
+        kn = A.start[hid + 1] - A.start[hid];
+      }
+    }
+    int pref = kn;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const int y = __shfl_up(pref, o, WAVE);
+      if (lane >= o) pref += y;
+    }
+    const int total = __shfl(pref, WAVE - 1, WAVE);
+    pref -= kn;
+    int n = 0;
+    for (int w0 = 0; w0 < total; w0 += MAXC) {
+      const int lo = max(0, w0 - pref), hi = min(kn, w0 + MAXC - pref);
+      for (int e = lo; e < hi; ++e) cand_sh[w][pref + e - w0] = ks + e;   // sorted carbon slots
+      wave_sync();
+      const int wn = min(MAXC, total - w0);
+      for (int k0 = 0; k0 < wn; k0 += WAVE) {
+        bool pred = false;
+        int k = 0;
+        if (k0 + lane < wn) {
+          const double4 c4 = A.hsorted[cand_sh[w][k0 + lane]];
+          k = (int)__double_as_longlong(c4.w);
+          const double ex = min_image(c4.x - pi.x, d.len[0], d.half[0], d.per[0]);
+          const double ey = min_image(c4.y - pi.y, d.len[1], d.half[1], d.per[1]);
+          const double ez = min_image((c4.z + iz) - pi.z, d.len[2], d.half[2], d.per[2]);
+          pred = dist_sq_exact(ex, ey, ez) < K.rxlist_sq;
+        }
+        const unsigned long long m2 = __ballot(pred);
+        const int below = __popcll(m2 & ((1ull << lane) - 1ull));
+        if (pred && n + below < K.xcap) A.xidx[pa * K.xcap + n + below] = k;
+        n += __popcll(m2);
+      }
+      wave_sync();
+    }
+    if (lane == 0) {
+      A.xcnt[pa] = min(n, K.xcap);
+      if (n > K.xcap) atomicMax(&S.xoverflow, n);
+    }
+  };
+  if (K.nrep <= XL_FLAT_MAXREP) {   // near atoms of all rebuilding replicas as one index space
+    const int total = flat_prefix(K.nrep, pre, [&](int r) { return A.S[r].rebuild ? A.S[r].nnear : 0; });
+    for (int g = gw; g < total; g += nw) {
+      const int r = flat_replica(pre, K.nrep, g);
+      one(r, g - pre[r]);
+    }
+  } else {
+    for (int r = 0; r < K.nrep; ++r) {
+      if (!A.S[r].rebuild) continue;
+      for (int item = gw; item < A.S[r].nnear; item += nw) one(r, item);
+    }
   }
 }
 
@@ -730,7 +824,15 @@ __global__ __launch_bounds__(LIST_BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts
   __shared__ int4 rslot[9];     // per row: slot of row-local candidate g is g + .x (g < .w),
                                 // g + .y (g < end of the main piece), else g + .z
   __shared__ float2 rsh[9];     // per row: FP32 image shift along y and z
-  const int b = blockIdx.x;
+  static_assert(LIST_BLOCK == BLOCK && sizeof(sq) >= sizeof(int) * (WAVES_PER_BLOCK * MAXC + XL_FLAT_MAXREP + 1),
+                "the Cr-C list blocks run with BLOCK threads in the staging buffer");
+  if ((int)blockIdx.x < A.xblocks) {   // leading blocks: the Cr-C lists
+    int* scratch = reinterpret_cast<int*>(sq);
+    xlist_pass(K, A, reinterpret_cast<int(*)[MAXC]>(scratch), scratch + WAVES_PER_BLOCK * MAXC, blockIdx.x,
+               A.xblocks);
+    return;
+  }
+  const int b = blockIdx.x - A.xblocks;
   if (b >= uniform(*A.nitems)) return;   // zero in a step without a rebuild
   const int2 it = A.items[b];
   const int grow = uniform(it.x), sx = uniform(it.y & 0xFFFF), nseg = uniform(it.y >> 16);
@@ -750,7 +852,6 @@ __global__ __launch_bounds__(LIST_BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts
   const int cbeg = sbase + uniform(A.start[crow + x0]);
   const int m = uniform(A.start[crow + x1 + 1]) - (cbeg - sbase);
   if (m == 0) return;
-  const int lane = threadIdx.x % WAVE;
   const double rl2 = K.rlist_sq;
   const int cap = K.cap, T = K.lt;
   const int64_t row = K.ntot * T;   // entry k of atom p at idx[(k / T) * row + p * T + k % T]
@@ -948,21 +1049,10 @@ __global__ __launch_bounds__(LIST_BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts
         }
       }
     }
-    bool near = false;
     if (live) {
       const double4 pi = tq[p];
       A.cnt[p] = min(count, cap);
       if (count > cap) atomicMax(&S.overflow, count);
-      if (d.nc > 0) {
-        int hx, hy, hz;
-        c_cell_coords(d, pi.x, pi.y, pi.z, hx, hy, hz);
-        near = A.hnear[d.h0 + (hz * d.hd[1] + hy) * d.hd[0] + hx] != 0;
-      }
-      A.xcnt[p] = 0;
-      A.fme[4 * (int64_t)p + 0] = 0.0;
-      A.fme[4 * (int64_t)p + 1] = 0.0;
-      A.fme[4 * (int64_t)p + 2] = 0.0;
-      A.fme[4 * (int64_t)p + 3] = 0.0;
       A.q[p] = pi;
       if (K.shadow) {
         const long long bc = pack_cell(cx, cy, cz);
@@ -981,99 +1071,14 @@ __global__ __launch_bounds__(LIST_BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts
       A.fixed[p] = A.tfixed[p];
       A.id[p] = A.tid[p];
     }
-    const unsigned long long nm_ = __ballot(near);
-    if (nm_) {   // append this wave's near atoms (order within the near list is irrelevant)
-      int first = 0;
-      if (lane == 0) first = atomicAdd(&S.nnear, __popcll(nm_));
-      first = __shfl(first, 0, WAVE);
-      if (near) A.near[d.a0 + first + __popcll(nm_ & ((1ull << lane) - 1ull))] = p;
-    }
   }
 }
 
-// Cr-C list {k : |xc_k + ind_z - q_p|^2 < (rc + skin)^2}, atom-major: xidx[p * xcap + n],
-// for the atoms of the near list of each rebuilding replica.  One wavefront per near atom
-// (grid-stride over those of all rebuilding replicas), its lanes sharing the 27 carbon cells
-// around the atom; the passing carbons are compacted in candidate order with a ballot.
 __global__ __launch_bounds__(BLOCK) void k_xlist(Consts K, BuildArgs A) {
   if (rebuild_off(A)) return;
   __shared__ int cand_sh[WAVES_PER_BLOCK][MAXC];
-  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
-  const int gw = blockIdx.x * WAVES_PER_BLOCK + w, nw = gridDim.x * WAVES_PER_BLOCK;
-  auto one = [&](int r, int item) {   // near atom `item` of replica r, on this wavefront
-    RepState& S = A.S[r];
-    const RepDesc& d = A.R[r];
-    const double iz = S.ind_z;
-    const int hbase = A.start[d.h0];
-    const int msx = stencil_n(d.hd[0], d.per[0]), msy = stencil_n(d.hd[1], d.per[1]),
-              msz = stencil_n(d.hd[2], d.per[2]);
-    const int ms = msx * msy * msz;
-    const int64_t pa = A.near[d.a0 + item];
-    const double4 pi = A.q[pa];
-    int hx, hy, hz;
-    c_cell_coords(d, pi.x, pi.y, pi.z, hx, hy, hz);
-    int ks = 0, kn = 0;
-    if (lane < ms) {
-      const int tx = lane % msx, ty = (lane / msx) % msy, tz = lane / (msx * msy);
-      const int x = stencil_cell(hx, tx, d.hd[0], d.per[0]);
-      const int y = stencil_cell(hy, ty, d.hd[1], d.per[1]);
-      const int z = stencil_cell(hz, tz, d.hd[2], d.per[2]);
-      if (x >= 0 && y >= 0 && z >= 0) {
-        const int hid = d.h0 + (z * d.hd[1] + y) * d.hd[0] + x;
-        ks = d.c0 + (A.start[hid] - hbase);
-        kn = A.start[hid + 1] - A.start[hid];
-      }
-    }
-    int pref = kn;
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-      const int y = __shfl_up(pref, o, WAVE);
-      if (lane >= o) pref += y;
-    }
-    const int total = __shfl(pref, WAVE - 1, WAVE);
-    pref -= kn;
-    int n = 0;
-    for (int w0 = 0; w0 < total; w0 += MAXC) {
-      const int lo = max(0, w0 - pref), hi = min(kn, w0 + MAXC - pref);
-      for (int e = lo; e < hi; ++e) cand_sh[w][pref + e - w0] = ks + e;   // sorted carbon slots
-      wave_sync();
-      const int wn = min(MAXC, total - w0);
-      for (int k0 = 0; k0 < wn; k0 += WAVE) {
-        bool pred = false;
-        int k = 0;
-        if (k0 + lane < wn) {
-          const double4 c4 = A.hsorted[cand_sh[w][k0 + lane]];
-          k = (int)__double_as_longlong(c4.w);
-          const double ex = min_image(c4.x - pi.x, d.len[0], d.half[0], d.per[0]);
-          const double ey = min_image(c4.y - pi.y, d.len[1], d.half[1], d.per[1]);
-          const double ez = min_image((c4.z + iz) - pi.z, d.len[2], d.half[2], d.per[2]);
-          pred = dist_sq_exact(ex, ey, ez) < K.rxlist_sq;
-        }
-        const unsigned long long m2 = __ballot(pred);
-        const int below = __popcll(m2 & ((1ull << lane) - 1ull));
-        if (pred && n + below < K.xcap) A.xidx[pa * K.xcap + n + below] = k;
-        n += __popcll(m2);
-      }
-      wave_sync();
-    }
-    if (lane == 0) {
-      A.xcnt[pa] = min(n, K.xcap);
-      if (n > K.xcap) atomicMax(&S.xoverflow, n);
-    }
-  };
-  __shared__ int pre[FLAT_MAXREP + 1];
-  if (K.nrep <= FLAT_MAXREP) {   // near atoms of all rebuilding replicas as one index space
-    const int total = flat_prefix(K.nrep, pre, [&](int r) { return A.S[r].rebuild ? A.S[r].nnear : 0; });
-    for (int g = gw; g < total; g += nw) {
-      const int r = flat_replica(pre, K.nrep, g);
-      one(r, g - pre[r]);
-    }
-  } else {
-    for (int r = 0; r < K.nrep; ++r) {
-      if (!A.S[r].rebuild) continue;
-      for (int item = gw; item < A.S[r].nnear; item += nw) one(r, item);
-    }
-  }
+  __shared__ int pre[XL_FLAT_MAXREP + 1];
+  xlist_pass(K, A, cand_sh, pre, blockIdx.x, gridDim.x);
 }
 
 }  // namespace md
