@@ -281,8 +281,8 @@ __global__ __launch_bounds__(BLOCK) void k_bin(Consts K, BuildArgs A) {
       p.x = xyz[0];
       p.y = xyz[1];
       p.z = xyz[2];
+      cid = cr_cell_of(d, A.S[r], p.x, p.y, p.z);   // before the stores (which could alias S)
       A.q[i] = p;
-      cid = cr_cell_of(d, A.S[r], p.x, p.y, p.z);
       A.cellid[i] = cid;
     }
     const int rank = bin_rank(A.count, cid, live);
@@ -444,19 +444,24 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Consts K, BuildArgs A) {
     A.hlist[d.c0 + (A.start[hid] - A.start[d.h0]) + rank] = (int)k;
     if (rank == 0) {
       // one carbon per occupied carbon cell: every cell of its stencil can hold Cr atoms
-      // within reach of a carbon (k_scan cleared the marks)
-      const int lc = hid - d.h0;
-      const int hx = lc % d.hd[0], hy = (lc / d.hd[0]) % d.hd[1], hz = lc / (d.hd[0] * d.hd[1]);
-      const int msx = stencil_n(d.hd[0], d.per[0]), msy = stencil_n(d.hd[1], d.per[1]),
-                msz = stencil_n(d.hd[2], d.per[2]);
-      for (int tz = 0; tz < msz; ++tz)
-        for (int ty = 0; ty < msy; ++ty)
+      // within reach of a carbon (k_scan cleared the marks).  The descriptor is read into
+      // registers first: a store could alias it and would make every read after it wait.
+      const int h0 = d.h0, hd0 = d.hd[0], hd1 = d.hd[1], hd2 = d.hd[2];
+      const int p0 = d.per[0], p1 = d.per[1], p2 = d.per[2];
+      int* __restrict__ hn = A.hnear + h0;
+      const int lc = hid - h0;
+      const int hx = lc % hd0, hy = (lc / hd0) % hd1, hz = lc / (hd0 * hd1);
+      const int msx = stencil_n(hd0, p0), msy = stencil_n(hd1, p1), msz = stencil_n(hd2, p2);
+      for (int tz = 0; tz < msz; ++tz) {
+        const int z = stencil_cell(hz, tz, hd2, p2);
+        for (int ty = 0; ty < msy; ++ty) {
+          const int y = stencil_cell(hy, ty, hd1, p1);
           for (int tx = 0; tx < msx; ++tx) {
-            const int x = stencil_cell(hx, tx, d.hd[0], d.per[0]);
-            const int y = stencil_cell(hy, ty, d.hd[1], d.per[1]);
-            const int z = stencil_cell(hz, tz, d.hd[2], d.per[2]);
-            if (x >= 0 && y >= 0 && z >= 0) A.hnear[d.h0 + (z * d.hd[1] + y) * d.hd[0] + x] = 1;
+            const int x = stencil_cell(hx, tx, hd0, p0);
+            if (x >= 0 && y >= 0 && z >= 0) hn[(z * hd1 + y) * hd0 + x] = 1;
           }
+        }
+      }
     }
   }
 }
@@ -483,15 +488,20 @@ __global__ __launch_bounds__(BLOCK) void k_sort_gather(Consts K, BuildArgs A) {
       const int s0 = sbase + A.start[c], s1 = sbase + A.start[c + 1];
       const int e = A.perm[u];
       int rank = 0;
-      for (int t = s0; t < s1; t += SG_KEYS) {   // SG_KEYS independent key loads at a time
+      // SG_KEYS independent key loads at a time: the index is clamped into the cell (which
+      // holds this atom) rather than the load made conditional, so that no load waits on
+      // the one before it
+      for (int t = s0; t < s1; t += SG_KEYS) {
         long long kk[SG_KEYS];
 #pragma unroll
-        for (int u = 0; u < SG_KEYS; ++u) kk[u] = t + u < s1 ? A.skey[t + u] : key;
+        for (int u = 0; u < SG_KEYS; ++u) kk[u] = A.skey[min(t + u, s1 - 1)];
 #pragma unroll
-        for (int u = 0; u < SG_KEYS; ++u) rank += kk[u] < key ? 1 : 0;
+        for (int u = 0; u < SG_KEYS; ++u) rank += (t + u < s1 && kk[u] < key) ? 1 : 0;
       }
       if (u == s0) A.count[c] = 0;   // zero again for the next rebuild
       p = s0 + rank;
+      // the atom's state, each value stored as it arrives (measured faster here than all
+      // loads first)
       const double4 qe = A.q[e];
       A.tq[p] = qe;
       A.tqf[p] = make_float4((float)(qe.x - S.glo[0]), (float)(qe.y - S.glo[1]), (float)(qe.z - S.glo[2]), 0.0f);
@@ -535,12 +545,12 @@ __global__ __launch_bounds__(BLOCK) void k_sort_gather(Consts K, BuildArgs A) {
     const int hb = d.c0 - A.start[d.h0];
     const int s0 = hb + A.start[c], s1 = hb + A.start[c + 1];
     int rank = 0;
-    for (int t = s0; t < s1; t += SG_KEYS) {   // SG_KEYS independent loads at a time
+    for (int t = s0; t < s1; t += SG_KEYS) {   // SG_KEYS independent loads at a time (as above)
       int hh[SG_KEYS];
 #pragma unroll
-      for (int u = 0; u < SG_KEYS; ++u) hh[u] = t + u < s1 ? A.hlist[t + u] : e;
+      for (int u = 0; u < SG_KEYS; ++u) hh[u] = A.hlist[min(t + u, s1 - 1)];
 #pragma unroll
-      for (int u = 0; u < SG_KEYS; ++u) rank += hh[u] < e ? 1 : 0;
+      for (int u = 0; u < SG_KEYS; ++u) rank += (t + u < s1 && hh[u] < e) ? 1 : 0;
     }
     A.hsorted[s0 + rank] = make_double4(A.xc[3 * e + 0], A.xc[3 * e + 1], A.xc[3 * e + 2],
                                         __longlong_as_double((long long)e));
@@ -683,7 +693,11 @@ __global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
     A.cnt[p] = min(count, cap);
     if (count > cap) atomicMax(&S.overflow, count);
     {
-      // copy-back of the sorted state
+      // copy-back of the sorted state, all loads before the first store
+      const double v0 = A.tv[3 * p + 0], v1 = A.tv[3 * p + 1], v2 = A.tv[3 * p + 2];
+      const double f0 = A.tf[3 * p + 0], f1 = A.tf[3 * p + 1], f2 = A.tf[3 * p + 2];
+      const uint8_t fx = A.tfixed[p];
+      const int ide = A.tid[p];
       A.q[p] = pi;
       if (K.shadow) {
         const long long bc = pack_cell(cx, cy, cz);
@@ -693,14 +707,14 @@ __global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
       A.xref[3 * p + 0] = pi.x;
       A.xref[3 * p + 1] = pi.y;
       A.xref[3 * p + 2] = pi.z;
-      A.v[3 * p + 0] = A.tv[3 * p + 0];
-      A.v[3 * p + 1] = A.tv[3 * p + 1];
-      A.v[3 * p + 2] = A.tv[3 * p + 2];
-      A.f[3 * p + 0] = A.tf[3 * p + 0];
-      A.f[3 * p + 1] = A.tf[3 * p + 1];
-      A.f[3 * p + 2] = A.tf[3 * p + 2];
-      A.fixed[p] = A.tfixed[p];
-      A.id[p] = A.tid[p];
+      A.v[3 * p + 0] = v0;
+      A.v[3 * p + 1] = v1;
+      A.v[3 * p + 2] = v2;
+      A.f[3 * p + 0] = f0;
+      A.f[3 * p + 1] = f1;
+      A.f[3 * p + 2] = f2;
+      A.fixed[p] = fx;
+      A.id[p] = ide;
     }
   }
 }
@@ -888,25 +902,25 @@ __global__ __launch_bounds__(LIST_BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts
     int tv[NIT], ts[NIT], tl[NIT], tm[NIT], tr[NIT], tL[NIT], tR[NIT];
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
+      // every load is unconditional and inside row rw (a row of this replica whether or not
+      // entry t names one), so that none waits on a branch
       const int t = threadIdx.x + it * LIST_BLOCK;
-      const int rr = t / nt, k = t % nt;
-      tv[it] = -1;
-      if (t < 9 * nt) {
-        const int z = stencil_cell(cz, rr / 3, gz, per2), y = stencil_cell(cy, rr % 3, gy, per1);
-        if (z >= 0 && y >= 0) {
-          const int rw = g0 + (z * gy + y) * gx;
-          const int u = min(max(x0 - 1 + k, xa), xb + 1);   // unwrapped cell, clamped
-          ts[it] = A.start[rw + xa];
-          tl[it] = wl ? A.start[rw + gx] - A.start[rw + gx - 1] : 0;
-          tm[it] = A.start[rw + xb + 1];
-          tr[it] = wr ? A.start[rw + 1] - A.start[rw] : 0;
-          tv[it] = A.start[rw + u];
-          tL[it] = k == 0 ? A.start[rw + gx - 1] : 0;
-          tR[it] = k == 0 ? A.start[rw] : 0;
-        } else {
-          tv[it] = -2;
-        }
-      }
+      const int rr = min(t / nt, 8), k = t % nt;
+      const bool in = t < 9 * nt;
+      const int z = stencil_cell(cz, rr / 3, gz, per2), y = stencil_cell(cy, rr % 3, gy, per1);
+      const bool row_ok = in && z >= 0 && y >= 0;
+      const int rw = row_ok ? g0 + (z * gy + y) * gx : g0;
+      const int u = min(max(x0 - 1 + k, xa), xb + 1);   // unwrapped cell, clamped
+      const int s_a = A.start[rw + xa], s_m = A.start[rw + xb + 1], s_u = A.start[rw + u];
+      const int s_0 = A.start[rw], s_1 = A.start[rw + 1];
+      const int s_l = A.start[rw + gx - 1], s_r = A.start[rw + gx];
+      ts[it] = s_a;
+      tl[it] = wl ? s_r - s_l : 0;
+      tm[it] = s_m;
+      tr[it] = wr ? s_1 - s_0 : 0;
+      tv[it] = row_ok ? s_u : (in ? -2 : -1);
+      tL[it] = s_l;
+      tR[it] = s_0;
     }
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
@@ -1050,7 +1064,13 @@ __global__ __launch_bounds__(LIST_BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts
       }
     }
     if (live) {
+      // all loads before the first store (a store could alias a later load, which would
+      // then wait for it)
       const double4 pi = tq[p];
+      const double v0 = A.tv[3 * p + 0], v1 = A.tv[3 * p + 1], v2 = A.tv[3 * p + 2];
+      const double f0 = A.tf[3 * p + 0], f1 = A.tf[3 * p + 1], f2 = A.tf[3 * p + 2];
+      const uint8_t fx = A.tfixed[p];
+      const int ide = A.tid[p];
       A.cnt[p] = min(count, cap);
       if (count > cap) atomicMax(&S.overflow, count);
       A.q[p] = pi;
@@ -1062,14 +1082,14 @@ __global__ __launch_bounds__(LIST_BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts
       A.xref[3 * p + 0] = pi.x;
       A.xref[3 * p + 1] = pi.y;
       A.xref[3 * p + 2] = pi.z;
-      A.v[3 * p + 0] = A.tv[3 * p + 0];
-      A.v[3 * p + 1] = A.tv[3 * p + 1];
-      A.v[3 * p + 2] = A.tv[3 * p + 2];
-      A.f[3 * p + 0] = A.tf[3 * p + 0];
-      A.f[3 * p + 1] = A.tf[3 * p + 1];
-      A.f[3 * p + 2] = A.tf[3 * p + 2];
-      A.fixed[p] = A.tfixed[p];
-      A.id[p] = A.tid[p];
+      A.v[3 * p + 0] = v0;
+      A.v[3 * p + 1] = v1;
+      A.v[3 * p + 2] = v2;
+      A.f[3 * p + 0] = f0;
+      A.f[3 * p + 1] = f1;
+      A.f[3 * p + 2] = f2;
+      A.fixed[p] = fx;
+      A.id[p] = ide;
     }
   }
 }
