@@ -321,6 +321,81 @@ def test_mixed_trajectory_stays_close():
 
 
 # ------------------------------------------------------------------------------------------
+# The whole-step run (md_run): the two half kicks of consecutive unobserved steps given at
+# once and, in FP64, the next step's drift done by the force pass
+# ------------------------------------------------------------------------------------------
+def _run(s, nsteps, energy_every, precision="fp64", tpa=1):
+    import torch
+    sim = sim_of(s, precision=precision, tpa=tpa)
+    sim.initial_forces()
+    st = sim.md_check()
+    assert st["overflow"] == 0 and st["xoverflow"] == 0, st
+    nobs = nsteps // energy_every if energy_every else 0
+    obs = torch.zeros((max(nobs, 1), 1, md.MD_NOBS), dtype=torch.float64, device="cuda")
+    print(f"  md_run {nsteps} steps, energies every {energy_every}", flush=True)
+    sim.md_run(nsteps, energy_every=energy_every, obs=obs if nobs else None)
+    return sim, obs.cpu().numpy()[:nobs, 0]
+
+
+def _check_run_fp64(sim, obs, s, nsteps, energy_every):
+    ref = O.md_run(s, nsteps)
+    st = sim.state()[0]
+    dx = np.abs(min_image_diff(st["x"], ref["x"], s)).max()
+    dv = np.abs(st["v"] - ref["v"]).max()
+    print(f"  max|dx| {dx:.2e}  max|dv| {dv:.2e}", flush=True)
+    assert dx < 1e-9 and dv < 1e-11
+    assert_forces(st["f"], ref["f"], 1e-9)
+    flags = sim.md_check()
+    assert not (flags["overflow"] or flags["xoverflow"] or flags["nonfinite"]), flags
+    ro = ref["obs"][[energy_every * (k + 1) for k in range(len(obs))]]
+    assert np.array_equal(obs[:, 14], ro[:, 14]), "list rebuild schedule differs"
+    if len(obs):
+        etot, rtot = obs[:, 0:4].sum(1), ro[:, 0:4].sum(1)
+        assert np.abs(etot - rtot).max() < 1e-9 * np.abs(rtot).max()
+        assert np.abs(obs[:, 10:13] - ro[:, 10:13]).max() < 1e-9
+        assert abs(obs[-1, 13] - ro[-1, 13]) < 1e-15
+
+
+@pytest.mark.parametrize("nsteps,energy_every,tpa", [(60, 10, 1), (37, 0, 1), (25, 7, 1), (60, 10, 2),
+                                                     (30, 10, 4)])
+def test_run_film_with_moving_indenter(nsteps, energy_every, tpa):
+    """md_run against the oracle's trajectory: energies every 10 steps, never, and every 7
+    steps (the last step then unobserved, its velocities completed by the final half kick);
+    with 1, 2 and 4 lanes per atom (the force pass's displacement maxima per lane group)."""
+    s = I.small_film(nx=8, ny=8, nz=6, radius=8.0, gap=0.2, seed=12, noise=0.03, steps=nsteps)
+    sim, obs = _run(s, nsteps, energy_every, tpa=tpa)
+    _check_run_fp64(sim, obs, s, nsteps, energy_every)
+
+
+def test_run_mixed_film_stays_close():
+    s = I.small_film(nx=8, ny=8, nz=6, radius=8.0, gap=0.2, seed=12, noise=0.03, steps=30)
+    sim, obs = _run(s, 30, 10, precision="mixed")
+    ref = O.md_run(s, 30)
+    st = sim.state()[0]
+    rel, _ = force_errors(st["f"], ref["f"])
+    print(f"  mixed md_run 30 steps: force rel-RMS vs FP64 oracle {rel:.2e}", flush=True)
+    assert rel < 1e-3
+    ro = ref["obs"][[10, 20, 30]]
+    e, er = obs[:, :4].sum(1), ro[:, :4].sum(1)
+    assert np.abs(e - er).max() < 1e-3 * np.abs(er).max()
+
+
+def test_cross_lists_and_run_film_fewer_than_three_cells():
+    """An indenter over a 4 x 4-cell film (11.54 A periodic faces): fewer than 3 Cr list
+    cells per periodic axis, so the lists come from the per-atom kernel and the Cr-C lists
+    from their own launch."""
+    s = I.small_film(nx=4, ny=4, nz=4, radius=5.0, gap=-1.5, seed=5, noise=0.05, steps=30)
+    sim = sim_of(s)
+    sim.md_build_neighbors(force=True)
+    st = sim.md_check()
+    assert st["overflow"] == 0 and st["xoverflow"] == 0
+    check_lists(sim, s)
+    assert check_lists(sim, s, cross=True) > 0
+    sim, obs = _run(s, 30, 10)
+    _check_run_fp64(sim, obs, s, 30, 10)
+
+
+# ------------------------------------------------------------------------------------------
 # Edge cases
 # ------------------------------------------------------------------------------------------
 def test_dimer_and_single_atom():
