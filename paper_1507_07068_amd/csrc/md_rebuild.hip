@@ -5,14 +5,17 @@
 //   k_bin           wrap periodic coordinates, cell of every atom / carbon, cell counts
 //   k_scan          exclusive scan of all cell counts (one pass, decoupled look-back)
 //   k_scatter       atom slots / carbon indices into their cells at the ranks k_bin took
-//                   (arbitrary order within a cell), with the (cell, id) sort keys
+//                   (arbitrary order within a cell), with the (cell, id) sort keys; marks
+//                   the 27-cell stencil of every occupied carbon cell
 //   k_sort_gather   one lane per slot: rank within its cell by (cell, id), gather the atom
-//                   state into sorted order (so the final order is canonical)
+//                   state into sorted order (so the final order is canonical); atoms in a
+//                   marked carbon cell join the near list
 //   k_list_tiles    one block per run of cells of a cell row: the neighbouring rows are
 //                   staged in LDS, each atom scans its window of them; copies the sorted
-//                   state back (k_list_rows: one lane per atom from global memory, for
-//                   periodic axes with fewer than 3 cells)
-//   k_xlist         Cr-C lists: one wavefront per Cr atom within reach of the carbons
+//                   state back.  Its leading blocks build the Cr-C lists (xlist_pass: one
+//                   wavefront per near atom).  k_list_rows (one lane per atom from global
+//                   memory, for periodic axes with fewer than 3 cells) is followed by
+//                   k_xlist, the same Cr-C pass as a launch of its own.
 //
 // Every kernel after k_decide returns at once when no replica needs a rebuild, so a step
 // without a rebuild costs a few empty launches.
