@@ -334,21 +334,25 @@ __global__ __launch_bounds__(BLOCK) void k_scan(BuildArgs A) {
   }
   int tot;
   const int pre = block_exclusive_scan(sum, &tot);
-  if (threadIdx.x < WAVE) {   // wave 0 publishes this chunk and looks back 64 chunks at a time
+  // wave 0 publishes this chunk and looks back 64 chunks at a time.  A published word holds
+  // both the flag and the sum, and nothing else a chunk writes is read before the next
+  // launch, so the atomics are relaxed (agent scope): a release or acquire here would write
+  // back or invalidate the per-XCD L2 at every publication and poll.
+  if (threadIdx.x < WAVE) {
     const int lane = threadIdx.x;
     long long* st = A.scan_state;
     int excl = 0;
     if (b == 0) {
       if (lane == 0)
-        __hip_atomic_store(&st[0], SCAN_INCL | (unsigned)tot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&st[0], SCAN_INCL | (unsigned)tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       if (lane == 0)
-        __hip_atomic_store(&st[b], SCAN_AGG | (unsigned)tot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&st[b], SCAN_AGG | (unsigned)tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       int top = b - 1, spins = 0;
       while (true) {
         const int j = top - lane;   // lane 0 is the nearest predecessor; j < 0 reads as prefix 0
         const long long w =
-            j >= 0 ? __hip_atomic_load(&st[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) : SCAN_INCL;
+            j >= 0 ? __hip_atomic_load(&st[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : SCAN_INCL;
         const long long flag = w & ~0xffffffffll;
         const unsigned long long incl = __ballot(flag == SCAN_INCL);
         const unsigned long long ready = __ballot(flag != 0);
@@ -367,7 +371,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan(BuildArgs A) {
         top -= WAVE;
       }
       if (lane == 0)
-        __hip_atomic_store(&st[b], SCAN_INCL | (unsigned)(excl + tot), __ATOMIC_RELEASE,
+        __hip_atomic_store(&st[b], SCAN_INCL | (unsigned)(excl + tot), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     }
     if (lane == 0) {
