@@ -445,9 +445,31 @@ __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __rest
   fx = group_sum<T>(fx);
   fy = group_sum<T>(fy);
   fz = group_sum<T>(fz);
-  if (c.live && c.sub == 0) {
+  const bool own = c.live && c.sub == 0;
+  double4 p = make_double4(0.0, 0.0, 0.0, 0.0);   // with DRIFT: the atom's next position
+  double d2 = 0.0;                                 // and its squared displacement since the build
+  if (own) {
     const int64_t i = c.i;
-    if (fme && xcnt[i] > 0) {   // the Cr-C force of this step (atoms with carbons in range)
+    // every value read here is loaded before the first store (a store could alias a later
+    // load, which would then wait for it) and used on every path (selects, not branches: a
+    // load used only past a branch is made there), so the loads go out together
+    const int xn = fme ? xcnt[i] : 0;
+    const bool move = KICK && !fixed[i];
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+    if (KICK) {
+      v0 = v[3 * i + 0];
+      v1 = v[3 * i + 1];
+      v2 = v[3 * i + 2];
+    }
+    double4 qi = make_double4(0.0, 0.0, 0.0, 0.0);
+    double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+    if (DRIFT) {
+      qi = q[i];
+      r0 = D.xref[3 * i + 0];
+      r1 = D.xref[3 * i + 1];
+      r2 = D.xref[3 * i + 2];
+    }
+    if (xn > 0) {   // the Cr-C force of this step (atoms with carbons in range)
       fx += fme[4 * i + 0];
       fy += fme[4 * i + 1];
       fz += fme[4 * i + 2];
@@ -456,35 +478,33 @@ __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __rest
     f[3 * i + 1] = fy;
     f[3 * i + 2] = fz;
     if (!(fabs(fx) + fabs(fy) + fabs(fz) < INFINITY)) S[c.r].nonfinite = 1;
-    if (KICK && !fixed[i]) {   // kick_h = dt a / 2 (Task 5), or dt a (with the next Task 3's)
-      const double vx = v[3 * i + 0] + kick_h * fx, vy = v[3 * i + 1] + kick_h * fy,
-                   vz = v[3 * i + 2] + kick_h * fz;
+    if (KICK) {   // kick_h = dt a / 2 (Task 5), or dt a (with the next Task 3's); fixed atoms
+                  // keep their velocity (written back unchanged)
+      const double vx = move ? v0 + kick_h * fx : v0, vy = move ? v1 + kick_h * fy : v1,
+                   vz = move ? v2 + kick_h * fz : v2;
       v[3 * i + 0] = vx;
       v[3 * i + 1] = vy;
       v[3 * i + 2] = vz;
-      if (DRIFT) {   // x(t + dt) = x + v(t + dt/2) dt into the other buffer
-        double4 p = q[i];
-        p.x += vx * K.dt;
-        p.y += vy * K.dt;
-        p.z += vz * K.dt;
-        D.q[i] = p;
+      if (DRIFT) {   // x(t + dt) = x + v(t + dt/2) dt into the other buffer (fixed: copied)
+        p = qi;
+        if (move) {
+          p.x += vx * K.dt;
+          p.y += vy * K.dt;
+          p.z += vz * K.dt;
+        }
       }
     } else if (DRIFT) {
-      D.q[i] = q[i];
+      p = qi;
     }
-  }
-  if (DRIFT) {
-    const bool own = c.live && c.sub == 0;
-    double4 p = make_double4(0.0, 0.0, 0.0, 0.0);
-    double d2 = 0.0;
-    if (own) {
-      const int64_t i = c.i;
-      p = D.q[i];
+    if (DRIFT) {
+      D.q[i] = p;
       if (K.shadow) D.qs[i] = cell_local(S[c.r], D.bcell[i], p.x, p.y, p.z, (float)p.w);
-      const double ex = p.x - D.xref[3 * i + 0], ey = p.y - D.xref[3 * i + 1], ez = p.z - D.xref[3 * i + 2];
+      const double ex = p.x - r0, ey = p.y - r1, ez = p.z - r2;
       d2 = (ex * ex + ey * ey) + ez * ez;
       if (!(d2 == d2)) d2 = INFINITY;   // NaN positions force a rebuild (and get flagged there)
     }
+  }
+  if (DRIFT) {
     // the part's displacement maximum and box (minima as maxima of the negated coordinates)
     double m[7] = {d2, own ? -p.x : -INFINITY, own ? -p.y : -INFINITY, own ? -p.z : -INFINITY,
                    own ? p.x : -INFINITY, own ? p.y : -INFINITY, own ? p.z : -INFINITY};
