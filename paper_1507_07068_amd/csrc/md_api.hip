@@ -490,11 +490,19 @@ int build_chain(md_system* s, const md_atoms* a, const md_lists* l, uint32_t fla
   A.scan_chunk = SCAN_CHUNK;
   A.scan_blocks = s->scan_blocks;
   const int cblocks = (int)((s->ctot + BLOCK - 1) / BLOCK);
-  if (flags & MD_B_FORCE)
-    k_tile_box<<<s->ntiles, BLOCK, 0, st>>>(A.R, A.tile_rep, A.q, at<double>(s, s->L.tbox));
-  k_decide<<<1, DECIDE_THREADS, 0, st>>>(s->K, A, at<double>(s, s->L.dmax), at<double>(s, s->L.tbox),
-                                (flags & MD_B_FORCE) ? 1 : 0, (flags & MD_B_FORCE) ? 1 : s->ppt);
-  k_bin<<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A);
+  // a single replica without a forced build: the skin decision is taken inside k_bin
+  const bool decide_in_bin = !(flags & MD_B_FORCE) && s->K.nrep == 1;
+  A.commit_ref = decide_in_bin ? 1 : 0;
+  if (decide_in_bin) {
+    k_bin<true><<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A, at<double>(s, s->L.dmax),
+                                                       at<double>(s, s->L.tbox), s->ppt);
+  } else {
+    if (flags & MD_B_FORCE)
+      k_tile_box<<<s->ntiles, BLOCK, 0, st>>>(A.R, A.tile_rep, A.q, at<double>(s, s->L.tbox));
+    k_decide<<<1, DECIDE_THREADS, 0, st>>>(s->K, A, at<double>(s, s->L.dmax), at<double>(s, s->L.tbox),
+                                  (flags & MD_B_FORCE) ? 1 : 0, (flags & MD_B_FORCE) ? 1 : s->ppt);
+    k_bin<false><<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A, nullptr, nullptr, 0);
+  }
   k_scan<<<s->scan_blocks, BLOCK, 0, st>>>(A);
   k_scatter<<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A);
   k_sort_gather<<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A);

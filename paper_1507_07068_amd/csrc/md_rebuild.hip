@@ -72,6 +72,7 @@ struct BuildArgs {
   int ncell_all, ncell_cr, ntiles, ctot;
   int near_blocks;       // grid of k_xlist
   int xblocks;           // leading blocks of k_list_tiles that build the Cr-C lists (0: none)
+  int commit_ref;        // k_scan records the indenter position of this build (k_bin decided)
   int scan_chunk, scan_blocks;
   int nrows, nlblk;      // cell rows at capacity; capacity of the work-item table
 };
@@ -121,58 +122,82 @@ constexpr int DECIDE_BLOCKWIDE = 4;   // replicas up to which the whole block ta
 
 // Per-replica part of k_decide.  Reduce(v, op) reduces over the threads that share the
 // replica (a wavefront or the block); `lead` marks the thread that writes.
+// Skin test (Section 2.6) and cell grid of replica r, the same in every thread that calls it
+// (every thread of the block calls it together: maxr is a block or wavefront reduction).
+struct BuildGrid {
+  int need;
+  double glo[3], ginv[3], gedge[3], qscale;
+  int gd[3];
+};
 template <class MaxReduce>
-__device__ __forceinline__ bool decide_replica(const Consts& K, BuildArgs& A, int r, const double* dmax_tile,
-                                               const double* tile_box, int force, int ppt, int t0, int tstep,
-                                               bool lead, MaxReduce maxr) {
+__device__ __forceinline__ BuildGrid decide_grid(const Consts& K, const BuildArgs& A, int r,
+                                                 const double* dmax_tile, const double* tile_box, int force,
+                                                 int ppt, int t0, int tstep, MaxReduce maxr) {
   const RepDesc& d = A.R[r];
-  RepState& s = A.S[r];
+  const RepState& s = A.S[r];
+  BuildGrid g;
   double m = 0.0;
-  for (int t = t0; t < d.nt * ppt; t += tstep) m = fmax(m, dmax_tile[d.t0 * ppt + t]);
+#pragma unroll 8
+  for (int t = t0; t < d.nt * ppt; t += tstep) m = fmax(m, dmax_tile[d.t0 * ppt + t]);   // loads together
   m = maxr(m);
-  const int need = force || (m > K.half_skin_sq) || (fabs(s.ind_z - s.ind_z_ref) > K.half_skin);
-  if (lead) {
-    s.rebuild = need;
-    if (need) s.nnear = 0;
-  }
-  if (!need) return false;   // uniform over the threads of the replica
+  g.need = force || (m > K.half_skin_sq) || (fabs(s.ind_z - s.ind_z_ref) > K.half_skin);
+  if (!g.need) return g;   // uniform over the threads of the replica
   // cell grid of this build: the box along periodic axes, the atoms' extent along open ones
   for (int a = 0; a < 3; ++a) {
     if (d.per[a]) {
-      if (lead) {
-        s.glo[a] = d.lo[a];
-        s.ginv[a] = d.ginv[a];
-        s.gedge[a] = d.len[a] / d.gcap[a];
-        s.gd[a] = d.gcap[a];
-      }
+      g.glo[a] = d.lo[a];
+      g.ginv[a] = d.ginv[a];
+      g.gedge[a] = d.len[a] / d.gcap[a];
+      g.gd[a] = d.gcap[a];
       continue;
     }
     double mn = INFINITY, mx = -INFINITY;
+#pragma unroll 4
     for (int t = t0; t < d.nt * ppt; t += tstep) {
       mn = fmin(mn, tile_box[6 * (int64_t)(d.t0 * ppt + t) + a]);
       mx = fmax(mx, tile_box[6 * (int64_t)(d.t0 * ppt + t) + 3 + a]);
     }
     mn = -maxr(-mn);
     mx = maxr(mx);
-    if (lead) {
-      if (!(mn <= mx)) {   // no atoms (or non-finite positions): fall back to the box
-        mn = d.lo[a];
-        mx = d.lo[a] + d.len[a];
-      }
-      const double edge = K.rlist * (1.0 + 1e-9);
-      const double ext = fmax(mx - mn, edge);
-      const int g = (int)fmin(fmax(floor(ext / edge), 1.0), (double)d.gcap[a]);
-      s.glo[a] = mn;
-      s.ginv[a] = g / ext;
-      s.gedge[a] = ext / g;
-      s.gd[a] = g;
+    if (!(mn <= mx)) {   // no atoms (or non-finite positions): fall back to the box
+      mn = d.lo[a];
+      mx = d.lo[a] + d.len[a];
     }
+    const double edge = K.rlist * (1.0 + 1e-9);
+    const double ext = fmax(mx - mn, edge);
+    const int gc = (int)fmin(fmax(floor(ext / edge), 1.0), (double)d.gcap[a]);
+    g.glo[a] = mn;
+    g.ginv[a] = gc / ext;
+    g.gedge[a] = ext / gc;
+    g.gd[a] = gc;
   }
-  if (lead) {   // shadow scale: the longest cell edge spans at most 2^29 units
-    const double emax = fmax(s.gedge[0], fmax(s.gedge[1], s.gedge[2]));
-    s.qscale = ldexp(1.0, 29 - (int)ceil(log2(emax)));
+  // shadow scale: the longest cell edge spans at most 2^29 units
+  const double emax = fmax(g.gedge[0], fmax(g.gedge[1], g.gedge[2]));
+  g.qscale = ldexp(1.0, 29 - (int)ceil(log2(emax)));
+  return g;
+}
+
+// Records the outcome in the replica's state (one thread).
+__device__ __forceinline__ void record_grid(RepState& s, const BuildGrid& g) {
+  s.rebuild = g.need;
+  if (!g.need) return;
+  s.nnear = 0;
+  for (int a = 0; a < 3; ++a) {
+    s.glo[a] = g.glo[a];
+    s.ginv[a] = g.ginv[a];
+    s.gedge[a] = g.gedge[a];
+    s.gd[a] = g.gd[a];
   }
-  return true;
+  s.qscale = g.qscale;
+}
+
+template <class MaxReduce>
+__device__ __forceinline__ bool decide_replica(const Consts& K, BuildArgs& A, int r, const double* dmax_tile,
+                                               const double* tile_box, int force, int ppt, int t0, int tstep,
+                                               bool lead, MaxReduce maxr) {
+  const BuildGrid g = decide_grid(K, A, r, dmax_tile, tile_box, force, ppt, t0, tstep, maxr);
+  if (lead) record_grid(A.S[r], g);
+  return g.need;
 }
 
 __global__ __launch_bounds__(DECIDE_THREADS) void k_decide(Consts K, BuildArgs A,
@@ -255,8 +280,28 @@ __device__ __forceinline__ int bin_rank(int* count, int cid, bool live) {
 }
 
 // Blocks [0, ntiles): one tile of Cr atoms each.  Blocks [ntiles, ...): 256 carbons each.
-__global__ __launch_bounds__(BLOCK) void k_bin(Consts K, BuildArgs A) {
-  if (rebuild_off(A)) return;
+// DECIDE (single replica, no forced build): every block takes the skin decision and the
+// cell grid itself from the per-part maxima and boxes (so no separate decision launch), all
+// blocks alike; block 0 records them.  The indenter reference position, which every block
+// reads for the decision, is recorded by k_scan.
+template <bool DECIDE>
+__global__ __launch_bounds__(BLOCK) void k_bin(Consts K, BuildArgs A, const double* __restrict__ dmax_tile,
+                                               const double* __restrict__ tile_box, int ppt) {
+  BuildGrid g1;
+  if (DECIDE) {
+    g1 = decide_grid(K, A, 0, dmax_tile, tile_box, 0, ppt, threadIdx.x, BLOCK,
+                     [](double v) { return block_max<BLOCK>(v); });
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      RepState& s0 = A.S[0];
+      record_grid(s0, g1);
+      if (g1.need) s0.nbuilds += 1;
+      *A.any = g1.need;
+      *A.nitems = 0;   // k_scatter lists the list-build work items of a rebuild
+    }
+    if (!g1.need) return;
+  } else if (rebuild_off(A)) {
+    return;
+  }
   const int b = blockIdx.x;
   if (b == 0) {   // fresh state for this build's k_scan
     for (int t = threadIdx.x; t < A.scan_blocks; t += BLOCK) A.scan_state[t] = 0;
@@ -264,7 +309,7 @@ __global__ __launch_bounds__(BLOCK) void k_bin(Consts K, BuildArgs A) {
   }
   if (b < A.ntiles) {
     const int r = A.tile_rep[b];
-    if (!A.S[r].rebuild) return;
+    if (!DECIDE && !A.S[r].rebuild) return;
     const RepDesc& d = A.R[r];
     const int64_t i = (int64_t)b * TILE + threadIdx.x;
     const bool live = i < (int64_t)d.a0 + d.n;
@@ -284,7 +329,14 @@ __global__ __launch_bounds__(BLOCK) void k_bin(Consts K, BuildArgs A) {
       p.x = xyz[0];
       p.y = xyz[1];
       p.z = xyz[2];
-      cid = cr_cell_of(d, A.S[r], p.x, p.y, p.z);   // before the stores (which could alias S)
+      if (DECIDE) {   // the grid just decided (block 0 may be recording it meanwhile)
+        const int cx = cell_coord(p.x, g1.glo[0], g1.ginv[0], g1.gd[0]);
+        const int cy = cell_coord(p.y, g1.glo[1], g1.ginv[1], g1.gd[1]);
+        const int cz = cell_coord(p.z, g1.glo[2], g1.ginv[2], g1.gd[2]);
+        cid = d.g0 + (cz * g1.gd[1] + cy) * g1.gd[0] + cx;
+      } else {
+        cid = cr_cell_of(d, A.S[r], p.x, p.y, p.z);   // before the stores (which could alias S)
+      }
       A.q[i] = p;
       A.cellid[i] = cid;
     }
@@ -295,7 +347,7 @@ __global__ __launch_bounds__(BLOCK) void k_bin(Consts K, BuildArgs A) {
     int r = -1;
     if (k < A.ctot) {
       r = A.c_rep[k];
-      if (!A.S[r].rebuild) r = -1;
+      if (!DECIDE && !A.S[r].rebuild) r = -1;
     }
     if (r >= 0) {
       const RepDesc& d = A.R[r];
@@ -324,6 +376,10 @@ __global__ __launch_bounds__(BLOCK) void k_scan(BuildArgs A) {
   if (threadIdx.x == 0) chunk_sh = atomicAdd(A.scan_ticket, 1);
   __syncthreads();
   const int b = chunk_sh;
+  if (A.commit_ref && b == 0 && threadIdx.x == 0) {   // k_bin decided: this build's indenter position
+    RepState& s0 = A.S[0];
+    s0.ind_z_ref = s0.ind_z;
+  }
   const int c0 = b * A.scan_chunk + threadIdx.x * SCAN_PER_THREAD;
   int v[SCAN_PER_THREAD];
   int sum = 0;
