@@ -42,15 +42,17 @@ def stats(d: str) -> str:
 
 def steps(d: str) -> str:
     """Kernel durations per step, split into steps with and without a list rebuild (Cr-Cr
-    list kernel longer than 20 us).  A step starts at its rebuild decision (k_decide, once per
-    step) or at the k_kick_drift launch just before it; FP64 runs drift inside the force pass
-    and launch k_kick_drift only after steps whose velocities are observed."""
+    list kernel longer than 20 us).  A step starts at its first build kernel (k_decide, or
+    k_bin when the binning blocks take the decision themselves) or at the k_kick_drift launch
+    just before it; FP64 runs drift inside the force pass and launch k_kick_drift only after
+    steps whose velocities are observed."""
     c = sqlite3.connect(_db(d))
     rows = list(c.execute("select name, start, end from kernels order by start"))
     groups, cur, prev = [], None, ""
     for n, s, e in rows:
         k = short_name(n)
-        if k.startswith("k_kick_drift") or (k.startswith("k_decide") and not prev.startswith("k_kick_drift")):
+        first_build = k.startswith("k_decide") or (k.startswith("k_bin") and not prev.startswith("k_decide"))
+        if k.startswith("k_kick_drift") or (first_build and not prev.startswith("k_kick_drift")):
             cur = []
             groups.append(cur)
         if cur is not None:
