@@ -2,7 +2,8 @@
 // md_kernels.hip.
 //
 //   k_decide        one block, a wavefront per replica: skin test (Section 2.6) -> rebuild flags
-//   k_bin           wrap periodic coordinates, cell of every atom / carbon, cell counts
+//   k_bin           wrap periodic coordinates, cell of every atom / carbon, cell counts (with a
+//                   single replica each block takes the skin decision itself, no k_decide)
 //   k_scan          exclusive scan of all cell counts (one pass, decoupled look-back)
 //   k_scatter       atom slots / carbon indices into their cells at the ranks k_bin took
 //                   (arbitrary order within a cell), with the (cell, id) sort keys; marks
@@ -17,8 +18,8 @@
 //                   memory, for periodic axes with fewer than 3 cells) is followed by
 //                   k_xlist, the same Cr-C pass as a launch of its own.
 //
-// Every kernel after k_decide returns at once when no replica needs a rebuild, so a step
-// without a rebuild costs a few empty launches.
+// Every build kernel after the decision returns at once when no replica needs a rebuild, so
+// a step without a rebuild costs a few empty launches.
 #pragma once
 
 #include "md_device.hpp"
