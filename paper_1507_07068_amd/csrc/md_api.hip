@@ -29,6 +29,7 @@ struct Layout {
 
 constexpr int MISC_INTS = 16;    // rebuild flag, status words
 constexpr int SCAN_CHUNK = 2048; // cells per block of the cell-count scan
+constexpr int64_t DECIDE_IN_BIN_MAX_LOADS = (int64_t)1 << 22;   // part loads over all k_bin blocks
 constexpr int MAXREP = 16384;    // replicas per system
 
 }  // namespace
@@ -490,8 +491,12 @@ int build_chain(md_system* s, const md_atoms* a, const md_lists* l, uint32_t fla
   A.scan_chunk = SCAN_CHUNK;
   A.scan_blocks = s->scan_blocks;
   const int cblocks = (int)((s->ctot + BLOCK - 1) / BLOCK);
-  // a single replica without a forced build: the skin decision is taken inside k_bin
-  const bool decide_in_bin = !(flags & MD_B_FORCE) && s->K.nrep == 1;
+  // a single replica without a forced build: the skin decision is taken inside k_bin, every
+  // block reducing all the per-part maxima, while those redundant loads stay few (they grow
+  // as blocks x parts: 1.4 M on the 216k-atom film, 2e9 on an 8M-atom one)
+  const int64_t bin_blocks = (int64_t)s->ntiles + cblocks;
+  const bool decide_in_bin = !(flags & MD_B_FORCE) && s->K.nrep == 1 &&
+                             bin_blocks * ((int64_t)s->ntiles * s->ppt) <= DECIDE_IN_BIN_MAX_LOADS;
   A.commit_ref = decide_in_bin ? 1 : 0;
   if (decide_in_bin) {
     k_bin<true><<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A, at<double>(s, s->L.dmax),
