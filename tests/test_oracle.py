@@ -380,3 +380,98 @@ def test_half_skin_rule_catches_approaching_pair():
     assert np.abs(a["f"]).max() > 0          # the pair interacts by the end
     builds = a["obs"][:, 14]
     assert builds[15] == 1 and builds[16] == 2
+
+
+# --------------------------------------------------------------------------------------
+# The indenter displacement (Task 2): how it enters the Cr-C geometry and the rebuild rule
+# --------------------------------------------------------------------------------------
+def _cr_c_pair(r, delta, axis=np.array([2.0, -1.0, 2.0]) / 3.0):
+    """One Cr atom and one carbon whose base position is the Cr position + r*axis raised by
+    delta along z: at indenter displacement -delta the pair is exactly r apart."""
+    s = two_atoms(3.0)
+    s.x = np.array([[20.0, 21.0, 22.0]])
+    s.fixed = np.zeros(1, np.uint8)
+    s.v = np.zeros((1, 3))
+    s.xc = s.x + r * axis + np.array([0.0, 0.0, delta])
+    return s, axis
+
+
+@pytest.mark.parametrize("delta", [0.75, -1.3, 2.5])
+@pytest.mark.parametrize("r", [1.6, 2.0, 3.1, 4.6])
+def test_morse_pair_at_indenter_displacement(r, delta):
+    """The carbon sits at its base position plus (0, 0, ind_z): with the base raised by delta
+    and ind_z = -delta, energy and force are the Morse closed form at r; at ind_z = 0 they are
+    the closed form at the base distance."""
+    s, u = _cr_c_pair(r, delta)
+    ev = O.evaluate(s, ind_z=-delta)
+    e = morse_cf(r) - morse_cf(MORSE["rc"])
+    assert abs(ev["obs"][2] - e) < 1e-13 * max(1.0, abs(e))
+    D, al, r0 = MORSE["D"], MORSE["alpha"], MORSE["r0"]
+    dphi = 2 * al * D * (np.exp(-al * (r - r0)) - np.exp(-2 * al * (r - r0)))
+    # force on the Cr atom: -phiM'(r) (q_Cr - q_C) / r = phiM'(r) u
+    assert np.allclose(ev["f"][0], dphi * u, rtol=1e-12, atol=1e-14)
+    assert np.allclose(ev["obs"][10:13], -dphi * u, rtol=1e-12, atol=1e-14)
+    base = s.xc[0] - s.x[0]
+    rb = np.sqrt(base @ base)
+    e0 = morse_cf(rb) - morse_cf(MORSE["rc"]) if rb < MORSE["rc"] else 0.0
+    assert abs(O.evaluate(s, ind_z=0.0)["obs"][2] - e0) < 1e-13 * max(1.0, abs(e0))
+
+
+def test_indenter_displacement_is_a_rigid_shift_of_the_carbons():
+    """A film with the indenter displaced by dz equals the same film with every carbon's base
+    position moved by dz along z at zero displacement (forces, energies, load)."""
+    s = I.small_film(nx=6, ny=6, nz=4, radius=6.0, gap=0.4, seed=13, noise=0.04)
+    dz = -1.7
+    a = O.evaluate(s, ind_z=dz)
+    t = s.copy()
+    t.xc = s.xc + np.array([0.0, 0.0, dz])
+    b = O.evaluate(t, ind_z=0.0)
+    assert np.abs(a["fm"]).sum() > 0 and abs(a["obs"][2] - O.evaluate(s)["obs"][2]) > 1e-3
+    assert np.array_equal(a["f"], b["f"]) and np.array_equal(a["obs"], b["obs"])
+
+
+def test_cross_list_follows_the_indenter():
+    """Cr-C list membership {k : |xc_k + (0,0,ind_z) - x_i| < rc + skin}: a carbon 0.4 A
+    beyond the list radius joins the list once the indenter has come 0.5 A closer."""
+    rl = MORSE["rc"] + I.SKIN
+    s, u = _cr_c_pair(rl + 0.4, 0.0, axis=np.array([0.0, 0.0, 1.0]))
+    cnt0, _ = O.cross_neighbors(s, rl, ind_z=0.0)
+    cnt1, idx1 = O.cross_neighbors(s, rl, ind_z=-0.5)
+    cnt2, _ = O.cross_neighbors(s, rl, ind_z=+0.5)
+    assert cnt0[0] == 0 and cnt1[0] == 1 and idx1[0, 0] == 0 and cnt2[0] == 0
+
+
+def indenter_only_film(v_ind=-0.004, seed=19, nx=6):
+    """A film whose Cr atoms are all held fixed, under an indenter moving v_ind per step: only
+    the indenter term of the half-skin rule can trigger a rebuild."""
+    s = I.small_film(nx=nx, ny=6, nz=4, radius=6.0, gap=0.6, seed=seed, noise=0.04)
+    s.fixed = np.ones(s.n, np.uint8)
+    s.v = np.zeros_like(s.v)
+    s.v_ind = v_ind
+    return s
+
+
+def expected_indenter_builds(nsteps, v_ind, dt, half_skin):
+    """Build count after each step 0..nsteps: a rebuild happens at the first step at which the
+    indenter has moved more than half the skin since the last build (here the crossings fall
+    far from any rounding boundary: 0.15 / 0.004 = 37.5 steps)."""
+    builds, ref, out = 1, 0.0, [1]
+    for k in range(1, nsteps + 1):
+        if abs(k * v_ind * dt - ref) > half_skin:
+            builds += 1
+            ref = k * v_ind * dt
+        out.append(builds)
+    return np.array(out, dtype=float)
+
+
+def test_rebuild_rule_indenter_term():
+    """Section 2.6 rule, indenter part: with every Cr atom fixed the lists are rebuilt exactly
+    every 38 steps (0.15 / 0.004 = 37.5), and list-mode forces still equal all pairs."""
+    s = indenter_only_film()
+    out = O.md_run(s, 200, use_lists=True, cap=64)
+    want = expected_indenter_builds(200, s.v_ind, s.dt, 0.5 * s.skin)
+    assert np.array_equal(out["obs"][:, 14], want)
+    assert want[-1] == 6 and want[37] == 1 and want[38] == 2
+    ref = O.md_run(s, 200, use_lists=False)
+    assert np.array_equal(out["f"], ref["f"]) and np.array_equal(out["obs"][:, :14], ref["obs"][:, :14])
+    assert np.abs(out["obs"][-1, 10:13]).max() > 1e-3   # the indenter is in contact by then

@@ -30,6 +30,14 @@ MUTATIONS = [
      T.test_lattice_energy_vs_lattice_constant_is_smooth_and_consistent),
     ("rebuild test at full skin", "double lim = 0.5 * P->skin;", "double lim = P->skin;",
      T.test_half_skin_rule_catches_approaching_pair),
+    ("carbon position ignores the indenter displacement", "p[2] = xc[3 * k + 2] + ind_z;",
+     "p[2] = xc[3 * k + 2];", lambda: T.test_morse_pair_at_indenter_displacement(2.0, 0.75)),
+    ("indenter displacement with the wrong sign", "p[2] = xc[3 * k + 2] + ind_z;",
+     "p[2] = xc[3 * k + 2] - ind_z;", lambda: T.test_morse_pair_at_indenter_displacement(3.1, -1.3)),
+    ("rebuild rule without the indenter term", "if (fabs(S->ind_z - S->ind_z_ref) > lim) return 1;",
+     "if (0 && fabs(S->ind_z - S->ind_z_ref) > lim) return 1;", T.test_rebuild_rule_indenter_term),
+    ("indenter reference not reset at a build", "S->ind_z_ref = S->ind_z;\n    S->nbuilds++;",
+     "S->nbuilds++;", T.test_rebuild_rule_indenter_term),
 ]
 
 
