@@ -156,7 +156,13 @@ typedef struct md_status {
     int32_t xoverflow;      /* same for the Cr-C list and xcap */
     int32_t nonfinite;      /* 1 if a non-finite force or density was produced */
     int32_t nbuilds;        /* list builds so far (summed over replicas) */
-    int32_t sync_timeout;   /* a bounded device-side wait of a list build gave up: that build is invalid */
+    int32_t sync_timeout;   /* a bounded device-side wait of a list build gave up: that build
+                               is invalid (its later kernels did nothing; the lists, reference
+                               positions and order are those of the build before, the positions
+                               may have been wrapped) and no list build runs until
+                               md_clear_flags.  The wait is 2^22 polls, or MD_SCAN_SPIN_LIMIT
+                               from the environment at the time of the build (negative: give up
+                               at once, for tests of this path) */
     int32_t nnear;          /* Cr atoms whose carbon cells are within reach of a carbon at the
                                last build (the candidates of the Cr-C lists), all replicas */
     int32_t pad[2];
@@ -275,7 +281,9 @@ MD_API int md_graph_destroy(void *graph_exec);
 /* Synchronise `stream` and copy the device flags to *st (summed / maxed over replicas). */
 MD_API int md_check(md_system *sys, md_status *st, void *stream);
 
-/* Clear overflow / non-finite flags (e.g. after enlarging the lists). */
+/* Clear overflow / non-finite / sync_timeout flags (e.g. after enlarging the lists), and
+ * after a list build that gave up, reset what it left behind (cell counts) so that builds run
+ * again; the next build should then be forced (MD_B_FORCE). */
 MD_API int md_clear_flags(md_system *sys, void *stream);
 
 MD_API const char *md_strerror(int code);

@@ -8,12 +8,20 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc", "md_api.hip")
-DEPS = [os.path.join(PKG, "csrc", f) for f in ("md_api.hip", "md_kernels.hip", "md_device.hpp")] + [
-    os.path.join(ROOT, "include", "md.h")]
+CSRC = os.path.join(PKG, "csrc")
+
+
+def deps() -> list:
+    """Every source the library is compiled from: all of csrc/ and the public headers."""
+    out = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith((".hip", ".hpp", ".h"))]
+    inc = os.path.join(ROOT, "include")
+    return out + [os.path.join(inc, f) for f in sorted(os.listdir(inc)) if f.endswith(".h")]
+
+
 LIB = os.path.join(PKG, "libmd.so")
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-fvisibility=hidden",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
@@ -45,7 +53,7 @@ def is_stale() -> bool:
     if not os.path.exists(LIB):
         return True
     t = os.path.getmtime(LIB)
-    return any(os.path.getmtime(d) > t for d in DEPS)
+    return any(os.path.getmtime(d) > t for d in deps())
 
 
 if __name__ == "__main__":

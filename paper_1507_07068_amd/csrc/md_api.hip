@@ -148,6 +148,14 @@ double4* qnext(md_system* s, const md_atoms* a) {
 int4* qscur(md_system* s) { return at<int4>(s, s->cur ? s->L.qs2 : s->L.qs); }
 int4* qsnext(md_system* s) { return at<int4>(s, s->cur ? s->L.qs : s->L.qs2); }
 
+// Polls of the cell-count scan's bounded wait before a build gives up: 2^22, or the value of
+// MD_SCAN_SPIN_LIMIT in the environment at the time of the build (a negative value gives up
+// at once: tests force the give-up path with it).
+int scan_spin_limit() {
+  const char* e = std::getenv("MD_SCAN_SPIN_LIMIT");
+  return e ? std::atoi(e) : (1 << 22);
+}
+
 // Grid of the kernels that walk the near-indenter atoms (one wavefront per atom, grid-stride).
 int near_blocks(const md_system* s) { return std::max(1, std::min(2048, s->ntiles)); }
 // Blocks of the Cr-C pass inside a density launch: about one wavefront per three carbons'
@@ -406,10 +414,10 @@ MD_API int64_t md_replica_offset(const md_system* s, int32_t r) {
 
 MD_API size_t md_workspace_bytes(const md_system* s) { return s ? s->L.total : 0; }
 
-MD_API int md_workspace_bind(md_system* s, void* ws, size_t bytes, void* stream) {
-  if (!s || !ws || bytes < s->L.total) return MD_ERR_ARG;
-  if (((uintptr_t)ws) % ALIGN) return MD_ERR_ARG;
-  hipStream_t st = (hipStream_t)stream;
+namespace {
+
+// Takes ws as the workspace of s: cleared, descriptors written, stream synchronised.
+int bind_workspace(md_system* s, void* ws, hipStream_t st) {
   s->ws = (char*)ws;
   int e;
   if ((e = hip_status(hipMemsetAsync(ws, 0, s->L.total, st)))) return e;
@@ -427,8 +435,19 @@ MD_API int md_workspace_bind(md_system* s, void* ws, size_t bytes, void* stream)
                                      hipMemcpyHostToDevice, st))))
     return e;
   s->have_embed = s->have_force = false;
+  s->cur = 0;
+  s->ppt = 1;
   return hip_status(hipStreamSynchronize(st));
 }
+
+}  // namespace
+
+MD_API int md_workspace_bind(md_system* s, void* ws, size_t bytes, void* stream) {
+  if (!s || !ws || bytes < s->L.total) return MD_ERR_ARG;
+  if (((uintptr_t)ws) % ALIGN) return MD_ERR_ARG;
+  return bind_workspace(s, ws, (hipStream_t)stream);
+}
+
 
 namespace {
 
@@ -448,6 +467,8 @@ int build_chain(md_system* s, const md_atoms* a, const md_lists* l, uint32_t fla
   A.nlblk = s->nlblk;
   A.c_rep = at<int>(s, s->L.c_rep);
   A.any = misc + 0;
+  A.abort = misc + 3;
+  A.spin_limit = scan_spin_limit();
   A.q = qcur(s, a);
   A.v = a->v;
   A.f = a->f;
@@ -755,7 +776,11 @@ MD_API int md_check(md_system* s, md_status* st_out, void* stream) {
 MD_API int md_clear_flags(md_system* s, void* stream) {
   if (!s) return MD_ERR_ARG;
   if (!s->ws) return MD_ERR_STATE;
-  k_clear_flags<<<(s->nrep + 63) / 64, 64, 0, (hipStream_t)stream>>>(at<RepState>(s, s->L.state), s->nrep);
+  hipStream_t st = (hipStream_t)stream;
+  k_clear_flags<<<(s->nrep + 63) / 64, 64, 0, st>>>(at<RepState>(s, s->L.state), s->nrep);
+  // a build that gave up left its cell counts behind: zero them and lift the abort word
+  k_clear_build<<<std::min(4096, (s->ncell_all + BLOCK - 1) / BLOCK + 1), BLOCK, 0, st>>>(
+      at<int>(s, s->L.count), s->ncell_all, at<int>(s, s->L.misc) + 3);
   return check_launch();
 }
 

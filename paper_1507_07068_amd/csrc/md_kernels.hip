@@ -217,6 +217,12 @@ __global__ void k_status(const RepState* __restrict__ S, int nrep, int* __restri
   out[5] = nn;
 }
 
+// Cell counts back to zero and the abort word of a build that gave up lifted.
+__global__ __launch_bounds__(BLOCK) void k_clear_build(int* __restrict__ count, int ncell, int* __restrict__ abort) {
+  for (int64_t c = (int64_t)blockIdx.x * BLOCK + threadIdx.x; c < ncell; c += (int64_t)gridDim.x * BLOCK) count[c] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *abort = 0;
+}
+
 __global__ void k_clear_flags(RepState* __restrict__ S, int nrep) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrep) return;

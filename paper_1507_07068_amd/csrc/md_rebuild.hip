@@ -35,6 +35,8 @@ struct BuildArgs {
   int* nitems;           // work items of this build
   const int* c_rep;      // [ctot] replica of each carbon
   int* any;              // 1 if some replica rebuilds in this step
+  int* abort;            // sticky: a bounded wait of a build gave up; no build runs until
+                         // md_clear_flags (which also zeroes the cell counts it left behind)
   double4* q;
   double* v;
   double* f;
@@ -75,6 +77,7 @@ struct BuildArgs {
   int xblocks;           // leading blocks of k_list_tiles that build the Cr-C lists (0: none)
   int commit_ref;        // k_scan records the indenter position of this build (k_bin decided)
   int scan_chunk, scan_blocks;
+  int spin_limit;        // polls of k_scan's look-back before it gives up (< 0: at once)
   int nrows, nlblk;      // cell rows at capacity; capacity of the work-item table
 };
 
@@ -141,7 +144,7 @@ __device__ __forceinline__ BuildGrid decide_grid(const Consts& K, const BuildArg
 #pragma unroll 8
   for (int t = t0; t < d.nt * ppt; t += tstep) m = fmax(m, dmax_tile[d.t0 * ppt + t]);   // loads together
   m = maxr(m);
-  g.need = force || (m > K.half_skin_sq) || (fabs(s.ind_z - s.ind_z_ref) > K.half_skin);
+  g.need = !*A.abort && (force || (m > K.half_skin_sq) || (fabs(s.ind_z - s.ind_z_ref) > K.half_skin));
   if (!g.need) return g;   // uniform over the threads of the replica
   // cell grid of this build: the box along periodic axes, the atoms' extent along open ones
   for (int a = 0; a < 3; ++a) {
@@ -369,7 +372,6 @@ __global__ __launch_bounds__(BLOCK) void k_bin(Consts K, BuildArgs A, const doub
 // wait is bounded and a timeout is reported in the status words.
 constexpr int SCAN_PER_THREAD = 8;
 constexpr long long SCAN_AGG = 1ll << 32, SCAN_INCL = 2ll << 32;
-constexpr int SCAN_SPIN_LIMIT = 1 << 22;
 
 __global__ __launch_bounds__(BLOCK) void k_scan(BuildArgs A) {
   if (rebuild_off(A)) return;
@@ -415,9 +417,16 @@ __global__ __launch_bounds__(BLOCK) void k_scan(BuildArgs A) {
         const unsigned long long ready = __ballot(flag != 0);
         const int first = incl ? __builtin_ctzll(incl) : WAVE;   // nearest inclusive prefix
         const unsigned long long need = first < WAVE ? ((2ull << first) - 1ull) : ~0ull;
-        if ((ready & need) != need) {   // some chunk in between has not published yet
-          if (++spins > SCAN_SPIN_LIMIT) {
-            if (lane == 0) A.S[0].sync_timeout = 1;
+        if ((ready & need) != need || A.spin_limit < 0) {   // some chunk in between has not published yet
+          if (++spins > A.spin_limit) {
+            // give up: this build is invalid.  The later build kernels of this step see no
+            // rebuild (so nothing is scattered with a wrong prefix), and no build runs until
+            // md_clear_flags.
+            if (lane == 0) {
+              A.S[0].sync_timeout = 1;
+              *A.abort = 1;
+              *A.any = 0;
+            }
             break;
           }
           __builtin_amdgcn_s_sleep(1);

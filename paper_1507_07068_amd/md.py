@@ -246,6 +246,10 @@ class Simulation:
                                        int(self.lib.md_workspace_bytes(self.handle)), self.stream),
             "md_workspace_bind")
 
+    def bind(self):
+        """Bind the workspace again (clears it: lists and forces must be rebuilt)."""
+        self._bind()
+
     def load(self, xs: Sequence[np.ndarray], vs: Sequence[np.ndarray]):
         """Copy positions / velocities (and fixed flags, ids, carbons) of every replica in."""
         torch = self.torch

@@ -106,3 +106,15 @@ def test_product_path_has_no_oracle_dependency():
             if fn.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
                 txt = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in txt and "orc_" not in txt, fn
+
+
+def test_library_exports_nothing_but_the_boundary(lib):
+    """Internal helpers stay hidden: the defined dynamic text symbols are the declared ones."""
+    import shutil
+    import subprocess
+    if not shutil.which("nm"):
+        pytest.skip("nm not available")
+    out = subprocess.run(["nm", "-D", "--defined-only", md.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    text = sorted(l.split()[-1] for l in out.splitlines() if len(l.split()) == 3 and l.split()[1] == "T")
+    assert text == sorted(declared_functions())

@@ -557,3 +557,69 @@ def test_graph_replay_equals_eager():
     for k in range(3):
         assert np.array_equal(oa[k], rows[k][0]), k
     assert a.md_check()["nbuilds"] == b.md_check()["nbuilds"]
+
+
+# ------------------------------------------------------------------------------------------
+# The indenter term of the rebuild rule (Section 2.6 with Task 2)
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("nrep,energy_every", [(1, 1), (1, 10), (6, 1), (6, 10)])
+def test_rebuild_schedule_indenter_only(nrep, energy_every):
+    """Every Cr atom fixed and the indenter moving 0.004 A per step: only the indenter term of
+    the half-skin rule fires (every 38 steps).  Rebuild schedule and forces match the oracle
+    for one replica (the skin decision taken inside the binning launch) and for six (the
+    decision launch, one wavefront per replica), with every step observed or every tenth
+    (then the force pass drifts the atoms of the unobserved steps)."""
+    import torch
+
+    import tests.test_oracle as T
+    nsteps = 120
+    reps = [T.indenter_only_film(seed=19 + r, nx=6 + r % 3) for r in range(nrep)]
+    print(f"[case] indenter-only nrep={nrep} energy_every={energy_every} sizes {[s.n for s in reps]}",
+          flush=True)
+    sim = md.Simulation(reps, precision="fp64", xcap=160)
+    sim.initial_forces()
+    nobs = nsteps // energy_every
+    obs = torch.zeros((nobs, nrep, md.MD_NOBS), dtype=torch.float64, device="cuda")
+    sim.md_run(nsteps, energy_every=energy_every, obs=obs)
+    flags = sim.md_check()
+    assert not (flags["overflow"] or flags["xoverflow"] or flags["nonfinite"] or flags["sync_timeout"]), flags
+    o = obs.cpu().numpy()
+    want = T.expected_indenter_builds(nsteps, reps[0].v_ind, reps[0].dt, 0.5 * reps[0].skin)
+    steps = np.arange(1, nobs + 1) * energy_every
+    states = sim.state()
+    for r, s in enumerate(reps):
+        ref = O.md_run(s, nsteps)
+        assert np.array_equal(ref["obs"][:, 14], want)
+        assert np.array_equal(o[:, r, 14], want[steps]), (r, o[:, r, 14], want[steps])
+        assert np.all(o[:, r, 13] == ref["obs"][steps, 13])
+        assert_forces(states[r]["f"], ref["f"], FP64_TOL)
+        assert np.abs(o[:, r, 10:13] - ref["obs"][steps, 10:13]).max() < 1e-10
+    assert flags["nbuilds"] == nrep * int(want[-1])
+
+
+def test_scan_give_up_is_flagged_and_recovers(monkeypatch):
+    """A list build whose cell-count scan gives up its bounded wait (forced from the host:
+    MD_SCAN_SPIN_LIMIT=-1 makes every chunk after the first give up at once) is flagged, does
+    nothing further, and no build runs until md_clear_flags; then a forced build gives the
+    oracle's lists and forces."""
+    s = I.small_film(nx=30, ny=30, nz=8, radius=8.0, gap=0.5, seed=51, noise=0.03)
+    monkeypatch.setenv("MD_SCAN_SPIN_LIMIT", "-1")
+    sim = sim_of(s)
+    sim.md_build_neighbors(force=True)
+    st = sim.md_check()
+    assert st["sync_timeout"] == 1 and st["nbuilds"] == 1, st
+    sim.md_build_neighbors(force=True)            # refused while the give-up stands
+    monkeypatch.delenv("MD_SCAN_SPIN_LIMIT")
+    sim.md_build_neighbors(force=True)
+    st = sim.md_check()
+    assert st["sync_timeout"] == 1 and st["nbuilds"] == 1, st
+    sim.md_clear_flags()
+    assert sim.md_check()["sync_timeout"] == 0
+    sim.md_build_neighbors(force=True)
+    sim.md_eam_forces(md.MD_F_DENSITY | md.MD_F_FORCE | md.MD_F_MORSE)
+    st = sim.md_check()
+    assert st["sync_timeout"] == 0 and st["nbuilds"] == 2 and st["overflow"] == 0, st
+    check_lists(sim, s)
+    check_lists(sim, s, cross=True)
+    ref = O.evaluate(s, O.wrap(s))
+    assert_forces(sim.state()[0]["f"], ref["f"], FP64_TOL)
