@@ -69,6 +69,10 @@ def lib():
         L.orc_neighbors.restype = i64
         L.orc_cross_neighbors.argtypes = [P, d, i64, P, i64, P, d, i64, P, i64, P, P]
         L.orc_cross_neighbors.restype = i64
+        L.orc_neighbors_cells.argtypes = [P, d, i64, P, i64, P, P]
+        L.orc_neighbors_cells.restype = i64
+        L.orc_cross_neighbors_cells.argtypes = [P, d, i64, P, i64, P, d, i64, P, P]
+        L.orc_cross_neighbors_cells.restype = i64
         L.orc_density.argtypes = [P, P, i64, P, P, P, i64, P, P]
         L.orc_eam_forces.argtypes = [P, P, i64, P, P, P, i64, P, P, P, P]
         L.orc_morse_forces.argtypes = [P, P, i64, P, i64, P, d, P, P, i64, P, P]
@@ -157,6 +161,34 @@ def cross_neighbors(s, r: float, x=None, ind_z: float = 0.0, rows=None, cap: int
     return cnt[:m], idx[:m]
 
 
+def neighbors_cells(s, r: float, x=None, cap: int = 128):
+    """The sets of `neighbors` for every atom, found through a cell grid (large systems)."""
+    x = _f64(s.x if x is None else x)
+    n = x.shape[0]
+    cnt = np.zeros(max(n, 1), np.int32)
+    idx = np.full((max(n, 1), cap), -1, np.int32)
+    b = box_of(s)
+    mx = lib().orc_neighbors_cells(C.byref(b), float(r), n, _p(x), cap, _p(cnt), _p(idx))
+    if mx > cap:
+        raise ValueError(f"neighbour set of {mx} exceeds cap {cap}")
+    return cnt[:n], idx[:n]
+
+
+def cross_neighbors_cells(s, r: float, x=None, ind_z: float = 0.0, cap: int = 128):
+    """The sets of `cross_neighbors` for every atom, found through a cell grid of the carbons."""
+    x = _f64(s.x if x is None else x)
+    xc = _f64(s.xc).reshape(-1, 3)
+    n = x.shape[0]
+    cnt = np.zeros(max(n, 1), np.int32)
+    idx = np.full((max(n, 1), cap), -1, np.int32)
+    b = box_of(s)
+    mx = lib().orc_cross_neighbors_cells(C.byref(b), float(r), n, _p(x), xc.shape[0], _p(xc),
+                                         float(ind_z), cap, _p(cnt), _p(idx))
+    if mx > cap:
+        raise ValueError(f"cross set of {mx} exceeds cap {cap}")
+    return cnt[:n], idx[:n]
+
+
 def neighbor_sets(cnt, idx):
     return [idx[t, :cnt[t]].tolist() for t in range(cnt.shape[0])]
 
@@ -222,7 +254,9 @@ def sample_forces(s, sample, x=None, ind_z: float = 0.0):
     return f[:ns], rho[:ns], dF[:ns], fm[:ns]
 
 
-def params_of(s, use_lists: bool = False, cap: int = 96) -> _Params:
+def params_of(s, use_lists=False, cap: int = 96) -> _Params:
+    """use_lists: False (all pairs), True (Verlet lists by brute force) or "cells" (the same
+    lists through a cell grid)."""
     P = _Params()
     P.box = box_of(s)
     P.eam = make_eam(s.eam)
@@ -231,7 +265,7 @@ def params_of(s, use_lists: bool = False, cap: int = 96) -> _Params:
     P.dt = float(s.dt)
     P.v_ind = float(s.v_ind)
     P.skin = float(s.skin)
-    P.use_lists = int(bool(use_lists))
+    P.use_lists = 2 if use_lists == "cells" else int(bool(use_lists))
     P.cap = int(cap)
     return P
 
@@ -253,8 +287,8 @@ def evaluate(s, x=None, ind_z: float = 0.0):
     return dict(f=f[:n], rho=rho[:n], dF=dF[:n], fm=fm[:n], obs=obs)
 
 
-def md_run(s, nsteps: int, use_lists: bool = False, cap: int = 96, ind_z: float = 0.0):
-    """Velocity-Verlet trajectory (Tasks 1-5).  Returns dict with the final x, v, f,
+def md_run(s, nsteps: int, use_lists=False, cap: int = 96, ind_z: float = 0.0):
+    """Velocity-Verlet trajectory (Tasks 1-5); use_lists as in params_of.  Returns dict with the final x, v, f,
     indenter displacement and the (nsteps+1, N_OBS) observables table."""
     x = _f64(s.x).copy()
     v = _f64(s.v).copy()

@@ -174,6 +174,179 @@ int64_t orc_cross_neighbors(const orc_box *b, double r, int64_t n, const double 
 }
 
 /* ---------------------------------------------------------------------------------- */
+/* Neighbour sets from a cell grid (the cell-linked list of Section 2.6)                 */
+/* ---------------------------------------------------------------------------------- */
+
+/*
+ * The same sets as orc_neighbors / orc_cross_neighbors (same predicate, ascending index),
+ * found by binning the candidates into cells of edge >= r so that only the 27 cells around
+ * an atom's own cell need testing: along each axis any pair closer than r lies in the same
+ * or an adjacent cell (across the face on periodic axes).  A periodic axis with fewer than
+ * three cells has every cell visited once.  For large systems only (the CPU baseline);
+ * the parity tests use the brute-force sets.
+ */
+typedef struct {
+    double lo[3], edge[3];
+    int64_t nc[3];
+    int64_t *start;    /* [ncell + 1] first entry of each cell in `item` */
+    int64_t *item;     /* [m] point indices by cell, ascending within a cell */
+} orc_grid;
+
+/* Cell coordinate of position coordinate v along axis a (folded into the box on periodic
+ * axes, clamped into the grid on open ones). */
+static int64_t grid_coord(const orc_box *b, const orc_grid *g, int a, double v)
+{
+    if (b->periodic[a]) v = v - b->len[a] * floor((v - b->lo[a]) / b->len[a]);
+    double t = floor((v - g->lo[a]) / g->edge[a]);
+    if (!(t >= 0.0)) t = 0.0;
+    if (t > (double)(g->nc[a] - 1)) t = (double)(g->nc[a] - 1);
+    return (int64_t)t;
+}
+
+/* Grid of cells of edge >= r over the box (periodic axes) or the points' extent (open axes),
+ * holding the m points p (stride 3, shifted by dz along z). */
+static void grid_build(const orc_box *b, double r, int64_t m, const double *p, double dz, orc_grid *g)
+{
+    for (int a = 0; a < 3; ++a) {
+        double lo, ext;
+        if (b->periodic[a]) {
+            lo = b->lo[a];
+            ext = b->len[a];
+        } else {
+            double mn = INFINITY, mx = -INFINITY;
+            for (int64_t i = 0; i < m; ++i) {
+                double v = p[3 * i + a] + (a == 2 ? dz : 0.0);
+                if (v < mn) mn = v;
+                if (v > mx) mx = v;
+            }
+            if (!(mn <= mx)) { mn = 0.0; mx = 0.0; }
+            lo = mn;
+            ext = mx - mn;
+        }
+        int64_t n = (int64_t)floor(ext / r);
+        if (n < 1) n = 1;
+        g->lo[a] = lo;
+        g->nc[a] = n;
+        g->edge[a] = ext > 0.0 ? ext / (double)n : r;
+        if (g->edge[a] < r) g->edge[a] = r;
+    }
+    int64_t ncell = g->nc[0] * g->nc[1] * g->nc[2];
+    int64_t *cell = (int64_t *)malloc(sizeof(int64_t) * (m ? m : 1));
+    g->start = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+    g->item = (int64_t *)malloc(sizeof(int64_t) * (m ? m : 1));
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t c[3];
+        for (int a = 0; a < 3; ++a) c[a] = grid_coord(b, g, a, p[3 * i + a] + (a == 2 ? dz : 0.0));
+        cell[i] = (c[2] * g->nc[1] + c[1]) * g->nc[0] + c[0];
+        g->start[cell[i] + 1]++;
+    }
+    for (int64_t c = 0; c < ncell; ++c) g->start[c + 1] += g->start[c];
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ncell ? ncell : 1));
+    memcpy(fill, g->start, sizeof(int64_t) * (size_t)ncell);
+    for (int64_t i = 0; i < m; ++i) g->item[fill[cell[i]]++] = i;   /* ascending i per cell */
+    free(fill);
+    free(cell);
+}
+
+static void grid_free(orc_grid *g)
+{
+    free(g->start);
+    free(g->item);
+}
+
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t u = *(const int32_t *)a, v = *(const int32_t *)b;
+    return (u > v) - (u < v);
+}
+
+/* Cells to visit along one axis around cell c: c-1, c, c+1 (periodic wrap; outside an open
+ * axis skipped), or every cell once on a periodic axis with fewer than three. */
+static int stencil_axis(const orc_box *b, const orc_grid *g, int a, int64_t c, int64_t out[3])
+{
+    int k = 0;
+    if (b->periodic[a] && g->nc[a] < 3) {
+        for (int64_t t = 0; t < g->nc[a]; ++t) out[k++] = t;
+        return k;
+    }
+    for (int64_t t = c - 1; t <= c + 1; ++t) {
+        int64_t u = t;
+        if (b->periodic[a]) u = (t + g->nc[a]) % g->nc[a];
+        else if (t < 0 || t >= g->nc[a]) continue;
+        out[k++] = u;
+    }
+    return k;
+}
+
+/* Row t of (cnt, idx): the points of grid g (positions p, shifted by dz along z) within r of
+ * position xi, except `self`, ascending; returns the set size (entries beyond cap dropped). */
+static int64_t grid_query(const orc_box *b, const orc_grid *g, const double *p, double dz, double r2,
+                          const double *xi, int64_t self, int64_t cap, int32_t *row)
+{
+    int64_t cx[3], cy[3], cz[3], c = 0;
+    int nx = stencil_axis(b, g, 0, grid_coord(b, g, 0, xi[0]), cx);
+    int ny = stencil_axis(b, g, 1, grid_coord(b, g, 1, xi[1]), cy);
+    int nz = stencil_axis(b, g, 2, grid_coord(b, g, 2, xi[2]), cz);
+    double s[3], pj[3];
+    for (int iz = 0; iz < nz; ++iz)
+        for (int iy = 0; iy < ny; ++iy)
+            for (int ix = 0; ix < nx; ++ix) {
+                int64_t cell = (cz[iz] * g->nc[1] + cy[iy]) * g->nc[0] + cx[ix];
+                for (int64_t e = g->start[cell]; e < g->start[cell + 1]; ++e) {
+                    int64_t j = g->item[e];
+                    if (j == self) continue;
+                    pj[0] = p[3 * j + 0];
+                    pj[1] = p[3 * j + 1];
+                    pj[2] = p[3 * j + 2] + dz;
+                    if (separation(b, xi, pj, s) < r2) {
+                        if (c < cap) row[c] = (int32_t)j;
+                        ++c;
+                    }
+                }
+            }
+    qsort(row, (size_t)(c < cap ? c : cap), sizeof(int32_t), cmp_i32);
+    return c;
+}
+
+/* orc_neighbors' sets (all atoms), from a cell grid.  cnt[i] is the full set size; a set
+ * larger than cap keeps cap of its entries, not necessarily the smallest (callers treat any
+ * count above cap as an error, as with orc_neighbors). */
+int64_t orc_neighbors_cells(const orc_box *b, double r, int64_t n, const double *x, int64_t cap,
+                            int32_t *cnt, int32_t *idx)
+{
+    orc_grid g;
+    grid_build(b, r, n, x, 0.0, &g);
+    const double r2 = r * r;
+    int64_t maxc = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(max : maxc)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c = grid_query(b, &g, x, 0.0, r2, x + 3 * i, i, cap, idx + i * cap);
+        cnt[i] = (int32_t)c;
+        if (c > maxc) maxc = c;
+    }
+    grid_free(&g);
+    return maxc;
+}
+
+/* orc_cross_neighbors' sets (all atoms), from a cell grid over the carbons. */
+int64_t orc_cross_neighbors_cells(const orc_box *b, double r, int64_t n, const double *x, int64_t nc,
+                                  const double *xc, double ind_z, int64_t cap, int32_t *cnt, int32_t *idx)
+{
+    orc_grid g;
+    grid_build(b, r, nc, xc, ind_z, &g);
+    const double r2 = r * r;
+    int64_t maxc = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(max : maxc)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c = nc ? grid_query(b, &g, xc, ind_z, r2, x + 3 * i, -1, cap, idx + i * cap) : 0;
+        cnt[i] = (int32_t)c;
+        if (c > maxc) maxc = c;
+    }
+    grid_free(&g);
+    return maxc;
+}
+
+/* ---------------------------------------------------------------------------------- */
 /* Potential functions                                                                  */
 /* ---------------------------------------------------------------------------------- */
 
@@ -439,7 +612,8 @@ typedef struct {
     double dt;       /* fs */
     double v_ind;    /* indenter velocity along z, Angstrom/fs */
     double skin;     /* Angstrom */
-    int32_t use_lists;   /* 1: forces over Verlet lists built by brute force; 0: all pairs */
+    int32_t use_lists;   /* 0: all pairs; 1: forces over Verlet lists built by brute force;
+                            2: the same lists built from a cell grid (large systems) */
     int32_t cap;         /* list capacity per atom when use_lists */
 } orc_params;
 
@@ -474,7 +648,14 @@ static void build_lists(const orc_params *P, orc_state *S)
     memcpy(S->x_ref, S->x, (size_t)S->n * 3 * sizeof(double));
     S->ind_z_ref = S->ind_z;
     S->nbuilds++;
-    if (P->use_lists) {
+    if (P->use_lists == 2) {
+        int64_t m1 = orc_neighbors_cells(&P->box, P->eam.c + P->skin, S->n, S->x, P->cap, S->nlcnt,
+                                         S->nl);
+        int64_t m2 = orc_cross_neighbors_cells(&P->box, P->morse.rc + P->skin, S->n, S->x, S->nc,
+                                               S->xc, S->ind_z, P->cap, S->xlcnt, S->xl);
+        int64_t mx = m1 > m2 ? m1 : m2;
+        if (mx > P->cap && mx > S->overflow) S->overflow = mx;
+    } else if (P->use_lists) {
         int64_t m1 = orc_neighbors(&P->box, P->eam.c + P->skin, S->n, S->x, 0, NULL, P->cap,
                                    S->nlcnt, S->nl);
         int64_t m2 = orc_cross_neighbors(&P->box, P->morse.rc + P->skin, S->n, S->x, S->nc,

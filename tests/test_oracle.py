@@ -475,3 +475,40 @@ def test_rebuild_rule_indenter_term():
     ref = O.md_run(s, 200, use_lists=False)
     assert np.array_equal(out["f"], ref["f"]) and np.array_equal(out["obs"][:, :14], ref["obs"][:, :14])
     assert np.abs(out["obs"][-1, 10:13]).max() > 1e-3   # the indenter is in contact by then
+
+
+# --------------------------------------------------------------------------------------
+# The cell-grid neighbour build (large systems only) gives the brute-force sets exactly
+# --------------------------------------------------------------------------------------
+@pytest.mark.parametrize("n,box,per", [(1, 10.0, (1, 1, 1)), (300, 12.0, (1, 1, 1)), (257, 15.0, (1, 1, 0)),
+                                       (64, 30.0, (0, 0, 0)), (500, 9.0, (1, 1, 1)), (1200, 20.0, (0, 1, 0))])
+def test_cell_grid_sets_equal_brute_force(n, box, per):
+    """Random gases (atoms up to 10% outside the box on periodic axes, periodic boxes of
+    fewer than three cells, open axes)."""
+    s = I.random_gas(n, box, 900 + n, periodic=per)
+    for x in (s.x, O.wrap(s)):
+        a = O.neighbors(s, 4.2, x=x, cap=512)
+        b = O.neighbors_cells(s, 4.2, x=x, cap=512)
+        assert np.array_equal(a[0], b[0])
+        for i in range(n):
+            assert np.array_equal(a[1][i, :a[0][i]], b[1][i, :b[0][i]]), i
+
+
+@pytest.mark.parametrize("ind_z", [0.0, -2.3])
+def test_cell_grid_sets_equal_brute_force_film(ind_z):
+    s = I.small_film(nx=9, ny=7, nz=5, radius=7.0, gap=-1.0, seed=23, noise=0.05)
+    x = O.wrap(s)
+    a, b = O.neighbors(s, s.r_list, x=x), O.neighbors_cells(s, s.r_list, x=x)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    a = O.cross_neighbors(s, s.r_list_cross, x=x, ind_z=ind_z, cap=256)
+    b = O.cross_neighbors_cells(s, s.r_list_cross, x=x, ind_z=ind_z, cap=256)
+    assert a[0].sum() > 0
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_cell_grid_trajectory_equals_brute_force_lists():
+    s = I.small_film(nx=7, ny=7, nz=5, radius=6.0, gap=0.2, seed=29, noise=0.03)
+    a = O.md_run(s, 40, use_lists=True, cap=64)
+    b = O.md_run(s, 40, use_lists="cells", cap=64)
+    for k in ("x", "v", "f", "obs"):
+        assert np.array_equal(a[k], b[k]), k
