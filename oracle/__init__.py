@@ -46,10 +46,18 @@ class _Morse(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("D", "alpha", "r0", "rc")]
 
 
+PAPER_KEYS = ("Fo", "n", "rho_e", "alpha", "P_e", "fe", "re", "beta", "a0", "a1", "a2", "a3", "d", "rc")
+
+
+class _Paper(C.Structure):
+    _fields_ = [(k, C.c_double) for k in PAPER_KEYS]
+
+
 class _Params(C.Structure):
     _fields_ = [("box", _Box), ("eam", _Eam), ("morse", _Morse), ("mass", C.c_double),
                 ("dt", C.c_double), ("v_ind", C.c_double), ("skin", C.c_double),
-                ("use_lists", C.c_int32), ("cap", C.c_int32)]
+                ("use_lists", C.c_int32), ("cap", C.c_int32), ("potential", C.c_int32),
+                ("pad", C.c_int32), ("paper", _Paper)]
 
 
 _lib = None
@@ -79,9 +87,13 @@ def lib():
         L.orc_sample_forces.argtypes = [P, P, P, i64, P, i64, P, d, i64, P, P, P, P, P]
         L.orc_md_run.argtypes = [P, i64, P, P, P, P, i64, P, P, i64, P]
         L.orc_md_run.restype = i64
-        L.orc_evaluate.argtypes = [P, i64, P, P, P, P, i64, P, d, P, P]
+        L.orc_evaluate.argtypes = [P, i64, P, P, P, P, i64, P, d, P, P, P, P]
+        L.orc_paper_values.argtypes = [P, d, d, d, P]
+        L.orc_density_paper.argtypes = [P, P, i64, P, P, P, i64, P, P, P, P]
+        L.orc_eam_forces_paper.argtypes = [P, P, i64, P, P, P, i64, P, P, P, P, P]
         L.orc_potential_values.argtypes = [P, P, d, P]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -99,6 +111,11 @@ def _f64(a, shape=None):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of the oracle's parallel loops."""
+    lib().orc_set_num_threads(int(n))
 
 
 def make_box(lo, length, periodic) -> _Box:
@@ -267,12 +284,27 @@ def params_of(s, use_lists=False, cap: int = 96) -> _Params:
     P.skin = float(s.skin)
     P.use_lists = 2 if use_lists == "cells" else int(bool(use_lists))
     P.cap = int(cap)
+    P.potential = 1 if getattr(s, "potential", "fs") == "paper" else 0
+    P.paper = make_paper(getattr(s, "paper", None) or {k: 0.0 for k in PAPER_KEYS})
     return P
+
+
+def make_paper(p: dict) -> _Paper:
+    return _Paper(**{k: float(p[k]) for k in PAPER_KEYS})
+
+
+def paper_values(s, r: float, rho: float = 1.0, P: float = 1.0) -> dict:
+    """f, f', Phi, Phi' at r, F, F' at rho and M, M' at P of the paper's form."""
+    out = np.zeros(8)
+    pp = make_paper(s.paper)
+    lib().orc_paper_values(C.byref(pp), float(r), float(rho), float(P), _p(out))
+    return dict(f=out[0], df=out[1], phi=out[2], dphi=out[3], F=out[4], dF=out[5], M=out[6], dM=out[7])
 
 
 def evaluate(s, x=None, ind_z: float = 0.0):
     """Forces (EAM + Morse), rho, F'(rho), Morse force and the observables vector of one
-    configuration, all pairs.  obs[e_kin], obs[ind_z], obs[nbuilds] are not filled."""
+    configuration, all pairs (with the paper's form also P and M'(P); obs[e_embed] then
+    holds sum F(rho) + M(P)).  obs[e_kin], obs[ind_z], obs[nbuilds] are not filled."""
     x = _f64(s.x if x is None else x)
     n = x.shape[0]
     xc = _f64(s.xc).reshape(-1, 3)
@@ -281,10 +313,12 @@ def evaluate(s, x=None, ind_z: float = 0.0):
     dF = np.zeros(max(n, 1))
     fm = np.zeros((max(n, 1), 3))
     obs = np.zeros(N_OBS)
+    Pd = np.zeros(max(n, 1))
+    dM = np.zeros(max(n, 1))
     P = params_of(s)
     lib().orc_evaluate(C.byref(P), n, _p(x), _p(f), _p(rho), _p(dF), xc.shape[0], _p(xc),
-                       float(ind_z), _p(fm), _p(obs))
-    return dict(f=f[:n], rho=rho[:n], dF=dF[:n], fm=fm[:n], obs=obs)
+                       float(ind_z), _p(fm), _p(obs), _p(Pd), _p(dM))
+    return dict(f=f[:n], rho=rho[:n], dF=dF[:n], fm=fm[:n], obs=obs, P=Pd[:n], dM=dM[:n])
 
 
 def md_run(s, nsteps: int, use_lists=False, cap: int = 96, ind_z: float = 0.0):

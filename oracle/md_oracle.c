@@ -21,7 +21,10 @@
  * Loops over atoms are owner-computes (each iteration writes only its own atom, as in
  * Section 3.3.1) and are split over OpenMP threads.
  *
- * Synthetic potential (the paper does not print its parameters):
+ * Two potentials.  The paper's own EAM form (Appendix, Eqs. A1-A4: logarithmic embedding
+ * F(rho), the M(P) term with P_i = sum_j f^2(r_ij), power-law density f, Pasianot pair Phi),
+ * evaluated with synthetic parameter values because the paper prints none, and:
+ * Synthetic potential of the benchmark workloads (the paper does not print its parameters):
  *   phi(r) = (r-c)^2 (c0 + c1 r + c2 r^2) for r < c        pair potential
  *   f(r)   = (r-d)^2                      for r < d        density function
  *   F(rho) = -A sqrt(rho), F'(0) taken as 0               embedding function
@@ -51,6 +54,16 @@ typedef struct {
     double D, alpha, r0, rc;
 } orc_morse;
 
+/* The paper's EAM form (Appendix):
+ *   F(rho) = -Fo [1 - n ln(rho/rho_e)] (rho/rho_e)^n          (A3; ln of a power written out)
+ *   M(P)   = alpha (P/P_e - 1)^2 exp(-(P/P_e - 1)^2)            (A3)
+ *   f(r)   = fe (re/r)^beta for r < rc, else 0                   (A2; rc the cutoff r*)
+ *   Phi(r) = (x-d)^2 (a3 x^3 + a2 x^2 + a1 x + a0), x = r/re < d  (A4)
+ *   rho_i = sum_j f(r_ij), P_i = sum_j f(r_ij)^2                (A2) */
+typedef struct {
+    double Fo, n, rho_e, alpha, P_e, fe, re, beta, a0, a1, a2, a3, d, rc;
+} orc_paper;
+
 /* Conversion factors between eV, u, Angstrom and fs (CODATA 2018 values of e and u). */
 static double orc_acc_factor(void)
 {
@@ -64,6 +77,15 @@ int orc_num_threads(void)
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }
 
@@ -407,6 +429,79 @@ void orc_potential_values(const orc_eam *p, const orc_morse *m, double r, double
     out[7] = r < m->rc ? morse_dphi(m, r) : 0.0;
 }
 
+/* The paper's form, each function the plain definition (derivatives by the product rule,
+ * not the paper's simplified A6-A8, which the tests use to check these). */
+static double paper_f(const orc_paper *p, double r)
+{
+    return r < p->rc ? p->fe * pow(p->re / r, p->beta) : 0.0;
+}
+
+static double paper_df(const orc_paper *p, double r)
+{
+    /* d/dr fe (re/r)^beta = fe beta (re/r)^(beta-1) (-re/r^2) */
+    return r < p->rc ? p->fe * p->beta * pow(p->re / r, p->beta - 1.0) * (-p->re / (r * r)) : 0.0;
+}
+
+static double paper_phi(const orc_paper *p, double r)
+{
+    double x = r / p->re;
+    if (!(x < p->d)) return 0.0;
+    double u = x - p->d;
+    return u * u * (p->a3 * x * x * x + p->a2 * x * x + p->a1 * x + p->a0);
+}
+
+static double paper_dphi(const orc_paper *p, double r)
+{
+    double x = r / p->re;
+    if (!(x < p->d)) return 0.0;
+    double u = x - p->d;
+    double poly = p->a3 * x * x * x + p->a2 * x * x + p->a1 * x + p->a0;
+    double dpoly = 3.0 * p->a3 * x * x + 2.0 * p->a2 * x + p->a1;
+    return (2.0 * u * poly + u * u * dpoly) / p->re;   /* dPhi/dx dx/dr */
+}
+
+static double paper_F(const orc_paper *p, double rho)
+{
+    if (!(rho > 0.0)) return 0.0;
+    double t = rho / p->rho_e;
+    return -p->Fo * (1.0 - p->n * log(t)) * pow(t, p->n);
+}
+
+static double paper_dF(const orc_paper *p, double rho)
+{
+    if (!(rho > 0.0)) return 0.0;   /* an atom without neighbours: taken as 0 */
+    double t = rho / p->rho_e;
+    /* product rule: d/drho of [1 - n ln t] is -n/rho; of t^n it is n t^n / rho */
+    return -p->Fo * ((-p->n / rho) * pow(t, p->n) + (1.0 - p->n * log(t)) * p->n * pow(t, p->n) / rho);
+}
+
+static double paper_M(const orc_paper *p, double P)
+{
+    double u = P / p->P_e - 1.0;
+    return p->alpha * u * u * exp(-u * u);
+}
+
+static double paper_dM(const orc_paper *p, double P)
+{
+    double u = P / p->P_e - 1.0;
+    /* d/dP of u^2 exp(-u^2) = (2u exp(-u^2) + u^2 exp(-u^2) (-2u)) / P_e */
+    return p->alpha * (2.0 * u * exp(-u * u) + u * u * exp(-u * u) * (-2.0 * u)) / p->P_e;
+}
+
+/* f, f', Phi, Phi', F, F', M, M' of the paper's form at one argument (r for the pair
+ * functions, rho for F, P for M), for the tests. */
+void orc_paper_values(const orc_paper *p, double r, double rho, double P, double out[8])
+{
+    out[0] = paper_f(p, r);
+    out[1] = paper_df(p, r);
+    out[2] = paper_phi(p, r);
+    out[3] = paper_dphi(p, r);
+    out[4] = paper_F(p, rho);
+    out[5] = paper_dF(p, rho);
+    out[6] = paper_M(p, P);
+    out[7] = paper_dM(p, P);
+}
+
 /* ---------------------------------------------------------------------------------- */
 /* Neumaier compensated sum                                                             */
 /* ---------------------------------------------------------------------------------- */
@@ -495,6 +590,72 @@ void orc_eam_forces(const orc_box *b, const orc_eam *p, int64_t n, const double 
                     fi[a] += fij[a];
                 }
                 e += 0.5 * pair_phi(p, r);
+                w[0] += 0.5 * qij[0] * fij[0];
+                w[1] += 0.5 * qij[1] * fij[1];
+                w[2] += 0.5 * qij[2] * fij[2];
+                w[3] += 0.5 * qij[0] * fij[1];
+                w[4] += 0.5 * qij[0] * fij[2];
+                w[5] += 0.5 * qij[1] * fij[2];
+            }
+        });
+        for (int a = 0; a < 3; ++a) f[3 * i + a] = fi[a];
+        if (epair) epair[i] = e;
+        if (vir)
+            for (int a = 0; a < 6; ++a) vir[6 * i + a] = w[a];
+    }
+}
+
+/* First pass with the paper's form: rho_i = sum_j f(r_ij), P_i = sum_j f(r_ij)^2 and the two
+ * derivatives F'(rho_i), M'(P_i) (the paper's position + two-derivative array, Section 3.1). */
+void orc_density_paper(const orc_box *b, const orc_paper *p, int64_t n, const double *x,
+                       const int32_t *nlcnt, const int32_t *nl, int64_t nlcap,
+                       double *rho, double *P, double *dF, double *dM)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double acc = 0.0, accp = 0.0, s[3];
+        FOR_CANDIDATES(i, j, {
+            double r = sqrt(separation(b, x + 3 * i, x + 3 * j, s));
+            if (r < p->rc) {
+                double fr = paper_f(p, r);
+                acc += fr;
+                accp += fr * fr;
+            }
+        });
+        rho[i] = acc;
+        P[i] = accp;
+        dF[i] = paper_dF(p, acc);
+        dM[i] = paper_dM(p, accp);
+    }
+}
+
+/*
+ * Second pass with the paper's form: Eq. (1) with V = Phi and the M(P) term added the same
+ * way (P_i and P_j both depend on r_ij through f^2):
+ *   F_i = - sum_j [ (F'(rho_i) + F'(rho_j)) f'(r) + (M'(P_i) + M'(P_j)) 2 f(r) f'(r) + Phi'(r) ]
+ *           (q_i - q_j) / r
+ * Per-atom half pair energy and half virial as in orc_eam_forces.
+ */
+void orc_eam_forces_paper(const orc_box *b, const orc_paper *p, int64_t n, const double *x,
+                          const int32_t *nlcnt, const int32_t *nl, int64_t nlcap,
+                          const double *dF, const double *dM, double *f, double *epair, double *vir)
+{
+    const double rmax = p->rc > p->d * p->re ? p->rc : p->d * p->re;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double fi[3] = {0.0, 0.0, 0.0}, e = 0.0, w[6] = {0, 0, 0, 0, 0, 0}, s[3];
+        FOR_CANDIDATES(i, j, {
+            double r = sqrt(separation(b, x + 3 * i, x + 3 * j, s));
+            if (r < rmax) {
+                double fr = paper_f(p, r), dfr = paper_df(p, r);
+                double g = paper_dphi(p, r) + (dF[i] + dF[j]) * dfr + (dM[i] + dM[j]) * 2.0 * fr * dfr;
+                double qij[3] = {-s[0], -s[1], -s[2]};   /* q_i - q_j */
+                double fij[3];
+                for (int a = 0; a < 3; ++a) {
+                    fij[a] = -g * qij[a] / r;
+                    fi[a] += fij[a];
+                }
+                e += 0.5 * paper_phi(p, r);
                 w[0] += 0.5 * qij[0] * fij[0];
                 w[1] += 0.5 * qij[1] * fij[1];
                 w[2] += 0.5 * qij[2] * fij[2];
@@ -615,7 +776,17 @@ typedef struct {
     int32_t use_lists;   /* 0: all pairs; 1: forces over Verlet lists built by brute force;
                             2: the same lists built from a cell grid (large systems) */
     int32_t cap;         /* list capacity per atom when use_lists */
+    int32_t potential;   /* 0: the synthetic potential `eam`; 1: the paper's form `paper` */
+    int32_t pad;
+    orc_paper paper;
 } orc_params;
+
+/* Largest cutoff of the Cr-Cr interaction (the Verlet list holds pairs within it + skin). */
+static double cr_cutoff(const orc_params *P)
+{
+    if (P->potential == 1) return P->paper.rc > P->paper.d * P->paper.re ? P->paper.rc : P->paper.d * P->paper.re;
+    return P->eam.c;
+}
 
 /* Energies and observables, in this order. */
 enum {
@@ -639,6 +810,7 @@ typedef struct {
     int64_t overflow;        /* largest list count seen above cap (0 if none) */
     /* scratch */
     double *rho, *dF, *epair, *vir, *fm, *em;
+    double *Pd, *dM;         /* P_i and M'(P_i) (paper's form) */
 } orc_state;
 
 /* Task 1: wrap periodic coordinates, record reference positions, rebuild the lists. */
@@ -649,14 +821,14 @@ static void build_lists(const orc_params *P, orc_state *S)
     S->ind_z_ref = S->ind_z;
     S->nbuilds++;
     if (P->use_lists == 2) {
-        int64_t m1 = orc_neighbors_cells(&P->box, P->eam.c + P->skin, S->n, S->x, P->cap, S->nlcnt,
+        int64_t m1 = orc_neighbors_cells(&P->box, cr_cutoff(P) + P->skin, S->n, S->x, P->cap, S->nlcnt,
                                          S->nl);
         int64_t m2 = orc_cross_neighbors_cells(&P->box, P->morse.rc + P->skin, S->n, S->x, S->nc,
                                                S->xc, S->ind_z, P->cap, S->xlcnt, S->xl);
         int64_t mx = m1 > m2 ? m1 : m2;
         if (mx > P->cap && mx > S->overflow) S->overflow = mx;
     } else if (P->use_lists) {
-        int64_t m1 = orc_neighbors(&P->box, P->eam.c + P->skin, S->n, S->x, 0, NULL, P->cap,
+        int64_t m1 = orc_neighbors(&P->box, cr_cutoff(P) + P->skin, S->n, S->x, 0, NULL, P->cap,
                                    S->nlcnt, S->nl);
         int64_t m2 = orc_cross_neighbors(&P->box, P->morse.rc + P->skin, S->n, S->x, S->nc,
                                          S->xc, S->ind_z, 0, NULL, P->cap, S->xlcnt, S->xl);
@@ -684,8 +856,14 @@ static void compute_forces(const orc_params *P, orc_state *S, double *obs)
 {
     const int32_t *nlc = P->use_lists ? S->nlcnt : NULL, *nl = P->use_lists ? S->nl : NULL;
     const int32_t *xlc = P->use_lists ? S->xlcnt : NULL, *xl = P->use_lists ? S->xl : NULL;
-    orc_density(&P->box, &P->eam, S->n, S->x, nlc, nl, P->cap, S->rho, S->dF);
-    orc_eam_forces(&P->box, &P->eam, S->n, S->x, nlc, nl, P->cap, S->dF, S->f, S->epair, S->vir);
+    if (P->potential == 1) {
+        orc_density_paper(&P->box, &P->paper, S->n, S->x, nlc, nl, P->cap, S->rho, S->Pd, S->dF, S->dM);
+        orc_eam_forces_paper(&P->box, &P->paper, S->n, S->x, nlc, nl, P->cap, S->dF, S->dM, S->f, S->epair,
+                             S->vir);
+    } else {
+        orc_density(&P->box, &P->eam, S->n, S->x, nlc, nl, P->cap, S->rho, S->dF);
+        orc_eam_forces(&P->box, &P->eam, S->n, S->x, nlc, nl, P->cap, S->dF, S->f, S->epair, S->vir);
+    }
     orc_morse_forces(&P->box, &P->morse, S->n, S->x, S->nc, S->xc, S->ind_z, xlc, xl, P->cap,
                      S->fm, S->em);
     orc_sum e_emb = {0, 0}, e_pair = {0, 0}, e_m = {0, 0}, w[6], fi[3];
@@ -696,7 +874,12 @@ static void compute_forces(const orc_params *P, orc_state *S, double *obs)
             S->f[3 * i + a] += S->fm[3 * i + a];
             sum_add(&fi[a], -S->fm[3 * i + a]);   /* load on the indenter */
         }
-        sum_add(&e_emb, embed_F(&P->eam, S->rho[i]));
+        if (P->potential == 1) {   /* the embedding and M(P) terms of Eq. (A1), per atom */
+            sum_add(&e_emb, paper_F(&P->paper, S->rho[i]));
+            sum_add(&e_emb, paper_M(&P->paper, S->Pd[i]));
+        } else {
+            sum_add(&e_emb, embed_F(&P->eam, S->rho[i]));
+        }
         sum_add(&e_pair, S->epair[i]);
         sum_add(&e_m, S->em[i]);
         for (int a = 0; a < 6; ++a) sum_add(&w[a], S->vir[6 * i + a]);
@@ -732,6 +915,8 @@ static void alloc_state(orc_state *S, int64_t cap, int use_lists)
     S->vir = (double *)malloc(sizeof(double) * 6 * (n ? n : 1));
     S->fm = (double *)malloc(sizeof(double) * 3 * (n ? n : 1));
     S->em = (double *)malloc(sizeof(double) * (n ? n : 1));
+    S->Pd = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
+    S->dM = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
     if (use_lists) {
         S->nlcnt = (int32_t *)malloc(sizeof(int32_t) * (n ? n : 1));
         S->nl = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1) * cap);
@@ -743,7 +928,7 @@ static void alloc_state(orc_state *S, int64_t cap, int use_lists)
 static void free_state(orc_state *S)
 {
     free(S->x_ref); free(S->rho); free(S->dF); free(S->epair); free(S->vir);
-    free(S->fm); free(S->em);
+    free(S->fm); free(S->em); free(S->Pd); free(S->dM);
     free(S->nlcnt); free(S->nl); free(S->xlcnt); free(S->xl);
 }
 
@@ -810,7 +995,8 @@ int64_t orc_md_run(const orc_params *P, int64_t n, double *x, double *v, double 
 
 /* Forces, per-atom density and observables of one configuration (no time stepping). */
 void orc_evaluate(const orc_params *P, int64_t n, const double *x, double *f, double *rho,
-                  double *dF, int64_t nc, const double *xc, double ind_z, double *fm, double *obs)
+                  double *dF, int64_t nc, const double *xc, double ind_z, double *fm, double *obs,
+                  double *Pout, double *dMout)
 {
     orc_state S;
     memset(&S, 0, sizeof S);
@@ -822,5 +1008,7 @@ void orc_evaluate(const orc_params *P, int64_t n, const double *x, double *f, do
     if (rho) memcpy(rho, S.rho, sizeof(double) * n);
     if (dF) memcpy(dF, S.dF, sizeof(double) * n);
     if (fm) memcpy(fm, S.fm, sizeof(double) * 3 * n);
+    if (Pout) memcpy(Pout, S.Pd, sizeof(double) * n);
+    if (dMout) memcpy(dMout, S.dM, sizeof(double) * n);
     free_state(&S);
 }

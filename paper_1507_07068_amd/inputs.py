@@ -27,6 +27,13 @@ EV_PER_U_TO_A2_FS2 = 1.602176634e-19 / 1.66053906660e-27 * 1e-10
 # Synthetic Finnis-Sinclair-form EAM for Cr-Cr and shifted Morse for Cr-C.
 EAM = dict(A=1.45, c=3.9, d=3.6, c0=29.14, c1=-23.37, c2=4.77)
 MORSE = dict(D=0.8, alpha=1.7, r0=2.0, rc=5.0)
+# The paper's own EAM form (Appendix, Eqs. A1-A4) with synthetic parameter values (the paper
+# prints none): r_e, r* = 3 r_e and the pair cutoff x < d are the paper's; rho_e and P_e are
+# rho and P of the perfect BCC lattice (a = 2.885 A, f cut at r*), so that F' and M' vanish
+# there; the Pasianot coefficients give a repulsive core, a shallow well and zero pair pressure
+# on that lattice.  Energies in eV, lengths in Angstrom.
+PAPER_EAM = dict(Fo=3.0, n=0.5, rho_e=21.69, alpha=0.05, P_e=29.32, fe=1.0, re=2.754, beta=6.0,
+                 a0=69.50, a1=-195.07, a2=178.68, a3=-53.50, d=1.65, rc=8.262)
 SKIN = 0.3
 DT = 1.0               # fs
 V_IND = -0.001         # indenter velocity along z (Angstrom/fs): -0.1 A per 100 steps
@@ -62,6 +69,8 @@ class System:
     eam: dict = field(default_factory=lambda: dict(EAM))
     morse: dict = field(default_factory=lambda: dict(MORSE))
     precision: str = "fp64"
+    potential: str = "fs"    # "fs": the synthetic potential `eam`; "paper": the paper's form `paper`
+    paper: dict = field(default_factory=lambda: dict(PAPER_EAM))
     meta: dict = field(default_factory=dict)
 
     @property
@@ -73,8 +82,15 @@ class System:
         return int(self.xc.shape[0])
 
     @property
+    def cutoff(self) -> float:
+        """Largest Cr-Cr cutoff of the potential."""
+        if self.potential == "paper":
+            return max(self.paper["rc"], self.paper["d"] * self.paper["re"])
+        return self.eam["c"]
+
+    @property
     def r_list(self) -> float:
-        return self.eam["c"] + self.skin
+        return self.cutoff + self.skin
 
     @property
     def r_list_cross(self) -> float:
@@ -85,7 +101,7 @@ class System:
             self, x=self.x.copy(), v=self.v.copy(), fixed=self.fixed.copy(),
             ids=self.ids.copy(), xc=self.xc.copy(), box_lo=self.box_lo.copy(),
             box_len=self.box_len.copy(), periodic=self.periodic.copy(),
-            eam=dict(self.eam), morse=dict(self.morse), meta=dict(self.meta))
+            eam=dict(self.eam), morse=dict(self.morse), paper=dict(self.paper), meta=dict(self.meta))
 
 
 # ----------------------------------------------------------------------------------------

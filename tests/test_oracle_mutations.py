@@ -8,6 +8,7 @@ import pytest
 
 import oracle as O
 import tests.test_oracle as T
+import tests.test_oracle_paper as TP
 
 SRC = os.path.join(os.path.dirname(O.__file__), "md_oracle.c")
 
@@ -38,6 +39,21 @@ MUTATIONS = [
      "if (0 && fabs(S->ind_z - S->ind_z_ref) > lim) return 1;", T.test_rebuild_rule_indenter_term),
     ("indenter reference not reset at a build", "S->ind_z_ref = S->ind_z;\n    S->nbuilds++;",
      "S->nbuilds++;", T.test_rebuild_rule_indenter_term),
+    # the paper's EAM form
+    ("paper form: M'(P_j) term dropped", "(dM[i] + dM[j]) * 2.0 * fr * dfr", "(dM[i] + dM[i]) * 2.0 * fr * dfr",
+     TP.test_force_is_minus_energy_gradient),
+    ("paper form: F'(rho_j) term dropped", "(dF[i] + dF[j]) * dfr", "(dF[i] + dF[i]) * dfr",
+     TP.test_force_is_minus_energy_gradient),
+    ("paper form: f' with the wrong power", "pow(p->re / r, p->beta - 1.0)", "pow(p->re / r, p->beta)",
+     lambda: TP.test_T1_embedding_term(2.9, 18.0)),
+    ("paper form: P sums f, not f^2", "accp += fr * fr;", "accp += fr;",
+     lambda: TP.test_perfect_lattice_closed_form(2.80)),
+    ("paper form: sign of M' cubic term", "exp(-u * u) * (-2.0 * u)", "exp(-u * u) * (2.0 * u)",
+     lambda: TP.test_T2_cauchy_term(2.5, 40.0)),
+    ("paper form: Phi' without dx/dr", "u * u * dpoly) / p->re;", "u * u * dpoly);",
+     lambda: TP.test_T3_pair_term(3.1)),
+    ("paper form: M(P) left out of the energy", "            sum_add(&e_emb, paper_M(&P->paper, S->Pd[i]));\n",
+     "", lambda: TP.test_perfect_lattice_closed_form(2.80)),
 ]
 
 
