@@ -1,16 +1,28 @@
 #!/usr/bin/env python3
 """Throughput of the whole MD step (Tasks 1-5: kick-drift, skin test + list rebuild when
-due, EAM density, EAM + Morse forces with the fused final kick, energies every 10 steps)
-on one MI355X, in atom-steps/s.
+due, EAM density with the Cr-C Morse pass, EAM + Morse forces with the fused final kick,
+energies every 10 steps) on one MI355X, in Cr atom-steps/s.
 
-Default workload: the 216,000-atom Cr film (60x60x30 BCC cells) with a 2 nm carbon
-hemisphere indenter moving -0.001 A/fs, FP64, 2000 steps of 1 fs, inputs resident in HBM
-before the timed region.  Beside it (in "variants"): the same film with FP32-mixed
-forces and their error against the FP64 path, the 64-replica ensemble in FP32-mixed run
-as captured HIP graphs with an autotuned launch shape, and the NVE energy drift of the
-periodic 2,000-atom bulk.  Prints one JSON line.
+Headline (`value`): the largest single-GPU workload, the 8M-atom Cr film (200x200x100 BCC
+cells, 5 nm carbon hemisphere pre-indented 2 nm, moving -0.001 A/fs) in FP64, inputs
+resident in HBM before the timed region, K timed steps after W warm-up steps.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1] [--precision fp64]
+Beside it, in the same JSON line, whatever --steps says:
+  kernels      per-kernel times from a separate pass of K steps with events around the force,
+               density and list kernels of every step (outside the timed region), the list
+               kernel split by whether the step rebuilt (read from the device);
+  roofline     for the kernel with the most GPU time in that pass;
+  variants     the same film in FP32-mixed (force error against the FP64 path on all atoms
+               and against the oracle on sampled atoms), the 64-replica ensemble in
+               FP32-mixed as captured HIP graphs with the autotuned launch shape, NVE drift of
+               the periodic 2,000-atom bulk (mean over seeds), and the drift of E_tot + W on the
+               216k-atom film with its moving indenter (W: work of the indenter's load);
+  full_runs    each workload over its full step count (8M film 500, 216k film 2000, ensemble
+               1000), with its list-build count;
+  cpu_baseline the FP64 oracle (cell-grid lists) on the same 8M-atom film, all host threads,
+               a bounded number of steps; cpu_baseline_1thread the same on the 216k film.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4] [--precision fp64]
     python bench.py --copy-probe 512      # plain copy of 512 MiB (counter calibration)
 """
 from __future__ import annotations
@@ -27,10 +39,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "atom-steps/s EAM+Morse MD step, FP32-mixed & batched vs FP64 at ≤1e-5 force err"
 HBM_PEAK_GBS = 8000.0
-TIME_EVERY = 8   # kernel timing events on one step in TIME_EVERY (--time-every)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c1_fp64_hbm_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c4_film_8m.txt")
 SOURCES = {k: [os.path.join(ROOT, "paper_1507_07068_amd", "csrc", f) for f in v]
            for k, v in (("force", ("md_forces.hip", "md_device.hpp")),
+                        ("density", ("md_forces.hip", "md_device.hpp")),
                         ("list", ("md_rebuild.hip", "md_device.hpp")))}
 
 WORKLOADS = {
@@ -40,31 +52,49 @@ WORKLOADS = {
     "c3": (3, "ensemble_64_replicas_1.6k-36k"),
     "c4": (4, "cr_film_200x200x100_8m_indenter_r50_preindented"),
 }
+KERNEL_NAMES = {
+    "force": "k_force (EAM Eq. 1 with the Cr-C forces and the fused kicks; FP64 steps whose "
+             "velocities are not observed also drift the atoms)",
+    "density": "k_density (rho and F'(rho), with the Cr-C Morse pass in its leading blocks)",
+    "list": "k_list_tiles (Cr-Cr Verlet list build with the Cr-C lists in leading blocks), "
+            "launches of steps that rebuilt",
+}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def force_bytes_per_atom(mean_list: float, drift: bool = False) -> float:
-    """Algorithmic HBM bytes of one EAM force launch per atom: q_i = (x, y, z, F') 32,
-    list count 4, list entries 4 each, Cr-C count 4 (the few atoms with carbons in range
-    also read their 32-byte Cr-C record), fixed flag 1, velocity read + write for the fused
-    kick 48, force write 24; with the next step's drift in the same launch (FP64 steps
-    whose velocities are not observed: all but the energy steps and the last) also the new
-    position 32 and the reference position 24.  Neighbour positions are gathered from
-    cache (atoms are cell-sorted, so each one is fetched from HBM once per pass)."""
-    return 32 + 4 + 4 * mean_list + 4 + 1 + 48 + 24 + (56 if drift else 0)
+# ------------------------------------------------------------------------------------------
+# Algorithmic bytes (HBM, per atom, per launch)
+# ------------------------------------------------------------------------------------------
+def force_bytes_per_atom(mean_list: float, mixed: bool, drift: bool) -> float:
+    """One EAM force launch: the atom's own record (FP64 q = x, y, z, F' 32 B; mixed: the
+    16-byte fixed-point shadow), list count 4, list entries 4 each, Cr-C count 4, fixed flag
+    1, velocity read + write for the fused kick 48, force write (24 FP64; the FP64 force array
+    in both paths) 24; with the next step's drift in the same launch (FP64 steps whose
+    velocities are not observed) also the new position 32 and the reference position 24.
+    Neighbour records are gathered from cache (atoms are cell-sorted, so each one comes from
+    HBM about once per pass): they are not counted."""
+    own = 16 if mixed else 32
+    return own + 4 + 4 * mean_list + 4 + 1 + 48 + 24 + (56 if drift else 0)
 
 
-def list_bytes_per_atom(mean_list: float) -> float:
-    """Algorithmic HBM bytes of one Cr-Cr list-build launch per rebuilt atom: read the
-    cell-sorted state (q 32, FP32 copy 16, v 24, f 24, fixed 1, id 4) = 101; write it back
-    (q 32, reference position 24, v 24, f 24, fixed 1, id 4) plus the list count 4 and list
-    entries 4 each = 113 + 4 L.  Candidate positions come from cache (each cell row is
-    staged once per block).  The Cr-C lists that the launch's leading blocks build for the
-    atoms near the indenter are not counted (a few thousand atoms of the 216,000)."""
-    return 101 + 113 + 4 * mean_list
+def density_bytes_per_atom(mean_list: float, mixed: bool) -> float:
+    """One density launch: own record (32 FP64 / 16 shadow), list count 4, entries 4 each,
+    F'(rho) written into the record (8; mixed also its FP32 copy in the shadow, 4).  The Cr-C
+    pass of its leading blocks touches the few atoms near the indenter only (not counted)."""
+    return (16 + 4 + 4 * mean_list + 8 + 4) if mixed else (32 + 4 + 4 * mean_list + 8)
+
+
+def list_bytes_per_atom(mean_list: float, mixed: bool) -> float:
+    """One Cr-Cr list-build launch that rebuilds, per atom: read the cell-sorted state (q 32,
+    FP32 copy 16, v 24, f 24, fixed 1, id 4) = 101; write it back (q 32, reference position
+    24, v 24, f 24, fixed 1, id 4) plus the list count 4 and the entries 4 each = 113 + 4 L;
+    mixed runs also write the fixed-point shadow 16 and the build cell 8.  Candidates come
+    from cache (each staged cell row once per block); the Cr-C lists of the leading blocks
+    (a few thousand atoms near the indenter) are not counted."""
+    return 101 + 113 + 4 * mean_list + (24 if mixed else 0)
 
 
 def source_hash(kind: str) -> str:
@@ -80,12 +110,11 @@ def source_hash(kind: str) -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kind: str, n_launch_atoms: int):
-    """HBM bytes per launch of the force ("force") or list-build ("list") kernel from the
-    committed counter summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by the
-    same counter's reading for a plain copy of known size), or None when there is no
-    summary for this workload or the kernel's sources changed since the counters were
-    taken."""
+def measured_traffic(kind: str, n_atoms: int, precision: str):
+    """HBM bytes per launch of a kernel from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE per dispatch, each scaled by the same counter's reading for a plain copy of
+    known size), with the mean list length of the run the counters were taken on, or None
+    when the summary is for another workload or the kernel's sources changed since."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -95,33 +124,22 @@ def measured_traffic(kind: str, n_launch_atoms: int):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
     try:
-        if kv[kind + "_source_sha256"] != source_hash(kind) or int(kv["atoms"]) != n_launch_atoms:
+        if (kv[kind + "_source_sha256"] != source_hash(kind) or int(kv["atoms"]) != n_atoms
+                or kv["precision"] != precision):
             return None
         copy_b = float(kv["copy_bytes"])
         f_scale = copy_b / (float(kv["copy_fetch_kib"]) * 1024.0)
         w_scale = copy_b / (float(kv["copy_write_kib"]) * 1024.0)
-        return (float(kv[kind + "_fetch_kib"]) * 1024.0 * f_scale
-                + float(kv[kind + "_write_kib"]) * 1024.0 * w_scale)
+        return {"bytes": float(kv[kind + "_fetch_kib"]) * 1024.0 * f_scale
+                + float(kv[kind + "_write_kib"]) * 1024.0 * w_scale,
+                "mean_list": float(kv["mean_list"])}
     except (KeyError, ValueError, ZeroDivisionError):
         return None
 
 
-def cpu_baseline(system, steps_per_build: float) -> dict:
-    """The FP64 oracle as it stands, on a bounded sample of the same workload: one list
-    build (brute force, O(N^2)) plus about one rebuild interval of list-mode steps."""
-    import oracle as O
-    k = int(max(1, min(round(steps_per_build), 50)))
-    t0 = time.perf_counter()
-    out = O.md_run(system, k, use_lists=True, cap=64)
-    t = time.perf_counter() - t0
-    builds = int(out["obs"][-1, 14])
-    return {"value": system.n * k / t, "unit": "atom-steps/s", "cores": O.num_threads(),
-            "kind": "oracle",
-            "sample": f"{system.name}: {k} steps of the FP64 oracle from t=0 in list mode, "
-                      f"{builds} O(N^2) list build(s) included (one rebuild interval of the GPU run), "
-                      f"{t:.1f} s wall"}
-
-
+# ------------------------------------------------------------------------------------------
+# Timing helpers
+# ------------------------------------------------------------------------------------------
 class TimingEvent:
     """A HIP event for kernel timing, created with hipEventDisableSystemFence: recording it
     skips the system-scope cache write-back and invalidation that a default event does,
@@ -154,109 +172,228 @@ class TimingEvent:
             TimingEvent._hip.hipEventDestroy(self.cuda_event)
 
 
-def timed_run(systems, precision, steps, warmup, ee, tpa, events=True, time_every=TIME_EVERY):
-    """Build, warm up, then time `steps` whole steps with md_run.  Returns a dict."""
+def check_flags(flags, what):
+    if flags["overflow"] or flags["xoverflow"] or flags["nonfinite"] or flags["sync_timeout"]:
+        raise SystemExit(f"{what}: invalid run: {flags}")
+
+
+def mean_list_len(sim, systems) -> float:
+    import numpy as np
+    cnt = sim.list_counts()
+    live = np.concatenate([np.arange(o, o + s.n) for o, s in zip(sim.offsets, systems)])
+    return float(cnt[live].mean()) if live.size else 0.0
+
+
+def make_sim(systems, precision, tpa, xcap=160):
+    from paper_1507_07068_amd import md
+    return md.Simulation(systems, precision=precision, xcap=xcap, tpa=tpa)
+
+
+def free_sim(sim):
+    """Destroy the handle and drop the device arrays now (not when the name goes away)."""
+    import torch
+    torch.cuda.synchronize()
+    sim.close()
+    sim.__dict__.clear()
+    torch.cuda.empty_cache()
+
+
+def timed_run(sim, systems, steps, warmup, ee, what):
+    """Warm up, then time `steps` whole steps with md_run (no events in the timed region)."""
+    import torch
+
+    from paper_1507_07068_amd import md
+    if warmup:
+        sim.md_run(warmup)
+    flags = sim.md_check()
+    check_flags(flags, what + " (warm-up)")
+    nobs = steps // ee if ee > 0 else 0
+    obs = torch.zeros((max(nobs, 1), sim.nrep, md.MD_NOBS), dtype=torch.float64, device="cuda")
+    builds0 = flags["nbuilds"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.md_run(steps, energy_every=ee, obs=obs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    flags = sim.md_check()
+    check_flags(flags, what)
+    n_atoms = sum(s.n for s in systems)
+    return dict(rate=n_atoms * steps / wall, wall=wall, ms_per_step=wall / steps * 1e3, steps=steps,
+                builds=flags["nbuilds"] - builds0, obs=obs.cpu().numpy()[:nobs], n_atoms=n_atoms,
+                mean_list=mean_list_len(sim, systems))
+
+
+def kernel_pass(sim, systems, steps, ee, precision):
+    """`steps` more whole steps with events around the force, list and density kernels of
+    every step and the build counts recorded after every step; per-kernel times."""
     import numpy as np
     import torch
 
     from paper_1507_07068_amd import md
-
-    stream = torch.cuda.Stream()
-    with torch.cuda.stream(stream):
-        sim = md.Simulation(systems, precision=precision, xcap=160, tpa=tpa)
-        sim.initial_forces()
-        if warmup:
-            sim.md_run(warmup)
-        flags = sim.md_check()
-        if flags["overflow"] or flags["xoverflow"] or flags["sync_timeout"]:
-            raise SystemExit(f"list capacity / sync problem after warm-up: {flags}")
-        nobs = steps // ee if ee > 0 else 0
-        obs = torch.zeros((max(nobs, 1), sim.nrep, md.MD_NOBS), dtype=torch.float64, device="cuda")
-        ev = None
-        timed = []
-        if events:   # a seeded random sample of the steps (a stride could alias with the
-                     # rebuild pattern, which is nearly periodic)
-            rng = np.random.default_rng(12345)
-            timed = sorted(rng.choice(steps, size=max(1, steps // max(time_every, 1)), replace=False).tolist())
-        if events:
-            # events around the force and list kernels of the sampled steps (on every step
-            # they would add several per cent to the step time)
-            ev = [None] * (4 * steps)
-            for k in timed:
-                for u in range(4):
-                    ev[4 * k + u] = TimingEvent()
-        builds0 = flags["nbuilds"]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sim.md_run(steps, energy_every=ee, obs=obs, events=ev)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        flags = sim.md_check()
-        if flags["overflow"] or flags["xoverflow"] or flags["nonfinite"] or flags["sync_timeout"]:
-            raise SystemExit(f"invalid run: {flags}")
-        k_ms = (np.array([ev[4 * k].elapsed_time(ev[4 * k + 1]) for k in timed])
-                if events else np.zeros(1))
-        l_ms = (np.array([ev[4 * k + 2].elapsed_time(ev[4 * k + 3]) for k in timed])
-                if events else np.zeros(1))
-        cnt = sim.list_counts()
-        live = np.concatenate([np.arange(o, o + s.n) for o, s in zip(sim.offsets, systems)])
-        mean_list = float(cnt[live].mean()) if live.size else 0.0
-        o = obs.cpu().numpy()
+    L0 = mean_list_len(sim, systems)
+    ev = [TimingEvent() for _ in range(md.MD_TRACE_EVENTS * steps)]
+    builds = torch.zeros((steps, sim.nrep), dtype=torch.int32, device="cuda")
+    nobs = steps // ee if ee > 0 else 0
+    obs = torch.zeros((max(nobs, 1), sim.nrep, md.MD_NOBS), dtype=torch.float64, device="cuda")
+    b0 = sim.md_check()["nbuilds"]
+    torch.cuda.synchronize()
+    sim.md_run(steps, energy_every=ee, obs=obs, events=ev, builds=builds)
+    torch.cuda.synchronize()
+    check_flags(sim.md_check(), "kernel timing pass")
+    L1 = mean_list_len(sim, systems)
+    E = md.MD_TRACE_EVENTS
+    t = {name: np.array([ev[E * k + a].elapsed_time(ev[E * k + a + 1]) for k in range(steps)]) * 1e-3
+         for name, a in (("force", 0), ("list", 2), ("density", 4))}
+    b = builds.cpu().numpy().sum(axis=1).astype(np.int64)
+    rebuilt = np.diff(np.concatenate([[b0], b])) > 0
     n_atoms = sum(s.n for s in systems)
-    builds = flags["nbuilds"] - builds0
-    # sampled list-kernel launches: those that rebuilt are far longer than those that return
-    # at once, so they are told apart by the geometric mean of the extremes (when the two
-    # kinds differ); the sample is random, so the run's list-kernel time is its mean x steps
-    l_avg = 0.0
-    if events and builds:
-        lo, hi = max(float(l_ms.min()), 1e-6), float(l_ms.max())
-        reb = l_ms[l_ms > np.sqrt(lo * hi)] if hi > 4 * lo else l_ms
-        l_avg = float(reb.mean()) * 1e-3
-    l_total = float(l_ms.mean()) * 1e-3 * steps if events else 0.0
-    return dict(sim=sim, rate=n_atoms * steps / wall, wall=wall, ms_per_step=wall / steps * 1e3,
-                k_avg=float(k_ms.mean()) * 1e-3, l_avg=l_avg, l_total=l_total,
-                k_total=float(k_ms.mean()) * 1e-3 * steps, mean_list=mean_list,
-                builds=builds, obs=o[:nobs], n_atoms=n_atoms)
+    L = 0.5 * (L0 + L1)
+    mixed = precision == "mixed"
+    # FP64 steps whose velocities are not observed drift the atoms inside the force launch
+    drift = np.array([(not mixed) and (k + 1) < steps and not (ee > 0 and (k + 1) % ee == 0)
+                      for k in range(steps)])
+    fbytes = n_atoms * np.array([force_bytes_per_atom(L, mixed, d) for d in drift])
+    out = {"steps": steps, "mean_list": L, "rebuilt_steps": int(rebuilt.sum())}
+    out["force"] = dict(avg_us=float(t["force"].mean() * 1e6), total_ms=float(t["force"].sum() * 1e3),
+                        bytes_per_launch=float(fbytes.mean()),
+                        achieved=float(fbytes.sum() / t["force"].sum() / 1e9))
+    dbytes = n_atoms * density_bytes_per_atom(L, mixed)
+    out["density"] = dict(avg_us=float(t["density"].mean() * 1e6), total_ms=float(t["density"].sum() * 1e3),
+                          bytes_per_launch=dbytes, achieved=float(dbytes / t["density"].mean() / 1e9))
+    lst = dict(total_ms=float(t["list"].sum() * 1e3), rebuild_launches=int(rebuilt.sum()),
+               avg_us_no_rebuild=float(t["list"][~rebuilt].mean() * 1e6) if (~rebuilt).any() else None)
+    if rebuilt.any() and len(systems) == 1:
+        lb = n_atoms * list_bytes_per_atom(L, mixed)
+        lst.update(avg_us=float(t["list"][rebuilt].mean() * 1e6), bytes_per_launch=lb,
+                   achieved=float(lb / t["list"][rebuilt].mean() / 1e9))
+    out["list"] = lst
+    out["step_ms"] = float(np.mean([ev[E * k].elapsed_time(ev[E * (k + 1)]) for k in range(steps - 1)])) \
+        if steps > 1 else None
+    return out
 
 
-def force_error_vs_fp64(systems, tpa):
-    """Relative RMS difference of the FP32-mixed and FP64 GPU forces on the start state
-    (the FP64 path itself matches the oracle to 1e-10, see the parity tests)."""
+def roofline_of(kern, kind, n_atoms, precision):
+    k = kern[kind]
+    if "achieved" not in k:
+        return None
+    r = {"bound": "hbm", "achieved": k["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": k["achieved"] / HBM_PEAK_GBS, "traffic": None, "kernel": KERNEL_NAMES[kind],
+         "avg_us": k["avg_us"], "bytes_per_launch": k["bytes_per_launch"],
+         "mean_list": kern["mean_list"], "gpu_ms_total": k["total_ms"]}
+    tr = measured_traffic(kind, n_atoms, precision)
+    if tr is not None:
+        # counter bytes per launch, and the algorithmic bytes at the list length of the run the
+        # counters were taken on (the same state), for the ratio
+        alg = {"force": lambda L: force_bytes_per_atom(L, precision == "mixed", True),
+               "density": lambda L: density_bytes_per_atom(L, precision == "mixed"),
+               "list": lambda L: list_bytes_per_atom(L, precision == "mixed")}[kind]
+        r["traffic"] = tr["bytes"]
+        r["traffic_state"] = {"mean_list": tr["mean_list"], "algorithmic_bytes": n_atoms * alg(tr["mean_list"]),
+                              "ratio": tr["bytes"] / (n_atoms * alg(tr["mean_list"]))}
+    return r
+
+
+# ------------------------------------------------------------------------------------------
+# Variants
+# ------------------------------------------------------------------------------------------
+def force_errors(f, ref):
+    import numpy as np
+    diff = np.sqrt(np.sum((f - ref) ** 2, axis=1))
+    rms = np.sqrt(np.mean(np.sum(ref ** 2, axis=1)))
+    return float(np.sqrt(np.sum(diff ** 2) / np.sum(ref ** 2))), float(diff.max() / rms)
+
+
+def mixed_force_errors(system, tpa, n_sample=24, seed=11):
+    """FP32-mixed forces at the start state against the FP64 GPU path on every atom, and
+    against the FP64 oracle (one atom at a time, all-atom loops) on sampled atoms: a seeded
+    draw plus the atoms nearest the indenter tip."""
     import numpy as np
 
-    from paper_1507_07068_amd import md
+    import oracle as O
     f = {}
     for prec in ("fp64", "mixed"):
-        sim = md.Simulation(systems, precision=prec, xcap=160, tpa=tpa)
+        sim = make_sim([system], prec, tpa)
         sim.initial_forces()
-        f[prec] = np.concatenate([st["f"] for st in sim.state()])
-        sim.close()
-    d = f["mixed"] - f["fp64"]
-    return float(np.sqrt((d * d).sum() / (f["fp64"] ** 2).sum()))
+        st = sim.state()[0]
+        f[prec] = st["f"]
+        free_sim(sim)
+    rel_all, max_all = force_errors(f["mixed"], f["fp64"])
+    rng = np.random.default_rng(seed)
+    rows = set(rng.choice(system.n, size=n_sample, replace=False).tolist())
+    if system.n_c:
+        tip = system.xc[np.argmin(system.xc[:, 2])]
+        d = system.x - tip
+        rows |= set(np.argsort(np.einsum("ij,ij->i", d, d))[:8].tolist())
+    rows = np.array(sorted(rows), dtype=np.int64)
+    fo, _, _, _ = O.sample_forces(system, rows, x=O.wrap(system))
+    rel_o, max_o = force_errors(f["mixed"][rows], fo)
+    rel_o64, _ = force_errors(f["fp64"][rows], fo)
+    return {"rel_rms_vs_fp64_gpu_all_atoms": rel_all, "max_over_rms_vs_fp64_gpu": max_all,
+            "rel_rms_vs_oracle_sampled": rel_o, "max_over_rms_vs_oracle_sampled": max_o,
+            "fp64_gpu_rel_rms_vs_oracle_sampled": rel_o64, "sampled_atoms": int(rows.size)}
 
 
-def drift_per_ns(obs, n_atoms, dt_fs, ee):
-    """Least-squares slope of E_total / N over time, in eV/atom/ns (obs rows every ee steps)."""
+def drift_per_ns(e_per_atom, t_fs):
+    """Least-squares slope of an energy per atom over time, in eV/atom/ns."""
     import numpy as np
-    e = obs[:, :, 0:4].sum(-1).sum(-1) / n_atoms
-    t_ns = (np.arange(1, e.size + 1) * ee * dt_fs) * 1e-6
-    return float(np.polyfit(t_ns, e, 1)[0])
+    return float(np.polyfit(t_fs * 1e-6, e_per_atom, 1)[0])
+
+
+def nve_drift(seeds=(0, 1, 2, 3), steps=10000, ee=10):
+    """NVE drift of the periodic 2,000-atom bulk (no indenter) over `steps`, per seed."""
+    import numpy as np
+
+    from paper_1507_07068_amd import inputs as I
+    out = {}
+    for prec in ("fp64", "mixed"):
+        d = []
+        for seed in seeds:
+            s = I.bulk(10, seed=seed, noise=0.02, steps=steps, name=f"c0_seed{seed}")
+            sim = make_sim([s], prec, 1)
+            sim.initial_forces()
+            r = timed_run(sim, [s], steps, 0, ee, "NVE drift")
+            free_sim(sim)
+            e = r["obs"][:, 0, 0:4].sum(-1) / s.n
+            d.append(drift_per_ns(e, np.arange(1, e.size + 1) * ee * s.dt))
+        out[prec] = {"mean": float(np.mean(d)), "std": float(np.std(d, ddof=1)), "per_seed": d}
+    return {"steps": steps, "dt_fs": 1.0, "seeds": list(seeds),
+            "drift_ev_per_atom_per_ns": out}
+
+
+def indenter_work_drift(system, tpa):
+    """E_tot + W on a film with its moving indenter (W = sum over steps of the trapezoid
+    (F_ind,z(t) + F_ind,z(t + dt)) / 2 * dz_ind, the work of the load on the indenter): its
+    drift, next to that of E_tot alone, energies every step."""
+    import numpy as np
+    sim = make_sim([system], "fp64", tpa)
+    sim.initial_forces()
+    o0 = sim.md_energy()[0]
+    r = timed_run(sim, [system], system.steps, 0, 1, "indenter work drift")
+    free_sim(sim)
+    o = np.concatenate([o0[None], r["obs"][:, 0]], axis=0)
+    e = o[:, 0:4].sum(-1)
+    fz, z = o[:, 12], o[:, 13]
+    w = np.concatenate([[0.0], np.cumsum(0.5 * (fz[1:] + fz[:-1]) * np.diff(z))])
+    t = np.arange(o.shape[0]) * system.dt
+    return {"steps": system.steps, "workload": system.name,
+            "drift_e_tot_ev_per_atom_per_ns": drift_per_ns(e / system.n, t),
+            "drift_e_tot_plus_w_ev_per_atom_per_ns": drift_per_ns((e + w) / system.n, t),
+            "w_total_ev": float(w[-1])}
 
 
 def batched_graph_run(systems, steps, tpa, chunk=100):
     """The ensemble as captured HIP graphs of `chunk` whole steps each."""
     import torch
-
-    from paper_1507_07068_amd import md
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         # small replicas can hold an indenter wider than their periodic box, whose
         # overlapping images crowd the Cr-C lists: give those lists more room
-        sim = md.Simulation(systems, precision="mixed", xcap=256, tpa=tpa)
+        sim = make_sim(systems, "mixed", tpa, xcap=256)
         sim.initial_forces()
         g = sim.md_graph_create(chunk)
         sim.md_graph_launch(g)                    # warm-up chunk
         torch.cuda.synchronize()
+        b0 = sim.md_check()["nbuilds"]
         n = max(1, steps // chunk)
         t0 = time.perf_counter()
         for _ in range(n):
@@ -264,46 +401,68 @@ def batched_graph_run(systems, steps, tpa, chunk=100):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         flags = sim.md_check()
-        sim.close()
-    if flags["overflow"] or flags["xoverflow"] or flags["nonfinite"] or flags["sync_timeout"]:
-        raise SystemExit(f"invalid batched run: {flags}")
+        free_sim(sim)
+    check_flags(flags, "batched run")
     n_atoms = sum(s.n for s in systems)
-    return dict(rate=n_atoms * n * chunk / wall, steps=n * chunk, ms_per_step=wall / (n * chunk) * 1e3)
+    return dict(rate=n_atoms * n * chunk / wall, steps=n * chunk, ms_per_step=wall / (n * chunk) * 1e3,
+                builds=flags["nbuilds"] - b0)
 
 
-def variants(tpa_main):
-    from paper_1507_07068_amd import inputs as I
-    from paper_1507_07068_amd import tune
+def full_run(systems, precision, tpa, warmup=20, ee=10):
+    sim = make_sim(systems, precision, tpa)
+    sim.initial_forces()
+    r = timed_run(sim, systems, systems[0].steps, warmup, ee, f"full run {systems[0].name}")
+    free_sim(sim)
+    return {"value": r["rate"], "unit": "atom-steps/s", "steps": r["steps"], "warmup": warmup,
+            "ms_per_step": r["ms_per_step"], "precision": precision, "list_builds": r["builds"],
+            "mean_list_len": round(r["mean_list"], 3)}
 
-    out = {}
-    c1 = I.config(1)
-    r = timed_run([c1], "mixed", c1.steps, 20, 10, tpa_main, events=False)
-    r["sim"].close()
-    out["mixed_c1"] = {"value": r["rate"], "unit": "atom-steps/s", "ms_per_step": r["ms_per_step"],
-                       "steps": c1.steps, "dtype": "f32 pair math, f64 state",
-                       "force_rel_rms_vs_fp64": force_error_vs_fp64([c1], tpa_main),
-                       "list_builds": r["builds"]}
-    log(f"[bench] mixed c1: {r['rate']:.4e} atom-steps/s, force rel-RMS vs FP64 "
-        f"{out['mixed_c1']['force_rel_rms_vs_fp64']:.2e}")
-    ens = I.config(3)
-    best, times = tune.choose_tpa(ens, "mixed")
-    b = batched_graph_run(ens, ens[0].steps, best)
-    out["batched_c3"] = {"value": b["rate"], "unit": "atom-steps/s", "ms_per_step": b["ms_per_step"],
-                         "steps": b["steps"], "replicas": len(ens), "cr_atoms": sum(s.n for s in ens),
-                         "precision": "mixed", "launch": "hipGraph of 100 whole steps",
-                         "tpa_autotuned": best,
-                         "tpa_ms_per_step": {str(k): round(v * 1e3, 4) for k, v in times.items()}}
-    log(f"[bench] batched c3: {b['rate']:.4e} atom-steps/s (tpa {best})")
-    c0 = I.config(0)
-    nve = {}
-    for prec in ("fp64", "mixed"):
-        r = timed_run([c0], prec, 10000, 0, 10, 1, events=False)
-        r["sim"].close()
-        nve[prec] = drift_per_ns(r["obs"], c0.n, c0.dt, 10)
-    out["nve_c0"] = {"steps": 10000, "dt_fs": c0.dt, "drift_ev_per_atom_per_ns_fp64": nve["fp64"],
-                     "drift_ev_per_atom_per_ns_mixed": nve["mixed"]}
-    log(f"[bench] NVE c0 drift: fp64 {nve['fp64']:.3e}, mixed {nve['mixed']:.3e} eV/atom/ns")
-    return out
+
+# ------------------------------------------------------------------------------------------
+# CPU baseline
+# ------------------------------------------------------------------------------------------
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(system, threads=None, budget_s=20.0, max_steps=20) -> dict:
+    """The FP64 oracle as it stands (lists through its cell grid), on the same workload: the
+    set-up at t = 0 (list build, first forces) is timed on its own and taken out, so the rate
+    is of whole steps (drift, skin test, rebuilds when due, forces, kicks).  The step count is
+    chosen from a 2-step probe to fit `budget_s`."""
+    import oracle as O
+    if threads:
+        O.set_num_threads(threads)
+    try:
+        def run(k):
+            t0 = time.perf_counter()
+            out = O.md_run(system, k, use_lists="cells", cap=64)
+            return time.perf_counter() - t0, int(out["obs"][-1, 14])
+        t_setup, _ = run(0)
+        t2, _ = run(2)
+        per_step = max((t2 - t_setup) / 2, 1e-6)
+        k = int(max(2, min(max_steps, budget_s // per_step)))
+        tk, builds = (t2, None) if k == 2 else run(k)
+        if builds is None:
+            builds = run(0)[1]
+        cores = O.num_threads()
+    finally:
+        if threads:
+            O.set_num_threads(os.cpu_count() or 1)
+    return {"value": system.n * k / max(tk - t_setup, 1e-9), "unit": "atom-steps/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{system.name} ({system.n} Cr): {k} whole steps of the FP64 oracle (cell-grid "
+                      f"Verlet lists, {builds} list builds incl. the one at t=0) in {tk:.1f} s, less "
+                      f"the {t_setup:.1f} s set-up at t=0 (first build + forces) timed alone",
+            "host": {"cpu_model": cpu_model(), "nproc": os.cpu_count(),
+                     "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}}
 
 
 def copy_probe(mib: int) -> int:
@@ -318,20 +477,19 @@ def copy_probe(mib: int) -> int:
     return 0
 
 
+# ------------------------------------------------------------------------------------------
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's own)")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
+    ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--energy-every", type=int, default=10)
     ap.add_argument("--tpa", type=int, default=2, choices=[1, 2, 4, 8],
                     help="lanes per atom in the density / force passes")
-    ap.add_argument("--time-every", type=int, default=TIME_EVERY, metavar="K",
-                    help="record the kernel timing events on a random one in K steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="headline and kernel pass only")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB")
     args = ap.parse_args(argv)
 
@@ -342,41 +500,40 @@ def main(argv=None):
     if args.copy_probe:
         return copy_probe(args.copy_probe)
 
+    import torch
+
     from paper_1507_07068_amd import inputs as I
+    from paper_1507_07068_amd import tune
 
     idx, wname = WORKLOADS[args.workload]
     cfg = I.config(idx)
     systems = cfg if isinstance(cfg, list) else [cfg]
-    precision = args.precision or systems[0].precision
+    precision = args.precision
     steps = args.steps if args.steps is not None else systems[0].steps
     ee = args.energy_every
-    log(f"[bench] workload {args.workload} ({wname}): {len(systems)} system(s), "
-        f"{sum(s.n for s in systems)} Cr, {sum(s.n_c for s in systems)} C, precision {precision}, "
-        f"steps {steps}, warmup {args.warmup}")
-    r = timed_run(systems, precision, steps, args.warmup, ee, args.tpa, time_every=args.time_every)
-    r["sim"].close()
-    n_atoms, rate, k_avg, mean_list = r["n_atoms"], r["rate"], r["k_avg"], r["mean_list"]
-    # FP64 runs (no shadow) drift the atoms in the force pass of most steps
-    bytes_launch = n_atoms * force_bytes_per_atom(mean_list, drift=precision == "fp64")
-    achieved = bytes_launch / k_avg / 1e9
-    e_tot = r["obs"][:, :, 0:4].sum(-1).sum(-1) if r["obs"].size else [0.0]
-    log(f"[bench] {rate:.4e} atom-steps/s, {r['ms_per_step']:.4f} ms/step, EAM force kernel "
-        f"{k_avg * 1e6:.2f} us avg ({achieved:.0f} GB/s algorithmic), mean list {mean_list:.2f}, "
-        f"{r['builds']} list builds, E_tot first/last {e_tot[0]:.6f} / {e_tot[-1]:.6f} eV")
-    # (+24 B per atom for the fixed-point shadow and build cell written in mixed runs)
-    lbytes = (n_atoms * (list_bytes_per_atom(mean_list) + (24 if precision == "mixed" else 0))
-              if len(systems) == 1 else None)
-    l_achieved = lbytes / r["l_avg"] / 1e9 if (lbytes and r["l_avg"] > 0) else None
-    traffic = ltraffic = None   # measured HBM bytes per launch (compare with bytes_per_launch)
-    if args.workload == "c1" and precision == "fp64" and args.tpa == 2:
-        traffic = measured_traffic("force", n_atoms)
-        ltraffic = measured_traffic("list", n_atoms)
-    log(f"[bench] list kernel {r['l_avg'] * 1e6:.2f} us per rebuild launch"
-        + (f" ({l_achieved:.0f} GB/s algorithmic)" if l_achieved else "")
-        + f"; GPU time in list / force kernels {r['l_total'] * 1e3:.1f} / {r['k_total'] * 1e3:.1f} ms")
+    n_atoms = sum(s.n for s in systems)
+    log(f"[bench] workload {args.workload} ({wname}): {len(systems)} system(s), {n_atoms} Cr, "
+        f"{sum(s.n_c for s in systems)} C, precision {precision}, steps {steps}, warmup {args.warmup}")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        sim = make_sim(systems, precision, args.tpa)
+        sim.initial_forces()
+        r = timed_run(sim, systems, steps, args.warmup, ee, "headline")
+        log(f"[bench] {r['rate']:.4e} atom-steps/s, {r['ms_per_step']:.4f} ms/step, {r['builds']} list "
+            f"builds, mean list {r['mean_list']:.2f}")
+        kern = kernel_pass(sim, systems, steps, ee, precision)
+        free_sim(sim)
+    log(f"[bench] kernel pass ({steps} steps, events on every step): force {kern['force']['avg_us']:.1f} us "
+        f"({kern['force']['achieved']:.0f} GB/s), density {kern['density']['avg_us']:.1f} us "
+        f"({kern['density']['achieved']:.0f} GB/s), list {kern['list'].get('avg_us', 0):.1f} us per rebuild "
+        f"over {kern['list']['rebuild_launches']} rebuilds, {kern['list']['avg_us_no_rebuild'] or 0:.1f} us "
+        f"otherwise")
+    totals = {k: kern[k]["total_ms"] for k in ("force", "density", "list")}
+    rl = {k: roofline_of(kern, k, n_atoms, precision) for k in totals}
+    dom = max((k for k in totals if rl[k] is not None), key=lambda k: totals[k])
     result = {
         "metric": METRIC,
-        "value": rate,
+        "value": r["rate"],
         "unit": "atom-steps/s",
         "n_gpus": 1,
         "steps": steps,
@@ -389,34 +546,61 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": wname, "cr_atoms": n_atoms, "c_atoms": sum(s.n_c for s in systems),
                    "replicas": len(systems), "precision": precision, "energy_every": ee,
-                   "list_builds": r["builds"], "mean_list_len": round(mean_list, 3),
+                   "list_builds": r["builds"], "mean_list_len": round(r["mean_list"], 3),
                    "lanes_per_atom": args.tpa},
-        "roofline": None,
-        "roofline_force": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                           "kernel": ("k_force (EAM Eq. 1 with the Cr-C forces, fused kicks"
-                                      + (" and next drift)" if precision == "fp64" else ")")),
-                           "avg_us": k_avg * 1e6, "bytes_per_launch": bytes_launch,
-                           "gpu_ms_total": r["k_total"] * 1e3},
+        "roofline": dict(rl[dom], dominant_of={k: round(v, 3) for k, v in totals.items()}),
+        "roofline_kernels": {k: v for k, v in rl.items() if v is not None},
+        "kernels": kern,
         "cpu_baseline": None,
     }
-    if l_achieved:
-        result["roofline_list"] = {"bound": "hbm", "achieved": l_achieved, "peak": HBM_PEAK_GBS,
-                                   "unit": "GB/s", "frac": l_achieved / HBM_PEAK_GBS, "traffic": ltraffic,
-                                   "kernel": "k_list_tiles (Cr-Cr Verlet list build with the Cr-C lists in leading blocks, rebuild launches)",
-                                   "avg_us": r["l_avg"] * 1e6, "bytes_per_launch": lbytes,
-                                   "gpu_ms_total": r["l_total"] * 1e3}
-    # the dominant kernel: the one with the most GPU time over the timed steps
-    dom = ("roofline_list" if ("roofline_list" in result
-                               and r["l_total"] > r["k_total"]) else "roofline_force")
-    result["roofline"] = dict(result[dom], dominant_of=["k_force", "k_list_tiles"])
-    if not args.no_variants and args.workload == "c1" and args.steps is None:
-        result["variants"] = variants(args.tpa)
-    if not args.no_cpu_baseline and len(systems) == 1 and systems[0].n <= 300_000:
-        spb = steps / max(r["builds"], 1)
-        log(f"[bench] CPU baseline: oracle on {systems[0].name}, ~{spb:.0f} steps ...")
-        result["cpu_baseline"] = cpu_baseline(I.config(idx), spb)
-        log(f"[bench] CPU baseline {result['cpu_baseline']['value']:.4e} atom-steps/s")
+    if not args.no_variants:
+        var, full = {}, {}
+        if len(systems) == 1:
+            other = "mixed" if precision == "fp64" else "fp64"
+            s0 = systems[0]
+            rr = full_run([s0], other, args.tpa, warmup=args.warmup, ee=ee)
+            rr["force_errors"] = mixed_force_errors(s0, args.tpa)
+            var[f"{other}_{args.workload}"] = rr
+            log(f"[bench] {other} {args.workload}: {rr['value']:.4e} atom-steps/s, force rel-RMS vs FP64 "
+                f"{rr['force_errors']['rel_rms_vs_fp64_gpu_all_atoms']:.2e} (all atoms), vs oracle "
+                f"{rr['force_errors']['rel_rms_vs_oracle_sampled']:.2e} (sampled)")
+            if steps == s0.steps:   # the headline run is the full run
+                full[f"{args.workload}_{precision}"] = {
+                    "value": r["rate"], "unit": "atom-steps/s", "steps": steps, "warmup": args.warmup,
+                    "ms_per_step": r["ms_per_step"], "precision": precision, "list_builds": r["builds"],
+                    "mean_list_len": round(r["mean_list"], 3)}
+            else:
+                full[f"{args.workload}_{precision}"] = full_run([s0], precision, args.tpa, warmup=args.warmup,
+                                                                ee=ee)
+            full[f"{args.workload}_{other}"] = {k: rr[k] for k in rr if k != "force_errors"}
+        ens = I.config(3)
+        best, times = tune.choose_tpa(ens, "mixed")
+        b = batched_graph_run(ens, ens[0].steps, best)
+        var["batched_c3"] = {"value": b["rate"], "unit": "atom-steps/s", "ms_per_step": b["ms_per_step"],
+                             "steps": b["steps"], "list_builds": b["builds"], "replicas": len(ens),
+                             "cr_atoms": sum(s.n for s in ens), "precision": "mixed",
+                             "launch": "hipGraph of 100 whole steps", "tpa_autotuned": best,
+                             "tpa_ms_per_step": {str(k): round(v * 1e3, 4) for k, v in times.items()}}
+        full["c3_mixed_graph"] = var["batched_c3"]
+        log(f"[bench] batched c3: {b['rate']:.4e} atom-steps/s (tpa {best})")
+        c1 = I.config(1)
+        full["c1_fp64"] = full_run([c1], "fp64", args.tpa)
+        log(f"[bench] c1 fp64 full: {full['c1_fp64']['value']:.4e} atom-steps/s")
+        var["nve_c0"] = nve_drift()
+        var["indenter_work_c1"] = indenter_work_drift(c1, args.tpa)
+        log(f"[bench] NVE c0 drift (mean of seeds): fp64 "
+            f"{var['nve_c0']['drift_ev_per_atom_per_ns']['fp64']['mean']:.3e}, mixed "
+            f"{var['nve_c0']['drift_ev_per_atom_per_ns']['mixed']['mean']:.3e} eV/atom/ns; c1 E_tot+W "
+            f"{var['indenter_work_c1']['drift_e_tot_plus_w_ev_per_atom_per_ns']:.3e}")
+        result["variants"] = var
+        result["full_runs"] = full
+    if not args.no_cpu_baseline and len(systems) == 1:
+        log(f"[bench] CPU baseline: oracle on {systems[0].name} ...")
+        result["cpu_baseline"] = cpu_baseline(systems[0])
+        log(f"[bench] CPU baseline {result['cpu_baseline']['value']:.4e} atom-steps/s "
+            f"({result['cpu_baseline']['cores']} threads)")
+        result["cpu_baseline_1thread"] = cpu_baseline(I.config(1), threads=1, budget_s=8.0, max_steps=10)
+        log(f"[bench] CPU baseline 1 thread (216k film) {result['cpu_baseline_1thread']['value']:.4e}")
     print(json.dumps(result), flush=True)
     return 0
 

@@ -70,7 +70,7 @@ extern "C" {
 #define MD_B_FORCE 0x01    /* rebuild now, whatever the skin test says */
 
 /* Observables written by md_energy, per replica (MD_NOBS doubles each). */
-#define MD_E_EMBED 0       /* sum_i F(rho_i)                         (Eq. A1, first term) */
+#define MD_E_EMBED 0       /* sum_i F(rho_i) (+ M(P_i) with the paper's form) (Eq. A1, first and third terms) */
 #define MD_E_PAIR 1        /* 1/2 sum_{i != j} phi(r_ij)             (Eq. A1, second term) */
 #define MD_E_MORSE 2       /* sum over Cr-C pairs of phiM(r) - phiM(rc) */
 #define MD_E_KIN 3         /* 1/2 m v^2 over mobile atoms */
@@ -96,6 +96,20 @@ typedef struct md_morse_params {
     double D, alpha, r0, rc;
 } md_morse_params;
 
+/* The paper's own EAM form (Appendix, Eqs. A1-A4), selected with potential = MD_POT_PAPER:
+ *   F(rho) = -Fo [1 - n ln(rho/rho_e)] (rho/rho_e)^n,  M(P) = alpha (P/P_e - 1)^2 exp(-(P/P_e - 1)^2),
+ *   f(r) = fe (re/r)^beta for r < rc,  Phi(r) = (x-d)^2 (a3 x^3 + a2 x^2 + a1 x + a0) for
+ *   x = r/re < d,  rho_i = sum_j f(r_ij), P_i = sum_j f(r_ij)^2, E = sum_i [F(rho_i) + M(P_i)]
+ *   + 1/2 sum_{i != j} Phi(r_ij).  Forces: Eq. (1) with V = Phi and the M term in the same form,
+ *   F_i = -sum_j [(F'_i + F'_j) f' + (M'_i + M'_j) 2 f f' + Phi'] (q_i - q_j) / r.
+ *   F'(0) is taken as 0.  beta / 2 a whole number from 1 to 8 takes a faster path. */
+typedef struct md_eam_paper_params {
+    double Fo, n, rho_e, alpha, P_e, fe, re, beta, a0, a1, a2, a3, d, rc;
+} md_eam_paper_params;
+
+#define MD_POT_FS 0        /* md_params.potential: the Finnis-Sinclair-form `eam` */
+#define MD_POT_PAPER 1     /* the paper's form `paper` */
+
 typedef struct md_params {
     md_eam_params eam;
     md_morse_params morse;
@@ -112,6 +126,10 @@ typedef struct md_params {
                            (updated by the list build and md_verlet_step), from which the
                            MD_F_MIXED passes take their separations; 0: those passes round FP64
                            separations instead */
+    int32_t potential;  /* MD_POT_FS (eam) or MD_POT_PAPER (paper); the list radius is the
+                           potential's largest Cr-Cr cutoff + skin */
+    int32_t pad;
+    md_eam_paper_params paper;
 } md_params;
 
 /* One system (replica). */
@@ -210,7 +228,8 @@ MD_API int md_build_neighbors(md_system *sys, const md_atoms *a, const md_lists 
 
 /* Task 4a/4b (Section 3.1, Eq. 1; Section 3.3.1.2-3): MD_F_DENSITY computes
  * rho_i = sum_j f(r_ij) and stores F'(rho_i) in q[i][3] (rho_out, if not NULL, receives rho
- * per atom slot); MD_F_FORCE computes
+ * per atom slot; the paper's form also takes P_i = sum_j f^2 and keeps M'(P_i) in the
+ * workspace, the second derivative of Section 3.1's array); MD_F_FORCE computes
  *   F_i = - sum_j [(F'(rho_i) + F'(rho_j)) f'(r_ij) + phi'(r_ij)] (q_i - q_j) / r_ij
  * into f over the Cr-Cr list (each atom gathers over its full list: no atomics).  With
  * MD_F_MORSE (and MD_F_FORCE) the Cr-C Morse forces of md_morse_forces are included in f:
@@ -245,6 +264,18 @@ MD_API int md_energy(md_system *sys, const md_atoms *a, double *out, void *strea
 /* Whole steps                                                                          */
 /* ---------------------------------------------------------------------------------- */
 
+/* Records md_run can make of its steps, for measurement (each member may be NULL). */
+#define MD_TRACE_EVENTS 6  /* events per step */
+typedef struct md_trace {
+    void *const *events;  /* MD_TRACE_EVENTS * nsteps hipEvent_t handles created by the caller
+                             (NULL entries are skipped), recorded on the stream around step k's
+                             kernels: [6k], [6k+1] the EAM force kernel (Eq. 1); [6k+2], [6k+3]
+                             the Cr-Cr list kernel (which returns at once when no rebuild is
+                             due); [6k+4], [6k+5] the density kernel (with the Cr-C pass) */
+    int32_t *builds;      /* device int32[nsteps][nrep]: each replica's list-build count after
+                             each step (a step rebuilt a replica's lists iff its count grew) */
+} md_trace;
+
 /* Enqueue nsteps whole time steps in the order of Table 1 (Tasks 2+3 -> 1 -> 4 -> 5) for
  * every replica: md_verlet_step(KICK_DRIFT), md_build_neighbors, then the Task 4 passes
  * with the Cr-C forces included in the Eq. 1 pass and the final half kick applied by it
@@ -258,15 +289,11 @@ MD_API int md_energy(md_system *sys, const md_atoms *a, double *out, void *strea
  * flags: MD_F_MIXED selects FP32 arithmetic.  energy_every > 0: after step k with
  * k % energy_every == 0 the energies are written as by md_energy to
  * obs[(k / energy_every - 1) * nrep * MD_NOBS ...] (device memory, caller-owned).
- * events: NULL, or 4*nsteps hipEvent_t handles (created by the caller) recorded on
- * `stream`, for timing: events[4k], events[4k+1] just before and after step k's EAM force
- * kernel (Eq. 1), events[4k+2], events[4k+3] just before and after its Cr-Cr list kernel
- * (which returns at once when no rebuild is due); NULL entries are not recorded (to time a
- * sample of the steps).
+ * trace: NULL, or timing and rebuild records of the steps (see md_trace).
  * Lists must have been built and forces evaluated once before the first step
  * (md_build_neighbors with MD_B_FORCE, md_eam_forces with DENSITY|FORCE|MORSE). */
 MD_API int md_run(md_system *sys, const md_atoms *a, const md_lists *l, int32_t nsteps,
-                  uint32_t flags, int32_t energy_every, double *obs, void *const *events,
+                  uint32_t flags, int32_t energy_every, double *obs, const md_trace *trace,
                   void *stream);
 
 /* Capture md_run(nsteps, flags, energy_every, obs, no events) on `stream` into an
@@ -277,6 +304,12 @@ MD_API int md_graph_create(md_system *sys, const md_atoms *a, const md_lists *l,
                            void **graph_exec);
 MD_API int md_graph_launch(void *graph_exec, void *stream);
 MD_API int md_graph_destroy(void *graph_exec);
+
+/* Task 2 of later steps moves the indenter by v_ind * dt along z (Angstrom/fs; the value given
+ * at md_system_create until changed here), for the load-unload protocol of Section 2.5: relax
+ * with 0, load with a negative, withdraw with a positive velocity.  Host state only: calls
+ * enqueued after it use the new value; a HIP graph keeps the value it was captured with. */
+MD_API int md_set_indenter_velocity(md_system *sys, double v_ind);
 
 /* Synchronise `stream` and copy the device flags to *st (summed / maxed over replicas). */
 MD_API int md_check(md_system *sys, md_status *st, void *stream);

@@ -89,6 +89,7 @@ def lib():
         L.orc_md_run.restype = i64
         L.orc_evaluate.argtypes = [P, i64, P, P, P, P, i64, P, d, P, P, P, P]
         L.orc_paper_values.argtypes = [P, d, d, d, P]
+        L.orc_sample_forces_paper.argtypes = [P, P, P, i64, P, i64, P, d, i64, P, P, P, P]
         L.orc_density_paper.argtypes = [P, P, i64, P, P, P, i64, P, P, P, P]
         L.orc_eam_forces_paper.argtypes = [P, P, i64, P, P, P, i64, P, P, P, P, P]
         L.orc_potential_values.argtypes = [P, P, d, P]
@@ -269,6 +270,22 @@ def sample_forces(s, sample, x=None, ind_z: float = 0.0):
     lib().orc_sample_forces(C.byref(b), C.byref(e), C.byref(m), x.shape[0], _p(x), xc.shape[0],
                             _p(xc), float(ind_z), ns, _p(smp), _p(f), _p(rho), _p(dF), _p(fm))
     return f[:ns], rho[:ns], dF[:ns], fm[:ns]
+
+
+def sample_forces_paper(s, sample, x=None, ind_z: float = 0.0):
+    """sample_forces for a system with the paper's form: (force, rho, F'(rho)) of the sampled
+    atoms from all-atom loops."""
+    x = _f64(s.x if x is None else x)
+    xc = _f64(s.xc).reshape(-1, 3)
+    smp = np.ascontiguousarray(sample, dtype=np.int64)
+    ns = smp.shape[0]
+    f = np.zeros((max(ns, 1), 3))
+    rho = np.zeros(max(ns, 1))
+    dF = np.zeros(max(ns, 1))
+    b, pp, m = box_of(s), make_paper(s.paper), make_morse(s.morse)
+    lib().orc_sample_forces_paper(C.byref(b), C.byref(pp), C.byref(m), x.shape[0], _p(x), xc.shape[0],
+                                  _p(xc), float(ind_z), ns, _p(smp), _p(f), _p(rho), _p(dF))
+    return f[:ns], rho[:ns], dF[:ns]
 
 
 def params_of(s, use_lists=False, cap: int = 96) -> _Params:

@@ -761,6 +761,67 @@ void orc_sample_forces(const orc_box *b, const orc_eam *p, const orc_morse *m, i
     }
 }
 
+/* rho_i and P_i of one atom with the paper's form, from all-atom loops. */
+static void paper_density_at(const orc_box *b, const orc_paper *p, int64_t n, const double *x, int64_t i,
+                             double *rho, double *P)
+{
+    double acc = 0.0, accp = 0.0, s[3];
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == i) continue;
+        double r = sqrt(separation(b, x + 3 * i, x + 3 * j, s));
+        if (r < p->rc) {
+            double fr = paper_f(p, r);
+            acc += fr;
+            accp += fr * fr;
+        }
+    }
+    *rho = acc;
+    *P = accp;
+}
+
+/* orc_sample_forces with the paper's form: for each sampled atom, rho, F'(rho) and the total
+ * force (the paper-form Eq. (1) plus Morse), each neighbour's rho and P recomputed from
+ * scratch. */
+void orc_sample_forces_paper(const orc_box *b, const orc_paper *p, const orc_morse *m, int64_t n,
+                             const double *x, int64_t nc, const double *xc, double ind_z,
+                             int64_t ns, const int64_t *sample, double *f_out, double *rho_out,
+                             double *dF_out)
+{
+    const double rmax = p->rc > p->d * p->re ? p->rc : p->d * p->re;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < ns; ++t) {
+        int64_t i = sample[t];
+        double rho_i, P_i;
+        paper_density_at(b, p, n, x, i, &rho_i, &P_i);
+        double dFi = paper_dF(p, rho_i), dMi = paper_dM(p, P_i);
+        double fi[3] = {0.0, 0.0, 0.0}, s[3];
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double r = sqrt(separation(b, x + 3 * i, x + 3 * j, s));
+            if (r < rmax) {
+                double rho_j = 0.0, P_j = 0.0;
+                if (r < p->rc) paper_density_at(b, p, n, x, j, &rho_j, &P_j);
+                double fr = paper_f(p, r), dfr = paper_df(p, r);
+                double g = paper_dphi(p, r) + (dFi + paper_dF(p, rho_j)) * dfr +
+                           (dMi + paper_dM(p, P_j)) * 2.0 * fr * dfr;
+                for (int a = 0; a < 3; ++a) fi[a] += -g * (-s[a]) / r;
+            }
+        }
+        double pk[3];
+        for (int64_t k = 0; k < nc; ++k) {
+            carbon_position(xc, k, ind_z, pk);
+            double r = sqrt(separation(b, x + 3 * i, pk, s));
+            if (r < m->rc) {
+                double g = morse_dphi(m, r);
+                for (int a = 0; a < 3; ++a) fi[a] += -g * (-s[a]) / r;
+            }
+        }
+        for (int a = 0; a < 3; ++a) f_out[3 * t + a] = fi[a];
+        if (rho_out) rho_out[t] = rho_i;
+        if (dF_out) dF_out[t] = dFi;
+    }
+}
+
 /* ---------------------------------------------------------------------------------- */
 /* Whole-system evaluation and the time loop                                            */
 /* ---------------------------------------------------------------------------------- */

@@ -22,9 +22,9 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Byte offsets of the workspace regions.
 struct Layout {
-  size_t desc, state, tile_rep, row_rep, items, c_rep, misc, xref, dmax, tbox, cellid, crank, perm, skey, tq, tqf, qs, q2, qs2, bcell, tv,
+  size_t desc, state, tile_rep, row_rep, items, c_rep, misc, chunks, chunk_out, xref, dmax, tbox, cellid, crank, perm, skey, tq, tqf, qs, q2, qs2, bcell, tv,
       tf, tfixed, tid, count, start, hcell, hrank, hlist, hsorted, scan_state, hnear, near, fme, p_embed, p_force,
-      p_morse, p_kin, total;
+      p_morse, p_kin, dm, total;
 };
 
 constexpr int MISC_INTS = 16;    // rebuild flag, status words
@@ -41,6 +41,7 @@ struct md_system {
   std::vector<int> tile_rep;
   std::vector<int> row_rep;    // replica of each cell row at capacity
   std::vector<int> c_rep;
+  std::vector<int2> chunks;    // energy sums: (first tile, tile count) of each chunk
   int64_t ntot, ctot;
   int ntiles;
   int nlblk;     // blocks of the list build (most work items)
@@ -57,7 +58,15 @@ struct md_system {
   // (outside md_run always the caller's).  ppt: parts per tile of the last displacement
   // maxima and boxes (1 from the kick-drift pass, T from a force pass with the drift).
   int cur = 0, ppt = 1;
+  // grids of the build kernels that stride over their work (set at bind from the device):
+  // tile kernels (256 threads) and the persistent list build
+  int tile_grid = 2048, list_grid = 2048;
 };
+
+namespace {
+// A workspace is bound.
+bool bound(const md_system* s) { return s->ws != nullptr; }
+}  // namespace
 
 namespace {
 
@@ -82,6 +91,8 @@ Layout make_layout(const md_system& s) {
   L.items = take(sizeof(int2) * (size_t)s.nlblk);
   L.c_rep = take(sizeof(int) * (size_t)s.ctot);
   L.misc = take(sizeof(int) * MISC_INTS);
+  L.chunks = take(sizeof(int2) * s.chunks.size());
+  L.chunk_out = take(sizeof(double) * 16 * s.chunks.size());
   L.xref = take(sizeof(double) * 3 * n);
   L.dmax = take(sizeof(double) * nt * 8);       // per tile, or per part of a tile (up to 8)
   L.tbox = take(sizeof(double) * 6 * nt * 8);
@@ -109,6 +120,7 @@ Layout make_layout(const md_system& s) {
   L.hnear = take(sizeof(int) * (size_t)s.ncell_all);
   L.near = take(sizeof(int) * n);
   L.fme = take(sizeof(double) * 4 * n);
+  L.dm = take(sizeof(double) * n);       // M'(P_i) of the paper's form
   L.p_embed = take(sizeof(double) * nt * s.K.lt);
   L.p_force = take(sizeof(double) * nt * s.K.lt * NP_FORCE);
   L.p_morse = take(sizeof(double) * nt * 4);
@@ -182,11 +194,15 @@ void launch_density(md_system* s, const md_atoms* a, const md_lists* l, bool mix
                   morse ? morse_fused_blocks(s) : 0};
   const int nb = s->ntiles * T + M.nblocks;
   int4* qs = qscur(s);
-#define DENS(M_, SH, E) \
-  k_density<T, M_, SH, E><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, qs, l->idx, l->cnt, rho_out, pe, M)
-  if (mixed && s->K.shadow && !s->list_mix) { if (energy) DENS(true, true, true); else DENS(true, true, false); }
-  else if (mixed) { if (energy) DENS(true, false, true); else DENS(true, false, false); }
-  else { if (energy) DENS(false, false, true); else DENS(false, false, false); }
+  double* dm = at<double>(s, s->L.dm);
+#define DENS(M_, SH, E, PA) \
+  k_density<T, M_, SH, E, PA><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, qs, l->idx, l->cnt, rho_out, pe, M, dm)
+#define DENS_P(M_, SH, E) \
+  if (s->K.pot == MD_POT_PAPER) DENS(M_, SH, E, true); else DENS(M_, SH, E, false)
+  if (mixed && s->K.shadow && !s->list_mix) { if (energy) { DENS_P(true, true, true); } else { DENS_P(true, true, false); } }
+  else if (mixed) { if (energy) { DENS_P(true, false, true); } else { DENS_P(true, false, false); } }
+  else { if (energy) { DENS_P(false, false, true); } else { DENS_P(false, false, false); } }
+#undef DENS_P
 #undef DENS
 }
 
@@ -206,15 +222,22 @@ void launch_force(md_system* s, const md_atoms* a, const md_lists* l, bool mixed
   double* pf = at<double>(s, s->L.p_force);
   const int nb = s->ntiles * T;
   const int4* qs = qscur(s);
+  const double* dm = at<double>(s, s->L.dm);
+  const bool paper = s->K.pot == MD_POT_PAPER;
+#define FORCE1(M, SH, KI, E, PA)                                                                                \
+  k_force<T, M, SH, KI, E, false, PA><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, qs, a->v, a->f, a->fixed, l->idx, \
+                                                             l->cnt, pf, l->xcnt,                                \
+                                                             add_fme ? at<double>(s, s->L.fme) : nullptr, kick_h, D, dm)
 #define FORCE(M, SH, KI, E) \
-  k_force<T, M, SH, KI, E><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, qs, a->v, a->f, a->fixed, l->idx, l->cnt, pf, \
-                                                  l->xcnt, add_fme ? at<double>(s, s->L.fme) : nullptr, kick_h, D)
-#define FORCE_DRIFT(M, SH)                                                                                       \
-  k_force<T, M, SH, true, false, true><<<nb, BLOCK, 0, st>>>(                                                    \
+  if (paper) FORCE1(M, SH, KI, E, true); else FORCE1(M, SH, KI, E, false)
+#define FORCE_DRIFT1(M, SH, PA)                                                                                  \
+  k_force<T, M, SH, true, false, true, PA><<<nb, BLOCK, 0, st>>>(                                                \
       s->K, R, S, tr, q, qs, a->v, a->f, a->fixed, l->idx, l->cnt, pf, l->xcnt,                                  \
-      add_fme ? at<double>(s, s->L.fme) : nullptr, kick_h, D)
+      add_fme ? at<double>(s, s->L.fme) : nullptr, kick_h, D, dm)
+#define FORCE_DRIFT(M, SH) \
+  if (paper) FORCE_DRIFT1(M, SH, true); else FORCE_DRIFT1(M, SH, false)
 #define FORCE_E(M, SH, KI) \
-  if (energy) FORCE(M, SH, KI, true); else FORCE(M, SH, KI, false)
+  if (energy) { FORCE(M, SH, KI, true); } else { FORCE(M, SH, KI, false); }
 #define FORCE_K(M, SH) \
   if (kick) { FORCE_E(M, SH, true); } else { FORCE_E(M, SH, false); }
   if (drift) {
@@ -225,9 +248,11 @@ void launch_force(md_system* s, const md_atoms* a, const md_lists* l, bool mixed
   else if (mixed) { FORCE_K(true, false); }
   else { FORCE_K(false, false); }
 #undef FORCE_DRIFT
+#undef FORCE_DRIFT1
 #undef FORCE_K
 #undef FORCE_E
 #undef FORCE
+#undef FORCE1
 }
 
 // add_f: the Cr-C forces are added into f (else only recorded in fme)
@@ -269,9 +294,16 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
   if (!(p->mass > 0) || !(p->dt > 0) || !(p->skin >= 0) || p->cap < 1 || p->xcap < 1) return MD_ERR_ARG;
   if (p->tpa != 1 && p->tpa != 2 && p->tpa != 4 && p->tpa != 8) return MD_ERR_ARG;
   if (p->cap % p->tpa != 0) return MD_ERR_ARG;
-  if (!(p->eam.c > 0) || !(p->eam.d > 0) || !(p->eam.d <= p->eam.c) || !(p->morse.rc > 0) ||
-      !(p->morse.alpha > 0))
+  if (p->potential != MD_POT_FS && p->potential != MD_POT_PAPER) return MD_ERR_ARG;
+  if (p->potential == MD_POT_FS && (!(p->eam.c > 0) || !(p->eam.d > 0) || !(p->eam.d <= p->eam.c)))
     return MD_ERR_ARG;
+  if (p->potential == MD_POT_PAPER) {
+    const md_eam_paper_params& q = p->paper;
+    if (!(q.rc > 0) || !(q.re > 0) || !(q.d > 0) || !(q.rho_e > 0) || !(q.P_e > 0) || !(q.fe >= 0) ||
+        !std::isfinite(q.beta) || !std::isfinite(q.n) || !std::isfinite(q.Fo) || !std::isfinite(q.alpha))
+      return MD_ERR_ARG;
+  }
+  if (!(p->morse.rc > 0) || !(p->morse.alpha > 0)) return MD_ERR_ARG;
   md_system* s = new (std::nothrow) md_system();
   if (!s) return MD_ERR_ARG;
   s->p = *p;
@@ -279,7 +311,9 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
   s->ws = nullptr;
   s->have_embed = s->have_force = false;
   s->list_mix = false;
-  const double rlist = p->eam.c + p->skin;
+  // the list holds pairs within the potential's largest Cr-Cr cutoff + skin
+  const double cut = p->potential == MD_POT_PAPER ? std::max(p->paper.rc, p->paper.d * p->paper.re) : p->eam.c;
+  const double rlist = cut + p->skin;
   const double rxlist = p->morse.rc + p->skin;
   int64_t a0 = 0, c0 = 0, nlblk = 0;
   int t0 = 0, g0 = 0;
@@ -337,6 +371,10 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
       return MD_ERR_ARG;
     }
     s->row_rep.insert(s->row_rep.end(), (size_t)nrw, r);
+    s->desc.back().ch0 = (int)s->chunks.size();
+    for (int t = 0; t < ntile; t += REDUCE_CHUNK)
+      s->chunks.push_back(make_int2(t0 - ntile + t, std::min(REDUCE_CHUNK, ntile - t)));
+    s->desc.back().nch = (int)s->chunks.size() - s->desc.back().ch0;
     for (int k = 0; k < rd.n_c; ++k) s->c_rep.push_back(r);
   }
   s->ncell_cr = g0;
@@ -398,6 +436,24 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
   K.lt_shift = p->tpa == 1 ? 0 : (p->tpa == 2 ? 1 : (p->tpa == 4 ? 2 : 3));
   K.shadow = p->shadow ? 1 : 0;
   K.ntot = s->ntot;
+  K.pot = p->potential;
+  if (p->potential == MD_POT_PAPER) {
+    const md_eam_paper_params& q = p->paper;
+    PaperConsts& P = K.P;
+    P.Fo = q.Fo; P.n = q.n; P.rho_e = q.rho_e; P.alpha = q.alpha; P.P_e = q.P_e;
+    P.fe = q.fe; P.re = q.re; P.beta = q.beta;
+    P.a0 = q.a0; P.a1 = q.a1; P.a2 = q.a2; P.a3 = q.a3; P.d = q.d;
+    P.rc_sq = q.rc * q.rc;
+    P.phi_sq = (q.d * q.re) * (q.d * q.re);
+    P.inv_re = 1.0 / q.re;
+    P.re2 = q.re * q.re;
+    P.b0 = q.a3 + q.a2 + q.a1 + q.a0;
+    P.b1 = 3.0 * q.a3 + 2.0 * q.a2 + q.a1;
+    P.b2 = 3.0 * q.a3 + q.a2;
+    P.b3 = q.a3;
+    const double bh = 0.5 * q.beta;
+    P.bh = (bh == std::floor(bh) && bh >= 1.0 && bh <= 8.0) ? (int)bh : 0;
+  }
   s->L = make_layout(*s);
   *out = s;
   return MD_OK;
@@ -434,9 +490,20 @@ int bind_workspace(md_system* s, void* ws, hipStream_t st) {
       (e = hip_status(hipMemcpyAsync(at<int>(s, s->L.c_rep), s->c_rep.data(), sizeof(int) * s->ctot,
                                      hipMemcpyHostToDevice, st))))
     return e;
+  if ((e = hip_status(hipMemcpyAsync(at<int2>(s, s->L.chunks), s->chunks.data(), sizeof(int2) * s->chunks.size(),
+                                     hipMemcpyHostToDevice, st))))
+    return e;
   s->have_embed = s->have_force = false;
   s->cur = 0;
   s->ppt = 1;
+  // the build kernels that stride over their work fill the chip once: as many blocks as its
+  // compute units hold at once
+  int dev = 0, cus = 0, per_cu = 0;
+  if ((e = hip_status(hipGetDevice(&dev)))) return e;
+  if ((e = hip_status(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)))) return e;
+  if ((e = hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_list_tiles, LIST_BLOCK, 0)))) return e;
+  s->list_grid = std::max(1, cus * std::max(1, per_cu));
+  s->tile_grid = std::max(1, cus * (2048 / BLOCK));
   return hip_status(hipStreamSynchronize(st));
 }
 
@@ -463,6 +530,7 @@ int build_chain(md_system* s, const md_atoms* a, const md_lists* l, uint32_t fla
   A.row_rep = at<int>(s, s->L.row_rep);
   A.items = at<int2>(s, s->L.items);
   A.nitems = misc + 2;
+  A.next_item = misc + 4;
   A.nrows = s->nrows;
   A.nlblk = s->nlblk;
   A.c_rep = at<int>(s, s->L.c_rep);
@@ -512,26 +580,28 @@ int build_chain(md_system* s, const md_atoms* a, const md_lists* l, uint32_t fla
   A.scan_chunk = SCAN_CHUNK;
   A.scan_blocks = s->scan_blocks;
   const int cblocks = (int)((s->ctot + BLOCK - 1) / BLOCK);
+  A.nbin = s->ntiles + cblocks;
+  const int tgrid = std::min(A.nbin, s->tile_grid);   // k_bin, k_scatter, k_sort_gather
   // a single replica without a forced build: the skin decision is taken inside k_bin, every
   // block reducing all the per-part maxima, while those redundant loads stay few (they grow
   // as blocks x parts: 1.4 M on the 216k-atom film, 2e9 on an 8M-atom one)
-  const int64_t bin_blocks = (int64_t)s->ntiles + cblocks;
+  const int64_t bin_blocks = tgrid;
   const bool decide_in_bin = !(flags & MD_B_FORCE) && s->K.nrep == 1 &&
                              bin_blocks * ((int64_t)s->ntiles * s->ppt) <= DECIDE_IN_BIN_MAX_LOADS;
   A.commit_ref = decide_in_bin ? 1 : 0;
   if (decide_in_bin) {
-    k_bin<true><<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A, at<double>(s, s->L.dmax),
+    k_bin<true><<<tgrid, BLOCK, 0, st>>>(s->K, A, at<double>(s, s->L.dmax),
                                                        at<double>(s, s->L.tbox), s->ppt);
   } else {
     if (flags & MD_B_FORCE)
       k_tile_box<<<s->ntiles, BLOCK, 0, st>>>(A.R, A.tile_rep, A.q, at<double>(s, s->L.tbox));
     k_decide<<<1, DECIDE_THREADS, 0, st>>>(s->K, A, at<double>(s, s->L.dmax), at<double>(s, s->L.tbox),
                                   (flags & MD_B_FORCE) ? 1 : 0, (flags & MD_B_FORCE) ? 1 : s->ppt);
-    k_bin<false><<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A, nullptr, nullptr, 0);
+    k_bin<false><<<tgrid, BLOCK, 0, st>>>(s->K, A, nullptr, nullptr, 0);
   }
   k_scan<<<s->scan_blocks, BLOCK, 0, st>>>(A);
-  k_scatter<<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A);
-  k_sort_gather<<<s->ntiles + cblocks, BLOCK, 0, st>>>(s->K, A);
+  k_scatter<<<tgrid, BLOCK, 0, st>>>(s->K, A);
+  k_sort_gather<<<tgrid, BLOCK, 0, st>>>(s->K, A);
   int e;
   if (ev0 && (e = hip_status(hipEventRecord(ev0, st)))) return e;
   // the Cr-C lists: leading blocks of the staged Cr-Cr list launch, else a launch of their own
@@ -539,7 +609,7 @@ int build_chain(md_system* s, const md_atoms* a, const md_lists* l, uint32_t fla
   if (s->list_mix)
     k_list_rows<false><<<s->ntiles, BLOCK, 0, st>>>(s->K, A);
   else
-    k_list_tiles<<<A.xblocks + s->nlblk, LIST_BLOCK, 0, st>>>(s->K, A);
+    k_list_tiles<<<A.xblocks + std::min(s->nlblk, s->list_grid), LIST_BLOCK, 0, st>>>(s->K, A);
   if (ev1 && (e = hip_status(hipEventRecord(ev1, st)))) return e;
   if (s->list_mix && s->ctot > 0) k_xlist<<<A.near_blocks, BLOCK, 0, st>>>(s->K, A);
   return check_launch();
@@ -550,7 +620,7 @@ int build_chain(md_system* s, const md_atoms* a, const md_lists* l, uint32_t fla
 MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l, uint32_t flags,
                               void* stream) {
   if (!s || !atoms_ok(a) || !lists_ok(l) || (s->ctot > 0 && !a->xc)) return MD_ERR_ARG;
-  if (!s->ws) return MD_ERR_STATE;
+  if (!bound(s)) return MD_ERR_STATE;
   return build_chain(s, a, l, flags, (hipStream_t)stream, nullptr, nullptr);
 }
 
@@ -591,8 +661,8 @@ MD_API int md_eam_forces(md_system* s, const md_atoms* a, const md_lists* l, uin
                          double* rho_out, void* stream) {
   if (!s || !atoms_ok(a) || !lists_ok(l)) return MD_ERR_ARG;
   if ((flags & MD_F_MORSE) && s->ctot > 0 && !a->xc) return MD_ERR_ARG;
-  if ((flags & MD_F_MIXED) && s->p.eam.c2 == 0.0) return MD_ERR_ARG;
-  if (!s->ws) return MD_ERR_STATE;
+  if ((flags & MD_F_MIXED) && s->K.pot == MD_POT_FS && s->p.eam.c2 == 0.0) return MD_ERR_ARG;
+  if (!bound(s)) return MD_ERR_STATE;
   hipStream_t st = (hipStream_t)stream;
   // With a force pass, the Cr-C forces go in with the Eq. 1 forces: computed into fme by
   // extra blocks of the density launch when there is one, else by their own launch first.
@@ -611,7 +681,7 @@ MD_API int md_morse_forces(md_system* s, const md_atoms* a, const md_lists* l, u
                            void* stream) {
   if (!s || !atoms_ok(a) || !lists_ok(l)) return MD_ERR_ARG;
   if (s->ctot > 0 && !a->xc) return MD_ERR_ARG;
-  if (!s->ws) return MD_ERR_STATE;
+  if (!bound(s)) return MD_ERR_STATE;
   if (s->ctot > 0) launch_morse(s, a, l, flags & MD_F_MIXED, flags & MD_F_KICK, true, (hipStream_t)stream);
   return check_launch();
 }
@@ -635,7 +705,7 @@ void launch_kick_drift(md_system* s, const md_atoms* a, hipStream_t st, bool kic
 MD_API int md_verlet_step(md_system* s, int32_t phase, const md_atoms* a, void* stream) {
   if (!s || !atoms_ok(a)) return MD_ERR_ARG;
   if (phase != MD_PHASE_KICK_DRIFT && phase != MD_PHASE_KICK) return MD_ERR_ARG;
-  if (!s->ws) return MD_ERR_STATE;
+  if (!bound(s)) return MD_ERR_STATE;
   hipStream_t st = (hipStream_t)stream;
   const RepDesc* R = at<RepDesc>(s, s->L.desc);
   const int* tr = at<int>(s, s->L.tile_rep);
@@ -649,25 +719,25 @@ MD_API int md_verlet_step(md_system* s, int32_t phase, const md_atoms* a, void* 
 
 MD_API int md_energy(md_system* s, const md_atoms* a, double* out, void* stream) {
   if (!s || !atoms_ok(a) || !out) return MD_ERR_ARG;
-  if (!s->ws) return MD_ERR_STATE;
+  if (!bound(s)) return MD_ERR_STATE;
   hipStream_t st = (hipStream_t)stream;
   const RepDesc* R = at<RepDesc>(s, s->L.desc);
   const int* tr = at<int>(s, s->L.tile_rep);
   double* pk = at<double>(s, s->L.p_kin);
   double* pm = at<double>(s, s->L.p_morse);
   k_kinetic<<<grid_tiles(s), BLOCK, 0, st>>>(s->K, R, tr, a->v, a->fixed, at<double>(s, s->L.fme), pk, pm);
-  k_reduce<<<s->nrep, BLOCK, 0, st>>>(R, at<RepState>(s, s->L.state),
-                                      s->have_embed ? at<double>(s, s->L.p_embed) : nullptr, s->K.lt,
-                                      s->have_force ? at<double>(s, s->L.p_force) : nullptr, s->K.lt,
-                                      pm, pk, out);
+  k_reduce_chunks<<<(int)s->chunks.size(), BLOCK, 0, st>>>(
+      at<int2>(s, s->L.chunks), s->have_embed ? at<double>(s, s->L.p_embed) : nullptr, s->K.lt,
+      s->have_force ? at<double>(s, s->L.p_force) : nullptr, s->K.lt, pm, pk, at<double>(s, s->L.chunk_out));
+  k_reduce<<<s->nrep, BLOCK, 0, st>>>(R, at<RepState>(s, s->L.state), at<double>(s, s->L.chunk_out), out);
   return check_launch();
 }
 
 MD_API int md_run(md_system* s, const md_atoms* a, const md_lists* l, int32_t nsteps, uint32_t flags,
-                  int32_t energy_every, double* obs, void* const* events, void* stream) {
+                  int32_t energy_every, double* obs, const md_trace* trace, void* stream) {
   if (!s || !atoms_ok(a) || !lists_ok(l) || nsteps < 0) return MD_ERR_ARG;
   if (energy_every > 0 && !obs) return MD_ERR_ARG;
-  if (!s->ws) return MD_ERR_STATE;
+  if (!bound(s)) return MD_ERR_STATE;
   hipStream_t st = (hipStream_t)stream;
   const uint32_t mixed = flags & MD_F_MIXED;
   int e;
@@ -685,17 +755,24 @@ MD_API int md_run(md_system* s, const md_atoms* a, const md_lists* l, int32_t ns
     const bool full = k < nsteps && !en;
     const bool drift = full && !s->K.shadow;
     if (!drifted) launch_kick_drift(s, a, st, whole);
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    if (events)
-      for (int u = 0; u < 4; ++u) ev[u] = (hipEvent_t)events[4 * (k - 1) + u];
+    hipEvent_t ev[MD_TRACE_EVENTS] = {};
+    if (trace && trace->events)
+      for (int u = 0; u < MD_TRACE_EVENTS; ++u) ev[u] = (hipEvent_t)trace->events[MD_TRACE_EVENTS * (k - 1) + u];
     if ((e = build_chain(s, a, l, 0, st, ev[2], ev[3]))) return e;
     // Task 4c runs in the density launch; the force pass includes it and gives the kick
     const bool morse = s->ctot > 0;
     const uint32_t ef = mixed | (en ? MD_F_ENERGY : 0);
+    if (ev[4] && (e = hip_status(hipEventRecord(ev[4], st)))) return e;
     if ((e = eam_density(s, a, l, MD_F_DENSITY | ef, nullptr, morse, st))) return e;
+    if (ev[5] && (e = hip_status(hipEventRecord(ev[5], st)))) return e;
     if (ev[0] && (e = hip_status(hipEventRecord(ev[0], st)))) return e;
     if ((e = eam_force(s, a, l, MD_F_FORCE | MD_F_KICK | ef, morse, st, full, drift))) return e;
     if (ev[1] && (e = hip_status(hipEventRecord(ev[1], st)))) return e;
+    if (trace && trace->builds) {
+      k_record_builds<<<(s->nrep + BLOCK - 1) / BLOCK, BLOCK, 0, st>>>(
+          at<RepState>(s, s->L.state), s->nrep, trace->builds + (int64_t)(k - 1) * s->nrep);
+      if ((e = check_launch())) return e;
+    }
     if (drift) {
       s->cur ^= 1;
       s->ppt = s->K.lt;
@@ -752,9 +829,16 @@ MD_API int md_graph_destroy(void* graph_exec) {
   return hip_status(hipGraphExecDestroy((hipGraphExec_t)graph_exec));
 }
 
+MD_API int md_set_indenter_velocity(md_system* s, double v_ind) {
+  if (!s || !std::isfinite(v_ind)) return MD_ERR_ARG;
+  s->p.v_ind = v_ind;
+  s->K.v_ind = v_ind;
+  return MD_OK;
+}
+
 MD_API int md_check(md_system* s, md_status* st_out, void* stream) {
   if (!s || !st_out) return MD_ERR_ARG;
-  if (!s->ws) return MD_ERR_STATE;
+  if (!bound(s)) return MD_ERR_STATE;
   hipStream_t st = (hipStream_t)stream;
   int* misc = at<int>(s, s->L.misc);
   k_status<<<1, 64, 0, st>>>(at<RepState>(s, s->L.state), s->nrep, misc + 8);
@@ -775,7 +859,7 @@ MD_API int md_check(md_system* s, md_status* st_out, void* stream) {
 
 MD_API int md_clear_flags(md_system* s, void* stream) {
   if (!s) return MD_ERR_ARG;
-  if (!s->ws) return MD_ERR_STATE;
+  if (!bound(s)) return MD_ERR_STATE;
   hipStream_t st = (hipStream_t)stream;
   k_clear_flags<<<(s->nrep + 63) / 64, 64, 0, st>>>(at<RepState>(s, s->L.state), s->nrep);
   // a build that gave up left its cell counts behind: zero them and lift the abort word

@@ -28,6 +28,7 @@ struct RepDesc {
                         // use along open axes follow the atoms, see RepState)
   int h0, hd[3];        // Cr-C cell grid: first cell (global, after all Cr grids), dims
   int rb0, nseg;        // list build: first cell row at capacity (global numbering), most runs per row
+  int ch0, nch;         // energy sums: first chunk of tiles, chunk count
   double ginv[3];       // cells per Angstrom of the Cr grid along periodic axes
   double hinv[3];       // cells per Angstrom of the carbon grid
 };
@@ -75,6 +76,68 @@ __device__ __forceinline__ int4 cell_local(const RepState& s, long long bc, doub
                    (int)rint((z - (s.glo[2] + (cz + 0.5) * s.gedge[2])) * s.qscale), __float_as_int(w));
 }
 
+// The paper's EAM form (Appendix, Eqs. A1-A4), in the terms the kernels use.
+struct PaperConsts {
+  double Fo, n, rho_e, alpha, P_e, fe, re, beta;
+  double a0, a1, a2, a3, d;
+  double rc_sq;       // f (and f^2) for r < rc
+  double phi_sq;      // Phi for r < d re
+  double inv_re, re2;
+  double b0, b1, b2, b3;   // the same cubic in t = x - 1 (b_k = poly^(k)(1) / k!, in FP64): its
+                           // terms stay small near the neighbour shells, so FP32 evaluation does
+                           // not lose digits to the cancelling large a_k
+  int bh;             // beta / 2 when it is a whole number 1..8 (then f needs r^2 only), else 0
+};
+
+// f(r) = fe (re / r)^beta from r^2 and 1/r: (re^2 / r^2)^(beta/2) by repeated squaring when
+// beta / 2 is a whole number, else through pow.
+__device__ __forceinline__ double paper_f(const PaperConsts& P, double rinv) {
+  if (P.bh > 0) {
+    const double t = P.re2 * (rinv * rinv);
+    double f = 1.0, b = t;
+    for (int e = P.bh; e; e >>= 1) {   // uniform over the wavefront
+      if (e & 1) f *= b;
+      b *= b;
+    }
+    return P.fe * f;
+  }
+  return P.fe * pow(P.re * rinv, P.beta);
+}
+__device__ __forceinline__ float paper_f32(const PaperConsts& P, float rinv) {
+  if (P.bh > 0) {
+    const float t = (float)P.re2 * (rinv * rinv);
+    float f = 1.0f, b = t;
+    for (int e = P.bh; e; e >>= 1) {
+      if (e & 1) f *= b;
+      b *= b;
+    }
+    return (float)P.fe * f;
+  }
+  return (float)P.fe * __powf((float)P.re * rinv, (float)P.beta);
+}
+
+// Per atom: F(rho), F'(rho) (0 without neighbours), M(P), M'(P) of Eq. A3, in FP64.
+//   F' = Fo n^2 (rho/rho_e)^n ln(rho/rho_e) / rho;  M' = (2 alpha / P_e) u (1 - u^2) exp(-u^2),
+//   u = P / P_e - 1.
+struct PaperEmbed {
+  double F, dF, M, dM;
+};
+__device__ __forceinline__ PaperEmbed paper_embed(const PaperConsts& P, double rho, double p) {
+  PaperEmbed e;
+  if (rho > 0.0) {
+    const double lt = log(rho / P.rho_e), tn = exp(P.n * lt);
+    e.F = -P.Fo * (1.0 - P.n * lt) * tn;
+    e.dF = P.Fo * P.n * P.n * tn * lt / rho;
+  } else {
+    e.F = 0.0;
+    e.dF = 0.0;
+  }
+  const double u = p / P.P_e - 1.0, w = exp(-u * u);
+  e.M = P.alpha * u * u * w;
+  e.dM = 2.0 * P.alpha / P.P_e * u * (1.0 - u * u) * w;
+  return e;
+}
+
 // Constants of the potential and the integrator (passed by value).
 struct Consts {
   // EAM
@@ -95,7 +158,9 @@ struct Consts {
   int lt;                 // list interleave: entries k..k+lt-1 of an atom are adjacent
   int lt_shift;           // log2(lt)
   int shadow;             // 1: keep the FP32 cell-local shadow of the positions
+  int pot;                // MD_POT_FS or MD_POT_PAPER
   int64_t ntot;           // atom slots (all replicas)
+  PaperConsts P;          // the paper's form (pot == MD_POT_PAPER)
 };
 
 // Order-preserving map of a double to an unsigned 64-bit integer (for atomic min/max).
@@ -192,6 +257,31 @@ __device__ __forceinline__ double min_image(double d, double len, double half, i
   double s = (per && d > half) ? -len : 0.0;
   s = (per && d < -half) ? len : s;
   return d + s;
+}
+
+// 1/sqrt(x) for a positive normal x: the hardware estimate refined by one cubic Newton step
+// (y (1 + e/2 + 3 e^2 / 8) with e = 1 - x y^2), accurate to about an ulp.  The same
+// steps as the math library's rsqrt without its fix-up of zero, infinite and denormal
+// arguments, which the callers never pass.
+__device__ __forceinline__ double rsq_nr(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
+// True if some live atom of the wavefront lies within `margin` of a periodic face of its
+// replica's box (every lane calls it).  A listed pair can cross a face only if one of its
+// atoms was within r_list of that face at the build and has moved less than skin / 2 since,
+// so with margin = r_list + skin every listed pair of a wavefront for which this is false
+// has its minimum image equal to the plain difference of the positions.
+__device__ __forceinline__ bool wave_near_face(const RepDesc& d, bool live, double x, double y, double z,
+                                               double margin) {
+  const double p[3] = {x, y, z};
+  bool near = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    near |= d.per[a] && !(p[a] - d.lo[a] >= margin && d.lo[a] + d.len[a] - p[a] >= margin);
+  return __ballot(live && near) != 0;
 }
 
 // Squared length (dx dx + dy dy) + dz dz with every product and sum rounded on its own:

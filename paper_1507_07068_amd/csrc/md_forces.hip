@@ -12,6 +12,8 @@
 // by one lane only: no atomics.
 #pragma once
 
+#include <type_traits>
+
 #include "md_device.hpp"
 
 namespace md {
@@ -36,27 +38,37 @@ constexpr int UNROLL = MD_UNROLL;
 template <int T, int U, class Fetch, class Body>
 __device__ __forceinline__ void for_entries(const int* __restrict__ idx, int i, int n, int sub, int ntot,
                                             int shift, Fetch fetch, Body body) {
-  int k = sub;
+  // this lane's entries k = sub + m T (m = 0 .. nl - 1) sit one stride apart, at
+  // idx[(m ntot + i) T + sub]; 32-bit word offsets (the list holds fewer than 2^31 words),
+  // running by the stride, and the index loads ahead clamped to the last entry so that they
+  // need no branch
+  const int nl = n > sub ? ((n - 1 - sub) >> shift) + 1 : 0;
+  if (nl == 0) return;
+  const unsigned stride = (unsigned)ntot * T;
+  const unsigned first = (unsigned)i * T + sub;
+  const unsigned last = first + (unsigned)(nl - 1) * stride;
+  unsigned base = first;   // offset of entry m
   int e[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) e[u] = (k + u * T < n) ? idx[list_pos(k + u * T, i, ntot, T, shift)] : 0;
-  for (; k + (U - 1) * T < n; k += U * T) {
+  for (int u = 0; u < U; ++u) e[u] = idx[min(base + u * stride, last)];
+  int m = 0;
+  for (; m + U <= nl; m += U) {
     decltype(fetch(0)) p[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) p[u] = fetch(e[u]);
+    base += U * stride;
     int en[U];
-    const int kn = k + U * T;
 #pragma unroll
-    for (int u = 0; u < U; ++u) en[u] = (kn + u * T < n) ? idx[list_pos(kn + u * T, i, ntot, T, shift)] : 0;
+    for (int u = 0; u < U; ++u) en[u] = idx[min(base + u * stride, last)];
 #pragma unroll
     for (int u = 0; u < U; ++u) body(p[u], e[u]);
 #pragma unroll
     for (int u = 0; u < U; ++u) e[u] = en[u];
   }
-  // fewer than U entries remain (k + (U - 1) T >= n); their indices are already in e[]
+  // fewer than U entries remain (m + U > nl); their indices are already in e[]
 #pragma unroll
   for (int u = 0; u < U - 1; ++u)
-    if (k + u * T < n) body(fetch(e[u]), e[u]);
+    if (m + u < nl) body(fetch(e[u]), e[u]);
 }
 
 // Offsets of the 27 relative cells of a list entry in the block's replica, in shadow units:
@@ -141,9 +153,11 @@ __device__ __forceinline__ void morse_pass(const Consts& K, const RepDesc* __res
             em += (double)((float)K.D * (e * e - 2.0f * e)) - K.mshift;
           }
         } else {
-          const double r2 = ex * ex + ey * ey + ez * ez;
-          if (r2 < K.mrc_sq) {
-            const double rr = sqrt(r2);
+          // the cutoff test on r = sqrt((ex ex + ey ey) + ez ez), rounded exactly as the plain
+          // definition does it: the unshifted force jumps at the cutoff, so a pair within an
+          // ulp of it must fall on the same side
+          const double rr = sqrt(dist_sq_exact(ex, ey, ez));
+          if (rr < K.mrc) {
             const double e = exp(-K.alpha * (rr - K.r0));
             const double g = 2.0 * K.alpha * K.D * (e - e * e);
             const double s = g / rr;
@@ -217,7 +231,9 @@ struct MorseIn {
 
 // SHADOW (with MIXED): separations from the fixed-point cell-local shadow qs and the entries'
 // relative cells; otherwise FP64 positions (rounded to FP32 for the MIXED arithmetic).
-template <int T, bool MIXED, bool SHADOW, bool ENERGY>
+// PAPER: the paper's form -- rho_i = sum f, P_i = sum f^2, F'(rho_i) into q.w and M'(P_i)
+// into dm[i] (the second derivative of the paper's per-atom array).
+template <int T, bool MIXED, bool SHADOW, bool ENERGY, bool PAPER = false>
 __global__ __launch_bounds__(BLOCK) void k_density(Consts K, const RepDesc* __restrict__ R,
                                                    RepState* __restrict__ S,
                                                    const int* __restrict__ tile_rep,
@@ -226,7 +242,8 @@ __global__ __launch_bounds__(BLOCK) void k_density(Consts K, const RepDesc* __re
                                                    const int* __restrict__ idx,
                                                    const int* __restrict__ cnt,
                                                    double* __restrict__ rho_out,
-                                                   double* __restrict__ part, MorseIn M) {
+                                                   double* __restrict__ part, MorseIn M,
+                                                   double* __restrict__ dm) {
   if ((int)blockIdx.x < M.nblocks) {   // uniform over the block
     morse_pass<MIXED, false, false>(K, R, S, q, nullptr, nullptr, nullptr, M.xc, M.xidx, M.xcnt, M.near, M.fme,
                                     blockIdx.x, M.nblocks);
@@ -236,11 +253,67 @@ __global__ __launch_bounds__(BLOCK) void k_density(Consts K, const RepDesc* __re
   const RepDesc& d = R[c.r];
   __shared__ int4 ctab[27];
   if (SHADOW) fill_cell_offsets(ctab, S[c.r]);
-  double rho = 0.0;
+  // FP64 separations: the minimum image only in wavefronts with an atom near a periodic face
+  const double4 pi = (!SHADOW && c.live) ? q[c.i] : make_double4(0.0, 0.0, 0.0, 0.0);
+  const bool img = !SHADOW && wave_near_face(d, c.live, pi.x, pi.y, pi.z, K.rlist + 2.0 * K.half_skin);
+  double rho = 0.0, pp = 0.0;   // pp: P_i (paper's form)
   if (c.live) {
     const int64_t i = c.i;
     const int n = cnt[i];
-    if (MIXED && SHADOW) {
+    if constexpr (PAPER) {
+      if (MIXED) {
+        float ar = 0.0f, ap = 0.0f;
+        const float rcs = (float)K.P.rc_sq;
+        auto add = [&](float ex, float ey, float ez) {
+          const float r2 = ex * ex + ey * ey + ez * ez;
+          const bool in = r2 < rcs;
+          const float f = paper_f32(K.P, __frsqrt_rn(in ? r2 : 1.0f));
+          ar += in ? f : 0.0f;
+          ap += in ? f * f : 0.0f;
+        };
+        if (SHADOW) {
+          const int4 ps = qs[i];
+          const float qi = (float)(1.0 / S[c.r].qscale);
+          for_entries<T, UNROLL>(idx, (int)i, n, c.sub, (int)K.ntot, K.lt_shift,
+                                 [&](int e) { return qs[list_slot(e)]; },
+                                 [&](const int4& pj, int e) {
+            const int4 o = ctab[list_code(e)];
+            add((float)(pj.x - ps.x + o.x) * qi, (float)(pj.y - ps.y + o.y) * qi, (float)(pj.z - ps.z + o.z) * qi);
+          });
+        } else {
+          auto pass = [&](auto img_c) {
+            constexpr bool IMG = decltype(img_c)::value;
+            for_entries<T, UNROLL>(idx, (int)i, n, c.sub, (int)K.ntot, K.lt_shift,
+                                   [&](int e) { return q[list_slot(e)]; },
+                                   [&](const double4& pj, int) {
+              add((float)(IMG ? min_image(pj.x - pi.x, d.len[0], d.half[0], d.per[0]) : pj.x - pi.x),
+                  (float)(IMG ? min_image(pj.y - pi.y, d.len[1], d.half[1], d.per[1]) : pj.y - pi.y),
+                  (float)(IMG ? min_image(pj.z - pi.z, d.len[2], d.half[2], d.per[2]) : pj.z - pi.z));
+            });
+          };
+          if (img) pass(std::true_type{}); else pass(std::false_type{});
+        }
+        rho = (double)ar;
+        pp = (double)ap;
+      } else {
+        auto pass = [&](auto img_c) {
+          constexpr bool IMG = decltype(img_c)::value;
+          for_entries<T, UNROLL>(idx, (int)i, n, c.sub, (int)K.ntot, K.lt_shift,
+                                 [&](int e) { return q[list_slot(e)]; },
+                                 [&](const double4& pj, int) {
+            const double ex = IMG ? min_image(pj.x - pi.x, d.len[0], d.half[0], d.per[0]) : pj.x - pi.x;
+            const double ey = IMG ? min_image(pj.y - pi.y, d.len[1], d.half[1], d.per[1]) : pj.y - pi.y;
+            const double ez = IMG ? min_image(pj.z - pi.z, d.len[2], d.half[2], d.per[2]) : pj.z - pi.z;
+            const double r2 = ex * ex + ey * ey + ez * ez;
+            const bool in = r2 < K.P.rc_sq;
+            const double f = paper_f(K.P, rsq_nr(in ? r2 : 1.0));
+            rho += in ? f : 0.0;
+            pp += in ? f * f : 0.0;
+          });
+        };
+        if (img) pass(std::true_type{}); else pass(std::false_type{});
+      }
+    } else if (MIXED && SHADOW) {
       const int4 ps = qs[i];
       const float qi = (float)(1.0 / S[c.r].qscale);
       float acc = 0.0f;
@@ -257,43 +330,61 @@ __global__ __launch_bounds__(BLOCK) void k_density(Consts K, const RepDesc* __re
       });
       rho = (double)acc;
     } else if (MIXED) {
-      const double4 pi = q[i];
       float acc = 0.0f;
       const float dd = (float)K.d, dd2 = (float)K.d_sq;
-      for_entries<T, UNROLL>(idx, (int)i, n, c.sub, (int)K.ntot, K.lt_shift,
-                             [&](int e) { return q[list_slot(e)]; },
-                             [&](const double4& pj, int) {
-        const float ex = (float)min_image(pj.x - pi.x, d.len[0], d.half[0], d.per[0]);
-        const float ey = (float)min_image(pj.y - pi.y, d.len[1], d.half[1], d.per[1]);
-        const float ez = (float)min_image(pj.z - pi.z, d.len[2], d.half[2], d.per[2]);
-        const float r2 = ex * ex + ey * ey + ez * ez;
-        const float u = __fsqrt_rn(r2) - dd;
-        acc += (r2 < dd2) ? u * u : 0.0f;
-      });
+      auto pass = [&](auto img_c) {
+        constexpr bool IMG = decltype(img_c)::value;
+        for_entries<T, UNROLL>(idx, (int)i, n, c.sub, (int)K.ntot, K.lt_shift,
+                               [&](int e) { return q[list_slot(e)]; },
+                               [&](const double4& pj, int) {
+          const float ex = (float)(IMG ? min_image(pj.x - pi.x, d.len[0], d.half[0], d.per[0]) : pj.x - pi.x);
+          const float ey = (float)(IMG ? min_image(pj.y - pi.y, d.len[1], d.half[1], d.per[1]) : pj.y - pi.y);
+          const float ez = (float)(IMG ? min_image(pj.z - pi.z, d.len[2], d.half[2], d.per[2]) : pj.z - pi.z);
+          const float r2 = ex * ex + ey * ey + ez * ez;
+          const float u = __fsqrt_rn(r2) - dd;
+          acc += (r2 < dd2) ? u * u : 0.0f;
+        });
+      };
+      if (img) pass(std::true_type{}); else pass(std::false_type{});
       rho = (double)acc;
     } else {
-      const double4 pi = q[i];
-      for_entries<T, UNROLL>(idx, (int)i, n, c.sub, (int)K.ntot, K.lt_shift,
-                             [&](int e) { return q[list_slot(e)]; },
-                             [&](const double4& pj, int) {
-        const double ex = min_image(pj.x - pi.x, d.len[0], d.half[0], d.per[0]);
-        const double ey = min_image(pj.y - pi.y, d.len[1], d.half[1], d.per[1]);
-        const double ez = min_image(pj.z - pi.z, d.len[2], d.half[2], d.per[2]);
-        const double r2 = ex * ex + ey * ey + ez * ez;
-        const double u = sqrt(r2) - K.d;
-        rho += (r2 < K.d_sq) ? u * u : 0.0;
-      });
+      auto pass = [&](auto img_c) {
+        constexpr bool IMG = decltype(img_c)::value;
+        for_entries<T, UNROLL>(idx, (int)i, n, c.sub, (int)K.ntot, K.lt_shift,
+                               [&](int e) { return q[list_slot(e)]; },
+                               [&](const double4& pj, int) {
+          const double ex = IMG ? min_image(pj.x - pi.x, d.len[0], d.half[0], d.per[0]) : pj.x - pi.x;
+          const double ey = IMG ? min_image(pj.y - pi.y, d.len[1], d.half[1], d.per[1]) : pj.y - pi.y;
+          const double ez = IMG ? min_image(pj.z - pi.z, d.len[2], d.half[2], d.per[2]) : pj.z - pi.z;
+          const double r2 = ex * ex + ey * ey + ez * ez;
+          const bool in = r2 < K.d_sq;
+          const double u = r2 * rsq_nr(in ? r2 : 1.0) - K.d;   // r - d (r = r2 / sqrt(r2))
+          rho += in ? u * u : 0.0;
+        });
+      };
+      if (img) pass(std::true_type{}); else pass(std::false_type{});
     }
   }
   rho = group_sum<T>(rho);
+  if (PAPER) pp = group_sum<T>(pp);
   double e_embed = 0.0;
   if (c.live && c.sub == 0) {
-    const double sr = sqrt(rho);
-    const double dF = rho > 0.0 ? -K.A / (2.0 * sr) : 0.0;
+    double dF, en;
+    if constexpr (PAPER) {
+      const PaperEmbed pe = paper_embed(K.P, rho, pp);
+      dF = pe.dF;
+      en = pe.F + pe.M;
+      dm[c.i] = pe.dM;
+      if (!(pp == pp)) S[c.r].nonfinite = 1;
+    } else {
+      const double sr = sqrt(rho);
+      dF = rho > 0.0 ? -K.A / (2.0 * sr) : 0.0;
+      en = -K.A * sr;
+    }
     q[c.i].w = dF;
     if (SHADOW) qs[c.i].w = __float_as_int((float)dF);
     if (rho_out) rho_out[c.i] = rho;
-    if (ENERGY) e_embed = -K.A * sr;
+    if (ENERGY) e_embed = en;
     if (!(rho == rho)) S[c.r].nonfinite = 1;
   }
   if (ENERGY) {
@@ -318,8 +409,24 @@ struct DriftOut {
   double* tbox;           // [6 (tile * T + part) + ...]
 };
 
-template <int T, bool MIXED, bool SHADOW, bool KICK, bool ENERGY, bool DRIFT = false>
-__global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __restrict__ R,
+// Occupancy floor of the force pass (wavefronts per SIMD its registers must allow).
+#ifndef MD_FORCE_WAVES
+#define MD_FORCE_WAVES 1
+#endif
+
+// A neighbour's record with its M'(P_j) (paper's form).
+struct QM {
+  double4 q;
+  double m;
+};
+struct SM {
+  int4 q;
+  double m;
+};
+
+// PAPER: the paper's form, dm[j] = M'(P_j) from the density pass.
+template <int T, bool MIXED, bool SHADOW, bool KICK, bool ENERGY, bool DRIFT = false, bool PAPER = false>
+__global__ __launch_bounds__(BLOCK, MD_FORCE_WAVES) void k_force(Consts K, const RepDesc* __restrict__ R,
                                                  RepState* __restrict__ S,
                                                  const int* __restrict__ tile_rep,
                                                  const double4* __restrict__ q,
@@ -331,11 +438,14 @@ __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __rest
                                                  double* __restrict__ part,
                                                  const int* __restrict__ xcnt,
                                                  const double* __restrict__ fme, double kick_h,
-                                                 DriftOut D) {
+                                                 DriftOut D, const double* __restrict__ dm) {
   const AtomCtx c = atom_ctx<T>(tile_rep, R, blockIdx.x, gridDim.x);
   const RepDesc& d = R[c.r];
   __shared__ int4 ctab[27];
   if (SHADOW) fill_cell_offsets(ctab, S[c.r]);
+  // FP64 separations: the minimum image only in wavefronts with an atom near a periodic face
+  const double4 pi = (!SHADOW && c.live) ? q[c.i] : make_double4(0.0, 0.0, 0.0, 0.0);
+  const bool img = !SHADOW && wave_near_face(d, c.live, pi.x, pi.y, pi.z, K.rlist + 2.0 * K.half_skin);
   double acc[NP_FORCE];
 #pragma unroll
   for (int k = 0; k < NP_FORCE; ++k) acc[k] = 0.0;
@@ -343,11 +453,122 @@ __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __rest
   if (c.live) {
     const int64_t i = c.i;
     const int n = cnt[i];
-    if (MIXED) {
+    if constexpr (PAPER) {
+      // dE/dr = Phi'(r) [x < d] + f'(r) [r < rc] ((F'_i + F'_j) + (M'_i + M'_j) 2 f(r)), Phi' by
+      // Horner in x = r / re; all lanes evaluate and the cutoffs select, with F'_j and M'_j
+      // used on every path (so the neighbour's record is loaded ahead of the arithmetic)
+      const PaperConsts& P = K.P;
+      if (MIXED) {
+        const float rcs = (float)P.rc_sq, phs = (float)P.phi_sq, ire = (float)P.inv_re, dd = (float)P.d,
+                    b0 = (float)P.b0, b1 = (float)P.b1, b2 = (float)P.b2, b3 = (float)P.b3, beta = (float)P.beta;
+        float ax = 0.f, ay = 0.f, az = 0.f;
+        double ep = 0.0, w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0, w4 = 0.0, w5 = 0.0;
+        auto pair = [&](float ex, float ey, float ez, float Fij, float Mij) {
+          const float r2 = ex * ex + ey * ey + ez * ez;
+          const bool in_f = r2 < rcs, in_p = r2 < phs, inc = in_f || in_p;
+          const float rinv = __frsqrt_rn(inc ? r2 : 1.0f);
+          const float r = r2 * rinv, x = r * ire, u = x - dd, t = x - 1.0f;
+          const float poly = ((b3 * t + b2) * t + b1) * t + b0, dpoly = (3.0f * b3 * t + 2.0f * b2) * t + b1;
+          const float fr = paper_f32(P, rinv);
+          const float dfr = in_f ? -beta * fr * rinv : 0.0f;
+          const float g = (in_p ? (2.0f * u * poly + u * u * dpoly) * ire : 0.0f) + dfr * (Fij + Mij * (2.0f * fr));
+          const float sc = inc ? g * rinv : 0.0f;
+          ax += sc * ex;
+          ay += sc * ey;
+          az += sc * ez;
+          if (ENERGY) {
+            ep += (double)(in_p ? 0.5f * u * u * poly : 0.0f);
+            const float hs = 0.5f * sc;
+            w0 -= (double)(hs * ex * ex);
+            w1 -= (double)(hs * ey * ey);
+            w2 -= (double)(hs * ez * ez);
+            w3 -= (double)(hs * ex * ey);
+            w4 -= (double)(hs * ex * ez);
+            w5 -= (double)(hs * ey * ez);
+          }
+        };
+        const float Mi = (float)dm[i];
+        if (SHADOW) {
+          const int4 ps = qs[i];
+          const float qi = (float)(1.0 / S[c.r].qscale);
+          const float Fi = __int_as_float(ps.w);
+          for_entries<T, UNROLL>(idx, (int)i, n, c.sub, (int)K.ntot, K.lt_shift,
+                                 [&](int e) { const int j = list_slot(e); return SM{qs[j], dm[j]}; },
+                                 [&](const SM& pj, int e) {
+            const int4 o = ctab[list_code(e)];
+            pair((float)(pj.q.x - ps.x + o.x) * qi, (float)(pj.q.y - ps.y + o.y) * qi,
+                 (float)(pj.q.z - ps.z + o.z) * qi, Fi + __int_as_float(pj.q.w), Mi + (float)pj.m);
+          });
+        } else {
+          const float Fi = (float)pi.w;
+          auto pass = [&](auto img_c) {
+            constexpr bool IMG = decltype(img_c)::value;
+            for_entries<T, UNROLL>(idx, (int)i, n, c.sub, (int)K.ntot, K.lt_shift,
+                                   [&](int e) { const int j = list_slot(e); return QM{q[j], dm[j]}; },
+                                   [&](const QM& pj, int) {
+              pair((float)(IMG ? min_image(pj.q.x - pi.x, d.len[0], d.half[0], d.per[0]) : pj.q.x - pi.x),
+                   (float)(IMG ? min_image(pj.q.y - pi.y, d.len[1], d.half[1], d.per[1]) : pj.q.y - pi.y),
+                   (float)(IMG ? min_image(pj.q.z - pi.z, d.len[2], d.half[2], d.per[2]) : pj.q.z - pi.z),
+                   Fi + (float)pj.q.w, Mi + (float)pj.m);
+            });
+          };
+          if (img) pass(std::true_type{}); else pass(std::false_type{});
+        }
+        fx = ax;
+        fy = ay;
+        fz = az;
+        if (ENERGY) {
+          acc[P_PAIR] = ep;
+          acc[P_WXX] = w0;
+          acc[P_WYY] = w1;
+          acc[P_WZZ] = w2;
+          acc[P_WXY] = w3;
+          acc[P_WXZ] = w4;
+          acc[P_WYZ] = w5;
+        }
+      } else {
+        const double Fi = pi.w, Mi = dm[i];
+        auto pass = [&](auto img_c) {
+          constexpr bool IMG = decltype(img_c)::value;
+          for_entries<T, UNROLL>(idx, (int)i, n, c.sub, (int)K.ntot, K.lt_shift,
+                                 [&](int e) { const int j = list_slot(e); return QM{q[j], dm[j]}; },
+                                 [&](const QM& pj, int) {
+            const double ex = IMG ? min_image(pj.q.x - pi.x, d.len[0], d.half[0], d.per[0]) : pj.q.x - pi.x;
+            const double ey = IMG ? min_image(pj.q.y - pi.y, d.len[1], d.half[1], d.per[1]) : pj.q.y - pi.y;
+            const double ez = IMG ? min_image(pj.q.z - pi.z, d.len[2], d.half[2], d.per[2]) : pj.q.z - pi.z;
+            const double r2 = ex * ex + ey * ey + ez * ez;
+            const bool in_f = r2 < P.rc_sq, in_p = r2 < P.phi_sq, inc = in_f || in_p;
+            const double rinv = rsq_nr(inc ? r2 : 1.0);
+            const double r = r2 * rinv, x = r * P.inv_re, u = x - P.d;
+            const double poly = ((P.a3 * x + P.a2) * x + P.a1) * x + P.a0;
+            const double dpoly = (3.0 * P.a3 * x + 2.0 * P.a2) * x + P.a1;
+            const double fr = paper_f(P, rinv);
+            const double dfr = in_f ? -P.beta * fr * rinv : 0.0;
+            const double g = (in_p ? (2.0 * u * poly + u * u * dpoly) * P.inv_re : 0.0) +
+                             dfr * ((Fi + pj.q.w) + (Mi + pj.m) * (2.0 * fr));
+            const double sc = inc ? g * rinv : 0.0;
+            fx += sc * ex;
+            fy += sc * ey;
+            fz += sc * ez;
+            if (ENERGY) {
+              acc[P_PAIR] += in_p ? 0.5 * u * u * poly : 0.0;
+              acc[P_WXX] -= 0.5 * sc * ex * ex;
+              acc[P_WYY] -= 0.5 * sc * ey * ey;
+              acc[P_WZZ] -= 0.5 * sc * ez * ez;
+              acc[P_WXY] -= 0.5 * sc * ex * ey;
+              acc[P_WXZ] -= 0.5 * sc * ex * ez;
+              acc[P_WYZ] -= 0.5 * sc * ey * ez;
+            }
+          });
+        };
+        if (img) pass(std::true_type{}); else pass(std::false_type{});
+      }
+    } else if (MIXED) {
       const float cc = (float)K.c, dd = (float)K.d, c2 = (float)K.c2, rv = (float)K.rv,
                   pmin = (float)K.pmin, csq = (float)K.c_sq, dsq = (float)K.d_sq;
       float ax = 0.f, ay = 0.f, az = 0.f;
-      float ep = 0.f, w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f, w4 = 0.f, w5 = 0.f;
+      // energy and virial terms are FP32 products, summed in FP64
+      double ep = 0.0, w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0, w4 = 0.0, w5 = 0.0;
       // pair term for separation (ex, ey, ez) and neighbour F' fj
       auto pair = [&](float ex, float ey, float ez, float Fi, float fj) {
         const float r2 = ex * ex + ey * ey + ez * ez;
@@ -364,13 +585,14 @@ __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __rest
         ay += s * ey;
         az += s * ez;
         if (ENERGY) {
-          ep += inc ? 0.5f * u * u * p : 0.0f;
-          w0 -= 0.5f * s * ex * ex;
-          w1 -= 0.5f * s * ey * ey;
-          w2 -= 0.5f * s * ez * ez;
-          w3 -= 0.5f * s * ex * ey;
-          w4 -= 0.5f * s * ex * ez;
-          w5 -= 0.5f * s * ey * ez;
+          ep += (double)(inc ? 0.5f * u * u * p : 0.0f);
+          const float hs = 0.5f * s;
+          w0 -= (double)(hs * ex * ex);
+          w1 -= (double)(hs * ey * ey);
+          w2 -= (double)(hs * ez * ez);
+          w3 -= (double)(hs * ex * ey);
+          w4 -= (double)(hs * ex * ez);
+          w5 -= (double)(hs * ey * ez);
         }
       };
       if (SHADOW) {
@@ -385,15 +607,19 @@ __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __rest
                (float)(pj.z - ps.z + o.z) * qi, Fi, __int_as_float(pj.w));
         });
       } else {
-        const double4 pi = q[i];
         const float Fi = (float)pi.w;
-        for_entries<T, UNROLL>(idx, (int)i, n, c.sub, (int)K.ntot, K.lt_shift,
-                               [&](int e) { return q[list_slot(e)]; },
-                               [&](const double4& pj, int) {
-          pair((float)min_image(pj.x - pi.x, d.len[0], d.half[0], d.per[0]),
-               (float)min_image(pj.y - pi.y, d.len[1], d.half[1], d.per[1]),
-               (float)min_image(pj.z - pi.z, d.len[2], d.half[2], d.per[2]), Fi, (float)pj.w);
-        });
+        auto pass = [&](auto img_c) {
+          constexpr bool IMG = decltype(img_c)::value;
+          for_entries<T, UNROLL>(idx, (int)i, n, c.sub, (int)K.ntot, K.lt_shift,
+                                 [&](int e) { return q[list_slot(e)]; },
+                                 [&](const double4& pj, int) {
+            pair((float)(IMG ? min_image(pj.x - pi.x, d.len[0], d.half[0], d.per[0]) : pj.x - pi.x),
+                 (float)(IMG ? min_image(pj.y - pi.y, d.len[1], d.half[1], d.per[1]) : pj.y - pi.y),
+                 (float)(IMG ? min_image(pj.z - pi.z, d.len[2], d.half[2], d.per[2]) : pj.z - pi.z), Fi,
+                 (float)pj.w);
+          });
+        };
+        if (img) pass(std::true_type{}); else pass(std::false_type{});
       }
       fx = ax;
       fy = ay;
@@ -408,24 +634,27 @@ __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __rest
         acc[P_WYZ] = w5;
       }
     } else {
-      const double4 pi = q[i];
       const double Fi = pi.w;
+      auto pass = [&](auto img_c) {
+      constexpr bool IMG = decltype(img_c)::value;
       for_entries<T, UNROLL>(idx, (int)i, n, c.sub, (int)K.ntot, K.lt_shift,
                              [&](int e) { return q[list_slot(e)]; },
                              [&](const double4& pj, int) {
-        const double ex = min_image(pj.x - pi.x, d.len[0], d.half[0], d.per[0]);
-        const double ey = min_image(pj.y - pi.y, d.len[1], d.half[1], d.per[1]);
-        const double ez = min_image(pj.z - pi.z, d.len[2], d.half[2], d.per[2]);
+        const double ex = IMG ? min_image(pj.x - pi.x, d.len[0], d.half[0], d.per[0]) : pj.x - pi.x;
+        const double ey = IMG ? min_image(pj.y - pi.y, d.len[1], d.half[1], d.per[1]) : pj.y - pi.y;
+        const double ez = IMG ? min_image(pj.z - pi.z, d.len[2], d.half[2], d.per[2]) : pj.z - pi.z;
         const double r2 = ex * ex + ey * ey + ez * ez;
         // all lanes evaluate; the cutoffs select (no branch: the whole 32-byte gather is
         // consumed up front)
         const bool inc = r2 < K.c_sq;
-        const double rinv = rsqrt(inc ? r2 : 1.0);
+        const double rinv = rsq_nr(inc ? r2 : 1.0);
         const double r = r2 * rinv;
         const double u = r - K.c;
         const double p = K.c0 + r * (K.c1 + r * K.c2);
         double g = u * (2.0 * p + u * (K.c1 + 2.0 * K.c2 * r));     // phi'(r)
-        g += (r2 < K.d_sq) ? (Fi + pj.w) * (2.0 * (r - K.d)) : 0.0;
+        // F'_j used on every path (times zero beyond d), so that the whole record is loaded
+        // ahead of the arithmetic rather than its last word behind a branch
+        g += (Fi + pj.w) * ((r2 < K.d_sq) ? 2.0 * (r - K.d) : 0.0);
         const double s = inc ? g * rinv : 0.0;
         fx += s * ex;
         fy += s * ey;
@@ -440,6 +669,8 @@ __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __rest
           acc[P_WYZ] -= 0.5 * s * ey * ez;
         }
       });
+      };
+      if (img) pass(std::true_type{}); else pass(std::false_type{});
     }
   }
   fx = group_sum<T>(fx);
@@ -464,7 +695,7 @@ __global__ __launch_bounds__(BLOCK) void k_force(Consts K, const RepDesc* __rest
     double4 qi = make_double4(0.0, 0.0, 0.0, 0.0);
     double r0 = 0.0, r1 = 0.0, r2 = 0.0;
     if (DRIFT) {
-      qi = q[i];
+      qi = SHADOW ? q[i] : pi;   // (loaded above on the FP64-separation paths)
       r0 = D.xref[3 * i + 0];
       r1 = D.xref[3 * i + 1];
       r2 = D.xref[3 * i + 2];

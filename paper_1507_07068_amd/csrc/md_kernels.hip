@@ -155,31 +155,34 @@ __global__ __launch_bounds__(BLOCK) void k_kinetic(Consts K, const RepDesc* __re
   block_sum_store<4, BLOCK>(mo, p_morse + (int64_t)c.tile * 4);
 }
 
-// One block per replica: sums the partials of that replica's blocks in block order.
-// out[r][MD_NOBS].  Partial arrays that were not produced are passed as NULL; tpe / tpf are
-// the blocks per tile of the density / force launches that wrote p_embed / p_force.
-__global__ __launch_bounds__(BLOCK) void k_reduce(const RepDesc* __restrict__ R,
-                                                  const RepState* __restrict__ S,
-                                                  const double* __restrict__ p_embed, int tpe,
-                                                  const double* __restrict__ p_force, int tpf,
-                                                  const double* __restrict__ p_morse,
-                                                  const double* __restrict__ p_kin,
-                                                  double* __restrict__ out) {
-  const int r = blockIdx.x;
-  const RepDesc& d = R[r];
+// Task 4d sums in two fixed-order stages, so that a large replica's partials are read by
+// many blocks: each replica's tiles are cut into chunks of REDUCE_CHUNK tiles (the cut
+// depends only on the replica's own tile count, so a replica's sums do not depend on the
+// batch), one block sums a chunk's partials, then one block per replica sums its chunks in
+// order.  Partial arrays that were not produced are passed as NULL; tpe / tpf are the
+// blocks per tile of the density / force launches that wrote p_embed / p_force.
+constexpr int REDUCE_CHUNK = 512;
+
+__global__ __launch_bounds__(BLOCK) void k_reduce_chunks(const int2* __restrict__ chunks,
+                                                         const double* __restrict__ p_embed, int tpe,
+                                                         const double* __restrict__ p_force, int tpf,
+                                                         const double* __restrict__ p_morse,
+                                                         const double* __restrict__ p_kin,
+                                                         double* __restrict__ chunk_out) {
+  const int2 ch = chunks[blockIdx.x];   // first tile, tile count
   double acc[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) acc[k] = 0.0;
   if (p_embed)
-    for (int b = d.t0 * tpe + threadIdx.x; b < (d.t0 + d.nt) * tpe; b += BLOCK) acc[MD_E_EMBED] += p_embed[b];
+    for (int b = ch.x * tpe + threadIdx.x; b < (ch.x + ch.y) * tpe; b += BLOCK) acc[MD_E_EMBED] += p_embed[b];
   if (p_force)
-    for (int b = d.t0 * tpf + threadIdx.x; b < (d.t0 + d.nt) * tpf; b += BLOCK) {
+    for (int b = ch.x * tpf + threadIdx.x; b < (ch.x + ch.y) * tpf; b += BLOCK) {
       const double* pf = p_force + (int64_t)b * NP_FORCE;
       acc[MD_E_PAIR] += pf[P_PAIR];
 #pragma unroll
       for (int k = 0; k < 6; ++k) acc[MD_W_XX + k] += pf[P_WXX + k];
     }
-  for (int t = d.t0 + threadIdx.x; t < d.t0 + d.nt; t += BLOCK) {
+  for (int t = ch.x + threadIdx.x; t < ch.x + ch.y; t += BLOCK) {
     if (p_kin) acc[MD_E_KIN] += p_kin[t];
     if (p_morse) {
       const double* pm = p_morse + (int64_t)t * 4;
@@ -189,12 +192,35 @@ __global__ __launch_bounds__(BLOCK) void k_reduce(const RepDesc* __restrict__ R,
       acc[MD_F_IND_X + 2] += pm[3];
     }
   }
+  block_sum_store<16, BLOCK>(acc, chunk_out + (int64_t)blockIdx.x * 16);
+}
+
+// One block per replica: its chunks' sums in chunk order -> out[r][MD_NOBS].
+__global__ __launch_bounds__(BLOCK) void k_reduce(const RepDesc* __restrict__ R,
+                                                  const RepState* __restrict__ S,
+                                                  const double* __restrict__ chunk_out,
+                                                  double* __restrict__ out) {
+  const int r = blockIdx.x;
+  const RepDesc& d = R[r];
+  double acc[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+  for (int c = d.ch0 + threadIdx.x; c < d.ch0 + d.nch; c += BLOCK)
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k] += chunk_out[(int64_t)c * 16 + k];
   block_sum_store<16, BLOCK>(acc, out + (int64_t)r * MD_NOBS);
   if (threadIdx.x == 0) {
     out[(int64_t)r * MD_NOBS + MD_IND_Z] = S[r].ind_z;
     out[(int64_t)r * MD_NOBS + MD_NBUILDS] = (double)S[r].nbuilds;
     out[(int64_t)r * MD_NOBS + 15] = 0.0;
   }
+}
+
+// Each replica's list-build count (md_run's trace).
+__global__ __launch_bounds__(BLOCK) void k_record_builds(const RepState* __restrict__ S, int nrep,
+                                                         int* __restrict__ out) {
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  if (r < nrep) out[r] = S[r].nbuilds;
 }
 
 // Status flags, folded over replicas.

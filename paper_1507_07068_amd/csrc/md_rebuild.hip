@@ -33,6 +33,7 @@ struct BuildArgs {
   const int* row_rep;    // [nrows] replica of each cell row at capacity
   int2* items;           // [list-build blocks] work items of k_list_tiles: (row, run | runs << 16)
   int* nitems;           // work items of this build
+  int* next_item;        // the next work item a k_list_tiles block takes (reset with nitems)
   const int* c_rep;      // [ctot] replica of each carbon
   int* any;              // 1 if some replica rebuilds in this step
   int* abort;            // sticky: a bounded wait of a build gave up; no build runs until
@@ -73,6 +74,8 @@ struct BuildArgs {
   int* near;             // [ntot]: replica r's near atoms at near[a0_r ...]
   double* fme;           // [ntot][4]: last Morse force and energy per atom (0 if none)
   int ncell_all, ncell_cr, ntiles, ctot;
+  int nbin;              // tile blocks' worth of work of k_bin, k_scatter, k_sort_gather: the Cr
+                         // tiles, then 256-carbon groups (the grids stride over them)
   int near_blocks;       // grid of k_xlist
   int xblocks;           // leading blocks of k_list_tiles that build the Cr-C lists (0: none)
   int commit_ref;        // k_scan records the indenter position of this build (k_bin decided)
@@ -230,6 +233,7 @@ __global__ __launch_bounds__(DECIDE_THREADS) void k_decide(Consts K, BuildArgs A
   if (threadIdx.x == 0) {
     *A.any = any_sh;
     *A.nitems = 0;   // k_scatter lists the list-build work items of a rebuild
+    *A.next_item = 0;
   }
   for (int r = threadIdx.x; r < K.nrep; r += DECIDE_THREADS) {   // builds are counted here
     RepState& s = A.S[r];
@@ -301,19 +305,20 @@ __global__ __launch_bounds__(BLOCK) void k_bin(Consts K, BuildArgs A, const doub
       if (g1.need) s0.nbuilds += 1;
       *A.any = g1.need;
       *A.nitems = 0;   // k_scatter lists the list-build work items of a rebuild
+      *A.next_item = 0;
     }
     if (!g1.need) return;
   } else if (rebuild_off(A)) {
     return;
   }
-  const int b = blockIdx.x;
-  if (b == 0) {   // fresh state for this build's k_scan
+  if (blockIdx.x == 0) {   // fresh state for this build's k_scan
     for (int t = threadIdx.x; t < A.scan_blocks; t += BLOCK) A.scan_state[t] = 0;
     if (threadIdx.x == 0) *A.scan_ticket = 0;
   }
+  for (int b = blockIdx.x; b < A.nbin; b += gridDim.x) {   // (b uniform over the block)
   if (b < A.ntiles) {
     const int r = A.tile_rep[b];
-    if (!DECIDE && !A.S[r].rebuild) return;
+    if (!DECIDE && !A.S[r].rebuild) continue;
     const RepDesc& d = A.R[r];
     const int64_t i = (int64_t)b * TILE + threadIdx.x;
     const bool live = i < (int64_t)d.a0 + d.n;
@@ -362,6 +367,7 @@ __global__ __launch_bounds__(BLOCK) void k_bin(Consts K, BuildArgs A, const doub
       A.hcell[k] = hid;
       A.hrank[k] = atomicAdd(&A.count[hid], 1);
     }
+  }
   }
 }
 
@@ -495,22 +501,22 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Consts K, BuildArgs A) {
     for (int k = 0, at = base + incl - nr; k < nr; ++k, ++at)
       if (at < A.nlblk) A.items[at] = make_int2((int)g, k | (nr << 16));
   }
-  const int b = blockIdx.x;
+  for (int b = blockIdx.x; b < A.nbin; b += gridDim.x) {   // (b uniform over the block)
   if (b < A.ntiles) {
     const int r = A.tile_rep[b];
-    if (!A.S[r].rebuild) return;
+    if (!A.S[r].rebuild) continue;
     const RepDesc& d = A.R[r];
     const int64_t i = (int64_t)b * TILE + threadIdx.x;
-    if (i >= (int64_t)d.a0 + d.n) return;
+    if (i >= (int64_t)d.a0 + d.n) continue;
     const int cid = A.cellid[i];
     const int pos = d.a0 + (A.start[cid] - A.start[d.g0]) + A.crank[i];
     A.perm[pos] = (int)i;
     A.skey[pos] = ((long long)cid << 32) | (unsigned)A.id[i];
   } else {
     const int64_t k = (int64_t)(b - A.ntiles) * BLOCK + threadIdx.x;
-    if (k >= A.ctot) return;
+    if (k >= A.ctot) continue;
     const int r = A.c_rep[k];
-    if (!A.S[r].rebuild) return;
+    if (!A.S[r].rebuild) continue;
     const RepDesc& d = A.R[r];
     const int hid = A.hcell[k];
     const int rank = A.hrank[k];
@@ -537,6 +543,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Consts K, BuildArgs A) {
       }
     }
   }
+  }
 }
 
 // One lane per slot in cell order.  Blocks [0, ntiles): Cr slots, one tile each; blocks
@@ -545,11 +552,11 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Consts K, BuildArgs A) {
 // atoms), so the final order is canonical; the atom's state is gathered there.
 __global__ __launch_bounds__(BLOCK) void k_sort_gather(Consts K, BuildArgs A) {
   if (rebuild_off(A)) return;
-  const int b = blockIdx.x;
+  for (int b = blockIdx.x; b < A.nbin; b += gridDim.x) {   // (b uniform over the block)
   if (b < A.ntiles) {
     const int r = A.tile_rep[b];
     RepState& S = A.S[r];
-    if (!S.rebuild) return;
+    if (!S.rebuild) continue;
     const RepDesc& d = A.R[r];
     const int u = b * TILE + threadIdx.x;
     bool near = false;
@@ -609,9 +616,9 @@ __global__ __launch_bounds__(BLOCK) void k_sort_gather(Consts K, BuildArgs A) {
     }
   } else {
     const int64_t u = (int64_t)(b - A.ntiles) * BLOCK + threadIdx.x;
-    if (u >= A.ctot) return;
+    if (u >= A.ctot) continue;
     const int r = A.c_rep[u];   // carbon slots of a replica are its carbon index range
-    if (!A.S[r].rebuild) return;
+    if (!A.S[r].rebuild) continue;
     const RepDesc& d = A.R[r];
     const int e = A.hlist[u];
     const int c = A.hcell[e];
@@ -628,6 +635,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_gather(Consts K, BuildArgs A) {
     A.hsorted[s0 + rank] = make_double4(A.xc[3 * e + 0], A.xc[3 * e + 1], A.xc[3 * e + 2],
                                         __longlong_as_double((long long)e));
     if (u == s0) A.count[c] = 0;   // zero again for the next rebuild
+  }
   }
 }
 
@@ -882,7 +890,7 @@ __device__ __forceinline__ void xlist_pass(const Consts& K, const BuildArgs& A, 
 // Cr-Cr lists with LDS-staged candidates (replicas whose periodic axes all have >= 3 list
 // cells).  A work item is a run of cells of one cell row (listed by k_scatter, see
 // row_runs), sized so that one pass of a block's threads covers a run's atoms, one center
-// per thread; one block per item, the blocks beyond the items return at once.  For each of the nine neighbouring cell rows (z-major, then y) the block
+// per thread; a grid that fills the chip once, each block taking items from a counter.  For each of the nine neighbouring cell rows (z-major, then y) the block
 // stages that row's atoms of x-cells x0-1 .. x1+1 -- with the cell seen across a periodic
 // x face placed at the end it is seen from -- into LDS as FP32 coordinates relative to the
 // grid origin plus the row's image shift, with the slot in the fourth word.  The nine
@@ -919,8 +927,16 @@ __global__ __launch_bounds__(LIST_BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts
                A.xblocks);
     return;
   }
-  const int b = blockIdx.x - A.xblocks;
-  if (b >= uniform(*A.nitems)) return;   // zero in a step without a rebuild
+  // the other blocks stay resident and take work items one at a time from a counter until
+  // none is left (zero items in a step without a rebuild)
+  __shared__ int item_sh;
+  const int nitems = uniform(*A.nitems);
+  for (;;) {
+  __syncthreads();   // the previous item's LDS tables and stage are no longer read
+  if (threadIdx.x == 0) item_sh = atomicAdd(A.next_item, 1);
+  __syncthreads();
+  const int b = uniform(item_sh);
+  if (b >= nitems) break;
   const int2 it = A.items[b];
   const int grow = uniform(it.x), sx = uniform(it.y & 0xFFFF), nseg = uniform(it.y >> 16);
   const int r = uniform(A.row_rep[grow]);
@@ -938,7 +954,7 @@ __global__ __launch_bounds__(LIST_BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts
   const int sbase = uniform(d.a0 - A.start[g0]);   // sorted slot = sbase + start[cell]
   const int cbeg = sbase + uniform(A.start[crow + x0]);
   const int m = uniform(A.start[crow + x1 + 1]) - (cbeg - sbase);
-  if (m == 0) return;
+  if (m == 0) continue;
   const double rl2 = K.rlist_sq;
   const int cap = K.cap, T = K.lt;
   const int64_t row = K.ntot * T;   // entry k of atom p at idx[(k / T) * row + p * T + k % T]
@@ -1164,6 +1180,7 @@ __global__ __launch_bounds__(LIST_BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts
       A.fixed[p] = fx;
       A.id[p] = ide;
     }
+  }
   }
 }
 

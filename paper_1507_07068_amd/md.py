@@ -26,14 +26,16 @@ MD_PHASE_KICK_DRIFT, MD_PHASE_KICK = 1, 2
 MD_F_DENSITY, MD_F_FORCE, MD_F_MORSE, MD_F_KICK, MD_F_ENERGY, MD_F_MIXED = 1, 2, 4, 8, 16, 32
 MD_B_FORCE = 1
 MD_NOBS = 16
+MD_E_EMBED, MD_E_PAIR, MD_E_MORSE, MD_E_KIN, MD_W_XX, MD_F_IND_X, MD_IND_Z, MD_NBUILDS = 0, 1, 2, 3, 4, 10, 13, 14
 OBS = ["e_embed", "e_pair", "e_morse", "e_kin", "w_xx", "w_yy", "w_zz", "w_xy", "w_xz", "w_yz",
        "find_x", "find_y", "find_z", "ind_z", "nbuilds", "unused"]
 
 API = ["md_system_create", "md_system_destroy", "md_system_atoms", "md_system_carbons",
-       "md_replica_offset", "md_workspace_bytes", "md_workspace_bind", "md_build_neighbors",
+       "md_replica_offset", "md_workspace_bytes", "md_workspace_bind",
+       "md_build_neighbors",
        "md_eam_forces", "md_morse_forces", "md_verlet_step", "md_energy", "md_run",
-       "md_graph_create", "md_graph_launch", "md_graph_destroy", "md_check", "md_clear_flags",
-       "md_strerror"]
+       "md_graph_create", "md_graph_launch", "md_graph_destroy", "md_set_indenter_velocity",
+       "md_check", "md_clear_flags", "md_strerror"]
 
 
 class EamParams(C.Structure):
@@ -44,10 +46,19 @@ class MorseParams(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("D", "alpha", "r0", "rc")]
 
 
+PAPER_KEYS = ("Fo", "n", "rho_e", "alpha", "P_e", "fe", "re", "beta", "a0", "a1", "a2", "a3", "d", "rc")
+MD_POT_FS, MD_POT_PAPER = 0, 1
+
+
+class PaperParams(C.Structure):
+    _fields_ = [(k, C.c_double) for k in PAPER_KEYS]
+
+
 class Params(C.Structure):
     _fields_ = [("eam", EamParams), ("morse", MorseParams), ("mass", C.c_double),
                 ("dt", C.c_double), ("v_ind", C.c_double), ("skin", C.c_double),
-                ("cap", C.c_int32), ("xcap", C.c_int32), ("tpa", C.c_int32), ("shadow", C.c_int32)]
+                ("cap", C.c_int32), ("xcap", C.c_int32), ("tpa", C.c_int32), ("shadow", C.c_int32),
+                ("potential", C.c_int32), ("pad", C.c_int32), ("paper", PaperParams)]
 
 
 class ReplicaDesc(C.Structure):
@@ -69,6 +80,13 @@ class Status(C.Structure):
     _fields_ = [("overflow", C.c_int32), ("xoverflow", C.c_int32), ("nonfinite", C.c_int32),
                 ("nbuilds", C.c_int32), ("sync_timeout", C.c_int32), ("nnear", C.c_int32),
                 ("pad", C.c_int32 * 2)]
+
+
+MD_TRACE_EVENTS = 6
+
+
+class Trace(C.Structure):
+    _fields_ = [("events", C.c_void_p), ("builds", C.c_void_p)]
 
 
 # A Cr-Cr list entry keeps the neighbour's slot in its low 27 bits (the bits above give the
@@ -114,13 +132,14 @@ def load_library(path: str = LIB_PATH):
     L.md_graph_create.argtypes = [P, P, P, i32, u32, i32, P, P, C.POINTER(P)]
     L.md_graph_launch.argtypes = [P, P]
     L.md_graph_destroy.argtypes = [P]
+    L.md_set_indenter_velocity.argtypes = [P, C.c_double]
     L.md_check.argtypes = [P, P, P]
     L.md_clear_flags.argtypes = [P, P]
     L.md_strerror.argtypes = [C.c_int]
     L.md_strerror.restype = C.c_char_p
     for name in ("md_workspace_bind", "md_build_neighbors", "md_eam_forces", "md_morse_forces",
                  "md_verlet_step", "md_energy", "md_run", "md_graph_create", "md_graph_launch",
-                 "md_graph_destroy", "md_check", "md_clear_flags"):
+                 "md_graph_destroy", "md_set_indenter_velocity", "md_check", "md_clear_flags"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -144,6 +163,9 @@ def make_params(s, cap: int = 64, xcap: int = 64, tpa: int = 1, shadow: bool = F
     p.xcap = int(xcap)
     p.tpa = int(tpa)
     p.shadow = int(bool(shadow))
+    if getattr(s, "potential", "fs") == "paper":
+        p.potential = MD_POT_PAPER
+        p.paper = PaperParams(**{k: float(s.paper[k]) for k in PAPER_KEYS})
     return p
 
 
@@ -320,27 +342,38 @@ class Simulation:
         return dict(overflow=st.overflow, xoverflow=st.xoverflow, nonfinite=st.nonfinite,
                     nbuilds=st.nbuilds, sync_timeout=st.sync_timeout, nnear=st.nnear)
 
+    def md_set_indenter_velocity(self, v_ind: float):
+        _ok(self.lib.md_set_indenter_velocity(self.handle, float(v_ind)), "md_set_indenter_velocity")
+
     def md_clear_flags(self):
         _ok(self.lib.md_clear_flags(self.handle, self.stream), "md_clear_flags")
 
-    def md_run(self, nsteps: int, energy_every: int = 0, obs=None, events=None):
+    def md_run(self, nsteps: int, energy_every: int = 0, obs=None, events=None, builds=None):
         """Enqueue nsteps whole steps in C.  obs: device float64 tensor with room for
-        nsteps // energy_every rows of (nrep, MD_NOBS); events: list of 4*nsteps
-        events (any object whose ``cuda_event`` is a HIP event handle, e.g. torch.cuda.Event
-        recorded once before so that its HIP event exists) or None, per step two around the
-        EAM force kernel and two around the Cr-Cr list kernel (None: not recorded)."""
+        nsteps // energy_every rows of (nrep, MD_NOBS).  For measurement (md_trace): events, a
+        list of MD_TRACE_EVENTS * nsteps events or None entries (objects whose ``cuda_event``
+        is a HIP event handle), per step two around the EAM force kernel, two around the Cr-Cr
+        list kernel and two around the density kernel; builds, a device int32 tensor of
+        (nsteps, nrep) receiving each replica's list-build count after every step."""
         flags = MD_F_MIXED if self.mixed else 0
-        ev = None
-        if events is not None:
-            if len(events) != 4 * nsteps:
-                raise MDError("md_run: give 4 timing events (or None) per step")
-            handles = [None if e is None else e.cuda_event for e in events]
-            if not all(h is None or h for h in handles):
-                raise MDError("md_run: record each timing event once before passing it")
-            ev = (C.c_void_p * len(events))(*handles)
+        tr = None
+        if events is not None or builds is not None:
+            tr = Trace()
+            if events is not None:
+                if len(events) != MD_TRACE_EVENTS * nsteps:
+                    raise MDError(f"md_run: give {MD_TRACE_EVENTS} timing events (or None) per step")
+                handles = [None if e is None else e.cuda_event for e in events]
+                if not all(h is None or h for h in handles):
+                    raise MDError("md_run: record each timing event once before passing it")
+                self._trace_events = (C.c_void_p * len(events))(*handles)
+                tr.events = C.cast(self._trace_events, C.c_void_p)
+            if builds is not None:
+                if builds.dtype != self.torch.int32 or builds.numel() < nsteps * self.nrep or not builds.is_cuda:
+                    raise MDError("md_run: builds must be a device int32 tensor of nsteps x nrep")
+                tr.builds = builds.data_ptr()
         _ok(self.lib.md_run(self.handle, C.byref(self._atoms()), C.byref(self._lists()), int(nsteps),
                             flags, int(energy_every), self._ptr(obs) if obs is not None else None,
-                            ev, self.stream), "md_run")
+                            C.byref(tr) if tr is not None else None, self.stream), "md_run")
 
     def md_graph_create(self, nsteps: int, energy_every: int = 0, obs=None):
         """Capture nsteps whole steps into a HIP graph; returns an opaque handle."""

@@ -41,11 +41,60 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_struct_sizes_match_header(lib):
-    assert C.sizeof(md.Params) == 6 * 8 + 4 * 8 + 4 * 8 + 4 * 4
+    assert C.sizeof(md.Params) == 6 * 8 + 4 * 8 + 4 * 8 + 4 * 4 + 2 * 4 + 14 * 8
     assert C.sizeof(md.ReplicaDesc) == 6 * 8 + 6 * 4
     assert C.sizeof(md.Atoms) == 6 * 8
     assert C.sizeof(md.Lists) == 4 * 8
     assert C.sizeof(md.Status) == 8 * 4
+
+
+def test_binding_constants_match_header():
+    """Every integer #define of include/md.h that the binding also names has the same value."""
+    txt = open(os.path.join(ROOT, "include", "md.h")).read()
+    seen = 0
+    for name, val in re.findall(r"#define\s+(MD_\w+)\s+(\(?[0-9x<\s]+\)?)\s", txt):
+        if hasattr(md, name):
+            assert getattr(md, name) == eval(val, {}), name
+            seen += 1
+    assert seen >= 20
+    for name in ("MD_E_EMBED", "MD_F_IND_X", "MD_IND_Z", "MD_NBUILDS", "MD_TRACE_EVENTS"):
+        assert hasattr(md, name), name
+
+
+STRUCTS = {"md_params": md.Params, "md_replica_desc": md.ReplicaDesc, "md_atoms": md.Atoms,
+           "md_lists": md.Lists, "md_status": md.Status, "md_trace": md.Trace,
+           "md_eam_params": md.EamParams, "md_morse_params": md.MorseParams,
+           "md_eam_paper_params": md.PaperParams}
+
+
+def test_binding_layout_matches_header(tmp_path):
+    """Every field offset and struct size of the Python binding equals what a C compiler makes
+    of include/md.h."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "md.h"', "int main(void) {"]
+    for cname, cls in STRUCTS.items():
+        lines.append(f'  printf("{cname} . %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln.strip():
+            cname, fname, v = ln.split()
+            got[(cname, fname)] = int(v)
+    for cname, cls in STRUCTS.items():
+        assert got[(cname, ".")] == C.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
 
 
 def _create(lib, systems, cap=64, xcap=64):

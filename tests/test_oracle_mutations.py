@@ -46,7 +46,7 @@ MUTATIONS = [
      TP.test_force_is_minus_energy_gradient),
     ("paper form: f' with the wrong power", "pow(p->re / r, p->beta - 1.0)", "pow(p->re / r, p->beta)",
      lambda: TP.test_T1_embedding_term(2.9, 18.0)),
-    ("paper form: P sums f, not f^2", "accp += fr * fr;", "accp += fr;",
+    ("paper form: P sums f, not f^2", "                accp += fr * fr;", "                accp += fr;",
      lambda: TP.test_perfect_lattice_closed_form(2.80)),
     ("paper form: sign of M' cubic term", "exp(-u * u) * (-2.0 * u)", "exp(-u * u) * (2.0 * u)",
      lambda: TP.test_T2_cauchy_term(2.5, 40.0)),

@@ -207,3 +207,14 @@ def test_film_with_indenter_balance_and_list_mode():
     b = O.md_run(s, 12, use_lists=True, cap=256)
     for k in ("x", "v", "f", "obs"):
         assert np.array_equal(a[k], b[k]), k
+
+
+def test_sampled_forces_equal_whole_system():
+    s = I.small_film(nx=7, ny=7, nz=4, radius=6.0, gap=-0.5, seed=33, noise=0.04)
+    s.potential = "paper"
+    ev = O.evaluate(s)
+    smp = np.array([0, 9, s.n // 2, s.n - 1] + list(np.nonzero(np.abs(ev["fm"]).sum(1))[0][:3]))
+    f, rho, dF = O.sample_forces_paper(s, smp)
+    assert np.allclose(f, ev["f"][smp], rtol=0, atol=1e-11)
+    assert np.allclose(rho, ev["rho"][smp], rtol=1e-14)
+    assert np.allclose(dF, ev["dF"][smp], rtol=1e-13)
