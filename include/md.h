@@ -211,6 +211,24 @@ MD_API size_t md_workspace_bytes(const md_system *sys);
  * replica descriptors, clears flags, and synchronises `stream`.  MD_ERR_ARG if too small. */
 MD_API int md_workspace_bind(md_system *sys, void *ws, size_t bytes, void *stream);
 
+/* Bytes of the library's static device scratch (one per GPU): see md_workspace_bind_static. */
+#define MD_SCRATCH_BYTES (16 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same as md_workspace_bind, with the
+ * library's own static device array of MD_SCRATCH_BYTES bytes as the workspace in place of a
+ * caller-owned buffer.  Nothing is allocated here or by any later call on `sys` (the atom and
+ * list arrays are still the caller's).  The array lives on every GPU the library runs on
+ * (each GPU its own copy, at its own address, looked up at the first such call on that GPU,
+ * which must be current) until the process ends.  MD_ERR_ARG, with a message on stderr, when
+ * md_workspace_bytes(sys) exceeds MD_SCRATCH_BYTES (about 60,000 atoms).
+ * One scratch per GPU: binding a system takes it over, clears it and keeps nothing of the
+ * previous system; calls on a system bound to it earlier then return MD_ERR_STATE (bind that
+ * system again to use it).  Calls on one GPU whose work overlaps on the device (several
+ * streams or host threads) race on the array.  Synchronises `stream`; a set-up call, not
+ * for use under stream capture (md_run and md_graph_create are). */
+MD_API int md_workspace_bind_static(md_system *sys, void *stream);
+
 /* ---------------------------------------------------------------------------------- */
 /* The step                                                                             */
 /* ---------------------------------------------------------------------------------- */

@@ -2,10 +2,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -61,11 +63,26 @@ struct md_system {
   // grids of the build kernels that stride over their work (set at bind from the device):
   // tile kernels (256 threads) and the persistent list build
   int tile_grid = 2048, list_grid = 2048;
+  int static_dev = -1;   // device whose static scratch is the workspace (md_workspace_bind_static)
 };
 
+// The workspace of md_workspace_bind_static: a file-scope device array, one copy per GPU
+// (each at its own address), held until the process ends.  Host code never names it except
+// to look up that address: g_scratch_ptr[dev] holds it, taken once per device with the
+// device current.
+static __device__ __align__(256) unsigned char scratch[MD_SCRATCH_BYTES];
+
 namespace {
-// A workspace is bound.
-bool bound(const md_system* s) { return s->ws != nullptr; }
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES];                            // device address of `scratch`
+std::atomic<const md_system*> g_scratch_owner[MAX_DEVICES];  // the system bound to it
+
+// A workspace is bound, and if it is a device's static scratch no other system has taken
+// that scratch over since.
+bool bound(const md_system* s) {
+  return s->ws && (s->static_dev < 0 || g_scratch_owner[s->static_dev].load() == s);
+}
 }  // namespace
 
 namespace {
@@ -459,7 +476,13 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
   return MD_OK;
 }
 
-MD_API void md_system_destroy(md_system* s) { delete s; }
+MD_API void md_system_destroy(md_system* s) {
+  if (s && s->static_dev >= 0) {
+    const md_system* me = s;
+    g_scratch_owner[s->static_dev].compare_exchange_strong(me, nullptr);
+  }
+  delete s;
+}
 
 MD_API int64_t md_system_atoms(const md_system* s) { return s ? s->ntot : -1; }
 MD_API int64_t md_system_carbons(const md_system* s) { return s ? s->ctot : -1; }
@@ -512,9 +535,41 @@ int bind_workspace(md_system* s, void* ws, hipStream_t st) {
 MD_API int md_workspace_bind(md_system* s, void* ws, size_t bytes, void* stream) {
   if (!s || !ws || bytes < s->L.total) return MD_ERR_ARG;
   if (((uintptr_t)ws) % ALIGN) return MD_ERR_ARG;
+  if (s->static_dev >= 0) {   // give up a static scratch this system held
+    const md_system* me = s;
+    g_scratch_owner[s->static_dev].compare_exchange_strong(me, nullptr);
+    s->static_dev = -1;
+  }
   return bind_workspace(s, ws, (hipStream_t)stream);
 }
 
+MD_API int md_workspace_bind_static(md_system* s, void* stream) {
+  if (!s) return MD_ERR_ARG;
+  if (s->L.total > (size_t)MD_SCRATCH_BYTES) {
+    std::fprintf(stderr,
+                 "md_workspace_bind_static: this system needs %zu bytes of workspace, more than the "
+                 "%d bytes of the static scratch; bind a caller-owned workspace with md_workspace_bind\n",
+                 s->L.total, (int)MD_SCRATCH_BYTES);
+    return MD_ERR_ARG;
+  }
+  int dev = 0, e;
+  if ((e = hip_status(hipGetDevice(&dev)))) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return MD_ERR_ARG;
+  void* ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {   // once per device, with that device current
+      void* p = nullptr;
+      if ((e = hip_status(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))))) return e;
+      if (!p) return MD_ERR_HIP;
+      g_scratch_ptr[dev] = p;
+    }
+    ptr = g_scratch_ptr[dev];
+    g_scratch_owner[dev].store(s);   // earlier systems bound to it are now refused
+  }
+  s->static_dev = dev;
+  return bind_workspace(s, ptr, (hipStream_t)stream);
+}
 
 namespace {
 

@@ -27,11 +27,12 @@ MD_F_DENSITY, MD_F_FORCE, MD_F_MORSE, MD_F_KICK, MD_F_ENERGY, MD_F_MIXED = 1, 2,
 MD_B_FORCE = 1
 MD_NOBS = 16
 MD_E_EMBED, MD_E_PAIR, MD_E_MORSE, MD_E_KIN, MD_W_XX, MD_F_IND_X, MD_IND_Z, MD_NBUILDS = 0, 1, 2, 3, 4, 10, 13, 14
+MD_SCRATCH_BYTES = 16 << 20
 OBS = ["e_embed", "e_pair", "e_morse", "e_kin", "w_xx", "w_yy", "w_zz", "w_xy", "w_xz", "w_yz",
        "find_x", "find_y", "find_z", "ind_z", "nbuilds", "unused"]
 
 API = ["md_system_create", "md_system_destroy", "md_system_atoms", "md_system_carbons",
-       "md_replica_offset", "md_workspace_bytes", "md_workspace_bind",
+       "md_replica_offset", "md_workspace_bytes", "md_workspace_bind", "md_workspace_bind_static",
        "md_build_neighbors",
        "md_eam_forces", "md_morse_forces", "md_verlet_step", "md_energy", "md_run",
        "md_graph_create", "md_graph_launch", "md_graph_destroy", "md_set_indenter_velocity",
@@ -123,6 +124,7 @@ def load_library(path: str = LIB_PATH):
     L.md_workspace_bytes.argtypes = [P]
     L.md_workspace_bytes.restype = sz
     L.md_workspace_bind.argtypes = [P, P, sz, P]
+    L.md_workspace_bind_static.argtypes = [P, P]
     L.md_build_neighbors.argtypes = [P, P, P, u32, P]
     L.md_eam_forces.argtypes = [P, P, P, u32, P, P]
     L.md_morse_forces.argtypes = [P, P, P, u32, P]
@@ -137,7 +139,7 @@ def load_library(path: str = LIB_PATH):
     L.md_clear_flags.argtypes = [P, P]
     L.md_strerror.argtypes = [C.c_int]
     L.md_strerror.restype = C.c_char_p
-    for name in ("md_workspace_bind", "md_build_neighbors", "md_eam_forces", "md_morse_forces",
+    for name in ("md_workspace_bind", "md_workspace_bind_static", "md_build_neighbors", "md_eam_forces", "md_morse_forces",
                  "md_verlet_step", "md_energy", "md_run", "md_graph_create", "md_graph_launch",
                  "md_graph_destroy", "md_set_indenter_velocity", "md_check", "md_clear_flags"):
         getattr(L, name).restype = C.c_int
@@ -188,9 +190,12 @@ class Simulation:
     """
 
     def __init__(self, systems, precision: str = "fp64", cap: int | None = None, xcap: int = 160,
-                 tpa: int = 1, device: str = "cuda:0", shadow: bool | None = None):
+                 tpa: int = 1, device: str = "cuda:0", shadow: bool | None = None,
+                 static_workspace: bool = False):
         """cap: Cr-Cr list capacity per atom (a multiple of tpa).  shadow: keep the FP32
-        cell-local positions for the FP32-mixed passes (default: when precision is mixed)."""
+        cell-local positions for the FP32-mixed passes (default: when precision is mixed).
+        static_workspace: bind the library's static device scratch (md_workspace_bind_static)
+        instead of a workspace tensor."""
         import torch
         if cap is None:
             cap = 64
@@ -234,8 +239,9 @@ class Simulation:
             self.xcnt = torch.zeros(n, dtype=torch.int32, device=dev)
             self.rho = torch.zeros(n, dtype=torch.float64, device=dev)
             self.obs_dev = torch.zeros((self.nrep, MD_NOBS), dtype=torch.float64, device=dev)
+            self.static_workspace = static_workspace
             wsb = int(self.lib.md_workspace_bytes(h))
-            self.ws = torch.empty(wsb + 256, dtype=torch.uint8, device=dev)
+            self.ws = None if static_workspace else torch.empty(wsb + 256, dtype=torch.uint8, device=dev)
             self.load([s.x for s in self.systems], [s.v for s in self.systems])
             self._bind()
 
@@ -261,6 +267,9 @@ class Simulation:
         return self._lists_c
 
     def _bind(self):
+        if self.static_workspace:
+            _ok(self.lib.md_workspace_bind_static(self.handle, self.stream), "md_workspace_bind_static")
+            return
         base = self.ws.data_ptr()
         aligned = (base + 255) // 256 * 256
         self.ws_ptr = aligned
@@ -269,7 +278,7 @@ class Simulation:
             "md_workspace_bind")
 
     def bind(self):
-        """Bind the workspace again (clears it: lists and forces must be rebuilt)."""
+        """Bind the workspace again (after another system took over the static scratch)."""
         self._bind()
 
     def load(self, xs: Sequence[np.ndarray], vs: Sequence[np.ndarray]):

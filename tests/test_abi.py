@@ -57,7 +57,7 @@ def test_binding_constants_match_header():
             assert getattr(md, name) == eval(val, {}), name
             seen += 1
     assert seen >= 20
-    for name in ("MD_E_EMBED", "MD_F_IND_X", "MD_IND_Z", "MD_NBUILDS", "MD_TRACE_EVENTS"):
+    for name in ("MD_E_EMBED", "MD_F_IND_X", "MD_IND_Z", "MD_NBUILDS", "MD_TRACE_EVENTS", "MD_SCRATCH_BYTES"):
         assert hasattr(md, name), name
 
 
