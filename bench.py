@@ -184,9 +184,9 @@ def mean_list_len(sim, systems) -> float:
     return float(cnt[live].mean()) if live.size else 0.0
 
 
-def make_sim(systems, precision, tpa, xcap=160):
+def make_sim(systems, precision, tpa, xcap=160, cap=None, icap=0):
     from paper_1507_07068_amd import md
-    return md.Simulation(systems, precision=precision, xcap=xcap, tpa=tpa)
+    return md.Simulation(systems, precision=precision, xcap=xcap, tpa=tpa, cap=cap, icap=icap)
 
 
 def free_sim(sim):
@@ -243,7 +243,7 @@ def kernel_pass(sim, systems, steps, ee, precision):
     L1 = mean_list_len(sim, systems)
     E = md.MD_TRACE_EVENTS
     t = {name: np.array([ev[E * k + a].elapsed_time(ev[E * k + a + 1]) for k in range(steps)]) * 1e-3
-         for name, a in (("force", 0), ("list", 2), ("density", 4))}
+         for name, a in (("force", 0), ("list", 2), ("density", 4), ("inner", 6))}
     b = builds.cpu().numpy().sum(axis=1).astype(np.int64)
     rebuilt = np.diff(np.concatenate([[b0], b])) > 0
     n_atoms = sum(s.n for s in systems)
@@ -267,6 +267,8 @@ def kernel_pass(sim, systems, steps, ee, precision):
         lst.update(avg_us=float(t["list"][rebuilt].mean() * 1e6), bytes_per_launch=lb,
                    achieved=float(lb / t["list"][rebuilt].mean() / 1e9))
     out["list"] = lst
+    if sim.icap:
+        out["inner"] = dict(avg_us=float(t["inner"].mean() * 1e6), total_ms=float(t["inner"].sum() * 1e3))
     out["step_ms"] = float(np.mean([ev[E * k].elapsed_time(ev[E * (k + 1)]) for k in range(steps - 1)])) \
         if steps > 1 else None
     return out
@@ -406,6 +408,40 @@ def batched_graph_run(systems, steps, tpa, chunk=100):
     n_atoms = sum(s.n for s in systems)
     return dict(rate=n_atoms * n * chunk / wall, steps=n * chunk, ms_per_step=wall / (n * chunk) * 1e3,
                 builds=flags["nbuilds"] - b0)
+
+
+def paper_form_run(system, tpa, two_tier, steps=300, warmup=20, ee=10, kern_steps=20):
+    """The paper's own EAM form on `system` with the indenter at rest (the set-up of the
+    paper's timing runs, Section 4.1: 300 steps), over one list (cutoff r* + 0.3 A) or over
+    Section 2.6's two-tier lists (outer 1.7 r*, inner r* refilled every step)."""
+    from paper_1507_07068_amd import inputs as I
+    s = system.copy()
+    s.v_ind = 0.0
+    s.potential = "paper"
+    if two_tier:
+        I.two_tier(s)
+        sim = make_sim([s], "fp64", tpa, xcap=320, cap=1152, icap=256)
+    else:
+        sim = make_sim([s], "fp64", tpa, cap=256)
+    sim.initial_forces()
+    what = f"paper form {s.name} {'two-tier' if two_tier else 'one list'}"
+    r = timed_run(sim, [s], steps, warmup, ee, what)
+    kern = kernel_pass(sim, [s], kern_steps, ee, "fp64")
+    inner_mean = None
+    if two_tier:
+        import numpy as np
+        inner_mean = float(np.mean(sim.icnt.cpu().numpy()[:s.n]))
+    free_sim(sim)
+    out = {"value": r["rate"], "unit": "atom-steps/s", "steps": steps, "warmup": warmup,
+           "ms_per_step": r["ms_per_step"], "precision": "fp64", "list_builds": r["builds"],
+           "mean_list_len": round(r["mean_list"], 3), "list_radius": round(s.r_list, 4),
+           "kernels_us": {k: round(kern[k]["avg_us"], 2) for k in ("force", "density", "inner") if k in kern}}
+    out["kernels_us"]["list_per_rebuild"] = kern["list"].get("avg_us")
+    if two_tier:
+        out["inner_mean_len"] = round(inner_mean, 3)
+    log(f"[bench] {what}: {r['rate']:.4e} atom-steps/s, {r['ms_per_step']:.4f} ms/step, "
+        f"{r['builds']} builds, kernels {out['kernels_us']}")
+    return out
 
 
 def full_run(systems, precision, tpa, warmup=20, ee=10):
@@ -586,6 +622,8 @@ def main(argv=None):
         c1 = I.config(1)
         full["c1_fp64"] = full_run([c1], "fp64", args.tpa)
         log(f"[bench] c1 fp64 full: {full['c1_fp64']['value']:.4e} atom-steps/s")
+        var["paper_form_c1"] = paper_form_run(c1, args.tpa, two_tier=False)
+        var["paper_form_two_tier_c1"] = paper_form_run(c1, args.tpa, two_tier=True)
         var["nve_c0"] = nve_drift()
         var["indenter_work_c1"] = indenter_work_drift(c1, args.tpa)
         log(f"[bench] NVE c0 drift (mean of seeds): fp64 "

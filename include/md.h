@@ -128,7 +128,13 @@ typedef struct md_params {
                            separations instead */
     int32_t potential;  /* MD_POT_FS (eam) or MD_POT_PAPER (paper); the list radius is the
                            potential's largest Cr-Cr cutoff + skin */
-    int32_t pad;
+    int32_t icap;       /* two-tier lists (Section 2.6) when > 0: the Cr-Cr list (md_lists.idx,
+                           radius cutoff + skin) is the outer list, rebuilt by the half-skin
+                           rule, and before every density pass the inner list (md_lists.iidx,
+                           capacity icap per atom, a multiple of tpa) is refilled with the
+                           outer list's entries whose pair is now closer than the potential's
+                           largest Cr-Cr cutoff; the passes then read the inner list.  0: one
+                           list, read by the passes */
     md_eam_paper_params paper;
 } md_params;
 
@@ -166,6 +172,10 @@ typedef struct md_lists {
     int32_t *cnt;       /* [n_total] */
     int32_t *xidx;      /* [n_total][xcap]: carbon indices (into xc) of atom i's Cr-C list */
     int32_t *xcnt;      /* [n_total] */
+    int32_t *iidx;      /* two-tier lists only (else NULL): the inner list, [icap * n_total] in
+                           idx's layout and entry format, atom i's entries in the order they
+                           have in its outer list */
+    int32_t *icnt;      /* [n_total] */
 } md_lists;
 
 /* Host copy of the device status flags (md_check). */
@@ -183,7 +193,8 @@ typedef struct md_status {
                                at once, for tests of this path) */
     int32_t nnear;          /* Cr atoms whose carbon cells are within reach of a carbon at the
                                last build (the candidates of the Cr-C lists), all replicas */
-    int32_t pad[2];
+    int32_t ioverflow;      /* largest inner-list count that did not fit in icap (0 = none) */
+    int32_t pad;
 } md_status;
 
 typedef struct md_system md_system;
@@ -255,7 +266,9 @@ MD_API int md_build_neighbors(md_system *sys, const md_atoms *a, const md_lists 
  * (Task 4c does not depend on the density), else by a launch of their own before the force
  * pass.  With MD_F_KICK the Task 5 half kick v += F/m dt/2 of the whole force follows
  * (mobile atoms).  MD_F_MIXED selects FP32 arithmetic.  Lists must be current
- * (md_build_neighbors in the same step). */
+ * (md_build_neighbors in the same step).  With two-tier lists (icap > 0) MD_F_DENSITY first
+ * refills the inner list from the outer one at the current positions (Section 2.6, Task 1:
+ * the inner list is updated every step), and both passes read it. */
 MD_API int md_eam_forces(md_system *sys, const md_atoms *a, const md_lists *l, uint32_t flags,
                          double *rho_out, void *stream);
 
@@ -283,13 +296,14 @@ MD_API int md_energy(md_system *sys, const md_atoms *a, double *out, void *strea
 /* ---------------------------------------------------------------------------------- */
 
 /* Records md_run can make of its steps, for measurement (each member may be NULL). */
-#define MD_TRACE_EVENTS 6  /* events per step */
+#define MD_TRACE_EVENTS 8  /* events per step */
 typedef struct md_trace {
     void *const *events;  /* MD_TRACE_EVENTS * nsteps hipEvent_t handles created by the caller
                              (NULL entries are skipped), recorded on the stream around step k's
-                             kernels: [6k], [6k+1] the EAM force kernel (Eq. 1); [6k+2], [6k+3]
+                             kernels: [8k], [8k+1] the EAM force kernel (Eq. 1); [8k+2], [8k+3]
                              the Cr-Cr list kernel (which returns at once when no rebuild is
-                             due); [6k+4], [6k+5] the density kernel (with the Cr-C pass) */
+                             due); [8k+4], [8k+5] the density kernel (with the Cr-C pass);
+                             [8k+6], [8k+7] the inner-list refill (two-tier lists only) */
     int32_t *builds;      /* device int32[nsteps][nrep]: each replica's list-build count after
                              each step (a step rebuilt a replica's lists iff its count grew) */
 } md_trace;

@@ -163,7 +163,13 @@ bool atoms_ok(const md_atoms* a) {
   return a && a->q && a->v && a->f && a->fixed && a->id;
 }
 
-bool lists_ok(const md_lists* l) { return l && l->idx && l->cnt && l->xidx && l->xcnt; }
+bool lists_ok(const md_system* s, const md_lists* l) {
+  return l && l->idx && l->cnt && l->xidx && l->xcnt && (s->p.icap == 0 || (l->iidx && l->icnt));
+}
+
+// The Cr-Cr list the density and force passes read: the inner list with two-tier lists.
+const int* pass_idx(const md_system* s, const md_lists* l) { return s->p.icap ? l->iidx : l->idx; }
+const int* pass_cnt(const md_system* s, const md_lists* l) { return s->p.icap ? l->icnt : l->cnt; }
 
 int grid_tiles(const md_system* s) { return s->ntiles; }
 
@@ -212,8 +218,9 @@ void launch_density(md_system* s, const md_atoms* a, const md_lists* l, bool mix
   const int nb = s->ntiles * T + M.nblocks;
   int4* qs = qscur(s);
   double* dm = at<double>(s, s->L.dm);
+  const int *li = pass_idx(s, l), *lc = pass_cnt(s, l);
 #define DENS(M_, SH, E, PA) \
-  k_density<T, M_, SH, E, PA><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, qs, l->idx, l->cnt, rho_out, pe, M, dm)
+  k_density<T, M_, SH, E, PA><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, qs, li, lc, rho_out, pe, M, dm)
 #define DENS_P(M_, SH, E) \
   if (s->K.pot == MD_POT_PAPER) DENS(M_, SH, E, true); else DENS(M_, SH, E, false)
   if (mixed && s->K.shadow && !s->list_mix) { if (energy) { DENS_P(true, true, true); } else { DENS_P(true, true, false); } }
@@ -241,15 +248,16 @@ void launch_force(md_system* s, const md_atoms* a, const md_lists* l, bool mixed
   const int4* qs = qscur(s);
   const double* dm = at<double>(s, s->L.dm);
   const bool paper = s->K.pot == MD_POT_PAPER;
+  const int *li = pass_idx(s, l), *lc = pass_cnt(s, l);
 #define FORCE1(M, SH, KI, E, PA)                                                                                \
-  k_force<T, M, SH, KI, E, false, PA><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, qs, a->v, a->f, a->fixed, l->idx, \
-                                                             l->cnt, pf, l->xcnt,                                \
+  k_force<T, M, SH, KI, E, false, PA><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, qs, a->v, a->f, a->fixed, li,     \
+                                                             lc, pf, l->xcnt,                                    \
                                                              add_fme ? at<double>(s, s->L.fme) : nullptr, kick_h, D, dm)
 #define FORCE(M, SH, KI, E) \
   if (paper) FORCE1(M, SH, KI, E, true); else FORCE1(M, SH, KI, E, false)
 #define FORCE_DRIFT1(M, SH, PA)                                                                                  \
   k_force<T, M, SH, true, false, true, PA><<<nb, BLOCK, 0, st>>>(                                                \
-      s->K, R, S, tr, q, qs, a->v, a->f, a->fixed, l->idx, l->cnt, pf, l->xcnt,                                  \
+      s->K, R, S, tr, q, qs, a->v, a->f, a->fixed, li, lc, pf, l->xcnt,                                          \
       add_fme ? at<double>(s, s->L.fme) : nullptr, kick_h, D, dm)
 #define FORCE_DRIFT(M, SH) \
   if (paper) FORCE_DRIFT1(M, SH, true); else FORCE_DRIFT1(M, SH, false)
@@ -311,6 +319,7 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
   if (!(p->mass > 0) || !(p->dt > 0) || !(p->skin >= 0) || p->cap < 1 || p->xcap < 1) return MD_ERR_ARG;
   if (p->tpa != 1 && p->tpa != 2 && p->tpa != 4 && p->tpa != 8) return MD_ERR_ARG;
   if (p->cap % p->tpa != 0) return MD_ERR_ARG;
+  if (p->icap < 0 || p->icap % p->tpa != 0) return MD_ERR_ARG;
   if (p->potential != MD_POT_FS && p->potential != MD_POT_PAPER) return MD_ERR_ARG;
   if (p->potential == MD_POT_FS && (!(p->eam.c > 0) || !(p->eam.d > 0) || !(p->eam.d <= p->eam.c)))
     return MD_ERR_ARG;
@@ -403,7 +412,8 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
   s->ncell_all = h;
   // list entries keep the slot in 27 bits; list offsets are 32-bit
   if (a0 >= ((int64_t)1 << 27)) { delete s; return MD_ERR_ARG; }
-  if ((int64_t)p->cap * a0 >= (int64_t)INT32_MAX || (int64_t)p->xcap * a0 >= (int64_t)INT32_MAX) {
+  if ((int64_t)p->cap * a0 >= (int64_t)INT32_MAX || (int64_t)p->xcap * a0 >= (int64_t)INT32_MAX ||
+      (int64_t)p->icap * a0 >= (int64_t)INT32_MAX) {
     delete s;
     return MD_ERR_ARG;
   }
@@ -445,9 +455,11 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
   K.half_skin_sq = K.half_skin * K.half_skin;
   K.rlist_sq = rlist * rlist;
   K.rlist = rlist;
+  K.icut_sq = cut * cut;
   K.rxlist_sq = rxlist * rxlist;
   K.cap = p->cap;
   K.xcap = p->xcap;
+  K.icap = p->icap;
   K.nrep = nrep;
   K.lt = p->tpa;
   K.lt_shift = p->tpa == 1 ? 0 : (p->tpa == 2 ? 1 : (p->tpa == 4 ? 2 : 3));
@@ -674,17 +686,31 @@ int build_chain(md_system* s, const md_atoms* a, const md_lists* l, uint32_t fla
 
 MD_API int md_build_neighbors(md_system* s, const md_atoms* a, const md_lists* l, uint32_t flags,
                               void* stream) {
-  if (!s || !atoms_ok(a) || !lists_ok(l) || (s->ctot > 0 && !a->xc)) return MD_ERR_ARG;
+  if (!s || !atoms_ok(a) || !lists_ok(s, l) || (s->ctot > 0 && !a->xc)) return MD_ERR_ARG;
   if (!bound(s)) return MD_ERR_STATE;
   return build_chain(s, a, l, flags, (hipStream_t)stream, nullptr, nullptr);
 }
 
 namespace {
 
-// The density pass (morse: with the Cr-C pass in the same launch).
+// Two-tier lists: the inner list refilled from the outer one at the current positions.
+int inner_list(md_system* s, const md_atoms* a, const md_lists* l, hipStream_t st) {
+  if (!s->p.icap) return MD_OK;
+  k_inner_list<<<grid_tiles(s), BLOCK, 0, st>>>(s->K, at<RepDesc>(s, s->L.desc), at<RepState>(s, s->L.state),
+                                                at<int>(s, s->L.tile_rep), qcur(s, a), l->idx, l->cnt, l->iidx,
+                                                l->icnt);
+  return check_launch();
+}
+
+// The density pass (morse: with the Cr-C pass in the same launch; inner: the inner list is
+// refilled first).
 int eam_density(md_system* s, const md_atoms* a, const md_lists* l, uint32_t flags, double* rho_out, bool morse,
-                hipStream_t st) {
+                hipStream_t st, bool inner = true) {
   const bool mixed = flags & MD_F_MIXED, energy = flags & MD_F_ENERGY;
+  if (inner) {
+    const int e = inner_list(s, a, l, st);
+    if (e) return e;
+  }
   switch (s->K.lt) {
     case 1: launch_density<1>(s, a, l, mixed, energy, rho_out, morse, st); break;
     case 2: launch_density<2>(s, a, l, mixed, energy, rho_out, morse, st); break;
@@ -714,7 +740,7 @@ int eam_force(md_system* s, const md_atoms* a, const md_lists* l, uint32_t flags
 
 MD_API int md_eam_forces(md_system* s, const md_atoms* a, const md_lists* l, uint32_t flags,
                          double* rho_out, void* stream) {
-  if (!s || !atoms_ok(a) || !lists_ok(l)) return MD_ERR_ARG;
+  if (!s || !atoms_ok(a) || !lists_ok(s, l)) return MD_ERR_ARG;
   if ((flags & MD_F_MORSE) && s->ctot > 0 && !a->xc) return MD_ERR_ARG;
   if ((flags & MD_F_MIXED) && s->K.pot == MD_POT_FS && s->p.eam.c2 == 0.0) return MD_ERR_ARG;
   if (!bound(s)) return MD_ERR_STATE;
@@ -734,7 +760,7 @@ MD_API int md_eam_forces(md_system* s, const md_atoms* a, const md_lists* l, uin
 
 MD_API int md_morse_forces(md_system* s, const md_atoms* a, const md_lists* l, uint32_t flags,
                            void* stream) {
-  if (!s || !atoms_ok(a) || !lists_ok(l)) return MD_ERR_ARG;
+  if (!s || !atoms_ok(a) || !lists_ok(s, l)) return MD_ERR_ARG;
   if (s->ctot > 0 && !a->xc) return MD_ERR_ARG;
   if (!bound(s)) return MD_ERR_STATE;
   if (s->ctot > 0) launch_morse(s, a, l, flags & MD_F_MIXED, flags & MD_F_KICK, true, (hipStream_t)stream);
@@ -790,7 +816,7 @@ MD_API int md_energy(md_system* s, const md_atoms* a, double* out, void* stream)
 
 MD_API int md_run(md_system* s, const md_atoms* a, const md_lists* l, int32_t nsteps, uint32_t flags,
                   int32_t energy_every, double* obs, const md_trace* trace, void* stream) {
-  if (!s || !atoms_ok(a) || !lists_ok(l) || nsteps < 0) return MD_ERR_ARG;
+  if (!s || !atoms_ok(a) || !lists_ok(s, l) || nsteps < 0) return MD_ERR_ARG;
   if (energy_every > 0 && !obs) return MD_ERR_ARG;
   if (!bound(s)) return MD_ERR_STATE;
   hipStream_t st = (hipStream_t)stream;
@@ -817,8 +843,11 @@ MD_API int md_run(md_system* s, const md_atoms* a, const md_lists* l, int32_t ns
     // Task 4c runs in the density launch; the force pass includes it and gives the kick
     const bool morse = s->ctot > 0;
     const uint32_t ef = mixed | (en ? MD_F_ENERGY : 0);
+    if (ev[6] && (e = hip_status(hipEventRecord(ev[6], st)))) return e;
+    if ((e = inner_list(s, a, l, st))) return e;
+    if (ev[7] && (e = hip_status(hipEventRecord(ev[7], st)))) return e;
     if (ev[4] && (e = hip_status(hipEventRecord(ev[4], st)))) return e;
-    if ((e = eam_density(s, a, l, MD_F_DENSITY | ef, nullptr, morse, st))) return e;
+    if ((e = eam_density(s, a, l, MD_F_DENSITY | ef, nullptr, morse, st, false))) return e;
     if (ev[5] && (e = hip_status(hipEventRecord(ev[5], st)))) return e;
     if (ev[0] && (e = hip_status(hipEventRecord(ev[0], st)))) return e;
     if ((e = eam_force(s, a, l, MD_F_FORCE | MD_F_KICK | ef, morse, st, full, drift))) return e;
@@ -900,7 +929,7 @@ MD_API int md_check(md_system* s, md_status* st_out, void* stream) {
   int e = check_launch();
   if (e) return e;
   int host[8] = {0};
-  if ((e = hip_status(hipMemcpyAsync(host, misc + 8, sizeof(int) * 6, hipMemcpyDeviceToHost, st)))) return e;
+  if ((e = hip_status(hipMemcpyAsync(host, misc + 8, sizeof(int) * 7, hipMemcpyDeviceToHost, st)))) return e;
   if ((e = hip_status(hipStreamSynchronize(st)))) return e;
   std::memset(st_out, 0, sizeof *st_out);
   st_out->overflow = host[0];
@@ -909,6 +938,7 @@ MD_API int md_check(md_system* s, md_status* st_out, void* stream) {
   st_out->nbuilds = host[3];
   st_out->sync_timeout = host[4];
   st_out->nnear = host[5];
+  st_out->ioverflow = host[6];
   return MD_OK;
 }
 

@@ -44,6 +44,7 @@ struct alignas(64) RepState {
   int nonfinite;
   int sync_timeout;
   int nnear;              // Cr atoms within reach of the carbons (entries of the near list)
+  int ioverflow;          // needed inner-list capacity (two-tier lists; 0 = fits)
   // Cr cell grid of the current build: origin, cells per Angstrom, dims (<= gcap).  Along
   // periodic axes it is the box; along open axes it spans the atoms' current extent.
   double glo[3], ginv[3];
@@ -153,7 +154,9 @@ struct Consts {
   double half_skin, half_skin_sq;
   double rlist_sq, rxlist_sq;
   double rlist;           // cutoff + skin
+  double icut_sq;         // two-tier lists: the inner list's radius (the largest Cr-Cr cutoff), squared
   int cap, xcap;
+  int icap;               // two-tier lists: inner-list capacity (0: one list)
   int nrep;
   int lt;                 // list interleave: entries k..k+lt-1 of an atom are adjacent
   int lt_shift;           // log2(lt)

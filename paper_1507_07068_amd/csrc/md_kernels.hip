@@ -226,9 +226,10 @@ __global__ __launch_bounds__(BLOCK) void k_record_builds(const RepState* __restr
 // Status flags, folded over replicas.
 __global__ void k_status(const RepState* __restrict__ S, int nrep, int* __restrict__ out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int o = 0, xo = 0, nf = 0, nb = 0, to = 0, nn = 0;
+  int o = 0, xo = 0, nf = 0, nb = 0, to = 0, nn = 0, io = 0;
   for (int r = 0; r < nrep; ++r) {
     o = max(o, S[r].overflow);
+    io = max(io, S[r].ioverflow);
     xo = max(xo, S[r].xoverflow);
     nf |= S[r].nonfinite;
     nb += S[r].nbuilds;
@@ -241,6 +242,7 @@ __global__ void k_status(const RepState* __restrict__ S, int nrep, int* __restri
   out[3] = nb;
   out[4] = to;
   out[5] = nn;
+  out[6] = io;
 }
 
 // Cell counts back to zero and the abort word of a build that gave up lifted.
@@ -254,6 +256,7 @@ __global__ void k_clear_flags(RepState* __restrict__ S, int nrep) {
   if (r >= nrep) return;
   S[r].overflow = 0;
   S[r].xoverflow = 0;
+  S[r].ioverflow = 0;
   S[r].nonfinite = 0;
   S[r].sync_timeout = 0;
 }

@@ -1191,4 +1191,62 @@ __global__ __launch_bounds__(BLOCK) void k_xlist(Consts K, BuildArgs A) {
   xlist_pass(K, A, cand_sh, pre, blockIdx.x, gridDim.x);
 }
 
+// Section 2.6's inner list, refilled every step from the outer (Verlet) list: atom i's outer
+// entries whose pair is closer than the largest Cr-Cr cutoff at the current positions
+// (minimum image, the list build's exact FP64 predicate), in their outer-list order and in
+// the outer list's layout and entry format.  One lane per atom walks its outer list INNER_U
+// entries at a time, the next group's indices loaded while the current group's positions
+// are gathered.
+constexpr int INNER_U = 8;
+__global__ __launch_bounds__(BLOCK) void k_inner_list(Consts K, const RepDesc* __restrict__ R,
+                                                      RepState* __restrict__ S, const int* __restrict__ tile_rep,
+                                                      const double4* __restrict__ q, const int* __restrict__ idx,
+                                                      const int* __restrict__ cnt, int* __restrict__ iidx,
+                                                      int* __restrict__ icnt) {
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  const int r = tile_rep[tile];
+  const RepDesc& d = R[r];
+  const int64_t i = (int64_t)tile * TILE + threadIdx.x;
+  const bool live = i < (int64_t)d.a0 + d.n;
+  const double4 pi = live ? q[i] : make_double4(0.0, 0.0, 0.0, 0.0);
+  const bool img = wave_near_face(d, live, pi.x, pi.y, pi.z, K.rlist + 2.0 * K.half_skin);
+  if (!live) return;
+  const int n = cnt[i];
+  const int T = K.lt, sh = K.lt_shift;
+  const unsigned stride = (unsigned)K.ntot * T, base = (unsigned)i * T;
+  // word offset of entry k of atom i (32-bit: the lists hold fewer than 2^31 words)
+  auto at_k = [&](int k) { return ((unsigned)k >> sh) * stride + base + (unsigned)(k & (T - 1)); };
+  const int icap = K.icap;
+  const double rc2 = K.icut_sq;
+  int c = 0;
+  int e[INNER_U];
+#pragma unroll
+  for (int u = 0; u < INNER_U; ++u) e[u] = n > 0 ? idx[at_k(min(u, n - 1))] : 0;
+  for (int k0 = 0; k0 < n; k0 += INNER_U) {
+    double4 pj[INNER_U];
+#pragma unroll
+    for (int u = 0; u < INNER_U; ++u) pj[u] = q[list_slot(e[u])];
+    int en[INNER_U];
+#pragma unroll
+    for (int u = 0; u < INNER_U; ++u) en[u] = idx[at_k(min(k0 + INNER_U + u, n - 1))];
+#pragma unroll
+    for (int u = 0; u < INNER_U; ++u) {
+      double ex = pj[u].x - pi.x, ey = pj[u].y - pi.y, ez = pj[u].z - pi.z;
+      if (img) {
+        ex = min_image(ex, d.len[0], d.half[0], d.per[0]);
+        ey = min_image(ey, d.len[1], d.half[1], d.per[1]);
+        ez = min_image(ez, d.len[2], d.half[2], d.per[2]);
+      }
+      if (k0 + u < n && dist_sq_exact(ex, ey, ez) < rc2) {
+        if (c < icap) iidx[at_k(c)] = e[u];
+        ++c;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < INNER_U; ++u) e[u] = en[u];
+  }
+  icnt[i] = min(c, icap);
+  if (c > icap) atomicMax(&S[r].ioverflow, c);
+}
+
 }  // namespace md

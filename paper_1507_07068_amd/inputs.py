@@ -251,6 +251,18 @@ def replica(r: int, steps: int = 1000) -> System:
     return s
 
 
+# Section 2.6's two-tier lists: the outer list reaches 1.7 r*, a skin of 0.7 r* beyond the
+# inner list's radius r* (the paper's cutoff).
+OUTER_SKIN_FACTOR = 0.7
+
+
+def two_tier(s: System) -> System:
+    """`s` with the paper's form and the two-tier lists' outer skin (0.7 r*)."""
+    s.potential = "paper"
+    s.skin = OUTER_SKIN_FACTOR * s.cutoff
+    return s
+
+
 def config(index: int) -> System | list:
     """The five benchmark workloads (c0..c4).  c3 returns a list of 64 replicas."""
     if index == 0:

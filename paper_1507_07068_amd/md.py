@@ -59,7 +59,7 @@ class Params(C.Structure):
     _fields_ = [("eam", EamParams), ("morse", MorseParams), ("mass", C.c_double),
                 ("dt", C.c_double), ("v_ind", C.c_double), ("skin", C.c_double),
                 ("cap", C.c_int32), ("xcap", C.c_int32), ("tpa", C.c_int32), ("shadow", C.c_int32),
-                ("potential", C.c_int32), ("pad", C.c_int32), ("paper", PaperParams)]
+                ("potential", C.c_int32), ("icap", C.c_int32), ("paper", PaperParams)]
 
 
 class ReplicaDesc(C.Structure):
@@ -74,16 +74,16 @@ class Atoms(C.Structure):
 
 class Lists(C.Structure):
     _fields_ = [("idx", C.c_void_p), ("cnt", C.c_void_p), ("xidx", C.c_void_p),
-                ("xcnt", C.c_void_p)]
+                ("xcnt", C.c_void_p), ("iidx", C.c_void_p), ("icnt", C.c_void_p)]
 
 
 class Status(C.Structure):
     _fields_ = [("overflow", C.c_int32), ("xoverflow", C.c_int32), ("nonfinite", C.c_int32),
                 ("nbuilds", C.c_int32), ("sync_timeout", C.c_int32), ("nnear", C.c_int32),
-                ("pad", C.c_int32 * 2)]
+                ("ioverflow", C.c_int32), ("pad", C.c_int32)]
 
 
-MD_TRACE_EVENTS = 6
+MD_TRACE_EVENTS = 8
 
 
 class Trace(C.Structure):
@@ -153,7 +153,7 @@ def _ok(code: int, what: str):
         raise MDError(f"{what}: {msg} ({code})")
 
 
-def make_params(s, cap: int = 64, xcap: int = 64, tpa: int = 1, shadow: bool = False) -> Params:
+def make_params(s, cap: int = 64, xcap: int = 64, tpa: int = 1, shadow: bool = False, icap: int = 0) -> Params:
     p = Params()
     p.eam = EamParams(**{k: float(s.eam[k]) for k in ("A", "c", "d", "c0", "c1", "c2")})
     p.morse = MorseParams(**{k: float(s.morse[k]) for k in ("D", "alpha", "r0", "rc")})
@@ -165,6 +165,7 @@ def make_params(s, cap: int = 64, xcap: int = 64, tpa: int = 1, shadow: bool = F
     p.xcap = int(xcap)
     p.tpa = int(tpa)
     p.shadow = int(bool(shadow))
+    p.icap = int(icap)
     if getattr(s, "potential", "fs") == "paper":
         p.potential = MD_POT_PAPER
         p.paper = PaperParams(**{k: float(s.paper[k]) for k in PAPER_KEYS})
@@ -191,9 +192,11 @@ class Simulation:
 
     def __init__(self, systems, precision: str = "fp64", cap: int | None = None, xcap: int = 160,
                  tpa: int = 1, device: str = "cuda:0", shadow: bool | None = None,
-                 static_workspace: bool = False):
+                 static_workspace: bool = False, icap: int = 0):
         """cap: Cr-Cr list capacity per atom (a multiple of tpa).  shadow: keep the FP32
         cell-local positions for the FP32-mixed passes (default: when precision is mixed).
+        icap: two-tier lists (Section 2.6) with this inner-list capacity per atom; the
+        Cr-Cr list of capacity cap is then the outer list (give the system the outer skin).
         static_workspace: bind the library's static device scratch (md_workspace_bind_static)
         instead of a workspace tensor."""
         import torch
@@ -211,7 +214,7 @@ class Simulation:
         s0 = self.systems[0]
         # the FP32 cell-local shadow serves the FP32-mixed passes only
         self.params = make_params(s0, cap, xcap, tpa,
-                                  shadow=(precision == "mixed") if shadow is None else shadow)
+                                  shadow=(precision == "mixed") if shadow is None else shadow, icap=icap)
         self.tpa = tpa
         descs = (ReplicaDesc * self.nrep)(*[make_replica_desc(s) for s in self.systems])
         h = C.c_void_p()
@@ -221,7 +224,7 @@ class Simulation:
         self.ntot = int(self.lib.md_system_atoms(h))
         self.ctot = int(self.lib.md_system_carbons(h))
         self.offsets = [int(self.lib.md_replica_offset(h, r)) for r in range(self.nrep)]
-        self.cap, self.xcap = cap, xcap
+        self.cap, self.xcap, self.icap = cap, xcap, icap
         self._atoms_c = self._lists_c = None
         self.graphs = []
         dev = self.device
@@ -237,6 +240,8 @@ class Simulation:
             self.cnt = torch.zeros(n, dtype=torch.int32, device=dev)
             self.xidx = torch.zeros((n, xcap), dtype=torch.int32, device=dev)
             self.xcnt = torch.zeros(n, dtype=torch.int32, device=dev)
+            self.iidx = torch.zeros(icap * n, dtype=torch.int32, device=dev) if icap else None
+            self.icnt = torch.zeros(n, dtype=torch.int32, device=dev) if icap else None
             self.rho = torch.zeros(n, dtype=torch.float64, device=dev)
             self.obs_dev = torch.zeros((self.nrep, MD_NOBS), dtype=torch.float64, device=dev)
             self.static_workspace = static_workspace
@@ -263,7 +268,8 @@ class Simulation:
     def _lists(self) -> Lists:
         if self._lists_c is None:
             self._lists_c = Lists(self.idx.data_ptr(), self.cnt.data_ptr(), self.xidx.data_ptr(),
-                                  self.xcnt.data_ptr())
+                                  self.xcnt.data_ptr(), self.iidx.data_ptr() if self.icap else None,
+                                  self.icnt.data_ptr() if self.icap else None)
         return self._lists_c
 
     def _bind(self):
@@ -349,7 +355,8 @@ class Simulation:
         st = Status()
         _ok(self.lib.md_check(self.handle, C.byref(st), self.stream), "md_check")
         return dict(overflow=st.overflow, xoverflow=st.xoverflow, nonfinite=st.nonfinite,
-                    nbuilds=st.nbuilds, sync_timeout=st.sync_timeout, nnear=st.nnear)
+                    nbuilds=st.nbuilds, sync_timeout=st.sync_timeout, nnear=st.nnear,
+                    ioverflow=st.ioverflow)
 
     def md_set_indenter_velocity(self, v_ind: float):
         _ok(self.lib.md_set_indenter_velocity(self.handle, float(v_ind)), "md_set_indenter_velocity")
@@ -449,9 +456,10 @@ class Simulation:
                             ids=ids[slots], slots=slots))
         return out
 
-    def neighbor_sets(self, r: int = 0, cross: bool = False, only=None) -> list:
+    def neighbor_sets(self, r: int = 0, cross: bool = False, only=None, inner: bool = False) -> list:
         """Neighbour sets of replica r in id space: [sorted ids of neighbours of id 0, ...]
-        (entries for the ids in `only` alone when given, None for the others)."""
+        (entries for the ids in `only` alone when given, None for the others).  inner: the
+        inner list of two-tier lists."""
         ids = self.id.cpu().numpy()
         cnt = (self.xcnt if cross else self.cnt).cpu().numpy()
         s = self.systems[r]
@@ -468,18 +476,18 @@ class Simulation:
             for p in slots:
                 sets[ids[p]] = sorted((xidx[p, :cnt[p]] - c0).tolist())
             return sets
-        lists = self.list_rows(slots)
+        lists = self.list_rows(slots, inner=inner)
         for p, row in zip(slots, lists):
             sets[ids[p]] = sorted(ids[row].tolist())
         return sets
 
-    def list_rows(self, slots=None) -> list:
+    def list_rows(self, slots=None, inner: bool = False) -> list:
         """Cr-Cr list of every atom slot, or of the given slots (slots of the neighbours, in
-        list order)."""
+        list order); inner: the inner list of two-tier lists."""
         T, n = self.tpa, self.ntot
-        idx = self.idx.cpu().numpy()
-        cnt = self.cnt.cpu().numpy()
-        k = np.arange(self.cap)
+        idx = (self.iidx if inner else self.idx).cpu().numpy()
+        cnt = (self.icnt if inner else self.cnt).cpu().numpy()
+        k = np.arange(self.icap if inner else self.cap)
         rows = []
         for p in (range(n) if slots is None else slots):
             kk = k[:cnt[p]]
