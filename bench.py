@@ -468,7 +468,7 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(system, threads=None, budget_s=20.0, max_steps=20) -> dict:
+def cpu_baseline(system, threads=None, budget_s=20.0, max_steps=40) -> dict:
     """The FP64 oracle as it stands (lists through its cell grid), on the same workload: the
     set-up at t = 0 (list build, first forces) is timed on its own and taken out, so the rate
     is of whole steps (drift, skin test, rebuilds when due, forces, kicks).  The step count is
