@@ -136,6 +136,9 @@ typedef struct md_params {
                            largest Cr-Cr cutoff; the passes then read the inner list.  0: one
                            list, read by the passes */
     md_eam_paper_params paper;
+    int32_t list_tgt;   /* atoms a work item of the Cr-Cr list build aims at (a launch-shape
+                           choice, 32 .. 256; 0: 224); results do not depend on it */
+    int32_t pad;
 } md_params;
 
 /* One system (replica). */

@@ -63,6 +63,7 @@ struct md_system {
   // grids of the build kernels that stride over their work (set at bind from the device):
   // tile kernels (256 threads) and the persistent list build
   int tile_grid = 2048, list_grid = 2048;
+  int list_tgt = LIST_TGT;   // atoms a list-build work item aims at
   int static_dev = -1;   // device whose static scratch is the workspace (md_workspace_bind_static)
 };
 
@@ -320,6 +321,7 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
   if (p->tpa != 1 && p->tpa != 2 && p->tpa != 4 && p->tpa != 8) return MD_ERR_ARG;
   if (p->cap % p->tpa != 0) return MD_ERR_ARG;
   if (p->icap < 0 || p->icap % p->tpa != 0) return MD_ERR_ARG;
+  if (p->list_tgt != 0 && (p->list_tgt < 32 || p->list_tgt > LIST_BLOCK)) return MD_ERR_ARG;
   if (p->potential != MD_POT_FS && p->potential != MD_POT_PAPER) return MD_ERR_ARG;
   if (p->potential == MD_POT_FS && (!(p->eam.c > 0) || !(p->eam.d > 0) || !(p->eam.d <= p->eam.c)))
     return MD_ERR_ARG;
@@ -337,6 +339,7 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
   s->ws = nullptr;
   s->have_embed = s->have_force = false;
   s->list_mix = false;
+  s->list_tgt = p->list_tgt ? p->list_tgt : LIST_TGT;
   // the list holds pairs within the potential's largest Cr-Cr cutoff + skin
   const double cut = p->potential == MD_POT_PAPER ? std::max(p->paper.rc, p->paper.d * p->paper.re) : p->eam.c;
   const double rlist = cut + p->skin;
@@ -389,7 +392,7 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
     // list build: rows at capacity, each cut into at most nseg runs of cells (twice the
     // runs of LIST_SEG cells, so that dense rows can be cut finer); one block per run
     s->desc.back().rb0 = (int)s->row_rep.size();
-    s->desc.back().nseg = 2 * ((d.gcap[0] + LIST_SEG - 1) / LIST_SEG) * ((224 + LIST_TGT - 1) / LIST_TGT);
+    s->desc.back().nseg = 2 * ((d.gcap[0] + LIST_SEG - 1) / LIST_SEG) * ((224 + s->list_tgt - 1) / s->list_tgt);
     const int64_t nrw = (int64_t)d.gcap[1] * d.gcap[2];
     nlblk += (int64_t)s->desc.back().nseg * nrw;
     if ((int64_t)s->row_rep.size() + nrw > (int64_t)INT32_MAX / 2 || nlblk > (int64_t)INT32_MAX / 2) {
@@ -600,6 +603,7 @@ int build_chain(md_system* s, const md_atoms* a, const md_lists* l, uint32_t fla
   A.next_item = misc + 4;
   A.nrows = s->nrows;
   A.nlblk = s->nlblk;
+  A.list_tgt = s->list_tgt;
   A.c_rep = at<int>(s, s->L.c_rep);
   A.any = misc + 0;
   A.abort = misc + 3;

@@ -82,6 +82,7 @@ struct BuildArgs {
   int scan_chunk, scan_blocks;
   int spin_limit;        // polls of k_scan's look-back before it gives up (< 0: at once)
   int nrows, nlblk;      // cell rows at capacity; capacity of the work-item table
+  int list_tgt;          // atoms a work item aims at (<= LIST_BLOCK)
 };
 
 #ifndef MD_LIST_BATCH
@@ -109,7 +110,7 @@ constexpr int LIST_STAGE = MD_LIST_STAGE;   // candidates k_list_tiles stages in
 #define MD_LIST_TGT 224
 #endif
 constexpr int LIST_BLOCK = MD_LIST_BLOCK;           // threads of k_list_tiles
-constexpr int LIST_TGT = MD_LIST_TGT;               // atoms per work item aimed at
+constexpr int LIST_TGT = MD_LIST_TGT;               // atoms per work item aimed at (default)
 constexpr int LIST_PT = LIST_STAGE / LIST_BLOCK;    // candidates each thread stages per piece
 static_assert(LIST_STAGE % LIST_BLOCK == 0, "a piece is a whole number of candidates per thread");
 static_assert(LIST_TGT <= LIST_BLOCK, "a work item's atoms aimed at fit one pass of the threads");
@@ -464,7 +465,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan(BuildArgs A) {
 }
 
 // Work items of k_list_tiles for cell row g (capacity numbering) of a rebuilding replica:
-// the row is cut into as many runs of cells as keep a run's atoms near LIST_TGT (and no run
+// the row is cut into as many runs of cells as keep a run's atoms near list_tgt (and no run
 // longer than LIST_SEG cells); empty rows get none.  Returns the number of runs.
 __device__ __forceinline__ int row_runs(const BuildArgs& A, int64_t g) {
   if (g >= A.nrows) return 0;
@@ -478,7 +479,7 @@ __device__ __forceinline__ int row_runs(const BuildArgs& A, int64_t g) {
   const int crow = d.g0 + (cz * gy + cy) * gx;
   const int n = A.start[crow + gx] - A.start[crow];
   if (n == 0) return 0;
-  return min(min(d.nseg, gx), max((gx + LIST_SEG - 1) / LIST_SEG, (n + LIST_TGT - 1) / LIST_TGT));
+  return min(min(d.nseg, gx), max((gx + LIST_SEG - 1) / LIST_SEG, (n + A.list_tgt - 1) / A.list_tgt));
 }
 
 __global__ __launch_bounds__(BLOCK) void k_scatter(Consts K, BuildArgs A) {

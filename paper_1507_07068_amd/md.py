@@ -59,7 +59,8 @@ class Params(C.Structure):
     _fields_ = [("eam", EamParams), ("morse", MorseParams), ("mass", C.c_double),
                 ("dt", C.c_double), ("v_ind", C.c_double), ("skin", C.c_double),
                 ("cap", C.c_int32), ("xcap", C.c_int32), ("tpa", C.c_int32), ("shadow", C.c_int32),
-                ("potential", C.c_int32), ("icap", C.c_int32), ("paper", PaperParams)]
+                ("potential", C.c_int32), ("icap", C.c_int32), ("paper", PaperParams),
+                ("list_tgt", C.c_int32), ("pad", C.c_int32)]
 
 
 class ReplicaDesc(C.Structure):
@@ -153,7 +154,8 @@ def _ok(code: int, what: str):
         raise MDError(f"{what}: {msg} ({code})")
 
 
-def make_params(s, cap: int = 64, xcap: int = 64, tpa: int = 1, shadow: bool = False, icap: int = 0) -> Params:
+def make_params(s, cap: int = 64, xcap: int = 64, tpa: int = 1, shadow: bool = False, icap: int = 0,
+                list_tgt: int = 0) -> Params:
     p = Params()
     p.eam = EamParams(**{k: float(s.eam[k]) for k in ("A", "c", "d", "c0", "c1", "c2")})
     p.morse = MorseParams(**{k: float(s.morse[k]) for k in ("D", "alpha", "r0", "rc")})
@@ -166,6 +168,7 @@ def make_params(s, cap: int = 64, xcap: int = 64, tpa: int = 1, shadow: bool = F
     p.tpa = int(tpa)
     p.shadow = int(bool(shadow))
     p.icap = int(icap)
+    p.list_tgt = int(list_tgt)
     if getattr(s, "potential", "fs") == "paper":
         p.potential = MD_POT_PAPER
         p.paper = PaperParams(**{k: float(s.paper[k]) for k in PAPER_KEYS})
@@ -192,11 +195,12 @@ class Simulation:
 
     def __init__(self, systems, precision: str = "fp64", cap: int | None = None, xcap: int = 160,
                  tpa: int = 1, device: str = "cuda:0", shadow: bool | None = None,
-                 static_workspace: bool = False, icap: int = 0):
+                 static_workspace: bool = False, icap: int = 0, list_tgt: int = 0):
         """cap: Cr-Cr list capacity per atom (a multiple of tpa).  shadow: keep the FP32
         cell-local positions for the FP32-mixed passes (default: when precision is mixed).
         icap: two-tier lists (Section 2.6) with this inner-list capacity per atom; the
         Cr-Cr list of capacity cap is then the outer list (give the system the outer skin).
+        list_tgt: atoms a list-build work item aims at (0: the library's default).
         static_workspace: bind the library's static device scratch (md_workspace_bind_static)
         instead of a workspace tensor."""
         import torch
@@ -214,7 +218,8 @@ class Simulation:
         s0 = self.systems[0]
         # the FP32 cell-local shadow serves the FP32-mixed passes only
         self.params = make_params(s0, cap, xcap, tpa,
-                                  shadow=(precision == "mixed") if shadow is None else shadow, icap=icap)
+                                  shadow=(precision == "mixed") if shadow is None else shadow, icap=icap,
+                                  list_tgt=list_tgt)
         self.tpa = tpa
         descs = (ReplicaDesc * self.nrep)(*[make_replica_desc(s) for s in self.systems])
         h = C.c_void_p()

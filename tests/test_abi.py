@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_struct_sizes_match_header(lib):
-    assert C.sizeof(md.Params) == 6 * 8 + 4 * 8 + 4 * 8 + 4 * 4 + 2 * 4 + 14 * 8
+    assert C.sizeof(md.Params) == 6 * 8 + 4 * 8 + 4 * 8 + 4 * 4 + 2 * 4 + 14 * 8 + 2 * 4
     assert C.sizeof(md.ReplicaDesc) == 6 * 8 + 6 * 4
     assert C.sizeof(md.Atoms) == 6 * 8
     assert C.sizeof(md.Lists) == 6 * 8
