@@ -20,7 +20,7 @@ Beside it, in the same JSON line, whatever --steps says:
   full_runs    each workload over its full step count (8M film 500, 216k film 2000, ensemble
                1000), with its list-build count;
   cpu_baseline the FP64 oracle (cell-grid lists) on the same 8M-atom film, all host threads,
-               a bounded number of steps; cpu_baseline_1thread the same on the 216k film.
+               a bounded number of steps; cpu_baseline_1thread the same with one thread (two steps).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4] [--precision fp64]
     python bench.py --copy-probe 512      # plain copy of 512 MiB (counter calibration)
@@ -680,8 +680,10 @@ def main(argv=None):
         result["cpu_baseline"] = cpu_baseline(systems[0])
         log(f"[bench] CPU baseline {result['cpu_baseline']['value']:.4e} atom-steps/s "
             f"({result['cpu_baseline']['cores']} threads)")
-        result["cpu_baseline_1thread"] = cpu_baseline(I.config(1), threads=1, budget_s=8.0, max_steps=10)
-        log(f"[bench] CPU baseline 1 thread (216k film) {result['cpu_baseline_1thread']['value']:.4e}")
+        # one thread on the same workload: two whole steps (a step of the 8M-atom film takes a
+        # single core several seconds)
+        result["cpu_baseline_1thread"] = cpu_baseline(systems[0], threads=1, budget_s=1.0, max_steps=2)
+        log(f"[bench] CPU baseline 1 thread ({systems[0].name}) {result['cpu_baseline_1thread']['value']:.4e}")
     print(json.dumps(result), flush=True)
     return 0
 

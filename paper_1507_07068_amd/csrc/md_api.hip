@@ -30,6 +30,11 @@ struct Layout {
 };
 
 constexpr int MISC_INTS = 16;    // rebuild flag, status words
+// The list build takes one block per work item while the item table's capacity is at most
+// this many waves of resident blocks: measured faster up to the 64-replica ensemble (~27
+// waves; the 216k-atom film 2.6 waves: 67 against 87 us per rebuild), even with a 1M-atom
+// film (~13), slower on the 8M-atom film (~95 waves of idle blocks per step).
+constexpr int LIST_ONE_PER_ITEM_WAVES = 32;
 constexpr int SCAN_CHUNK = 2048; // cells per block of the cell-count scan
 constexpr int64_t DECIDE_IN_BIN_MAX_LOADS = (int64_t)1 << 22;   // part loads over all k_bin blocks
 constexpr int MAXREP = 16384;    // replicas per system
@@ -190,6 +195,13 @@ int4* qsnext(md_system* s) { return at<int4>(s, s->cur ? s->L.qs : s->L.qs2); }
 int scan_spin_limit() {
   const char* e = std::getenv("MD_SCAN_SPIN_LIMIT");
   return e ? std::atoi(e) : (1 << 22);
+}
+
+// The list build's work distribution (see build_chain).
+bool list_persistent(const md_system* s) {
+  const char* e = std::getenv("MD_LIST_PERSISTENT");
+  if (e && *e) return std::atoi(e) != 0;
+  return s->nlblk > LIST_ONE_PER_ITEM_WAVES * s->list_grid;
 }
 
 // Grid of the kernels that walk the near-indenter atoms (one wavefront per atom, grid-stride).
@@ -677,10 +689,16 @@ int build_chain(md_system* s, const md_atoms* a, const md_lists* l, uint32_t fla
   if (ev0 && (e = hip_status(hipEventRecord(ev0, st)))) return e;
   // the Cr-C lists: leading blocks of the staged Cr-Cr list launch, else a launch of their own
   A.xblocks = (s->list_mix || s->ctot == 0) ? 0 : morse_fused_blocks(s);
+  // the Cr-Cr list: one block per work item while the item table's capacity is a few waves
+  // of resident blocks (the idle blocks then cost less than taking items from a counter),
+  // else resident blocks that take items from a counter (MD_LIST_PERSISTENT=0/1 in the
+  // environment overrides the choice)
+  A.persistent = list_persistent(s);
   if (s->list_mix)
     k_list_rows<false><<<s->ntiles, BLOCK, 0, st>>>(s->K, A);
   else
-    k_list_tiles<<<A.xblocks + std::min(s->nlblk, s->list_grid), LIST_BLOCK, 0, st>>>(s->K, A);
+    k_list_tiles<<<A.xblocks + (A.persistent ? std::min(s->nlblk, s->list_grid) : s->nlblk), LIST_BLOCK, 0, st>>>(
+        s->K, A);
   if (ev1 && (e = hip_status(hipEventRecord(ev1, st)))) return e;
   if (s->list_mix && s->ctot > 0) k_xlist<<<A.near_blocks, BLOCK, 0, st>>>(s->K, A);
   return check_launch();

@@ -78,6 +78,8 @@ struct BuildArgs {
                          // tiles, then 256-carbon groups (the grids stride over them)
   int near_blocks;       // grid of k_xlist
   int xblocks;           // leading blocks of k_list_tiles that build the Cr-C lists (0: none)
+  int persistent;        // k_list_tiles: blocks take work items from a counter (else one block
+                         // per item of the table's capacity, the blocks past the items idle)
   int commit_ref;        // k_scan records the indenter position of this build (k_bin decided)
   int scan_chunk, scan_blocks;
   int spin_limit;        // polls of k_scan's look-back before it gives up (< 0: at once)
@@ -928,15 +930,18 @@ __global__ __launch_bounds__(LIST_BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts
                A.xblocks);
     return;
   }
-  // the other blocks stay resident and take work items one at a time from a counter until
-  // none is left (zero items in a step without a rebuild)
+  // the other blocks either stay resident and take work items one at a time from a counter
+  // until none is left (zero items in a step without a rebuild), or take one item each
   __shared__ int item_sh;
   const int nitems = uniform(*A.nitems);
-  for (;;) {
-  __syncthreads();   // the previous item's LDS tables and stage are no longer read
-  if (threadIdx.x == 0) item_sh = atomicAdd(A.next_item, 1);
-  __syncthreads();
-  const int b = uniform(item_sh);
+  for (int pass = 0;; ++pass) {
+  if (!A.persistent && pass > 0) break;
+  if (A.persistent) {
+    __syncthreads();   // the previous item's LDS tables and stage are no longer read
+    if (threadIdx.x == 0) item_sh = atomicAdd(A.next_item, 1);
+    __syncthreads();
+  }
+  const int b = A.persistent ? uniform(item_sh) : (int)blockIdx.x - A.xblocks;
   if (b >= nitems) break;
   const int2 it = A.items[b];
   const int grow = uniform(it.x), sx = uniform(it.y & 0xFFFF), nseg = uniform(it.y >> 16);

@@ -43,3 +43,26 @@ def test_tuner_picks_a_candidate_and_caches(tmp_path, monkeypatch):
     tune._CACHE.clear()
     r3 = tune.choose(ens, "mixed")
     assert r3["from_cache"] == "file" and r3["list_tgt"] == r1["list_tgt"]
+
+
+@pytest.mark.parametrize("nrep", [1, 5])
+def test_list_work_distribution_does_not_change_results(nrep, monkeypatch):
+    """The list build's two ways of handing out work items (one block per item of the table's
+    capacity, or resident blocks taking items from a counter) give bitwise equal runs."""
+    reps = [I.small_film(nx=12 + r, ny=12, nz=6, radius=6.0, gap=0.3, seed=120 + r, noise=0.04)
+            for r in range(nrep)]
+    states = []
+    for mode in ("0", "1"):
+        monkeypatch.setenv("MD_LIST_PERSISTENT", mode)
+        print(f"[case] MD_LIST_PERSISTENT={mode} nrep={nrep}", flush=True)
+        sim = md.Simulation(reps, precision="fp64", xcap=160, tpa=2)
+        sim.initial_forces()
+        sim.md_run(40)
+        st = sim.md_check()
+        assert not (st["overflow"] or st["xoverflow"] or st["nonfinite"] or st["sync_timeout"]), st
+        states.append((sim.state(), [sim.neighbor_sets(r) for r in range(nrep)]))
+    (sa, la), (sb, lb) = states
+    for r in range(nrep):
+        assert la[r] == lb[r]
+        for k in ("x", "v", "f", "dF"):
+            assert np.array_equal(sa[r][k], sb[r][k]), (r, k)
