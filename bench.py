@@ -53,8 +53,9 @@ WORKLOADS = {
     "c4": (4, "cr_film_200x200x100_8m_indenter_r50_preindented"),
 }
 KERNEL_NAMES = {
-    "force": "k_force (EAM Eq. 1 with the Cr-C forces and the fused kicks; FP64 steps whose "
-             "velocities are not observed also drift the atoms)",
+    "force": "k_force (EAM Eq. 1 with the Cr-C forces and the fused kicks; on steps whose "
+             "velocities are not observed the full kick without the force store, and in FP64 the "
+             "drift)",
     "density": "k_density (rho and F'(rho), with the Cr-C Morse pass in its leading blocks)",
     "list": "k_list_tiles (Cr-Cr Verlet list build with the Cr-C lists in leading blocks), "
             "launches of steps that rebuilt",
@@ -68,16 +69,18 @@ def log(*a):
 # ------------------------------------------------------------------------------------------
 # Algorithmic bytes (HBM, per atom, per launch)
 # ------------------------------------------------------------------------------------------
-def force_bytes_per_atom(mean_list: float, mixed: bool, drift: bool) -> float:
+def force_bytes_per_atom(mean_list: float, mixed: bool, full: bool) -> float:
     """One EAM force launch: the atom's own record (FP64 q = x, y, z, F' 32 B; mixed: the
     16-byte fixed-point shadow), list count 4, list entries 4 each, Cr-C count 4, fixed flag
-    1, velocity read + write for the fused kick 48, force write (24 FP64; the FP64 force array
-    in both paths) 24; with the next step's drift in the same launch (FP64 steps whose
-    velocities are not observed) also the new position 32 and the reference position 24.
+    1, velocity read + write for the fused kick 48.  A launch whose full kick stands in for
+    the next step's first half kick (full: steps whose velocities are not observed) does not
+    store the force; the others write it (24, the FP64 force array in both paths).  A full
+    FP64 launch also drifts the atoms: the new position 32 and the reference position 24.
     Neighbour records are gathered from cache (atoms are cell-sorted, so each one comes from
     HBM about once per pass): they are not counted."""
     own = 16 if mixed else 32
-    return own + 4 + 4 * mean_list + 4 + 1 + 48 + 24 + (56 if drift else 0)
+    drift = full and not mixed
+    return own + 4 + 4 * mean_list + 4 + 1 + 48 + (0 if full else 24) + (56 if drift else 0)
 
 
 def density_bytes_per_atom(mean_list: float, mixed: bool) -> float:
@@ -249,10 +252,10 @@ def kernel_pass(sim, systems, steps, ee, precision):
     n_atoms = sum(s.n for s in systems)
     L = 0.5 * (L0 + L1)
     mixed = precision == "mixed"
-    # FP64 steps whose velocities are not observed drift the atoms inside the force launch
-    drift = np.array([(not mixed) and (k + 1) < steps and not (ee > 0 and (k + 1) % ee == 0)
-                      for k in range(steps)])
-    fbytes = n_atoms * np.array([force_bytes_per_atom(L, mixed, d) for d in drift])
+    # steps whose velocities are not observed give the full kick (and, in FP64, the drift)
+    # inside the force launch
+    full = np.array([(k + 1) < steps and not (ee > 0 and (k + 1) % ee == 0) for k in range(steps)])
+    fbytes = n_atoms * np.array([force_bytes_per_atom(L, mixed, u) for u in full])
     out = {"steps": steps, "mean_list": L, "rebuilt_steps": int(rebuilt.sum())}
     out["force"] = dict(avg_us=float(t["force"].mean() * 1e6), total_ms=float(t["force"].sum() * 1e3),
                         bytes_per_launch=float(fbytes.mean()),

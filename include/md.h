@@ -319,8 +319,10 @@ typedef struct md_trace {
  * step's first one are given together (a full kick of the same force) and the next Task 3
  * only drifts: the same velocity Verlet steps, rounded once per kick pair instead of twice.
  * Without the FP32 shadow that drift is done by the force pass itself, into a second
- * position buffer in the workspace.  After md_run the velocities are at the last whole step
- * and the positions are back in a->q.
+ * position buffer in the workspace.  The force pass of such a step leaves a->f alone: no
+ * kick reads the force before the next pass that stores it (within md_run a->f is stale
+ * meanwhile).  After md_run the velocities are at the last whole step, the positions are
+ * back in a->q and a->f holds the forces at them.
  * flags: MD_F_MIXED selects FP32 arithmetic.  energy_every > 0: after step k with
  * k % energy_every == 0 the energies are written as by md_energy to
  * obs[(k / energy_every - 1) * nrep * MD_NOBS ...] (device memory, caller-owned).

@@ -250,6 +250,7 @@ template <int T>
 void launch_force(md_system* s, const md_atoms* a, const md_lists* l, bool mixed, bool kick, bool energy,
                   bool add_fme, hipStream_t st, bool full_kick = false, bool drift = false) {
   const double kick_h = (full_kick ? 1.0 : 0.5) * s->K.dt * s->K.acc;
+  const int store_f = full_kick ? 0 : 1;
   const DriftOut D{qnext(s, a), qsnext(s), at<double>(s, s->L.xref), at<long long>(s, s->L.bcell),
                    at<double>(s, s->L.dmax), at<double>(s, s->L.tbox)};
   const RepDesc* R = at<RepDesc>(s, s->L.desc);
@@ -265,13 +266,13 @@ void launch_force(md_system* s, const md_atoms* a, const md_lists* l, bool mixed
 #define FORCE1(M, SH, KI, E, PA)                                                                                \
   k_force<T, M, SH, KI, E, false, PA><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, qs, a->v, a->f, a->fixed, li,     \
                                                              lc, pf, l->xcnt,                                    \
-                                                             add_fme ? at<double>(s, s->L.fme) : nullptr, kick_h, D, dm)
+                                                             add_fme ? at<double>(s, s->L.fme) : nullptr, kick_h, D, dm, store_f)
 #define FORCE(M, SH, KI, E) \
   if (paper) FORCE1(M, SH, KI, E, true); else FORCE1(M, SH, KI, E, false)
 #define FORCE_DRIFT1(M, SH, PA)                                                                                  \
   k_force<T, M, SH, true, false, true, PA><<<nb, BLOCK, 0, st>>>(                                                \
       s->K, R, S, tr, q, qs, a->v, a->f, a->fixed, li, lc, pf, l->xcnt,                                          \
-      add_fme ? at<double>(s, s->L.fme) : nullptr, kick_h, D, dm)
+      add_fme ? at<double>(s, s->L.fme) : nullptr, kick_h, D, dm, store_f)
 #define FORCE_DRIFT(M, SH) \
   if (paper) FORCE_DRIFT1(M, SH, true); else FORCE_DRIFT1(M, SH, false)
 #define FORCE_E(M, SH, KI) \

@@ -438,7 +438,7 @@ __global__ __launch_bounds__(BLOCK, MD_FORCE_WAVES) void k_force(Consts K, const
                                                  double* __restrict__ part,
                                                  const int* __restrict__ xcnt,
                                                  const double* __restrict__ fme, double kick_h,
-                                                 DriftOut D, const double* __restrict__ dm) {
+                                                 DriftOut D, const double* __restrict__ dm, int store_f) {
   const AtomCtx c = atom_ctx<T>(tile_rep, R, blockIdx.x, gridDim.x);
   const RepDesc& d = R[c.r];
   __shared__ int4 ctab[27];
@@ -705,9 +705,12 @@ __global__ __launch_bounds__(BLOCK, MD_FORCE_WAVES) void k_force(Consts K, const
       fy += fme[4 * i + 1];
       fz += fme[4 * i + 2];
     }
-    f[3 * i + 0] = fx;
-    f[3 * i + 1] = fy;
-    f[3 * i + 2] = fz;
+    if (store_f) {   // (a pass whose full kick stands in for the next step's first half kick
+                     // leaves f alone: no kick reads it before the next pass that stores it)
+      f[3 * i + 0] = fx;
+      f[3 * i + 1] = fy;
+      f[3 * i + 2] = fz;
+    }
     if (!(fabs(fx) + fabs(fy) + fabs(fz) < INFINITY)) S[c.r].nonfinite = 1;
     if (KICK) {   // kick_h = dt a / 2 (Task 5), or dt a (with the next Task 3's); fixed atoms
                   // keep their velocity (written back unchanged)
