@@ -91,13 +91,14 @@ def density_bytes_per_atom(mean_list: float, mixed: bool) -> float:
 
 
 def list_bytes_per_atom(mean_list: float, mixed: bool) -> float:
-    """One Cr-Cr list-build launch that rebuilds, per atom: read the cell-sorted state (q 32,
-    FP32 copy 16, v 24, f 24, fixed 1, id 4) = 101; write it back (q 32, reference position
-    24, v 24, f 24, fixed 1, id 4) plus the list count 4 and the entries 4 each = 113 + 4 L;
-    mixed runs also write the fixed-point shadow 16 and the build cell 8.  Candidates come
-    from cache (each staged cell row once per block); the Cr-C lists of the leading blocks
-    (a few thousand atoms near the indenter) are not counted."""
-    return 101 + 113 + 4 * mean_list + (24 if mixed else 0)
+    """One Cr-Cr list-build launch of md_run that rebuilds, per atom: read the cell-sorted
+    state (q 32, FP32 copy 16, v 24, fixed 1, id 4) = 77; write it back (q 32, reference
+    position 24, v 24, fixed 1, id 4) plus the list count 4 and the entries 4 each = 89 + 4 L
+    (inside md_run the forces are not permuted: no kick reads them before the next force
+    pass stores them); mixed runs also write the fixed-point shadow 16 and the build cell 8.
+    Candidates come from cache (each staged cell row once per block); the Cr-C lists of the
+    leading blocks (a few thousand atoms near the indenter) are not counted."""
+    return 77 + 89 + 4 * mean_list + (24 if mixed else 0)
 
 
 def source_hash(kind: str) -> str:

@@ -603,8 +603,10 @@ namespace {
 
 // The list build; ev0 / ev1 (or null) are recorded just before and after the Cr-Cr list
 // kernel.
+// copy_f: the forces are permuted with the atoms (md_run passes false: its kicks read a->f
+// only after a force pass has stored it since the last build).
 int build_chain(md_system* s, const md_atoms* a, const md_lists* l, uint32_t flags, hipStream_t st,
-                hipEvent_t ev0, hipEvent_t ev1) {
+                hipEvent_t ev0, hipEvent_t ev1, bool copy_f = true) {
   int* misc = at<int>(s, s->L.misc);
   BuildArgs A;
   A.R = at<RepDesc>(s, s->L.desc);
@@ -624,6 +626,7 @@ int build_chain(md_system* s, const md_atoms* a, const md_lists* l, uint32_t fla
   A.q = qcur(s, a);
   A.v = a->v;
   A.f = a->f;
+  A.copy_f = copy_f ? 1 : 0;
   A.fixed = a->fixed;
   A.id = a->id;
   A.xc = a->xc;
@@ -862,7 +865,7 @@ MD_API int md_run(md_system* s, const md_atoms* a, const md_lists* l, int32_t ns
     hipEvent_t ev[MD_TRACE_EVENTS] = {};
     if (trace && trace->events)
       for (int u = 0; u < MD_TRACE_EVENTS; ++u) ev[u] = (hipEvent_t)trace->events[MD_TRACE_EVENTS * (k - 1) + u];
-    if ((e = build_chain(s, a, l, 0, st, ev[2], ev[3]))) return e;
+    if ((e = build_chain(s, a, l, 0, st, ev[2], ev[3], false))) return e;
     // Task 4c runs in the density launch; the force pass includes it and gives the kick
     const bool morse = s->ctot > 0;
     const uint32_t ef = mixed | (en ? MD_F_ENERGY : 0);

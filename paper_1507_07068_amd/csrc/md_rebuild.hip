@@ -81,6 +81,8 @@ struct BuildArgs {
   int persistent;        // k_list_tiles: blocks take work items from a counter (else one block
                          // per item of the table's capacity, the blocks past the items idle)
   int commit_ref;        // k_scan records the indenter position of this build (k_bin decided)
+  int copy_f;            // the forces are permuted with the atoms (0 inside md_run: no kick reads
+                         // them before the next force pass that stores them)
   int scan_chunk, scan_blocks;
   int spin_limit;        // polls of k_scan's look-back before it gives up (< 0: at once)
   int nrows, nlblk;      // cell rows at capacity; capacity of the work-item table
@@ -591,9 +593,11 @@ __global__ __launch_bounds__(BLOCK) void k_sort_gather(Consts K, BuildArgs A) {
       A.tv[3 * p + 0] = A.v[3 * e + 0];
       A.tv[3 * p + 1] = A.v[3 * e + 1];
       A.tv[3 * p + 2] = A.v[3 * e + 2];
-      A.tf[3 * p + 0] = A.f[3 * e + 0];
-      A.tf[3 * p + 1] = A.f[3 * e + 1];
-      A.tf[3 * p + 2] = A.f[3 * e + 2];
+      if (A.copy_f) {
+        A.tf[3 * p + 0] = A.f[3 * e + 0];
+        A.tf[3 * p + 1] = A.f[3 * e + 1];
+        A.tf[3 * p + 2] = A.f[3 * e + 2];
+      }
       A.tfixed[p] = A.fixed[e];
       A.tid[p] = A.id[e];
       // no Cr-C force or list until the Cr-C list build of this rebuild says otherwise
@@ -779,7 +783,8 @@ __global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
     {
       // copy-back of the sorted state, all loads before the first store
       const double v0 = A.tv[3 * p + 0], v1 = A.tv[3 * p + 1], v2 = A.tv[3 * p + 2];
-      const double f0 = A.tf[3 * p + 0], f1 = A.tf[3 * p + 1], f2 = A.tf[3 * p + 2];
+      const bool cf = A.copy_f;
+      const double f0 = cf ? A.tf[3 * p + 0] : 0.0, f1 = cf ? A.tf[3 * p + 1] : 0.0, f2 = cf ? A.tf[3 * p + 2] : 0.0;
       const uint8_t fx = A.tfixed[p];
       const int ide = A.tid[p];
       A.q[p] = pi;
@@ -794,9 +799,11 @@ __global__ __launch_bounds__(BLOCK) void k_list_rows(Consts K, BuildArgs A) {
       A.v[3 * p + 0] = v0;
       A.v[3 * p + 1] = v1;
       A.v[3 * p + 2] = v2;
-      A.f[3 * p + 0] = f0;
-      A.f[3 * p + 1] = f1;
-      A.f[3 * p + 2] = f2;
+      if (cf) {
+        A.f[3 * p + 0] = f0;
+        A.f[3 * p + 1] = f1;
+        A.f[3 * p + 2] = f2;
+      }
       A.fixed[p] = fx;
       A.id[p] = ide;
     }
@@ -1163,7 +1170,8 @@ __global__ __launch_bounds__(LIST_BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts
       // then wait for it)
       const double4 pi = tq[p];
       const double v0 = A.tv[3 * p + 0], v1 = A.tv[3 * p + 1], v2 = A.tv[3 * p + 2];
-      const double f0 = A.tf[3 * p + 0], f1 = A.tf[3 * p + 1], f2 = A.tf[3 * p + 2];
+      const bool cf = A.copy_f;
+      const double f0 = cf ? A.tf[3 * p + 0] : 0.0, f1 = cf ? A.tf[3 * p + 1] : 0.0, f2 = cf ? A.tf[3 * p + 2] : 0.0;
       const uint8_t fx = A.tfixed[p];
       const int ide = A.tid[p];
       A.cnt[p] = min(count, cap);
@@ -1180,9 +1188,11 @@ __global__ __launch_bounds__(LIST_BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts
       A.v[3 * p + 0] = v0;
       A.v[3 * p + 1] = v1;
       A.v[3 * p + 2] = v2;
-      A.f[3 * p + 0] = f0;
-      A.f[3 * p + 1] = f1;
-      A.f[3 * p + 2] = f2;
+      if (cf) {
+        A.f[3 * p + 0] = f0;
+        A.f[3 * p + 1] = f1;
+        A.f[3 * p + 2] = f2;
+      }
       A.fixed[p] = fx;
       A.id[p] = ide;
     }
