@@ -44,6 +44,7 @@ struct alignas(64) RepState {
   int nonfinite;
   int sync_timeout;
   int nnear;              // Cr atoms within reach of the carbons (entries of the near list)
+  int nnear_old;          // entries of the previous build's near list (during a rebuild)
   int ioverflow;          // needed inner-list capacity (two-tier lists; 0 = fits)
   // Cr cell grid of the current build: origin, cells per Angstrom, dims (<= gcap).  Along
   // periodic axes it is the box; along open axes it spans the atoms' current extent.

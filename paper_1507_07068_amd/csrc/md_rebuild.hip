@@ -193,6 +193,7 @@ __device__ __forceinline__ BuildGrid decide_grid(const Consts& K, const BuildArg
 __device__ __forceinline__ void record_grid(RepState& s, const BuildGrid& g) {
   s.rebuild = g.need;
   if (!g.need) return;
+  s.nnear_old = s.nnear;
   s.nnear = 0;
   for (int a = 0; a < 3; ++a) {
     s.glo[a] = g.glo[a];
@@ -517,6 +518,17 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Consts K, BuildArgs A) {
     const int pos = d.a0 + (A.start[cid] - A.start[d.g0]) + A.crank[i];
     A.perm[pos] = (int)i;
     A.skey[pos] = ((long long)cid << 32) | (unsigned)A.id[i];
+    // the Cr-C records (force, energy) are nonzero only at near-list slots: zeroing those of
+    // the previous build's near list (lane k takes entry k) leaves every record zero, and the
+    // Cr-C pass rewrites the new near atoms' records
+    const int64_t k = i - d.a0;
+    if (k < A.S[r].nnear_old) {
+      const int64_t pn = A.near[d.a0 + k];
+      A.fme[4 * pn + 0] = 0.0;
+      A.fme[4 * pn + 1] = 0.0;
+      A.fme[4 * pn + 2] = 0.0;
+      A.fme[4 * pn + 3] = 0.0;
+    }
   } else {
     const int64_t k = (int64_t)(b - A.ntiles) * BLOCK + threadIdx.x;
     if (k >= A.ctot) continue;
@@ -600,12 +612,9 @@ __global__ __launch_bounds__(BLOCK) void k_sort_gather(Consts K, BuildArgs A) {
       }
       A.tfixed[p] = A.fixed[e];
       A.tid[p] = A.id[e];
-      // no Cr-C force or list until the Cr-C list build of this rebuild says otherwise
+      // no Cr-C list until the Cr-C list build of this rebuild says otherwise (k_scatter
+      // zeroed the Cr-C records)
       A.xcnt[p] = 0;
-      A.fme[4 * (int64_t)p + 0] = 0.0;
-      A.fme[4 * (int64_t)p + 1] = 0.0;
-      A.fme[4 * (int64_t)p + 2] = 0.0;
-      A.fme[4 * (int64_t)p + 3] = 0.0;
       if (d.nc > 0) {   // in the stencil of an occupied carbon cell: the atom gets a Cr-C list
         int hx, hy, hz;
         c_cell_coords(d, qe.x, qe.y, qe.z, hx, hy, hz);
