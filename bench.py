@@ -72,10 +72,10 @@ def log(*a):
 def force_bytes_per_atom(mean_list: float, mixed: bool, full: bool) -> float:
     """One EAM force launch: the atom's own record (FP64 q = x, y, z, F' 32 B; mixed: the
     16-byte fixed-point shadow), list count 4, list entries 4 each, Cr-C count 4, fixed flag
-    1, velocity read + write for the fused kick 48.  A launch whose full kick stands in for
-    the next step's first half kick (full: steps whose velocities are not observed) does not
-    store the force; the others write it (24, the FP64 force array in both paths).  A full
-    FP64 launch also drifts the atoms: the new position 32 and the reference position 24.
+    1, velocity read + write for the fused kick 48.  A launch that also gives the next step's
+    first half kick (full: every step of md_run but the last) does not store the force; the
+    last writes it (24, the FP64 force array in both paths).  A full FP64 launch also drifts
+    the atoms: the new position 32 and the reference position 24.
     Neighbour records are gathered from cache (atoms are cell-sorted, so each one comes from
     HBM about once per pass): they are not counted."""
     own = 16 if mixed else 32
@@ -253,9 +253,10 @@ def kernel_pass(sim, systems, steps, ee, precision):
     n_atoms = sum(s.n for s in systems)
     L = 0.5 * (L0 + L1)
     mixed = precision == "mixed"
-    # steps whose velocities are not observed give the full kick (and, in FP64, the drift)
-    # inside the force launch
-    full = np.array([(k + 1) < steps and not (ee > 0 and (k + 1) % ee == 0) for k in range(steps)])
+    # every step but the last gives the next step's first half kick (and, in FP64, the drift)
+    # inside the force launch: steps whose velocities are not observed as one full kick,
+    # observed ones as two half kicks around the energies
+    full = np.array([(k + 1) < steps for k in range(steps)])
     fbytes = n_atoms * np.array([force_bytes_per_atom(L, mixed, u) for u in full])
     out = {"steps": steps, "mean_list": L, "rebuilt_steps": int(rebuilt.sum())}
     out["force"] = dict(avg_us=float(t["force"].mean() * 1e6), total_ms=float(t["force"].sum() * 1e3),

@@ -325,7 +325,10 @@ typedef struct md_trace {
  * back in a->q and a->f holds the forces at them.
  * flags: MD_F_MIXED selects FP32 arithmetic.  energy_every > 0: after step k with
  * k % energy_every == 0 the energies are written as by md_energy to
- * obs[(k / energy_every - 1) * nrep * MD_NOBS ...] (device memory, caller-owned).
+ * obs[(k / energy_every - 1) * nrep * MD_NOBS ...] (device memory, caller-owned).  For such
+ * a step other than the last, the force pass takes the kinetic energy and the Cr-C sums at
+ * the whole step itself and then gives the next step's first half kick as well (the same
+ * sums grouped per block of the pass, equal to md_energy's to rounding).
  * trace: NULL, or timing and rebuild records of the steps (see md_trace).
  * Lists must have been built and forces evaluated once before the first step
  * (md_build_neighbors with MD_B_FORCE, md_eam_forces with DENSITY|FORCE|MORSE). */

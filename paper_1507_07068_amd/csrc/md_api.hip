@@ -60,6 +60,9 @@ struct md_system {
   int scan_blocks;
   bool list_mix;   // some periodic axis has fewer than 3 list cells
   bool have_embed, have_force;
+  // md_run's energy steps other than the last take the kinetic energy inside the force pass
+  // (KinOut); MD_FUSE_ENERGY=0 in the environment at creation: by a pass of its own
+  bool fuse_energy = true;
   // Inside md_run the positions alternate between the caller's q (with the workspace
   // shadow qs) and the workspace pair q2, qs2: cur says which holds the current ones
   // (outside md_run always the caller's).  ppt: parts per tile of the last displacement
@@ -146,8 +149,9 @@ Layout make_layout(const md_system& s) {
   L.dm = take(sizeof(double) * n);       // M'(P_i) of the paper's form
   L.p_embed = take(sizeof(double) * nt * s.K.lt);
   L.p_force = take(sizeof(double) * nt * s.K.lt * NP_FORCE);
-  L.p_morse = take(sizeof(double) * nt * 4);
-  L.p_kin = take(sizeof(double) * nt);
+  // k_kinetic's partials per tile, or those of a force pass that takes them (per block)
+  L.p_morse = take(sizeof(double) * nt * s.K.lt * 4);
+  L.p_kin = take(sizeof(double) * nt * s.K.lt);
   L.total = o;
   return L;
 }
@@ -246,11 +250,15 @@ void launch_density(md_system* s, const md_atoms* a, const md_lists* l, bool mix
 template <int T>
 // add_fme: the force includes the Cr-C force of this step from fme; full_kick: the kick is
 // dt a (the two half kicks of Task 5 and the next step's Task 3 at once), else dt a / 2;
-// drift (with full_kick): the pass also drifts the atoms into the next position buffer.
+// drift (with full_kick or fuse_ke): the pass also drifts the atoms into the next position
+// buffer; fuse_ke (with kick and energy): the two half kicks around an observed whole step,
+// with its kinetic energy and Cr-C sums (KinOut).
 void launch_force(md_system* s, const md_atoms* a, const md_lists* l, bool mixed, bool kick, bool energy,
-                  bool add_fme, hipStream_t st, bool full_kick = false, bool drift = false) {
+                  bool add_fme, hipStream_t st, bool full_kick, bool drift, bool fuse_ke) {
   const double kick_h = (full_kick ? 1.0 : 0.5) * s->K.dt * s->K.acc;
-  const int store_f = full_kick ? 0 : 1;
+  const int store_f = (full_kick || fuse_ke) ? 0 : 1;
+  const KinOut KO = fuse_ke ? KinOut{at<double>(s, s->L.p_kin), at<double>(s, s->L.p_morse)}
+                            : KinOut{nullptr, nullptr};
   const DriftOut D{qnext(s, a), qsnext(s), at<double>(s, s->L.xref), at<long long>(s, s->L.bcell),
                    at<double>(s, s->L.dmax), at<double>(s, s->L.tbox)};
   const RepDesc* R = at<RepDesc>(s, s->L.desc);
@@ -266,15 +274,17 @@ void launch_force(md_system* s, const md_atoms* a, const md_lists* l, bool mixed
 #define FORCE1(M, SH, KI, E, PA)                                                                                \
   k_force<T, M, SH, KI, E, false, PA><<<nb, BLOCK, 0, st>>>(s->K, R, S, tr, q, qs, a->v, a->f, a->fixed, li,     \
                                                              lc, pf, l->xcnt,                                    \
-                                                             add_fme ? at<double>(s, s->L.fme) : nullptr, kick_h, D, dm, store_f)
+                                                             add_fme ? at<double>(s, s->L.fme) : nullptr, kick_h, D, dm, store_f, KO)
 #define FORCE(M, SH, KI, E) \
   if (paper) FORCE1(M, SH, KI, E, true); else FORCE1(M, SH, KI, E, false)
-#define FORCE_DRIFT1(M, SH, PA)                                                                                  \
-  k_force<T, M, SH, true, false, true, PA><<<nb, BLOCK, 0, st>>>(                                                \
+#define FORCE_DRIFT1(M, SH, E, PA)                                                                               \
+  k_force<T, M, SH, true, E, true, PA><<<nb, BLOCK, 0, st>>>(                                                    \
       s->K, R, S, tr, q, qs, a->v, a->f, a->fixed, li, lc, pf, l->xcnt,                                          \
-      add_fme ? at<double>(s, s->L.fme) : nullptr, kick_h, D, dm, store_f)
+      add_fme ? at<double>(s, s->L.fme) : nullptr, kick_h, D, dm, store_f, KO)
+#define FORCE_DRIFT2(M, SH, E) \
+  if (paper) FORCE_DRIFT1(M, SH, E, true); else FORCE_DRIFT1(M, SH, E, false)
 #define FORCE_DRIFT(M, SH) \
-  if (paper) FORCE_DRIFT1(M, SH, true); else FORCE_DRIFT1(M, SH, false)
+  if (energy) { FORCE_DRIFT2(M, SH, true); } else { FORCE_DRIFT2(M, SH, false); }
 #define FORCE_E(M, SH, KI) \
   if (energy) { FORCE(M, SH, KI, true); } else { FORCE(M, SH, KI, false); }
 #define FORCE_K(M, SH) \
@@ -287,6 +297,7 @@ void launch_force(md_system* s, const md_atoms* a, const md_lists* l, bool mixed
   else if (mixed) { FORCE_K(true, false); }
   else { FORCE_K(false, false); }
 #undef FORCE_DRIFT
+#undef FORCE_DRIFT2
 #undef FORCE_DRIFT1
 #undef FORCE_K
 #undef FORCE_E
@@ -498,6 +509,10 @@ MD_API int md_system_create(const md_replica_desc* reps, int32_t nrep, const md_
     P.b3 = q.a3;
     const double bh = 0.5 * q.beta;
     P.bh = (bh == std::floor(bh) && bh >= 1.0 && bh <= 8.0) ? (int)bh : 0;
+  }
+  {
+    const char* fe = std::getenv("MD_FUSE_ENERGY");
+    s->fuse_energy = !(fe && std::atoi(fe) == 0);
   }
   s->L = make_layout(*s);
   *out = s;
@@ -750,13 +765,13 @@ int eam_density(md_system* s, const md_atoms* a, const md_lists* l, uint32_t fla
 // The force pass (add_fme: the Cr-C forces recorded in fme this step are included;
 // full_kick: see launch_force).
 int eam_force(md_system* s, const md_atoms* a, const md_lists* l, uint32_t flags, bool add_fme, hipStream_t st,
-              bool full_kick = false, bool drift = false) {
+              bool full_kick = false, bool drift = false, bool fuse_ke = false) {
   const bool mixed = flags & MD_F_MIXED, energy = flags & MD_F_ENERGY, kick = flags & MD_F_KICK;
   switch (s->K.lt) {
-    case 1: launch_force<1>(s, a, l, mixed, kick, energy, add_fme, st, full_kick, drift); break;
-    case 2: launch_force<2>(s, a, l, mixed, kick, energy, add_fme, st, full_kick, drift); break;
-    case 4: launch_force<4>(s, a, l, mixed, kick, energy, add_fme, st, full_kick, drift); break;
-    default: launch_force<8>(s, a, l, mixed, kick, energy, add_fme, st, full_kick, drift); break;
+    case 1: launch_force<1>(s, a, l, mixed, kick, energy, add_fme, st, full_kick, drift, fuse_ke); break;
+    case 2: launch_force<2>(s, a, l, mixed, kick, energy, add_fme, st, full_kick, drift, fuse_ke); break;
+    case 4: launch_force<4>(s, a, l, mixed, kick, energy, add_fme, st, full_kick, drift, fuse_ke); break;
+    default: launch_force<8>(s, a, l, mixed, kick, energy, add_fme, st, full_kick, drift, fuse_ke); break;
   }
   s->have_force = energy;
   return check_launch();
@@ -824,6 +839,23 @@ MD_API int md_verlet_step(md_system* s, int32_t phase, const md_atoms* a, void* 
   return check_launch();
 }
 
+namespace {
+
+// Task 4d: the per-replica sums of the last passes' partials into out (tpk: blocks per tile
+// of the pass that wrote the kinetic and Cr-C partials; ind_obs: that pass, taking them
+// (KinOut) with the drift, has moved the indenter on and kept the observed step's position).
+int energy_sums(md_system* s, double* out, int tpk, bool ind_obs, hipStream_t st) {
+  k_reduce_chunks<<<(int)s->chunks.size(), BLOCK, 0, st>>>(
+      at<int2>(s, s->L.chunks), s->have_embed ? at<double>(s, s->L.p_embed) : nullptr, s->K.lt,
+      s->have_force ? at<double>(s, s->L.p_force) : nullptr, s->K.lt, at<double>(s, s->L.p_morse),
+      at<double>(s, s->L.p_kin), tpk, at<double>(s, s->L.chunk_out));
+  k_reduce<<<s->nrep, BLOCK, 0, st>>>(at<RepDesc>(s, s->L.desc), at<RepState>(s, s->L.state),
+                                      at<double>(s, s->L.chunk_out), out, ind_obs ? 1 : 0);
+  return check_launch();
+}
+
+}  // namespace
+
 MD_API int md_energy(md_system* s, const md_atoms* a, double* out, void* stream) {
   if (!s || !atoms_ok(a) || !out) return MD_ERR_ARG;
   if (!bound(s)) return MD_ERR_STATE;
@@ -833,11 +865,7 @@ MD_API int md_energy(md_system* s, const md_atoms* a, double* out, void* stream)
   double* pk = at<double>(s, s->L.p_kin);
   double* pm = at<double>(s, s->L.p_morse);
   k_kinetic<<<grid_tiles(s), BLOCK, 0, st>>>(s->K, R, tr, a->v, a->fixed, at<double>(s, s->L.fme), pk, pm);
-  k_reduce_chunks<<<(int)s->chunks.size(), BLOCK, 0, st>>>(
-      at<int2>(s, s->L.chunks), s->have_embed ? at<double>(s, s->L.p_embed) : nullptr, s->K.lt,
-      s->have_force ? at<double>(s, s->L.p_force) : nullptr, s->K.lt, pm, pk, at<double>(s, s->L.chunk_out));
-  k_reduce<<<s->nrep, BLOCK, 0, st>>>(R, at<RepState>(s, s->L.state), at<double>(s, s->L.chunk_out), out);
-  return check_launch();
+  return energy_sums(s, out, 1, false, st);
 }
 
 MD_API int md_run(md_system* s, const md_atoms* a, const md_lists* l, int32_t nsteps, uint32_t flags,
@@ -860,7 +888,10 @@ MD_API int md_run(md_system* s, const md_atoms* a, const md_lists* l, int32_t ns
   for (int k = 1; k <= nsteps; ++k) {
     const bool en = energy_every > 0 && k % energy_every == 0;
     const bool full = k < nsteps && !en;
-    const bool drift = full && !s->K.shadow;
+    // an observed step other than the last: its energies taken inside the force pass, which
+    // then also gives the next step's first half kick (KinOut)
+    const bool fuse = en && k < nsteps && s->fuse_energy;
+    const bool drift = (full || fuse) && !s->K.shadow;
     if (!drifted) launch_kick_drift(s, a, st, whole);
     hipEvent_t ev[MD_TRACE_EVENTS] = {};
     if (trace && trace->events)
@@ -876,7 +907,7 @@ MD_API int md_run(md_system* s, const md_atoms* a, const md_lists* l, int32_t ns
     if ((e = eam_density(s, a, l, MD_F_DENSITY | ef, nullptr, morse, st, false))) return e;
     if (ev[5] && (e = hip_status(hipEventRecord(ev[5], st)))) return e;
     if (ev[0] && (e = hip_status(hipEventRecord(ev[0], st)))) return e;
-    if ((e = eam_force(s, a, l, MD_F_FORCE | MD_F_KICK | ef, morse, st, full, drift))) return e;
+    if ((e = eam_force(s, a, l, MD_F_FORCE | MD_F_KICK | ef, morse, st, full, drift, fuse))) return e;
     if (ev[1] && (e = hip_status(hipEventRecord(ev[1], st)))) return e;
     if (trace && trace->builds) {
       k_record_builds<<<(s->nrep + BLOCK - 1) / BLOCK, BLOCK, 0, st>>>(
@@ -888,10 +919,10 @@ MD_API int md_run(md_system* s, const md_atoms* a, const md_lists* l, int32_t ns
       s->ppt = s->K.lt;
     }
     drifted = drift;
-    whole = !full;
+    whole = !(full || fuse);
     if (en) {
       double* out = obs + (int64_t)(k / energy_every - 1) * s->nrep * MD_NOBS;
-      if ((e = md_energy(s, a, out, stream))) return e;
+      if ((e = fuse ? energy_sums(s, out, s->K.lt, drift, st) : md_energy(s, a, out, stream))) return e;
     }
   }
   if (s->cur) {   // the positions back into the caller's q

@@ -37,6 +37,7 @@ struct RepDesc {
 struct alignas(64) RepState {
   double ind_z;           // indenter displacement along z
   double ind_z_ref;       // ind_z at the last list build
+  double ind_z_obs;       // ind_z of the step whose energies a force pass took (KinOut)
   int rebuild;            // 1: the next k_rebuild rebuilds this replica
   int nbuilds;
   int overflow;           // needed Cr-Cr capacity (0 = fits)

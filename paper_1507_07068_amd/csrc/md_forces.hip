@@ -409,6 +409,17 @@ struct DriftOut {
   double* tbox;           // [6 (tile * T + part) + ...]
 };
 
+// An energy step of md_run whose end velocities are observed but which is not the last: with
+// kin set (and KICK, ENERGY), the pass kicks to the whole step, takes the kinetic energy and
+// the Cr-C sums there (the k_kinetic terms, as partials per block), then gives the next
+// step's first half kick too, so that the next Task 3 only drifts (done by this pass with
+// DRIFT).  Each velocity sees the same two kicks, in the same order, as with the separate
+// passes.
+struct KinOut {
+  double* kin;            // [tile * T + part] kinetic energy (NULL: not such a step)
+  double* morse;          // [4 (tile * T + part) + ...] Cr-C energy and indenter load
+};
+
 // Occupancy floor of the force pass (wavefronts per SIMD its registers must allow).
 #ifndef MD_FORCE_WAVES
 #define MD_FORCE_WAVES 1
@@ -438,7 +449,8 @@ __global__ __launch_bounds__(BLOCK, MD_FORCE_WAVES) void k_force(Consts K, const
                                                  double* __restrict__ part,
                                                  const int* __restrict__ xcnt,
                                                  const double* __restrict__ fme, double kick_h,
-                                                 DriftOut D, const double* __restrict__ dm, int store_f) {
+                                                 DriftOut D, const double* __restrict__ dm, int store_f,
+                                                 KinOut KO) {
   const AtomCtx c = atom_ctx<T>(tile_rep, R, blockIdx.x, gridDim.x);
   const RepDesc& d = R[c.r];
   __shared__ int4 ctab[27];
@@ -677,6 +689,7 @@ __global__ __launch_bounds__(BLOCK, MD_FORCE_WAVES) void k_force(Consts K, const
   fy = group_sum<T>(fy);
   fz = group_sum<T>(fz);
   const bool own = c.live && c.sub == 0;
+  double ke[1] = {0.0}, mo[4] = {0.0, 0.0, 0.0, 0.0};   // with KO.kin: this atom's k_kinetic terms
   double4 p = make_double4(0.0, 0.0, 0.0, 0.0);   // with DRIFT: the atom's next position
   double d2 = 0.0;                                 // and its squared displacement since the build
   if (own) {
@@ -704,6 +717,12 @@ __global__ __launch_bounds__(BLOCK, MD_FORCE_WAVES) void k_force(Consts K, const
       fx += fme[4 * i + 0];
       fy += fme[4 * i + 1];
       fz += fme[4 * i + 2];
+      if (ENERGY && KO.kin) {   // (records of atoms without carbons in range are zero)
+        mo[0] = fme[4 * i + 3];
+        mo[1] = -fme[4 * i + 0];
+        mo[2] = -fme[4 * i + 1];
+        mo[3] = -fme[4 * i + 2];
+      }
     }
     if (store_f) {   // (a pass whose full kick stands in for the next step's first half kick
                      // leaves f alone: no kick reads it before the next pass that stores it)
@@ -714,8 +733,16 @@ __global__ __launch_bounds__(BLOCK, MD_FORCE_WAVES) void k_force(Consts K, const
     if (!(fabs(fx) + fabs(fy) + fabs(fz) < INFINITY)) S[c.r].nonfinite = 1;
     if (KICK) {   // kick_h = dt a / 2 (Task 5), or dt a (with the next Task 3's); fixed atoms
                   // keep their velocity (written back unchanged)
-      const double vx = move ? v0 + kick_h * fx : v0, vy = move ? v1 + kick_h * fy : v1,
-                   vz = move ? v2 + kick_h * fz : v2;
+      double vx = move ? v0 + kick_h * fx : v0, vy = move ? v1 + kick_h * fy : v1,
+             vz = move ? v2 + kick_h * fz : v2;
+      if (ENERGY && KO.kin) {   // kinetic energy at the whole step, then the next half kick
+        if (move) {
+          ke[0] = K.ke_fac * ((vx * vx + vy * vy) + vz * vz);
+          vx += kick_h * fx;
+          vy += kick_h * fy;
+          vz += kick_h * fz;
+        }
+      }
       v[3 * i + 0] = vx;
       v[3 * i + 1] = vy;
       v[3 * i + 2] = vz;
@@ -750,10 +777,17 @@ __global__ __launch_bounds__(BLOCK, MD_FORCE_WAVES) void k_force(Consts K, const
         D.tbox[6 * (int64_t)c.blk + a] = -m[1 + a];
         D.tbox[6 * (int64_t)c.blk + 3 + a] = m[4 + a];
       }
-      if (c.blk == d.t0 * T) S[c.r].ind_z += K.v_ind * K.dt;   // Task 2, once per replica
+      if (c.blk == d.t0 * T) {   // Task 2, once per replica (the observed step's position kept)
+        if (ENERGY && KO.kin) S[c.r].ind_z_obs = S[c.r].ind_z;
+        S[c.r].ind_z += K.v_ind * K.dt;
+      }
     }
   }
   if (ENERGY) block_sum_store<NP_FORCE, BLOCK>(acc, part + (int64_t)c.blk * NP_FORCE);
+  if (ENERGY && KO.kin) {
+    block_sum_store<1, BLOCK>(ke, KO.kin + c.blk);
+    block_sum_store<4, BLOCK>(mo, KO.morse + (int64_t)c.blk * 4);
+  }
 }
 
 // Task 5 alone.

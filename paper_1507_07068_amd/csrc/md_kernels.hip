@@ -160,14 +160,15 @@ __global__ __launch_bounds__(BLOCK) void k_kinetic(Consts K, const RepDesc* __re
 // depends only on the replica's own tile count, so a replica's sums do not depend on the
 // batch), one block sums a chunk's partials, then one block per replica sums its chunks in
 // order.  Partial arrays that were not produced are passed as NULL; tpe / tpf are the
-// blocks per tile of the density / force launches that wrote p_embed / p_force.
+// blocks per tile of the density / force launches that wrote p_embed / p_force, tpk of the
+// launch that wrote p_kin and p_morse (k_kinetic: 1, a force pass that took them: T).
 constexpr int REDUCE_CHUNK = 512;
 
 __global__ __launch_bounds__(BLOCK) void k_reduce_chunks(const int2* __restrict__ chunks,
                                                          const double* __restrict__ p_embed, int tpe,
                                                          const double* __restrict__ p_force, int tpf,
                                                          const double* __restrict__ p_morse,
-                                                         const double* __restrict__ p_kin,
+                                                         const double* __restrict__ p_kin, int tpk,
                                                          double* __restrict__ chunk_out) {
   const int2 ch = chunks[blockIdx.x];   // first tile, tile count
   double acc[16];
@@ -182,7 +183,7 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_chunks(const int2* __restrict_
 #pragma unroll
       for (int k = 0; k < 6; ++k) acc[MD_W_XX + k] += pf[P_WXX + k];
     }
-  for (int t = ch.x + threadIdx.x; t < ch.x + ch.y; t += BLOCK) {
+  for (int t = ch.x * tpk + threadIdx.x; t < (ch.x + ch.y) * tpk; t += BLOCK) {
     if (p_kin) acc[MD_E_KIN] += p_kin[t];
     if (p_morse) {
       const double* pm = p_morse + (int64_t)t * 4;
@@ -199,7 +200,7 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_chunks(const int2* __restrict_
 __global__ __launch_bounds__(BLOCK) void k_reduce(const RepDesc* __restrict__ R,
                                                   const RepState* __restrict__ S,
                                                   const double* __restrict__ chunk_out,
-                                                  double* __restrict__ out) {
+                                                  double* __restrict__ out, int ind_obs) {
   const int r = blockIdx.x;
   const RepDesc& d = R[r];
   double acc[16];
@@ -210,7 +211,8 @@ __global__ __launch_bounds__(BLOCK) void k_reduce(const RepDesc* __restrict__ R,
     for (int k = 0; k < 16; ++k) acc[k] += chunk_out[(int64_t)c * 16 + k];
   block_sum_store<16, BLOCK>(acc, out + (int64_t)r * MD_NOBS);
   if (threadIdx.x == 0) {
-    out[(int64_t)r * MD_NOBS + MD_IND_Z] = S[r].ind_z;
+    // (ind_obs: a force pass that took the energies has moved the indenter on already)
+    out[(int64_t)r * MD_NOBS + MD_IND_Z] = ind_obs ? S[r].ind_z_obs : S[r].ind_z;
     out[(int64_t)r * MD_NOBS + MD_NBUILDS] = (double)S[r].nbuilds;
     out[(int64_t)r * MD_NOBS + 15] = 0.0;
   }
