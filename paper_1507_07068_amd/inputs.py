@@ -270,14 +270,14 @@ def config(index: int) -> System | list:
     if index == 1:
         return film(60, 60, 30, 20.0, 3.0, 1, steps=2000, name="c1_film_216k_fp64")
     if index == 2:
-        s = film(100, 100, 50, 30.0, 3.0, 2, steps=2000, name="c2_film_1m_mixed")
+        s = film(100, 100, 50, 30.0, 3.0, 2, steps=2000, name="c2_film_1m")
         s.precision = "mixed"
         return s
     if index == 3:
         return [replica(r) for r in range(64)]
     if index == 4:
         s = film(200, 200, 100, 50.0, 0.0, 4, steps=500, preindent=20.0,
-                 name="c4_film_8m_mixed")
+                 name="c4_film_8m")
         s.precision = "mixed"
         return s
     raise ValueError(f"no workload {index}")
