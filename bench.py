@@ -54,8 +54,7 @@ WORKLOADS = {
 }
 KERNEL_NAMES = {
     "force": "k_force (EAM Eq. 1 with the Cr-C forces and the fused kicks; on steps whose "
-             "velocities are not observed the full kick without the force store, and in FP64 the "
-             "drift)",
+             "velocities are not observed the full kick without the force store, and the drift)",
     "density": "k_density (rho and F'(rho), with the Cr-C Morse pass in its leading blocks)",
     "list": "k_list_tiles (Cr-Cr Verlet list build with the Cr-C lists in leading blocks), "
             "launches of steps that rebuilt",
@@ -74,13 +73,14 @@ def force_bytes_per_atom(mean_list: float, mixed: bool, full: bool) -> float:
     16-byte fixed-point shadow), list count 4, list entries 4 each, Cr-C count 4, fixed flag
     1, velocity read + write for the fused kick 48.  A launch that also gives the next step's
     first half kick (full: every step of md_run but the last) does not store the force; the
-    last writes it (24, the FP64 force array in both paths).  A full FP64 launch also drifts
-    the atoms: the new position 32 and the reference position 24.
+    last writes it (24, the FP64 force array in both paths).  A full launch also drifts the
+    atoms: the new position 32 and the reference position 24 (mixed: also the FP64 position
+    32, the new shadow 16 and the build cell 8).
     Neighbour records are gathered from cache (atoms are cell-sorted, so each one comes from
     HBM about once per pass): they are not counted."""
     own = 16 if mixed else 32
-    drift = full and not mixed
-    return own + 4 + 4 * mean_list + 4 + 1 + 48 + (0 if full else 24) + (56 if drift else 0)
+    drift = (56 + (56 if mixed else 0)) if full else 0
+    return own + 4 + 4 * mean_list + 4 + 1 + 48 + (0 if full else 24) + drift
 
 
 def density_bytes_per_atom(mean_list: float, mixed: bool) -> float:
@@ -253,9 +253,9 @@ def kernel_pass(sim, systems, steps, ee, precision):
     n_atoms = sum(s.n for s in systems)
     L = 0.5 * (L0 + L1)
     mixed = precision == "mixed"
-    # every step but the last gives the next step's first half kick (and, in FP64, the drift)
-    # inside the force launch: steps whose velocities are not observed as one full kick,
-    # observed ones as two half kicks around the energies
+    # every step but the last gives the next step's first half kick and drift inside the force
+    # launch: steps whose velocities are not observed as one full kick, observed ones as two
+    # half kicks around the energies
     full = np.array([(k + 1) < steps for k in range(steps)])
     fbytes = n_atoms * np.array([force_bytes_per_atom(L, mixed, u) for u in full])
     out = {"steps": steps, "mean_list": L, "rebuilt_steps": int(rebuilt.sum())}

@@ -318,8 +318,8 @@ typedef struct md_trace {
  * not observed (no energies after it, not the last step), its final half kick and the next
  * step's first one are given together (a full kick of the same force) and the next Task 3
  * only drifts: the same velocity Verlet steps, rounded once per kick pair instead of twice.
- * Without the FP32 shadow that drift is done by the force pass itself, into a second
- * position buffer in the workspace.  The force pass of such a step leaves a->f alone: no
+ * That drift is done by the force pass itself, into a second position buffer (and FP32
+ * shadow) in the workspace.  The force pass of such a step leaves a->f alone: no
  * kick reads the force before the next pass that stores it (within md_run a->f is stale
  * meanwhile).  After md_run the velocities are at the last whole step, the positions are
  * back in a->q and a->f holds the forces at them.

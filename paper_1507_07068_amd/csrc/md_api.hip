@@ -880,9 +880,8 @@ MD_API int md_run(md_system* s, const md_atoms* a, const md_lists* l, int32_t ns
   // not observed (no energies, not the last step), its final half kick and the next step's
   // first one are given together by the force pass (a full kick of the same force), and
   // the next Task 3 only drifts.
-  // Without the FP32 shadow, the force pass of such a step also does the next step's drift
-  // (into the other position buffer; the positions come back to the caller's q at the end).
-  // With it, the shadow's update made that slower than the drift pass of its own.
+  // The force pass of such a step also does the next step's drift (into the other position
+  // buffer and shadow; the positions come back to the caller's q at the end).
   bool drifted = false;   // this step's Task 2 + 3 was done by the previous force pass
   bool whole = true;      // the velocities are at a whole step
   for (int k = 1; k <= nsteps; ++k) {
@@ -891,7 +890,7 @@ MD_API int md_run(md_system* s, const md_atoms* a, const md_lists* l, int32_t ns
     // an observed step other than the last: its energies taken inside the force pass, which
     // then also gives the next step's first half kick (KinOut)
     const bool fuse = en && k < nsteps && s->fuse_energy;
-    const bool drift = (full || fuse) && !s->K.shadow;
+    const bool drift = full || fuse;
     if (!drifted) launch_kick_drift(s, a, st, whole);
     hipEvent_t ev[MD_TRACE_EVENTS] = {};
     if (trace && trace->events)
