@@ -26,7 +26,7 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 struct Layout {
   size_t desc, state, tile_rep, row_rep, items, c_rep, misc, chunks, chunk_out, xref, dmax, tbox, cellid, crank, perm, skey, tq, tqf, qs, q2, qs2, bcell, tv,
       tf, tfixed, tid, count, start, hcell, hrank, hlist, hsorted, scan_state, hnear, near, fme, p_embed, p_force,
-      p_morse, p_kin, dm, total;
+      p_morse, p_kin, dm, dmax_p, tbox_p, total;
 };
 
 constexpr int MISC_INTS = 16;    // rebuild flag, status words
@@ -37,6 +37,7 @@ constexpr int MISC_INTS = 16;    // rebuild flag, status words
 constexpr int LIST_ONE_PER_ITEM_WAVES = 32;
 constexpr int SCAN_CHUNK = 2048; // cells per block of the cell-count scan
 constexpr int64_t DECIDE_IN_BIN_MAX_LOADS = (int64_t)1 << 22;   // part loads over all k_bin blocks
+constexpr int PARTS_REDUCED = 64;   // partial reductions of a large single replica's parts
 constexpr int MAXREP = 16384;    // replicas per system
 
 }  // namespace
@@ -147,6 +148,8 @@ Layout make_layout(const md_system& s) {
   L.near = take(sizeof(int) * n);
   L.fme = take(sizeof(double) * 4 * n);
   L.dm = take(sizeof(double) * n);       // M'(P_i) of the paper's form
+  L.dmax_p = take(sizeof(double) * PARTS_REDUCED);   // k_parts_reduce's partial maxima and boxes
+  L.tbox_p = take(sizeof(double) * 6 * PARTS_REDUCED);
   L.p_embed = take(sizeof(double) * nt * s.K.lt);
   L.p_force = take(sizeof(double) * nt * s.K.lt * NP_FORCE);
   // k_kinetic's partials per tile, or those of a force pass that takes them (per block)
@@ -685,15 +688,21 @@ int build_chain(md_system* s, const md_atoms* a, const md_lists* l, uint32_t fla
   A.nbin = s->ntiles + cblocks;
   const int tgrid = std::min(A.nbin, s->tile_grid);   // k_bin, k_scatter, k_sort_gather
   // a single replica without a forced build: the skin decision is taken inside k_bin, every
-  // block reducing all the per-part maxima, while those redundant loads stay few (they grow
-  // as blocks x parts: 1.4 M on the 216k-atom film, 2e9 on an 8M-atom one)
-  const int64_t bin_blocks = tgrid;
-  const bool decide_in_bin = !(flags & MD_B_FORCE) && s->K.nrep == 1 &&
-                             bin_blocks * ((int64_t)s->ntiles * s->ppt) <= DECIDE_IN_BIN_MAX_LOADS;
+  // block reducing the per-part maxima, while those redundant loads stay few (they grow as
+  // blocks x parts: 1.4 M on the 216k-atom film); else (2e9 on an 8M-atom one) from
+  // PARTS_REDUCED partial reductions of them by a launch of many blocks
+  const int64_t bin_blocks = tgrid, nparts = (int64_t)s->ntiles * s->ppt;
+  const bool decide_in_bin = !(flags & MD_B_FORCE) && s->K.nrep == 1;
   A.commit_ref = decide_in_bin ? 1 : 0;
-  if (decide_in_bin) {
-    k_bin<true><<<tgrid, BLOCK, 0, st>>>(s->K, A, at<double>(s, s->L.dmax),
-                                                       at<double>(s, s->L.tbox), s->ppt);
+  if (decide_in_bin && bin_blocks * nparts <= DECIDE_IN_BIN_MAX_LOADS) {
+    k_bin<true><<<tgrid, BLOCK, 0, st>>>(s->K, A, at<double>(s, s->L.dmax), at<double>(s, s->L.tbox),
+                                         (int)nparts);
+  } else if (decide_in_bin) {
+    k_parts_reduce<<<PARTS_REDUCED, BLOCK, 0, st>>>(at<double>(s, s->L.dmax), at<double>(s, s->L.tbox),
+                                                    (int)nparts, at<double>(s, s->L.dmax_p),
+                                                    at<double>(s, s->L.tbox_p));
+    k_bin<true><<<tgrid, BLOCK, 0, st>>>(s->K, A, at<double>(s, s->L.dmax_p), at<double>(s, s->L.tbox_p),
+                                         PARTS_REDUCED);
   } else {
     if (flags & MD_B_FORCE)
       k_tile_box<<<s->ntiles, BLOCK, 0, st>>>(A.R, A.tile_rep, A.q, at<double>(s, s->L.tbox));

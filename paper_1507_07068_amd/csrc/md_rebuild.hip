@@ -141,16 +141,17 @@ struct BuildGrid {
   double glo[3], ginv[3], gedge[3], qscale;
   int gd[3];
 };
+// The replica's parts are entries first .. first + count - 1 of dmax_tile / tile_box.
 template <class MaxReduce>
 __device__ __forceinline__ BuildGrid decide_grid(const Consts& K, const BuildArgs& A, int r,
                                                  const double* dmax_tile, const double* tile_box, int force,
-                                                 int ppt, int t0, int tstep, MaxReduce maxr) {
+                                                 int first, int count, int t0, int tstep, MaxReduce maxr) {
   const RepDesc& d = A.R[r];
   const RepState& s = A.S[r];
   BuildGrid g;
   double m = 0.0;
 #pragma unroll 8
-  for (int t = t0; t < d.nt * ppt; t += tstep) m = fmax(m, dmax_tile[d.t0 * ppt + t]);   // loads together
+  for (int t = t0; t < count; t += tstep) m = fmax(m, dmax_tile[first + t]);   // loads together
   m = maxr(m);
   g.need = !*A.abort && (force || (m > K.half_skin_sq) || (fabs(s.ind_z - s.ind_z_ref) > K.half_skin));
   if (!g.need) return g;   // uniform over the threads of the replica
@@ -165,9 +166,9 @@ __device__ __forceinline__ BuildGrid decide_grid(const Consts& K, const BuildArg
     }
     double mn = INFINITY, mx = -INFINITY;
 #pragma unroll 4
-    for (int t = t0; t < d.nt * ppt; t += tstep) {
-      mn = fmin(mn, tile_box[6 * (int64_t)(d.t0 * ppt + t) + a]);
-      mx = fmax(mx, tile_box[6 * (int64_t)(d.t0 * ppt + t) + 3 + a]);
+    for (int t = t0; t < count; t += tstep) {
+      mn = fmin(mn, tile_box[6 * (int64_t)(first + t) + a]);
+      mx = fmax(mx, tile_box[6 * (int64_t)(first + t) + 3 + a]);
     }
     mn = -maxr(-mn);
     mx = maxr(mx);
@@ -208,7 +209,8 @@ template <class MaxReduce>
 __device__ __forceinline__ bool decide_replica(const Consts& K, BuildArgs& A, int r, const double* dmax_tile,
                                                const double* tile_box, int force, int ppt, int t0, int tstep,
                                                bool lead, MaxReduce maxr) {
-  const BuildGrid g = decide_grid(K, A, r, dmax_tile, tile_box, force, ppt, t0, tstep, maxr);
+  const BuildGrid g = decide_grid(K, A, r, dmax_tile, tile_box, force, A.R[r].t0 * ppt, A.R[r].nt * ppt, t0,
+                                  tstep, maxr);
   if (lead) record_grid(A.S[r], g);
   return g.need;
 }
@@ -293,17 +295,49 @@ __device__ __forceinline__ int bin_rank(int* count, int cid, bool live) {
   return base + (lane - start);
 }
 
+// The nparts per-part displacement maxima and boxes of a single replica reduced to
+// gridDim.x partial ones in the same layout (block b takes a contiguous chunk): the
+// maximum, the minima and the maxima of each axis (the neutral values where a chunk is
+// empty).  The skin decision then reads those few instead of every part.
+__global__ __launch_bounds__(BLOCK) void k_parts_reduce(const double* __restrict__ dmax_tile,
+                                                        const double* __restrict__ tile_box, int nparts,
+                                                        double* __restrict__ dmax_out,
+                                                        double* __restrict__ box_out) {
+  const int chunk = (nparts + gridDim.x - 1) / gridDim.x;
+  const int p0 = blockIdx.x * chunk, p1 = min(p0 + chunk, nparts);
+  // the maximum, then per axis the negated minimum and the maximum
+  double v[7] = {0.0, -INFINITY, -INFINITY, -INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  for (int p = p0 + threadIdx.x; p < p1; p += BLOCK) {
+    v[0] = fmax(v[0], dmax_tile[p]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      v[1 + a] = fmax(v[1 + a], -tile_box[6 * (int64_t)p + a]);
+      v[4 + a] = fmax(v[4 + a], tile_box[6 * (int64_t)p + 3 + a]);
+    }
+  }
+  block_max_to0<BLOCK, 7>(v);
+  if (threadIdx.x == 0) {
+    dmax_out[blockIdx.x] = v[0];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      box_out[6 * blockIdx.x + a] = -v[1 + a];
+      box_out[6 * blockIdx.x + 3 + a] = v[4 + a];
+    }
+  }
+}
+
 // Blocks [0, ntiles): one tile of Cr atoms each.  Blocks [ntiles, ...): 256 carbons each.
 // DECIDE (single replica, no forced build): every block takes the skin decision and the
-// cell grid itself from the per-part maxima and boxes (so no separate decision launch), all
-// blocks alike; block 0 records them.  The indenter reference position, which every block
-// reads for the decision, is recorded by k_scan.
+// cell grid itself from the nparts per-part maxima and boxes (or their partial reductions by
+// k_parts_reduce; so no separate decision launch), all blocks alike; block 0 records them.
+// The indenter reference position, which every block reads for the decision, is recorded by
+// k_scan.
 template <bool DECIDE>
 __global__ __launch_bounds__(BLOCK) void k_bin(Consts K, BuildArgs A, const double* __restrict__ dmax_tile,
-                                               const double* __restrict__ tile_box, int ppt) {
+                                               const double* __restrict__ tile_box, int nparts) {
   BuildGrid g1;
   if (DECIDE) {
-    g1 = decide_grid(K, A, 0, dmax_tile, tile_box, 0, ppt, threadIdx.x, BLOCK,
+    g1 = decide_grid(K, A, 0, dmax_tile, tile_box, 0, 0, nparts, threadIdx.x, BLOCK,
                      [](double v) { return block_max<BLOCK>(v); });
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       RepState& s0 = A.S[0];
