@@ -1253,59 +1253,68 @@ __global__ __launch_bounds__(BLOCK) void k_xlist(Consts K, BuildArgs A) {
 // Section 2.6's inner list, refilled every step from the outer (Verlet) list: atom i's outer
 // entries whose pair is closer than the largest Cr-Cr cutoff at the current positions
 // (minimum image, the list build's exact FP64 predicate), in their outer-list order and in
-// the outer list's layout and entry format.  One lane per atom walks its outer list INNER_U
-// entries at a time, the next group's indices loaded while the current group's positions
-// are gathered.
-constexpr int INNER_U = 8;
+// the outer list's layout and entry format.  INNER_G lanes share an atom and test INNER_G
+// consecutive outer entries at a time (the next ones' indices loaded while the current
+// positions are gathered); a ballot over the group gives each kept entry its place, so the
+// order is the outer list's.  One block per 256 / INNER_G atoms.
+#ifndef MD_INNER_G
+#define MD_INNER_G 8   // 4: 1190 us on the 216k-atom film (paper's form); 8: 973; 16: 969
+#endif
+constexpr int INNER_G = MD_INNER_G;
 __global__ __launch_bounds__(BLOCK) void k_inner_list(Consts K, const RepDesc* __restrict__ R,
                                                       RepState* __restrict__ S, const int* __restrict__ tile_rep,
                                                       const double4* __restrict__ q, const int* __restrict__ idx,
                                                       const int* __restrict__ cnt, int* __restrict__ iidx,
                                                       int* __restrict__ icnt) {
-  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  static_assert(WAVE % INNER_G == 0 && INNER_G < 32, "a lane group lies in one wavefront, its mask in 32 bits");
+  constexpr int APB = BLOCK / INNER_G;   // atoms per block
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int tile = lb / INNER_G;
   const int r = tile_rep[tile];
   const RepDesc& d = R[r];
-  const int64_t i = (int64_t)tile * TILE + threadIdx.x;
+  const int sub = threadIdx.x % INNER_G;
+  const int64_t i = (int64_t)tile * TILE + (lb % INNER_G) * APB + threadIdx.x / INNER_G;
   const bool live = i < (int64_t)d.a0 + d.n;
   const double4 pi = live ? q[i] : make_double4(0.0, 0.0, 0.0, 0.0);
   const bool img = wave_near_face(d, live, pi.x, pi.y, pi.z, K.rlist + 2.0 * K.half_skin);
-  if (!live) return;
-  const int n = cnt[i];
+  // every lane takes part in the ballots (atoms past the replica with an empty list)
+  const int n = live ? cnt[i] : 0;
+  int nw = n;   // the wavefront's longest list
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) nw = max(nw, __shfl_xor(nw, o, WAVE));
   const int T = K.lt, sh = K.lt_shift;
-  const unsigned stride = (unsigned)K.ntot * T, base = (unsigned)i * T;
+  const unsigned stride = (unsigned)K.ntot * T, base = (unsigned)(live ? i : 0) * T;
   // word offset of entry k of atom i (32-bit: the lists hold fewer than 2^31 words)
   auto at_k = [&](int k) { return ((unsigned)k >> sh) * stride + base + (unsigned)(k & (T - 1)); };
   const int icap = K.icap;
   const double rc2 = K.icut_sq;
-  int c = 0;
-  int e[INNER_U];
-#pragma unroll
-  for (int u = 0; u < INNER_U; ++u) e[u] = n > 0 ? idx[at_k(min(u, n - 1))] : 0;
-  for (int k0 = 0; k0 < n; k0 += INNER_U) {
-    double4 pj[INNER_U];
-#pragma unroll
-    for (int u = 0; u < INNER_U; ++u) pj[u] = q[list_slot(e[u])];
-    int en[INNER_U];
-#pragma unroll
-    for (int u = 0; u < INNER_U; ++u) en[u] = idx[at_k(min(k0 + INNER_U + u, n - 1))];
-#pragma unroll
-    for (int u = 0; u < INNER_U; ++u) {
-      double ex = pj[u].x - pi.x, ey = pj[u].y - pi.y, ez = pj[u].z - pi.z;
-      if (img) {
-        ex = min_image(ex, d.len[0], d.half[0], d.per[0]);
-        ey = min_image(ey, d.len[1], d.half[1], d.per[1]);
-        ez = min_image(ez, d.len[2], d.half[2], d.per[2]);
-      }
-      if (k0 + u < n && dist_sq_exact(ex, ey, ez) < rc2) {
-        if (c < icap) iidx[at_k(c)] = e[u];
-        ++c;
-      }
+  const int gshift = (int)(threadIdx.x % WAVE) - sub;   // the group's first lane
+  const unsigned below = (1u << sub) - 1u;
+  int c = 0;        // entries kept so far
+  int e = sub < n ? idx[at_k(sub)] : 0;   // (slot 0 stands in for an entry past the list)
+  for (int m0 = 0; m0 < nw; m0 += INNER_G) {
+    const int k = m0 + sub;
+    const double4 pj = q[list_slot(e)];
+    const int en = k + INNER_G < n ? idx[at_k(k + INNER_G)] : 0;
+    double ex = pj.x - pi.x, ey = pj.y - pi.y, ez = pj.z - pi.z;
+    if (img) {
+      ex = min_image(ex, d.len[0], d.half[0], d.per[0]);
+      ey = min_image(ey, d.len[1], d.half[1], d.per[1]);
+      ez = min_image(ez, d.len[2], d.half[2], d.per[2]);
     }
-#pragma unroll
-    for (int u = 0; u < INNER_U; ++u) e[u] = en[u];
+    const bool keep = k < n && dist_sq_exact(ex, ey, ez) < rc2;
+    const unsigned gm = (unsigned)(__ballot(keep) >> gshift) & ((1u << INNER_G) - 1u);
+    if (keep) {
+      const int j = c + __popc(gm & below);
+      if (j < icap) iidx[at_k(j)] = e;
+    }
+    c += __popc(gm);
+    e = en;
   }
-  icnt[i] = min(c, icap);
-  if (c > icap) atomicMax(&S[r].ioverflow, c);
+  if (live && sub == 0) {
+    icnt[i] = min(c, icap);
+    if (c > icap) atomicMax(&S[r].ioverflow, c);
+  }
 }
 
 }  // namespace md
