@@ -260,8 +260,9 @@ void launch_force(md_system* s, const md_atoms* a, const md_lists* l, bool mixed
                   bool add_fme, hipStream_t st, bool full_kick, bool drift, bool fuse_ke) {
   const double kick_h = (full_kick ? 1.0 : 0.5) * s->K.dt * s->K.acc;
   const int store_f = (full_kick || fuse_ke) ? 0 : 1;
-  const KinOut KO = fuse_ke ? KinOut{at<double>(s, s->L.p_kin), at<double>(s, s->L.p_morse)}
-                            : KinOut{nullptr, nullptr};
+  // (an energy pass with the drift takes the kinetic terms: fuse_ke implies drift, and only
+  // such a pass drifts with energies)
+  const KinOut KO{at<double>(s, s->L.p_kin), at<double>(s, s->L.p_morse)};
   const DriftOut D{qnext(s, a), qsnext(s), at<double>(s, s->L.xref), at<long long>(s, s->L.bcell),
                    at<double>(s, s->L.dmax), at<double>(s, s->L.tbox)};
   const RepDesc* R = at<RepDesc>(s, s->L.desc);

@@ -409,20 +409,23 @@ struct DriftOut {
   double* tbox;           // [6 (tile * T + part) + ...]
 };
 
-// An energy step of md_run whose end velocities are observed but which is not the last: with
-// kin set (and KICK, ENERGY), the pass kicks to the whole step, takes the kinetic energy and
-// the Cr-C sums there (the k_kinetic terms, as partials per block), then gives the next
-// step's first half kick too, so that the next Task 3 only drifts (done by this pass with
-// DRIFT).  Each velocity sees the same two kicks, in the same order, as with the separate
-// passes.
+// An energy step of md_run whose end velocities are observed but which is not the last (the
+// pass with ENERGY and DRIFT): it kicks to the whole step, takes the kinetic energy and the
+// Cr-C sums there (the k_kinetic terms, as partials per block), then gives the next step's
+// first half kick too and drifts.  Each velocity sees the same two kicks, in the same order,
+// as with the separate passes.
 struct KinOut {
-  double* kin;            // [tile * T + part] kinetic energy (NULL: not such a step)
+  double* kin;            // [tile * T + part] kinetic energy
   double* morse;          // [4 (tile * T + part) + ...] Cr-C energy and indenter load
 };
 
-// Occupancy floor of the force pass (wavefronts per SIMD its registers must allow).
+// Occupancy floor of the force pass (wavefronts per SIMD its registers must allow); the
+// pass that takes energies and drifts (KinOut) is held to MD_FORCE_KIN_WAVES.
 #ifndef MD_FORCE_WAVES
 #define MD_FORCE_WAVES 1
+#endif
+#ifndef MD_FORCE_KIN_WAVES
+#define MD_FORCE_KIN_WAVES 5
 #endif
 
 // A neighbour's record with its M'(P_j) (paper's form).
@@ -437,7 +440,7 @@ struct SM {
 
 // PAPER: the paper's form, dm[j] = M'(P_j) from the density pass.
 template <int T, bool MIXED, bool SHADOW, bool KICK, bool ENERGY, bool DRIFT = false, bool PAPER = false>
-__global__ __launch_bounds__(BLOCK, MD_FORCE_WAVES) void k_force(Consts K, const RepDesc* __restrict__ R,
+__global__ __launch_bounds__(BLOCK, (ENERGY && DRIFT) ? MD_FORCE_KIN_WAVES : MD_FORCE_WAVES) void k_force(Consts K, const RepDesc* __restrict__ R,
                                                  RepState* __restrict__ S,
                                                  const int* __restrict__ tile_rep,
                                                  const double4* __restrict__ q,
@@ -689,7 +692,8 @@ __global__ __launch_bounds__(BLOCK, MD_FORCE_WAVES) void k_force(Consts K, const
   fy = group_sum<T>(fy);
   fz = group_sum<T>(fz);
   const bool own = c.live && c.sub == 0;
-  double ke[1] = {0.0}, mo[4] = {0.0, 0.0, 0.0, 0.0};   // with KO.kin: this atom's k_kinetic terms
+  constexpr bool KIN = ENERGY && DRIFT;   // the k_kinetic terms into KO (see KinOut)
+  double ke[1] = {0.0}, mo[4] = {0.0, 0.0, 0.0, 0.0};
   double4 p = make_double4(0.0, 0.0, 0.0, 0.0);   // with DRIFT: the atom's next position
   double d2 = 0.0;                                 // and its squared displacement since the build
   if (own) {
@@ -717,15 +721,16 @@ __global__ __launch_bounds__(BLOCK, MD_FORCE_WAVES) void k_force(Consts K, const
       fx += fme[4 * i + 0];
       fy += fme[4 * i + 1];
       fz += fme[4 * i + 2];
-      if (ENERGY && KO.kin) {   // (records of atoms without carbons in range are zero)
+      if (KIN) {   // (records of atoms without carbons in range are zero)
         mo[0] = fme[4 * i + 3];
         mo[1] = -fme[4 * i + 0];
         mo[2] = -fme[4 * i + 1];
         mo[3] = -fme[4 * i + 2];
       }
     }
-    if (store_f) {   // (a pass whose full kick stands in for the next step's first half kick
-                     // leaves f alone: no kick reads it before the next pass that stores it)
+    if (!DRIFT && store_f) {   // (a pass that also gives the next step's first half kick
+                               // leaves f alone: no kick reads it before the next pass that
+                               // stores it; drifting passes are such passes)
       f[3 * i + 0] = fx;
       f[3 * i + 1] = fy;
       f[3 * i + 2] = fz;
@@ -735,7 +740,7 @@ __global__ __launch_bounds__(BLOCK, MD_FORCE_WAVES) void k_force(Consts K, const
                   // keep their velocity (written back unchanged)
       double vx = move ? v0 + kick_h * fx : v0, vy = move ? v1 + kick_h * fy : v1,
              vz = move ? v2 + kick_h * fz : v2;
-      if (ENERGY && KO.kin) {   // kinetic energy at the whole step, then the next half kick
+      if (KIN) {   // kinetic energy at the whole step, then the next half kick
         if (move) {
           ke[0] = K.ke_fac * ((vx * vx + vy * vy) + vz * vz);
           vx += kick_h * fx;
@@ -778,13 +783,13 @@ __global__ __launch_bounds__(BLOCK, MD_FORCE_WAVES) void k_force(Consts K, const
         D.tbox[6 * (int64_t)c.blk + 3 + a] = m[4 + a];
       }
       if (c.blk == d.t0 * T) {   // Task 2, once per replica (the observed step's position kept)
-        if (ENERGY && KO.kin) S[c.r].ind_z_obs = S[c.r].ind_z;
+        if (KIN) S[c.r].ind_z_obs = S[c.r].ind_z;
         S[c.r].ind_z += K.v_ind * K.dt;
       }
     }
   }
   if (ENERGY) block_sum_store<NP_FORCE, BLOCK>(acc, part + (int64_t)c.blk * NP_FORCE);
-  if (ENERGY && KO.kin) {
+  if (KIN) {
     block_sum_store<1, BLOCK>(ke, KO.kin + c.blk);
     block_sum_store<4, BLOCK>(mo, KO.morse + (int64_t)c.blk * 4);
   }
