@@ -420,7 +420,8 @@ struct KinOut {
 };
 
 // Occupancy floor of the force pass (wavefronts per SIMD its registers must allow); the
-// pass that takes energies and drifts (KinOut) is held to MD_FORCE_KIN_WAVES.
+// pass that takes energies and drifts (KinOut) is held to MD_FORCE_KIN_WAVES, but for the
+// paper's form (whose registers would spill there).
 #ifndef MD_FORCE_WAVES
 #define MD_FORCE_WAVES 1
 #endif
@@ -440,7 +441,7 @@ struct SM {
 
 // PAPER: the paper's form, dm[j] = M'(P_j) from the density pass.
 template <int T, bool MIXED, bool SHADOW, bool KICK, bool ENERGY, bool DRIFT = false, bool PAPER = false>
-__global__ __launch_bounds__(BLOCK, (ENERGY && DRIFT) ? MD_FORCE_KIN_WAVES : MD_FORCE_WAVES) void k_force(Consts K, const RepDesc* __restrict__ R,
+__global__ __launch_bounds__(BLOCK, (ENERGY && DRIFT && !PAPER) ? MD_FORCE_KIN_WAVES : MD_FORCE_WAVES) void k_force(Consts K, const RepDesc* __restrict__ R,
                                                  RepState* __restrict__ S,
                                                  const int* __restrict__ tile_rep,
                                                  const double4* __restrict__ q,
