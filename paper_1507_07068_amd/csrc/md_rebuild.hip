@@ -128,7 +128,7 @@ __device__ __forceinline__ bool rebuild_off(const BuildArgs& A) { return *A.any 
 
 // One block of DECIDE_THREADS decides every replica (skin test, then the cell grid of the
 // build) and ORs the outcomes into the launch-wide flag: the whole block per replica when
-// there are few, else one wavefront per replica (wavefront w takes replicas w, w + 16, ...).
+// there are few, else a group of lanes per replica (up to a wavefront; see below).
 constexpr int DECIDE_THREADS = 1024;
 constexpr int DECIDE_BLOCKWIDE = 4;   // replicas up to which the whole block takes each one
 
@@ -229,12 +229,22 @@ __global__ __launch_bounds__(DECIDE_THREADS) void k_decide(Consts K, BuildArgs A
       if (need && threadIdx.x == 0) any_sh = 1;
     }
   } else {
-    const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
-    constexpr int NW = DECIDE_THREADS / WAVE;
-    for (int r = w; r < K.nrep; r += NW) {
-      const bool need = decide_replica(K, A, r, dmax_tile, tile_box, force, ppt, lane, WAVE, lane == 0,
-                                       [](double v) { return wave_max(v); });
-      if (need && lane == 0) atomicOr(&any_sh, 1);
+    // groups of G lanes (a power of two, G <= 64), as many as there are replicas up to
+    // 1024 / G: group g takes replicas g, g + 1024 / G, ... (so the replicas' loads go out
+    // together rather than a wavefront's replicas one after another)
+    int G = WAVE;
+    while (G > 1 && (DECIDE_THREADS / G) < K.nrep) G >>= 1;
+    const int sub = threadIdx.x % G, grp = threadIdx.x / G, ng = DECIDE_THREADS / G;
+    for (int r0 = 0; r0 < K.nrep; r0 += ng) {   // (uniform: every group steps together)
+      const int r = r0 + grp;
+      const bool mine = r < K.nrep;
+      // groups past the last replica repeat replica 0's decision without recording it
+      const bool need = decide_replica(K, A, mine ? r : 0, dmax_tile, tile_box, force, ppt, sub, G,
+                                       mine && sub == 0, [G](double v) {
+                                         for (int o = G / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+                                         return v;
+                                       });
+      if (need && mine && sub == 0) atomicOr(&any_sh, 1);
     }
   }
   __syncthreads();
