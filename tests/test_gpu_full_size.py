@@ -61,6 +61,22 @@ def check_sampled(sim, r, s, rows, tol, lists=True):
         assert np.allclose(st["dF"][rows], dF, rtol=1e-12, atol=0)
 
 
+def check_after_run(sim, s, rows, tol, nsteps, r=0):
+    """After nsteps whole steps (skin decisions, rebuilds and fused energy passes on the
+    way): the forces the last step stored against the oracle at the positions reached, with
+    the indenter where it has moved to."""
+    flags = sim.md_check()
+    ind_z = float(sim.md_energy()[r, md.MD_IND_Z])
+    assert abs(ind_z - nsteps * s.v_ind * s.dt) <= 1e-12 * max(1.0, abs(ind_z))
+    st = sim.state()[r]
+    print(f"[case] {s.name} after {nsteps} steps: builds={flags['nbuilds']} ind_z={ind_z:.6f}",
+          flush=True)
+    f, rho, dF, fm = O.sample_forces(s, rows, x=st["x"], ind_z=ind_z)
+    rel, mx = rel_errors(st["f"][rows], f)
+    print(f"  sampled force rel-RMS {rel:.3e} max/RMS {mx:.3e}", flush=True)
+    assert rel <= tol and mx <= tol * (10 if tol > FP64_TOL else 1), (rel, mx)
+
+
 def check_properties(sim, s, r=0, n_check=256, seed=5):
     """Right after a build: every listed pair is within the list radius, the list is
     symmetric, sampled atoms miss no neighbour, and the forces balance the indenter load."""
@@ -132,7 +148,8 @@ def test_large_films_sampled(index, n_random):
         sim.initial_forces()
         check_sampled(sim, 0, s, rows, FP64_TOL if precision == "fp64" else MIXED_TOL,
                       lists=(precision == "fp64"))
-        sim.md_run(20)
+        sim.md_run(150)
         flags = sim.md_check()
         assert not (flags["overflow"] or flags["xoverflow"] or flags["nonfinite"] or flags["sync_timeout"]), flags
+        check_after_run(sim, s, rows, FP64_TOL if precision == "fp64" else MIXED_TOL, 150)
         sim.close()
