@@ -122,6 +122,7 @@ static_assert(LIST_TGT <= LIST_BLOCK, "a work item's atoms aimed at fit one pass
 #define MD_LIST_GROUP 4
 #endif
 constexpr int LIST_GROUP = MD_LIST_GROUP;   // candidates screened together per atom in k_list_tiles
+static_assert(LIST_GROUP >= 1 && LIST_GROUP <= 32, "a group's passing bits fit the 32-bit mask k_list_tiles appends from");
 
 
 __device__ __forceinline__ bool rebuild_off(const BuildArgs& A) { return *A.any == 0; }
@@ -1047,6 +1048,7 @@ __global__ __launch_bounds__(LIST_BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts
   const int xa = max(x0 - 1, 0), xb = min(x1 + 1, gx - 1);   // main piece of a staged row
   const bool wl = per0 && x0 == 0, wr = per0 && x1 == gx - 1;   // wrapped end cells
   const int nt = x1 - x0 + 4;
+  const bool tiny = gx < 3 || gy < 3 || gz < 3;   // a center may meet its own images
   const float fxl = (float)(-len0), fxr = (float)len0;
   // the first pass's centers: their loads go out before the tables' round of loads
   const int cfirst = min((int)threadIdx.x, m - 1);
@@ -1163,6 +1165,8 @@ __global__ __launch_bounds__(LIST_BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts
       }
       __syncthreads();
       if (live) {
+        // the center's staged position (middle row, main piece), relative to this piece
+        const int s_self = roff[4] + (p - rslot[4].y) - G0;
 #pragma unroll 1
         for (int rr = 0; rr < 9; ++rr) {   // this center's window in each row
           const int* to = toff[rr] + (cx - x0);
@@ -1180,11 +1184,46 @@ __global__ __launch_bounds__(LIST_BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts
             const double4 pi = tq[p], pj4 = tq[__float_as_int(sq[s].w)];
             return dist_sq_exact((pj4.x - pi.x) + shx, (pj4.y - pi.y) + shy, (pj4.z - pi.z) + shz) < rl2;
           };
-          // LIST_GROUP candidates at a time: the FP32 screen gives in / band bit masks, the
-          // rare band candidates get the exact test, then the passing ones are appended in
-          // order
+          // The passing candidates of up to 32 consecutive staged positions from sb on are
+          // gathered as bits of one mask and appended in order together: the appending
+          // loop then runs as often as the most passing candidates of a lane in those 32,
+          // not once per group for the lane with the most in each group.
+          // With three or more cells along every axis the center occurs once among the
+          // staged positions, in the middle row: its bit is cleared from the mask, and
+          // while all of a mask's entries fit under the capacity they are stored with no
+          // further test.  Smaller grids, and a lane about to overflow, test every entry.
+          auto flush = [&](unsigned acc, int sb) {
+            if (!tiny && rr == 4) {
+              const unsigned d = (unsigned)(s_self - sb);
+              if (d < 32u) acc &= ~(1u << d);
+            }
+            if (!tiny && count + __builtin_popcount(acc) <= cap) {
+              for (; acc; acc &= acc - 1) {
+                const int su = sb + __builtin_ctz(acc);
+                const int j = __float_as_int(sq[su].w);
+                *wp = shadow ? j | ((rcode + (su + G0 >= b1) + (su + G0 >= b2)) << LIST_IDX_BITS) : j;
+                ++count;
+                wp += (count & (T - 1)) ? 1 : row - (T - 1);
+              }
+            } else {
+              for (; acc; acc &= acc - 1) {
+                const int su = sb + __builtin_ctz(acc);
+                const int j = __float_as_int(sq[su].w);
+                if (j != p) append(shadow ? j | ((rcode + (su + G0 >= b1) + (su + G0 >= b2)) << LIST_IDX_BITS) : j);
+              }
+            }
+          };
+          unsigned acc = 0;
+          int sb = e0;
+          // LIST_GROUP candidates at a time: the FP32 screen gives in / band bit masks, and
+          // the rare band candidates get the exact test
           int s = e0;
           for (; s + LIST_GROUP <= e1; s += LIST_GROUP) {
+            if (s - sb > 32 - LIST_GROUP) {   // the same step for every lane of the loop
+              flush(acc, sb);
+              acc = 0;
+              sb = s;
+            }
             unsigned in = 0, band = 0;
 #pragma unroll
             for (int u = 0; u < LIST_GROUP; ++u) {
@@ -1200,21 +1239,22 @@ __global__ __launch_bounds__(LIST_BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts
                 if (exact(s + u)) in |= 1u << u;
               }
             }
-            for (; in; in &= in - 1) {
-              const int su = s + __builtin_ctz(in);
-              const int j = __float_as_int(sq[su].w);
-              if (j != p) append(shadow ? j | ((rcode + (su + G0 >= b1) + (su + G0 >= b2)) << LIST_IDX_BITS) : j);
-            }
+            acc |= in << (s - sb);
           }
           for (; s < e1; ++s) {
+            if (s - sb > 31) {
+              flush(acc, sb);
+              acc = 0;
+              sb = s;
+            }
             const float4 cf = sq[s];
             const float ex = cf.x - pf.x, ey = cf.y - pf.y, ez = cf.z - pf.z;
             const float r2f = ex * ex + ey * ey + ez * ez;
             bool ok = r2f < lo_f;
             if (__builtin_expect(!ok && !(r2f >= hi_f), 0)) ok = exact(s);
-            const int j = __float_as_int(cf.w);
-            if (ok && j != p) append(shadow ? j | ((rcode + (s + G0 >= b1) + (s + G0 >= b2)) << LIST_IDX_BITS) : j);
+            acc |= (ok ? 1u : 0u) << (s - sb);
           }
+          flush(acc, sb);
         }
       }
     }
