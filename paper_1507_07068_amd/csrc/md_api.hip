@@ -571,7 +571,7 @@ int bind_workspace(md_system* s, void* ws, hipStream_t st) {
   int dev = 0, cus = 0, per_cu = 0;
   if ((e = hip_status(hipGetDevice(&dev)))) return e;
   if ((e = hip_status(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)))) return e;
-  if ((e = hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_list_tiles, LIST_BLOCK, 0)))) return e;
+  if ((e = hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_list_tiles<MD_LIST_WAVES_RESIDENT>, LIST_BLOCK, 0)))) return e;
   s->list_grid = std::max(1, cus * std::max(1, per_cu));
   s->tile_grid = std::max(1, cus * (2048 / BLOCK));
   return hip_status(hipStreamSynchronize(st));
@@ -725,9 +725,10 @@ int build_chain(md_system* s, const md_atoms* a, const md_lists* l, uint32_t fla
   A.persistent = list_persistent(s);
   if (s->list_mix)
     k_list_rows<false><<<s->ntiles, BLOCK, 0, st>>>(s->K, A);
+  else if (A.persistent)
+    k_list_tiles<MD_LIST_WAVES_RESIDENT><<<A.xblocks + std::min(s->nlblk, s->list_grid), LIST_BLOCK, 0, st>>>(s->K, A);
   else
-    k_list_tiles<<<A.xblocks + (A.persistent ? std::min(s->nlblk, s->list_grid) : s->nlblk), LIST_BLOCK, 0, st>>>(
-        s->K, A);
+    k_list_tiles<MD_LIST_WAVES><<<A.xblocks + s->nlblk, LIST_BLOCK, 0, st>>>(s->K, A);
   if (ev1 && (e = hip_status(hipEventRecord(ev1, st)))) return e;
   if (s->list_mix && s->ctot > 0) k_xlist<<<A.near_blocks, BLOCK, 0, st>>>(s->K, A);
   return check_launch();

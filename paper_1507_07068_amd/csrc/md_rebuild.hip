@@ -107,6 +107,9 @@ constexpr int LIST_STAGE = MD_LIST_STAGE;   // candidates k_list_tiles stages in
 #ifndef MD_LIST_WAVES
 #define MD_LIST_WAVES 7
 #endif
+#ifndef MD_LIST_WAVES_RESIDENT
+#define MD_LIST_WAVES_RESIDENT 6
+#endif
 #ifndef MD_LIST_BLOCK
 #define MD_LIST_BLOCK 256
 #endif
@@ -974,8 +977,12 @@ __device__ __forceinline__ void row_shift(int rr, int cy, int cz, int gy, int gz
 }
 
 // Occupancy floor: this kernel hides the latency of its LDS and global reads with waves, so
-// its registers are held to what MD_LIST_WAVES wavefronts per SIMD can share.
-__global__ __launch_bounds__(LIST_BLOCK, MD_LIST_WAVES) void k_list_tiles(Consts K, BuildArgs A) {
+// its registers are held to what WAVES wavefronts per SIMD can share: MD_LIST_WAVES with one
+// block per work item, MD_LIST_WAVES_RESIDENT for resident blocks that take items from a
+// counter (measured best on the 8M-atom film: 1.42 against 1.46 ms per rebuild at 7, while
+// the 216k-atom film's one block per item does best at 7, 62 against 69 us at 6).
+template <int WAVES>
+__global__ __launch_bounds__(LIST_BLOCK, WAVES) void k_list_tiles(Consts K, BuildArgs A) {
   if (rebuild_off(A)) return;
   __shared__ float4 sq[LIST_STAGE];        // staged candidates: x, y, z, slot bits
   __shared__ int toff[9][LIST_SEG + 4];    // per row: row-local staged offset of cells x0-1 .. x1+2
