@@ -1052,6 +1052,7 @@ __global__ __launch_bounds__(LIST_BLOCK, WAVES) void k_list_tiles(Consts K, Buil
     lo_f = uniform((float)(rl2 - delta));
     hi_f = uniform((float)(rl2 + delta));
   }
+  const unsigned band_bits = __float_as_uint(hi_f - lo_f);   // hi - lo, exact
   const int xa = max(x0 - 1, 0), xb = min(x1 + 1, gx - 1);   // main piece of a staged row
   const bool wl = per0 && x0 == 0, wr = per0 && x1 == gx - 1;   // wrapped end cells
   const int nt = x1 - x0 + 4;
@@ -1231,20 +1232,25 @@ __global__ __launch_bounds__(LIST_BLOCK, WAVES) void k_list_tiles(Consts K, Buil
               acc = 0;
               sb = s;
             }
-            unsigned in = 0, band = 0;
+            // d = |r2| - lo: in when negative (its sign bit); in the band when
+            // 0 <= d < hi - lo, which compares as unsigned bit patterns (both differences
+            // are exact there, by Sterbenz's lemma, and d >= lo beyond 2 lo).  The absolute
+            // value clears the sign of a NaN, which then falls in neither: out, as the
+            // exact test would decide.
+            unsigned in = 0, dmin = ~0u;
+            float d[LIST_GROUP];
 #pragma unroll
             for (int u = 0; u < LIST_GROUP; ++u) {
               const float4 cf = sq[s + u];
               const float ex = cf.x - pf.x, ey = cf.y - pf.y, ez = cf.z - pf.z;
-              const float r2f = ex * ex + ey * ey + ez * ez;
-              in |= (r2f < lo_f ? 1u : 0u) << u;
-              band |= (!(r2f < lo_f) && !(r2f >= hi_f) ? 1u : 0u) << u;
+              d[u] = fabsf(ex * ex + ey * ey + ez * ez) - lo_f;
+              in |= (__float_as_uint(d[u]) >> 31) << u;
+              dmin = min(dmin, __float_as_uint(d[u]));   // one test for the whole group
             }
-            if (__builtin_expect(band != 0, 0)) {
-              for (unsigned bm = band; bm; bm &= bm - 1) {
-                const int u = __builtin_ctz(bm);
-                if (exact(s + u)) in |= 1u << u;
-              }
+            if (__builtin_expect(dmin < band_bits, 0)) {
+#pragma unroll
+              for (int u = 0; u < LIST_GROUP; ++u)
+                if (__float_as_uint(d[u]) < band_bits && exact(s + u)) in |= 1u << u;
             }
             acc |= in << (s - sb);
           }
