@@ -1183,7 +1183,8 @@ __global__ __launch_bounds__(LIST_BLOCK, WAVES) void k_list_tiles(Consts K, Buil
           if (e0 >= e1) continue;
           const int b1 = roff[rr] + to[1], b2 = roff[rr] + to[2];
           const int rcode = 9 * (rr / 3) + 3 * (rr % 3);
-          // exact FP64 test of staged candidate s (band or NaN)
+          // exact FP64 test of staged candidate s (in the band, or NaN in the single-candidate
+          // loop)
           auto exact = [&](int s) {
             double shy, shz;
             row_shift(rr, cy, cz, gy, gz, per1, per2, len1, len2, shy, shz);
@@ -1223,8 +1224,8 @@ __global__ __launch_bounds__(LIST_BLOCK, WAVES) void k_list_tiles(Consts K, Buil
           };
           unsigned acc = 0;
           int sb = e0;
-          // LIST_GROUP candidates at a time: the FP32 screen gives in / band bit masks, and
-          // the rare band candidates get the exact test
+          // LIST_GROUP candidates at a time: the FP32 screen gives their in bits, and the
+          // rare candidates in the band get the exact test
           int s = e0;
           for (; s + LIST_GROUP <= e1; s += LIST_GROUP) {
             if (s - sb > 32 - LIST_GROUP) {   // the same step for every lane of the loop
