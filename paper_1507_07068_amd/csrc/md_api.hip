@@ -31,10 +31,11 @@ struct Layout {
 
 constexpr int MISC_INTS = 16;    // rebuild flag, status words
 // The list build takes one block per work item while the item table's capacity is at most
-// this many waves of resident blocks: measured faster up to the 64-replica ensemble (~27
-// waves; the 216k-atom film 2.6 waves: 67 against 87 us per rebuild), even with a 1M-atom
-// film (~13), slower on the 8M-atom film (~95 waves of idle blocks per step).
-constexpr int LIST_ONE_PER_ITEM_WAVES = 32;
+// this many waves of resident blocks (six per compute unit): measured faster on the
+// 216k-atom film (3 waves: 63 against 76 us per rebuild), slower on the 1M-atom film (15
+// waves: 203 against 196 us, and 6.7 against 4.4 us for a step without a rebuild) and on the
+// 8M-atom film (~110 waves of idle blocks per step), even on the 64-replica ensemble (~32).
+constexpr int LIST_ONE_PER_ITEM_WAVES = 8;
 constexpr int SCAN_CHUNK = 2048; // cells per block of the cell-count scan
 constexpr int64_t DECIDE_IN_BIN_MAX_LOADS = (int64_t)1 << 22;   // part loads over all k_bin blocks
 constexpr int PARTS_REDUCED = 64;   // partial reductions of a large single replica's parts
