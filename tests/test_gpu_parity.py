@@ -166,6 +166,22 @@ def test_list_overflow_is_flagged():
     assert sim.md_check()["overflow"] == 0
 
 
+@pytest.mark.parametrize("precision,tpa", [("fp64", 1), ("fp64", 2), ("mixed", 2)])
+def test_list_overflow_keeps_the_first_entries(precision, tpa):
+    """A list cut at its capacity holds the first cap entries of the whole list, in order."""
+    s = I.config(0)
+    full = sim_of(s, precision=precision, cap=96, tpa=tpa)
+    cut = sim_of(s, precision=precision, cap=8, tpa=tpa)
+    for sim in (full, cut):
+        sim.md_build_neighbors(force=True)
+    assert full.md_check()["overflow"] == 0 and cut.md_check()["overflow"] > 8
+    assert np.array_equal(full.id.cpu().numpy(), cut.id.cpu().numpy())
+    a, b = full.list_rows(), cut.list_rows()
+    assert sum(len(r) > 8 for r in a) > s.n // 2
+    for p in range(s.n):
+        assert np.array_equal(b[p], a[p][:8]), p
+
+
 # ------------------------------------------------------------------------------------------
 # Forces, densities, energies
 # ------------------------------------------------------------------------------------------
