@@ -749,9 +749,11 @@ namespace {
 // Two-tier lists: the inner list refilled from the outer one at the current positions.
 int inner_list(md_system* s, const md_atoms* a, const md_lists* l, hipStream_t st) {
   if (!s->p.icap) return MD_OK;
+  k_inner_pos<<<grid_tiles(s), BLOCK, 0, st>>>(at<RepDesc>(s, s->L.desc), at<RepState>(s, s->L.state),
+                                               at<int>(s, s->L.tile_rep), qcur(s, a), at<float4>(s, s->L.tqf));
   k_inner_list<<<grid_tiles(s) * INNER_G, BLOCK, 0, st>>>(s->K, at<RepDesc>(s, s->L.desc), at<RepState>(s, s->L.state),
-                                                at<int>(s, s->L.tile_rep), qcur(s, a), l->idx, l->cnt, l->iidx,
-                                                l->icnt);
+                                                at<int>(s, s->L.tile_rep), qcur(s, a), at<float4>(s, s->L.tqf),
+                                                l->idx, l->cnt, l->iidx, l->icnt);
   return check_launch();
 }
 

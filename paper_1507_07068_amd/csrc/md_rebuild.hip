@@ -1325,11 +1325,38 @@ __global__ __launch_bounds__(BLOCK) void k_xlist(Consts K, BuildArgs A) {
 #define MD_INNER_G 8   // 4: 1190 us on the 216k-atom film (paper's form); 8: 973; 16: 969
 #endif
 constexpr int INNER_G = MD_INNER_G;
+
+// FP32 positions relative to the replica's grid origin at the current positions, for the
+// inner-list screen (one lane per atom slot; the list build's scratch copy, free between
+// builds).
+__global__ __launch_bounds__(BLOCK) void k_inner_pos(const RepDesc* __restrict__ R, const RepState* __restrict__ S,
+                                                     const int* __restrict__ tile_rep, const double4* __restrict__ q,
+                                                     float4* __restrict__ qf) {
+  static_assert(TILE == BLOCK, "one block per tile");
+  const int r = tile_rep[blockIdx.x];
+  const int64_t i = (int64_t)blockIdx.x * TILE + threadIdx.x;
+  if (i >= (int64_t)R[r].a0 + R[r].n) return;
+  const double4 p = q[i];
+  const RepState& s = S[r];
+  qf[i] = make_float4((float)(p.x - s.glo[0]), (float)(p.y - s.glo[1]), (float)(p.z - s.glo[2]), 0.0f);
+}
+
+__device__ __forceinline__ float min_image_f(float d, float len, float half, int per) {
+  float s = (per && d > half) ? -len : 0.0f;
+  s = (per && d < -half) ? len : s;
+  return d + s;
+}
+
+// The screen: the FP32 squared separation from those positions decides outside a band
+// around r*^2 that covers its error (the list build's bound, with R = r* + 1 and positions
+// within R of the grid); the band gets the exact FP64 test.  On a replica with a periodic
+// length under 2 R + 1 the FP32 minimum image could pick the other image of a pair inside
+// r*, and every entry gets the exact test.
 __global__ __launch_bounds__(BLOCK) void k_inner_list(Consts K, const RepDesc* __restrict__ R,
                                                       RepState* __restrict__ S, const int* __restrict__ tile_rep,
-                                                      const double4* __restrict__ q, const int* __restrict__ idx,
-                                                      const int* __restrict__ cnt, int* __restrict__ iidx,
-                                                      int* __restrict__ icnt) {
+                                                      const double4* __restrict__ q, const float4* __restrict__ qf,
+                                                      const int* __restrict__ idx, const int* __restrict__ cnt,
+                                                      int* __restrict__ iidx, int* __restrict__ icnt) {
   static_assert(WAVE % INNER_G == 0 && INNER_G < 32, "a lane group lies in one wavefront, its mask in 32 bits");
   constexpr int APB = BLOCK / INNER_G;   // atoms per block
   const int lb = xcd_block(blockIdx.x, gridDim.x);
@@ -1340,6 +1367,7 @@ __global__ __launch_bounds__(BLOCK) void k_inner_list(Consts K, const RepDesc* _
   const int64_t i = (int64_t)tile * TILE + (lb % INNER_G) * APB + threadIdx.x / INNER_G;
   const bool live = i < (int64_t)d.a0 + d.n;
   const double4 pi = live ? q[i] : make_double4(0.0, 0.0, 0.0, 0.0);
+  const float4 pif = live ? qf[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   const bool img = wave_near_face(d, live, pi.x, pi.y, pi.z, K.rlist + 2.0 * K.half_skin);
   // every lane takes part in the ballots (atoms past the replica with an empty list)
   const int n = live ? cnt[i] : 0;
@@ -1352,21 +1380,54 @@ __global__ __launch_bounds__(BLOCK) void k_inner_list(Consts K, const RepDesc* _
   auto at_k = [&](int k) { return ((unsigned)k >> sh) * stride + base + (unsigned)(k & (T - 1)); };
   const int icap = K.icap;
   const double rc2 = K.icut_sq;
+  float lo_f = -1.0f, hi_f = INFINITY;   // (everything in the band)
+  {
+    const RepState& s = S[r];
+    const double u = 0x1p-24, Rr = sqrt(rc2) + 1.0;
+    double err = 4.0 * u * (rc2 + Rr * Rr);
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double E = s.gd[a] / s.ginv[a] + 2.0 * Rr;
+      const double eta = u * (3.0 * E + (d.per[a] ? 2.0 * d.len[a] : 0.0) + 3.0 * Rr);
+      err += 2.0 * Rr * eta + eta * eta;
+      ok = ok && !(d.per[a] && d.len[a] <= 2.0 * Rr + 1.0);
+    }
+    if (ok) {
+      const double delta = 2.0 * err + 1e-6;
+      lo_f = (float)(rc2 - delta);
+      hi_f = (float)(rc2 + delta);
+    }
+  }
+  const float len0 = (float)d.len[0], len1 = (float)d.len[1], len2 = (float)d.len[2];
+  const float hf0 = (float)d.half[0], hf1 = (float)d.half[1], hf2 = (float)d.half[2];
   const int gshift = (int)(threadIdx.x % WAVE) - sub;   // the group's first lane
   const unsigned below = (1u << sub) - 1u;
   int c = 0;        // entries kept so far
   int e = sub < n ? idx[at_k(sub)] : 0;   // (slot 0 stands in for an entry past the list)
   for (int m0 = 0; m0 < nw; m0 += INNER_G) {
     const int k = m0 + sub;
-    const double4 pj = q[list_slot(e)];
+    const float4 pjf = qf[list_slot(e)];
     const int en = k + INNER_G < n ? idx[at_k(k + INNER_G)] : 0;
-    double ex = pj.x - pi.x, ey = pj.y - pi.y, ez = pj.z - pi.z;
+    float fx = pjf.x - pif.x, fy = pjf.y - pif.y, fz = pjf.z - pif.z;
     if (img) {
-      ex = min_image(ex, d.len[0], d.half[0], d.per[0]);
-      ey = min_image(ey, d.len[1], d.half[1], d.per[1]);
-      ez = min_image(ez, d.len[2], d.half[2], d.per[2]);
+      fx = min_image_f(fx, len0, hf0, d.per[0]);
+      fy = min_image_f(fy, len1, hf1, d.per[1]);
+      fz = min_image_f(fz, len2, hf2, d.per[2]);
     }
-    const bool keep = k < n && dist_sq_exact(ex, ey, ez) < rc2;
+    const float r2f = fx * fx + fy * fy + fz * fz;
+    bool keep = r2f < lo_f;
+    if (k < n && !keep && !(r2f >= hi_f)) {   // the band (or NaN): the exact test
+      const double4 pj = q[list_slot(e)];
+      double ex = pj.x - pi.x, ey = pj.y - pi.y, ez = pj.z - pi.z;
+      if (img) {
+        ex = min_image(ex, d.len[0], d.half[0], d.per[0]);
+        ey = min_image(ey, d.len[1], d.half[1], d.per[1]);
+        ez = min_image(ez, d.len[2], d.half[2], d.per[2]);
+      }
+      keep = dist_sq_exact(ex, ey, ez) < rc2;
+    }
+    keep = keep && k < n;
     const unsigned gm = (unsigned)(__ballot(keep) >> gshift) & ((1u << INNER_G) - 1u);
     if (keep) {
       const int j = c + __popc(gm & below);
