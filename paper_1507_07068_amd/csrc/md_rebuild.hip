@@ -1322,7 +1322,7 @@ __global__ __launch_bounds__(BLOCK) void k_xlist(Consts K, BuildArgs A) {
 // positions are gathered); a ballot over the group gives each kept entry its place, so the
 // order is the outer list's.  One block per 256 / INNER_G atoms.
 #ifndef MD_INNER_G
-#define MD_INNER_G 8   // 4: 1190 us on the 216k-atom film (paper's form); 8: 973; 16: 969
+#define MD_INNER_G 16   // 4: 978 us on the 216k-atom film (paper's form); 8: 823; 16: 790
 #endif
 constexpr int INNER_G = MD_INNER_G;
 
