@@ -73,6 +73,28 @@ def test_two_tier_bulk_sets_and_forces(nc):
     assert_forces(st["f"], ref["f"], FP64_TOL)
 
 
+def test_two_tier_short_periodic_box():
+    """A periodic box under 2 (r* + 1) + 1 (6 cells of 3.2 A; an outer skin of 0.9 A keeps it
+    over twice the list radius): the inner refill's FP32 screen is off there and every outer
+    entry gets the exact test.  Inner sets against brute force at the start and after whole
+    steps; forces against the oracle."""
+    s = I.two_tier(I.bulk(6, a=3.2, seed=66, noise=0.06, name="two_tier_short_box"))
+    s.skin = 0.9
+    assert 2 * s.r_list < s.box_len.min() and s.box_len.max() <= 2 * (s.cutoff + 1.0) + 1.0
+    sim = tsim(s, tpa=2)
+    sim.md_build_neighbors(force=True)
+    sim.md_eam_forces(md.MD_F_DENSITY | md.MD_F_FORCE | md.MD_F_ENERGY, rho=True)
+    flags_clean(sim)
+    assert check_inner(sim, s) > 100 * s.n
+    ref = O.evaluate(s, O.wrap(s))
+    st = sim.state()[0]
+    assert np.allclose(st["rho"], ref["rho"], rtol=1e-12, atol=0)
+    assert_forces(st["f"], ref["f"], FP64_TOL)
+    sim.md_run(10)
+    flags_clean(sim)
+    assert check_inner(sim, s) > 100 * s.n
+
+
 @pytest.mark.parametrize("precision,tpa", [("fp64", 1), ("fp64", 4), ("mixed", 2), ("mixed", 8)])
 def test_two_tier_film_with_indenter(precision, tpa):
     s = film(seed=62)
